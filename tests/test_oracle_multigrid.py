@@ -1,0 +1,133 @@
+"""Pins of the oracle's multigrid pieces (Sec. 7.1, Alg. v_cycle) and of
+its FGMRES (Sec. 7.1-7.2)."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse.linalg as spla
+
+from oracle import fgmres, multigrid, rhs, sipg
+from paper_2407_09621_amd import inputs
+
+
+def _random_qk(k, seed):
+    c = np.random.default_rng(seed).standard_normal((k + 1, k + 1, k + 1))
+    def u(x, y, z):
+        out = 0 * x
+        for a in range(k + 1):
+            for b in range(k + 1):
+                for d in range(k + 1):
+                    out = out + c[a, b, d] * x ** a * y ** b * z ** d
+        return out
+    return u
+
+
+@pytest.mark.parametrize("k,nc", [(1, 1), (2, 2), (3, 2), (5, 1)])
+def test_prolongation_reproduces_coarse_polynomials(k, nc):
+    q = _random_qk(k, k)
+    P = multigrid.prolongation(nc, k)
+    Xc = sipg.node_coordinates(nc, k)
+    Xf = sipg.node_coordinates(2 * nc, k)
+    uc = q(Xc[:, 0], Xc[:, 1], Xc[:, 2])
+    uf = q(Xf[:, 0], Xf[:, 1], Xf[:, 2])
+    np.testing.assert_allclose(P @ uc, uf, atol=1e-10 * np.abs(uf).max())
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_restriction_maps_fine_load_to_coarse_load(k):
+    """Coarse basis functions are combinations of fine ones with the
+    coefficients of P, so P^T b_fine = b_coarse when quadrature is exact."""
+    nc = 2
+    P = multigrid.prolongation(nc, k)
+    bf = rhs.rhs(rhs.BubbleQ2, 2 * nc, k)
+    bc = rhs.rhs(rhs.BubbleQ2, nc, k)
+    np.testing.assert_allclose(P.T @ bf, bc, atol=1e-15)
+
+
+def test_patch_colouring_disjoint_and_type_cache():
+    n, k = 4, 1
+    lev = multigrid.Level(n, k)
+    for colour in range(8):
+        seen = set()
+        for v, c in lev.patches:
+            if c == colour:
+                idx = set(multigrid.patch_dofs(n, k, v).tolist())
+                assert not (idx & seen)
+                seen |= idx
+    # cached factor by type equals a direct factorization of A_PP
+    for v, _ in lev.patches:
+        idx = multigrid.patch_dofs(n, k, v)
+        App = lev.A[idx][:, idx].toarray()
+        Lc, _ = lev.patch_factor(v)
+        np.testing.assert_allclose(np.tril(Lc) @ np.tril(Lc).T, App, atol=1e-11 * np.abs(App).max())
+
+
+def test_patch_correction_zeroes_local_residual():
+    n, k = 4, 2
+    lev = multigrid.Level(n, k)
+    b = inputs.uniform_vector(lev.A.shape[0], 7)
+    x = inputs.uniform_vector(lev.A.shape[0], 8)
+    v = (2, 1, 3)
+    idx = multigrid.patch_dofs(n, k, v)
+    r = b - lev.A @ x
+    x[idx] += sla.cho_solve(lev.patch_factor(v), r[idx])
+    r2 = b - lev.A @ x
+    assert np.abs(r2[idx]).max() < 1e-12 * np.abs(r).max()
+
+
+def test_single_patch_mesh_sweep_is_exact_solve():
+    """With n = 2 the one vertex patch is the whole domain."""
+    n, k = 2, 3
+    lev = multigrid.Level(n, k)
+    b = inputs.uniform_vector(lev.A.shape[0], 9)
+    x = multigrid.smooth(lev, np.zeros_like(b), b, 1)
+    np.testing.assert_allclose(x, spla.spsolve(lev.A.tocsc(), b), rtol=1e-11, atol=1e-13)
+
+
+def test_vcycle_contracts_strongly():
+    H = multigrid.Hierarchy(8, 2)
+    A = H.levels[-1].A
+    b = inputs.uniform_vector(A.shape[0], 11)
+    xs = spla.spsolve(A.tocsc(), b)
+    x = np.zeros_like(b)
+    errs = []
+    for _ in range(3):
+        x = H.vcycle(len(H.levels) - 1, x, b)
+        errs.append(np.linalg.norm(x - xs))
+    assert errs[1] < 0.05 * errs[0] and errs[2] < 0.05 * errs[1]
+
+
+def test_one_level_vcycle_is_coarse_solve():
+    H = multigrid.Hierarchy(2, 2)
+    b = inputs.uniform_vector(H.levels[0].A.shape[0], 12)
+    x = H.precondition(b)
+    np.testing.assert_allclose(H.levels[0].A @ x, b, atol=1e-11)
+
+
+def test_fgmres_finite_termination_and_exact_preconditioner():
+    A = sipg.assemble(1, 1)
+    b = inputs.uniform_vector(8, 13)
+    x, info = fgmres.fgmres(lambda v: A @ v, b, lambda v: v, rtol=1e-12, restart=30)
+    assert info["iterations"] <= 8 and info["rel_res_true"] < 1e-11
+    Ad = A.toarray()
+    x, info = fgmres.fgmres(lambda v: A @ v, b, lambda v: np.linalg.solve(Ad, v), rtol=1e-12)
+    assert info["iterations"] == 1 and info["rel_res_true"] < 1e-12
+
+
+def test_fgmres_restart_still_converges():
+    A = sipg.assemble(2, 2)
+    b = inputs.uniform_vector(A.shape[0], 14)
+    x, info = fgmres.fgmres(lambda v: A @ v, b, lambda v: v, rtol=1e-8, restart=5, max_iters=5000)
+    assert info["converged"] and info["rel_res_true"] < 2e-8
+
+
+def test_fgmres_multigrid_small_problem():
+    """8^3 cells, Q2, V(2,2), rtol 1e-10: a few iterations (the paper reports
+    3 iterations to 1e-8 for every FP64 configuration), same solution as a
+    sparse direct solve."""
+    H = multigrid.Hierarchy(8, 2)
+    A = H.levels[-1].A
+    b = rhs.rhs(rhs.single_sine(), 8, 2)
+    x, info = fgmres.fgmres(lambda v: A @ v, b, H.precondition, rtol=1e-10)
+    assert info["iterations"] <= 5 and info["rel_res_true"] < 1e-10
+    xs = spla.spsolve(A.tocsc(), b)
+    assert np.linalg.norm(x - xs) < 1e-9 * np.linalg.norm(xs)

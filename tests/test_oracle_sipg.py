@@ -1,0 +1,105 @@
+"""Pins of the oracle's SIPG operator (Sec. 2, eq. bilinear_form; Sec. 2.1,
+eq. tensorproduct_3d) and its right-hand side / L2 error (Sec. 7.2)."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import rhs, sipg
+from paper_2407_09621_amd import inputs
+
+
+def _interp(fun, n, k):
+    P = sipg.node_coordinates(n, k)
+    return fun(P[:, 0], P[:, 1], P[:, 2])
+
+
+@pytest.mark.parametrize("k,n", [(1, 1), (1, 3), (2, 2), (3, 2), (4, 2), (2, 4)])
+def test_symmetric_positive_definite(k, n):
+    A = sipg.assemble(n, k).toarray()
+    assert np.abs(A - A.T).max() <= 1e-14 * np.abs(A).max()
+    if A.shape[0] <= 2000:
+        assert np.linalg.eigvalsh(A).min() > 0
+    np.linalg.cholesky(A)
+
+
+@pytest.mark.parametrize("k,n", [(1, 3), (2, 2), (3, 3), (5, 2), (7, 1)])
+def test_constants_annihilated_without_boundary_faces(k, n):
+    A = sipg.assemble(n, k, boundary_terms=False)
+    one = np.ones(A.shape[0])
+    assert np.abs(A @ one).max() <= 1e-13 * abs(A).max()
+
+
+@pytest.mark.parametrize("k,n", [(1, 1), (1, 4), (2, 3), (3, 2), (4, 2)])
+def test_energy_closed_forms(k, n):
+    """Exact values of the form for globally smooth functions (no interior
+    jumps), gamma = 2k(k+1) n:  a(1,1) = 6 gamma, a(x,x) = 7 gamma/3 - 1,
+    a(x,y) = 3 gamma/2."""
+    A = sipg.assemble(n, k)
+    g = 2 * k * (k + 1) * n
+    one = np.ones(A.shape[0])
+    X = _interp(lambda x, y, z: x, n, k)
+    Y = _interp(lambda x, y, z: y, n, k)
+    assert abs(one @ (A @ one) - 6 * g) < 1e-10 * g
+    assert abs(X @ (A @ X) - (7 * g / 3 - 1)) < 1e-10 * g
+    assert abs(Y @ (A @ X) - 1.5 * g) < 1e-10 * g
+
+
+@pytest.mark.parametrize("k,n", [(1, 2), (2, 3), (3, 3), (4, 2), (5, 2), (7, 2)])
+def test_quadrature_assembly_equals_kronecker_sum(k, n):
+    A = sipg.assemble(n, k)
+    u = inputs.uniform_vector(A.shape[0], seed=100 + k)
+    v = A @ u
+    w = sipg.kron_apply(u, n, k)
+    assert np.linalg.norm(v - w) <= 1e-13 * np.linalg.norm(v)
+    rows = np.random.default_rng(k).choice(A.shape[0], 40, replace=False)
+    np.testing.assert_allclose(sipg.apply_rows(u, n, k, rows), v[rows],
+                               rtol=0, atol=1e-12 * np.abs(v).max())
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_q2_solution_reproduced_exactly(k):
+    """u = x(1-x)y(1-y)z(1-z) lies in V_h for k >= 2 and SIPG is consistent,
+    so the discrete solution equals its nodal interpolant."""
+    n = 3
+    A = sipg.assemble(n, k)
+    b = rhs.rhs(rhs.BubbleQ2, n, k)
+    x = spla.spsolve(A.tocsc(), b)
+    assert np.abs(x - rhs.interpolate(rhs.BubbleQ2, n, k)).max() < 1e-13
+    assert rhs.l2_error(rhs.BubbleQ2, x, n, k) < 1e-14
+
+
+@pytest.mark.parametrize("k,ns", [(1, (2, 4, 8)), (2, (2, 4, 8)), (3, (2, 4, 6))])
+def test_l2_convergence_order(k, ns):
+    errs = []
+    for n in ns:
+        A = sipg.assemble(n, k)
+        b = rhs.rhs(rhs.single_sine(), n, k)
+        x = spla.spsolve(A.tocsc(), b)
+        errs.append(rhs.l2_error(rhs.single_sine(), x, n, k))
+    rate = np.log(errs[-2] / errs[-1]) / np.log(ns[-1] / ns[-2])
+    assert abs(rate - (k + 1)) < 0.35, (errs, rate)
+
+
+def test_rhs_and_l2_of_polynomials():
+    n, k = 2, 3
+    # interpolant of a Q_k polynomial has zero L2 error
+    class Poly:
+        u = staticmethod(lambda x, y, z: x ** 3 * y - 2 * z ** 2 * x + 1)
+        f = staticmethod(lambda x, y, z: 0 * x + 1.0)
+    assert rhs.l2_error(Poly, rhs.interpolate(Poly, n, k), n, k) < 1e-14
+    # f = 1: sum of b_I is the volume, b_I is the integral of phi_I
+    b = rhs.rhs(Poly, n, k)
+    assert abs(b.sum() - 1.0) < 1e-14
+    # sine: the total load is int f = 3 pi^2 (2/pi)^3 up to quadrature error
+    b = rhs.rhs(rhs.single_sine(), 8, 3)
+    assert abs(b.sum() - 3 * np.pi ** 2 * (2 / np.pi) ** 3) < 1e-6
+
+
+def test_cell_blocked_tensor_permutation_roundtrip():
+    n, k = 3, 2
+    u = inputs.uniform_vector(sipg.n_dofs(n, k), 5)
+    assert np.array_equal(sipg.from_tensor(sipg.to_tensor(u, n, k), n, k), u)
+    # GLL node coordinates are monotone along the global tensor axes
+    P = sipg.node_coordinates(n, k)
+    X = sipg.to_tensor(P[:, 0], n, k)
+    assert np.all(np.diff(X, axis=2) >= 0) and np.all(np.diff(X, axis=1) == 0)
