@@ -1,0 +1,172 @@
+/*
+ * sipg.h - C ABI of the MI355X (gfx950) SIPG-DG Poisson library.
+ *
+ * The library evaluates the symmetric interior-penalty DG Laplacian on a
+ * uniform Cartesian hexahedral mesh of the unit cube matrix-free by sum
+ * factorization, and solves the Poisson problem with flexible GMRES
+ * preconditioned by a geometric multigrid V-cycle with a multiplicative
+ * vertex-patch smoother whose local solves use fast diagonalization.
+ * Method: Cui, "Acceleration of Tensor-Product Operations with Tensor Cores",
+ * arXiv 2407.09621 (Sec. 2, 2.1, 7).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Mesh level l has n_l^3 cells of size h_l = 1/n_l; level 0 is the coarsest,
+ * level L-1 the finest (n_{L-1} = n_cells), n_{l-1} = n_l / 2.
+ * Degree k (1..7), N = k + 1 nodes per direction (Gauss-Lobatto points).
+ * Vectors are cell-blocked: cell c = cx + n*cy + n*n*cz owns the N^3
+ * contiguous entries c*N^3 + i + N*j + N*N*l (x fastest).  Every vector
+ * argument is a DEVICE pointer owned by the caller, holding sipg_n_dofs()
+ * entries, 8-byte aligned (FP64) or 4-byte aligned (FP32).  Input and output
+ * vectors of one call must not overlap unless the entry point says so.
+ * Calls are asynchronous on the given HIP stream (NULL = default stream)
+ * unless stated otherwise; the host arguments are read before return.
+ * A handle is not thread-safe; different handles are independent.
+ * Errors: a sipg_status is returned, and sipg_last_error() gives a
+ * thread-local message for the last failing call.  No C++ exception crosses
+ * the ABI.
+ */
+#ifndef SIPG_H
+#define SIPG_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SIPG_OK = 0,
+  SIPG_ERR_ARG = 1,            /* bad size, degree, level, NULL pointer, alias */
+  SIPG_ERR_UNSUPPORTED = 2,    /* valid request the library does not implement */
+  SIPG_ERR_OOM = 3,            /* device allocation failed */
+  SIPG_ERR_HIP = 4,            /* a HIP runtime call failed (text in last_error) */
+  SIPG_ERR_NOT_CONVERGED = 5,  /* iteration limit reached; x holds the last iterate */
+  SIPG_ERR_NONFINITE = 6       /* a NaN/Inf appeared and could not be recovered */
+} sipg_status;
+
+typedef enum {
+  SIPG_F64 = 0,   /* FP64 storage and arithmetic */
+  SIPG_F32 = 1,   /* FP32 storage and arithmetic */
+  SIPG_F16 = 2,   /* FP32 storage, FP16 products with FP32 accumulation */
+  SIPG_BF16 = 3   /* FP32 storage, BF16 products with FP32 accumulation */
+} sipg_precision;
+
+typedef struct {
+  int k;                 /* polynomial degree, 1..7 */
+  int n_cells;           /* cells per direction on the finest level */
+  int n_levels;          /* 0: coarsen down to 1, 2 or 3 cells per direction */
+  int mg_precision;      /* sipg_precision of the V-cycle (preconditioner) */
+  int error_correction;  /* 1: split-operand error correction in FP16/BF16 */
+  int nu_pre;            /* pre-smoothing sweeps (2 for V(2,2)) */
+  int nu_post;           /* post-smoothing sweeps */
+} sipg_config;
+
+typedef struct sipg_problem sipg_problem;
+
+/* Build the level hierarchy, 1D tables and workspace (Sec. 2.1, Sec. 7.1).
+ * The penalty is gamma = k(k+1)(1/h+ + 1/h-) = 2k(k+1)/h on every face
+ * (Sec. 2).  Requires n_cells = n0 * 2^(L-1) with n0 in {1, 2, 3}.  The
+ * handle owns its workspace (freed by sipg_destroy).  Synchronous. */
+sipg_status sipg_create(const sipg_config* cfg, sipg_problem** out);
+
+/* Free the handle and its workspace.  NULL-safe.  Synchronizes the device. */
+void sipg_destroy(sipg_problem* p);
+
+/* Number of levels and per-level sizes.  Return -1 on a bad argument. */
+int sipg_num_levels(const sipg_problem* p);
+int sipg_level_cells(const sipg_problem* p, int level);
+int64_t sipg_n_dofs(const sipg_problem* p, int level);
+
+/* v = A_l u in FP64 (Sec. 2.1 matrix-free loop with eq. tensorproduct_3d:
+ * cell integrals by sum factorization, face integrals through neighbour
+ * traces).  u, v: n_dofs(level) doubles, must not overlap. */
+sipg_status sipg_apply(sipg_problem* p, int level, const double* u, double* v,
+                       hipStream_t stream);
+
+/* r = b - A_l x in FP64.  r must not overlap x or b. */
+sipg_status sipg_residual(sipg_problem* p, int level, const double* b,
+                          const double* x, double* r, hipStream_t stream);
+
+/* Multiplicative vertex-patch smoother, FP64, in place on x (Sec. 7.1; the
+ * paper's references for the smoother): for colours 0..7 in order,
+ * r = b - A x, then every patch P of the colour (the 2x2x2 cells around an
+ * interior vertex, colour = parity of the vertex coordinates) adds
+ * A_PP^{-1} r_P, computed by fast diagonalization.  `sweeps` >= 0.
+ * x and b must not overlap. */
+sipg_status sipg_smooth(sipg_problem* p, int level, double* x, const double* b,
+                        int sweeps, hipStream_t stream);
+
+/* One colour step of the smoother, split for testing: for all patches of
+ * `colour` (0..7) x_P += A_PP^{-1} r_P, with r given.  r and x must not
+ * overlap. */
+sipg_status sipg_patch_correct(sipg_problem* p, int level, int colour,
+                               const double* r, double* x, hipStream_t stream);
+
+/* Level transfers (canonical embedding of nested spaces and its transpose;
+ * Alg. v_cycle coarsen / coarse-grid correction).  `level` is the FINE
+ * level (>= 1).  restrict: rc = P^T rf.  prolongate_add: xf += P ec. */
+sipg_status sipg_restrict(sipg_problem* p, int level, const double* rf,
+                          double* rc, hipStream_t stream);
+sipg_status sipg_prolongate_add(sipg_problem* p, int level, const double* ec,
+                                double* xf, hipStream_t stream);
+
+/* x = A_0^{-1} b on the coarsest level, exactly, by fast diagonalization of
+ * the Kronecker-sum coarse matrix (Alg. v_cycle, coarse grid solver). */
+sipg_status sipg_coarse_solve(sipg_problem* p, const double* b, double* x,
+                              hipStream_t stream);
+
+/* x <- V-cycle_l(x, b) with nu_pre/nu_post sweeps (Alg. v_cycle), in the
+ * handle's mg_precision (FP64 vectors in and out; converted internally).
+ * x and b must not overlap. */
+sipg_status sipg_vcycle(sipg_problem* p, int level, double* x, const double* b,
+                        hipStream_t stream);
+
+typedef struct {
+  double rtol;        /* stop when |Arnoldi residual| <= rtol * ||b||_2 */
+  int restart;        /* Krylov dimension before restart (<= 64) */
+  int max_iters;      /* total iteration limit */
+  int use_learned;    /* reserved, must be 0 */
+  int log_history;    /* 1: record the residual estimate of every iteration */
+} sipg_solve_opts;
+
+typedef struct {
+  int iterations;
+  int fell_back;           /* 1 if a non-finite preconditioner output was replaced */
+  double rel_res_est;      /* last Arnoldi estimate / ||b|| */
+  double rel_res_true;     /* ||b - A x||_2 / ||b||_2, recomputed in FP64 */
+  double seconds;          /* wall time of the solve */
+  double history[128];     /* history[i] = estimate after i iterations (i <= 127) */
+} sipg_solve_info;
+
+/* Solve A x = b on the finest level with right-preconditioned flexible GMRES
+ * (Saad 1993; Sec. 7.1-7.2), FP64 outer iteration and Gram-Schmidt
+ * (classical, twice), preconditioner = one V-cycle from zero.  x is the
+ * initial guess on entry (pass zeros for x0 = 0) and the solution on return.
+ * Blocks until done.  Returns SIPG_ERR_NOT_CONVERGED if max_iters is hit. */
+sipg_status sipg_fgmres(sipg_problem* p, double* x, const double* b,
+                        const sipg_solve_opts* opts, sipg_solve_info* info,
+                        hipStream_t stream);
+
+/* Manufactured data u = sum_m a_m sin(p_m pi x) sin(q_m pi y) sin(r_m pi z)
+ * (Sec. 7.2 uses one mode with p = q = r = 1).  amps[n_modes] and
+ * pqr[3*n_modes] are HOST arrays.
+ * rhs_sines: b_I = int f phi_I with f = -Laplace u, (k+2)-point Gauss.
+ * l2_error_sines: *err (HOST) = ||u - u_h||_L2 with (k+3)-point Gauss;
+ * synchronizes the stream. */
+sipg_status sipg_rhs_sines(sipg_problem* p, int level, int n_modes,
+                           const double* amps, const int* pqr, double* b,
+                           hipStream_t stream);
+sipg_status sipg_l2_error_sines(sipg_problem* p, int level, int n_modes,
+                                const double* amps, const int* pqr,
+                                const double* x, double* err,
+                                hipStream_t stream);
+
+/* Thread-local text of the last error ("" if none). */
+const char* sipg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SIPG_H */

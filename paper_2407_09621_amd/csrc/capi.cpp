@@ -1,0 +1,517 @@
+// C ABI of the library (include/sipg.h): the level hierarchy, the V-cycle
+// (Alg. v_cycle) and the FP64 flexible GMRES outer iteration (Sec. 7.1) as
+// host-side sequences of kernel launches on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sipg.h"
+#include "kernels.h"
+#include "tables.h"
+
+using namespace sipg;
+
+namespace {
+
+thread_local std::string g_err;
+
+sipg_status fail(sipg_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define SIPG_HIP(expr)                                                               \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail(SIPG_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define SIPG_TRY(expr)                \
+  do {                                \
+    sipg_status s_ = (expr);          \
+    if (s_ != SIPG_OK) return s_;     \
+  } while (0)
+
+}  // namespace
+
+struct sipg_problem {
+  sipg_config cfg{};
+  int k = 0, N = 0, L = 0, n0 = 0;
+  std::vector<int> n;
+  std::vector<int64_t> ndofs;
+  DevTab tab;
+  double* d_tab = nullptr;
+  std::vector<double*> wx, wb, wr;  // per-level V-cycle vectors
+  double* V = nullptr;              // Krylov basis, (restart + 1) vectors
+  double* Z = nullptr;              // preconditioned vectors, restart vectors
+  int restart_alloc = 0;
+  double* d_partial = nullptr;      // kDotBlocks * 65 doubles
+  double* d_small = nullptr;        // 512 doubles of scalars
+  int* d_flag = nullptr;
+  double* d_aux = nullptr;          // tables for rhs / l2 (grown on demand)
+  size_t aux_size = 0;
+};
+
+namespace {
+
+sipg_status check_level(const sipg_problem* p, int level) {
+  if (!p) return fail(SIPG_ERR_ARG, "NULL handle");
+  if (level < 0 || level >= p->L) return fail(SIPG_ERR_ARG, "level out of range");
+  return SIPG_OK;
+}
+
+template <typename T>
+sipg_status dev_alloc(T** ptr, size_t count) {
+  *ptr = nullptr;
+  if (count == 0) return SIPG_OK;
+  hipError_t e = hipMalloc((void**)ptr, count * sizeof(T));
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    return fail(SIPG_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  return SIPG_OK;
+}
+
+double level_h(const sipg_problem* p, int l) { return 1.0 / p->n[l]; }
+
+sipg_status residual(sipg_problem* p, int l, const double* b, const double* x, double* r,
+                     hipStream_t s) {
+  SIPG_HIP(launch_apply_f64(p->N, x, r, b, p->tab, p->n[l], level_h(p, l), s));
+  return SIPG_OK;
+}
+
+sipg_status smooth(sipg_problem* p, int l, double* x, const double* b, int sweeps,
+                   hipStream_t s) {
+  if (p->n[l] < 2) return SIPG_OK;
+  for (int sw = 0; sw < sweeps; ++sw)
+    for (int colour = 0; colour < 8; ++colour) {
+      SIPG_TRY(residual(p, l, b, x, p->wr[l], s));
+      SIPG_HIP(launch_patch_fd_f64(p->N, colour, p->wr[l], x, p->tab, p->n[l], level_h(p, l), s));
+    }
+  return SIPG_OK;
+}
+
+sipg_status vcycle(sipg_problem* p, int l, double* x, const double* b, hipStream_t s) {
+  if (l == 0) {
+    if (p->n0 > 3) return fail(SIPG_ERR_UNSUPPORTED, "coarsest level above 3 cells per direction");
+    SIPG_HIP(launch_coarse_fd_f64(p->N, p->n0, b, x, p->tab, level_h(p, 0), s));
+    return SIPG_OK;
+  }
+  SIPG_TRY(smooth(p, l, x, b, p->cfg.nu_pre, s));
+  SIPG_TRY(residual(p, l, b, x, p->wr[l], s));
+  SIPG_HIP(launch_restrict_f64(p->N, p->wr[l], p->wb[l - 1], p->tab, p->n[l - 1], s));
+  if (l - 1 > 0) SIPG_HIP(launch_fill(p->wx[l - 1], 0.0, p->ndofs[l - 1], s));
+  SIPG_TRY(vcycle(p, l - 1, p->wx[l - 1], p->wb[l - 1], s));
+  SIPG_HIP(launch_prolongate_add_f64(p->N, p->wx[l - 1], x, p->tab, p->n[l - 1], s));
+  SIPG_TRY(smooth(p, l, x, b, p->cfg.nu_post, s));
+  return SIPG_OK;
+}
+
+// dot products of V[0..nv) with w; result copied to the host
+sipg_status mdot_host(sipg_problem* p, const double* V, int64_t ld, int nv, const double* w,
+                      int64_t n, double* dev_out, double* host_out, hipStream_t s) {
+  SIPG_HIP(launch_mdot(V, ld, nv, w, n, p->d_partial, dev_out, s));
+  if (host_out) {
+    SIPG_HIP(hipMemcpyAsync(host_out, dev_out, sizeof(double) * nv, hipMemcpyDeviceToHost, s));
+    SIPG_HIP(hipStreamSynchronize(s));
+  }
+  return SIPG_OK;
+}
+
+sipg_status ensure_aux(sipg_problem* p, size_t count) {
+  if (count <= p->aux_size) return SIPG_OK;
+  if (p->d_aux) hipFree(p->d_aux);
+  p->d_aux = nullptr;
+  p->aux_size = 0;
+  SIPG_TRY(dev_alloc(&p->d_aux, count));
+  p->aux_size = count;
+  return SIPG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sipg_last_error(void) { return g_err.c_str(); }
+
+sipg_status sipg_create(const sipg_config* cfg, sipg_problem** out) {
+  if (!cfg || !out) return fail(SIPG_ERR_ARG, "NULL argument");
+  *out = nullptr;
+  if (cfg->k < 1 || cfg->k > 7) return fail(SIPG_ERR_ARG, "k must be in 1..7");
+  if (cfg->n_cells < 1 || cfg->n_cells > 1024) return fail(SIPG_ERR_ARG, "n_cells must be in 1..1024");
+  if (cfg->nu_pre < 0 || cfg->nu_post < 0 || cfg->nu_pre > 16 || cfg->nu_post > 16)
+    return fail(SIPG_ERR_ARG, "smoothing steps must be in 0..16");
+  if (cfg->mg_precision != SIPG_F64)
+    return fail(SIPG_ERR_UNSUPPORTED, "only the FP64 V-cycle is available in this build");
+  if (cfg->error_correction != 0 && cfg->error_correction != 1)
+    return fail(SIPG_ERR_ARG, "error_correction must be 0 or 1");
+  // level sizes: halve while even and above 3
+  // (a coarsest level above 3 cells per direction is allowed for operator
+  // work; its exact coarse solve then reports SIPG_ERR_UNSUPPORTED)
+  // Default hierarchy: halve while even and above 3 (coarsest 2 for powers of
+  // two, 3 for three times a power of two); n_levels > 0 takes that many of
+  // the finest levels of the full halving sequence (down to 1 cell).
+  std::vector<int> ns{cfg->n_cells};
+  while (ns.back() % 2 == 0) ns.push_back(ns.back() / 2);
+  std::vector<int> lv(ns.rbegin(), ns.rend());
+  if (cfg->n_levels < 0) return fail(SIPG_ERR_ARG, "n_levels must be >= 0");
+  if (cfg->n_levels > 0) {
+    if (cfg->n_levels > (int)lv.size()) return fail(SIPG_ERR_ARG, "too many levels for n_cells");
+    lv.erase(lv.begin(), lv.end() - cfg->n_levels);
+  } else if (lv.size() > 1 && lv.front() == 1) {
+    lv.erase(lv.begin());  // powers of two stop at 2 cells
+  }
+  auto* p = new sipg_problem();
+  p->cfg = *cfg;
+  p->k = cfg->k;
+  p->N = cfg->k + 1;
+  p->n = lv;
+  p->L = (int)lv.size();
+  p->n0 = lv.front();
+  const int64_t N3 = (int64_t)p->N * p->N * p->N;
+  for (int m : lv) p->ndofs.push_back((int64_t)m * m * m * N3);
+  std::vector<double> tab;
+  try {
+    tab = build_device_table(p->k, p->n0, p->tab.lay);
+  } catch (const std::exception& e) {
+    delete p;
+    return fail(SIPG_ERR_ARG, e.what());
+  }
+  sipg_status st = dev_alloc(&p->d_tab, tab.size());
+  if (st == SIPG_OK && hipMemcpy(p->d_tab, tab.data(), tab.size() * sizeof(double),
+                                 hipMemcpyHostToDevice) != hipSuccess)
+    st = fail(SIPG_ERR_HIP, "table upload failed");
+  p->tab.tab = p->d_tab;
+  p->wx.assign(p->L, nullptr);
+  p->wb.assign(p->L, nullptr);
+  p->wr.assign(p->L, nullptr);
+  for (int l = 0; l < p->L && st == SIPG_OK; ++l) {
+    st = dev_alloc(&p->wr[l], p->ndofs[l]);
+    if (st == SIPG_OK && l < p->L - 1) st = dev_alloc(&p->wx[l], p->ndofs[l]);
+    if (st == SIPG_OK && l < p->L - 1) st = dev_alloc(&p->wb[l], p->ndofs[l]);
+  }
+  if (st == SIPG_OK) st = dev_alloc(&p->d_partial, (size_t)kDotBlocks * 65);
+  if (st == SIPG_OK) st = dev_alloc(&p->d_small, 512);
+  if (st == SIPG_OK) st = dev_alloc(&p->d_flag, 1);
+  if (st != SIPG_OK) {
+    std::string msg = g_err;
+    sipg_destroy(p);
+    return fail(st, msg);
+  }
+  *out = p;
+  return SIPG_OK;
+}
+
+void sipg_destroy(sipg_problem* p) {
+  if (!p) return;
+  hipDeviceSynchronize();
+  auto fr = [](void* q) { if (q) hipFree(q); };
+  fr(p->d_tab);
+  for (auto q : p->wx) fr(q);
+  for (auto q : p->wb) fr(q);
+  for (auto q : p->wr) fr(q);
+  fr(p->V);
+  fr(p->Z);
+  fr(p->d_partial);
+  fr(p->d_small);
+  fr(p->d_flag);
+  fr(p->d_aux);
+  delete p;
+}
+
+int sipg_num_levels(const sipg_problem* p) { return p ? p->L : -1; }
+
+int sipg_level_cells(const sipg_problem* p, int level) {
+  if (!p || level < 0 || level >= p->L) return -1;
+  return p->n[level];
+}
+
+int64_t sipg_n_dofs(const sipg_problem* p, int level) {
+  if (!p || level < 0 || level >= p->L) return -1;
+  return p->ndofs[level];
+}
+
+sipg_status sipg_apply(sipg_problem* p, int level, const double* u, double* v, hipStream_t s) {
+  SIPG_TRY(check_level(p, level));
+  if (!u || !v) return fail(SIPG_ERR_ARG, "NULL vector");
+  if (u == v) return fail(SIPG_ERR_ARG, "u and v must not alias");
+  SIPG_HIP(launch_apply_f64(p->N, u, v, nullptr, p->tab, p->n[level], level_h(p, level), s));
+  return SIPG_OK;
+}
+
+sipg_status sipg_residual(sipg_problem* p, int level, const double* b, const double* x, double* r,
+                          hipStream_t s) {
+  SIPG_TRY(check_level(p, level));
+  if (!b || !x || !r) return fail(SIPG_ERR_ARG, "NULL vector");
+  if (r == x || r == b) return fail(SIPG_ERR_ARG, "r must not alias x or b");
+  return residual(p, level, b, x, r, s);
+}
+
+sipg_status sipg_smooth(sipg_problem* p, int level, double* x, const double* b, int sweeps,
+                        hipStream_t s) {
+  SIPG_TRY(check_level(p, level));
+  if (!x || !b) return fail(SIPG_ERR_ARG, "NULL vector");
+  if (x == b) return fail(SIPG_ERR_ARG, "x and b must not alias");
+  if (sweeps < 0) return fail(SIPG_ERR_ARG, "sweeps must be >= 0");
+  return smooth(p, level, x, b, sweeps, s);
+}
+
+sipg_status sipg_patch_correct(sipg_problem* p, int level, int colour, const double* r, double* x,
+                               hipStream_t s) {
+  SIPG_TRY(check_level(p, level));
+  if (!x || !r) return fail(SIPG_ERR_ARG, "NULL vector");
+  if (x == r) return fail(SIPG_ERR_ARG, "x and r must not alias");
+  if (colour < 0 || colour > 7) return fail(SIPG_ERR_ARG, "colour must be in 0..7");
+  if (p->n[level] < 2) return SIPG_OK;
+  SIPG_HIP(launch_patch_fd_f64(p->N, colour, r, x, p->tab, p->n[level], level_h(p, level), s));
+  return SIPG_OK;
+}
+
+sipg_status sipg_restrict(sipg_problem* p, int level, const double* rf, double* rc,
+                          hipStream_t s) {
+  SIPG_TRY(check_level(p, level));
+  if (level < 1) return fail(SIPG_ERR_ARG, "restrict needs a fine level >= 1");
+  if (!rf || !rc) return fail(SIPG_ERR_ARG, "NULL vector");
+  SIPG_HIP(launch_restrict_f64(p->N, rf, rc, p->tab, p->n[level - 1], s));
+  return SIPG_OK;
+}
+
+sipg_status sipg_prolongate_add(sipg_problem* p, int level, const double* ec, double* xf,
+                                hipStream_t s) {
+  SIPG_TRY(check_level(p, level));
+  if (level < 1) return fail(SIPG_ERR_ARG, "prolongate needs a fine level >= 1");
+  if (!ec || !xf) return fail(SIPG_ERR_ARG, "NULL vector");
+  SIPG_HIP(launch_prolongate_add_f64(p->N, ec, xf, p->tab, p->n[level - 1], s));
+  return SIPG_OK;
+}
+
+sipg_status sipg_coarse_solve(sipg_problem* p, const double* b, double* x, hipStream_t s) {
+  if (!p) return fail(SIPG_ERR_ARG, "NULL handle");
+  if (!b || !x) return fail(SIPG_ERR_ARG, "NULL vector");
+  if (b == x) return fail(SIPG_ERR_ARG, "x and b must not alias");
+  if (p->n0 > 3) return fail(SIPG_ERR_UNSUPPORTED, "coarsest level above 3 cells per direction");
+  SIPG_HIP(launch_coarse_fd_f64(p->N, p->n0, b, x, p->tab, level_h(p, 0), s));
+  return SIPG_OK;
+}
+
+sipg_status sipg_vcycle(sipg_problem* p, int level, double* x, const double* b, hipStream_t s) {
+  SIPG_TRY(check_level(p, level));
+  if (!x || !b) return fail(SIPG_ERR_ARG, "NULL vector");
+  if (x == b) return fail(SIPG_ERR_ARG, "x and b must not alias");
+  return vcycle(p, level, x, b, s);
+}
+
+sipg_status sipg_fgmres(sipg_problem* p, double* x, const double* b, const sipg_solve_opts* o,
+                        sipg_solve_info* info, hipStream_t s) {
+  if (!p || !x || !b || !o || !info) return fail(SIPG_ERR_ARG, "NULL argument");
+  if (x == b) return fail(SIPG_ERR_ARG, "x and b must not alias");
+  if (o->restart < 1 || o->restart > 64) return fail(SIPG_ERR_ARG, "restart must be in 1..64");
+  if (o->max_iters < 1) return fail(SIPG_ERR_ARG, "max_iters must be >= 1");
+  if (!(o->rtol > 0.0)) return fail(SIPG_ERR_ARG, "rtol must be > 0");
+  if (o->use_learned) return fail(SIPG_ERR_UNSUPPORTED, "learned stage not available in this build");
+  std::memset(info, 0, sizeof(*info));
+  const int m = o->restart;
+  const int L = p->L - 1;
+  const int64_t n = p->ndofs[L];
+  if (m > p->restart_alloc) {
+    if (p->V) hipFree(p->V);
+    if (p->Z) hipFree(p->Z);
+    p->V = p->Z = nullptr;
+    p->restart_alloc = 0;
+    SIPG_TRY(dev_alloc(&p->V, (size_t)(m + 1) * n));
+    SIPG_TRY(dev_alloc(&p->Z, (size_t)m * n));
+    p->restart_alloc = m;
+  }
+  SIPG_HIP(hipStreamSynchronize(s));
+  const auto t0 = std::chrono::steady_clock::now();
+  double* d_h = p->d_small;        // [0, 65)
+  double* d_h2 = p->d_small + 80;  // [80, 145)
+  double* d_nrm = p->d_small + 160;
+  double nb2 = 0.0;
+  SIPG_TRY(mdot_host(p, b, n, 1, b, n, d_nrm, &nb2, s));
+  const double nb = std::sqrt(nb2);
+  if (!std::isfinite(nb)) return fail(SIPG_ERR_NONFINITE, "right-hand side is not finite");
+  if (nb == 0.0) {
+    SIPG_HIP(launch_fill(x, 0.0, n, s));
+    SIPG_HIP(hipStreamSynchronize(s));
+    return SIPG_OK;
+  }
+  const double tol = o->rtol * nb;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hcol(m + 1);
+  auto Hm = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
+  int it = 0, hist = 0;
+  bool converged = false;
+  double est = 1.0;
+  auto record = [&](double v) {
+    est = v;
+    if (o->log_history && hist < 128) info->history[hist] = v;
+    ++hist;
+  };
+  while (it < o->max_iters && !converged) {
+    SIPG_TRY(residual(p, L, b, x, p->V, s));
+    double beta2 = 0.0;
+    SIPG_TRY(mdot_host(p, p->V, n, 1, p->V, n, d_nrm, &beta2, s));
+    const double beta = std::sqrt(beta2);
+    if (!std::isfinite(beta)) return fail(SIPG_ERR_NONFINITE, "residual is not finite");
+    record(beta / nb);
+    if (beta <= tol) {
+      converged = true;
+      break;
+    }
+    SIPG_HIP(launch_scale_copy(p->V, 1.0 / beta, p->V, n, s));
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int jd = 0;
+    for (int j = 0; j < m; ++j) {
+      double* Vj = p->V + (size_t)j * n;
+      double* Zj = p->Z + (size_t)j * n;
+      double* w = p->V + (size_t)(j + 1) * n;
+      SIPG_HIP(launch_fill(Zj, 0.0, n, s));
+      SIPG_TRY(vcycle(p, L, Zj, Vj, s));
+      SIPG_HIP(hipMemsetAsync(p->d_flag, 0, sizeof(int), s));
+      SIPG_HIP(launch_finite_check(Zj, n, p->d_flag, s));
+      int flag = 0;
+      SIPG_HIP(hipMemcpyAsync(&flag, p->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+      SIPG_HIP(hipStreamSynchronize(s));
+      if (flag) {  // preconditioner broke down: fall back to the identity
+        SIPG_HIP(launch_scale_copy(Vj, 1.0, Zj, n, s));
+        info->fell_back = 1;
+      }
+      SIPG_HIP(launch_apply_f64(p->N, Zj, w, nullptr, p->tab, p->n[L], level_h(p, L), s));
+      // classical Gram-Schmidt, twice
+      SIPG_HIP(launch_mdot(p->V, n, j + 1, w, n, p->d_partial, d_h, s));
+      SIPG_HIP(launch_maxpy(p->V, n, j + 1, d_h, w, n, nullptr, 1.0, s));
+      SIPG_HIP(launch_mdot(p->V, n, j + 1, w, n, p->d_partial, d_h2, s));
+      SIPG_HIP(launch_maxpy(p->V, n, j + 1, d_h2, w, n, d_h, 1.0, s));
+      double w2 = 0.0;
+      SIPG_TRY(mdot_host(p, w, n, 1, w, n, d_nrm, &w2, s));
+      SIPG_HIP(hipMemcpy(hcol.data(), d_h, sizeof(double) * (j + 1), hipMemcpyDeviceToHost));
+      const double hn = std::sqrt(w2);
+      if (!std::isfinite(hn)) return fail(SIPG_ERR_NONFINITE, "Arnoldi vector is not finite");
+      for (int i = 0; i <= j; ++i) Hm(i, j) = hcol[i];
+      Hm(j + 1, j) = hn;
+      if (hn > 0.0) SIPG_HIP(launch_scale_copy(w, 1.0 / hn, w, n, s));
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * Hm(i, j) + sn[i] * Hm(i + 1, j);
+        Hm(i + 1, j) = -sn[i] * Hm(i, j) + cs[i] * Hm(i + 1, j);
+        Hm(i, j) = t;
+      }
+      const double den = std::hypot(Hm(j, j), Hm(j + 1, j));
+      cs[j] = Hm(j, j) / den;
+      sn[j] = Hm(j + 1, j) / den;
+      Hm(j, j) = den;
+      Hm(j + 1, j) = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++it;
+      jd = j + 1;
+      record(std::fabs(g[j + 1]) / nb);
+      if (std::fabs(g[j + 1]) <= tol || it >= o->max_iters || den == 0.0) break;
+    }
+    for (int i = jd - 1; i >= 0; --i) {
+      double sacc = g[i];
+      for (int c = i + 1; c < jd; ++c) sacc -= Hm(i, c) * y[c];
+      y[i] = sacc / Hm(i, i);
+    }
+    SIPG_HIP(hipMemcpy(p->d_small + 192, y.data(), sizeof(double) * jd, hipMemcpyHostToDevice));
+    SIPG_HIP(launch_maxpy(p->Z, n, jd, p->d_small + 192, x, n, nullptr, -1.0, s));
+    if (std::fabs(g[jd]) <= tol) converged = true;
+  }
+  SIPG_TRY(residual(p, L, b, x, p->V, s));
+  double rr = 0.0;
+  SIPG_TRY(mdot_host(p, p->V, n, 1, p->V, n, d_nrm, &rr, s));
+  const auto t1 = std::chrono::steady_clock::now();
+  info->iterations = it;
+  info->rel_res_est = est;
+  info->rel_res_true = std::sqrt(rr) / nb;
+  info->seconds = std::chrono::duration<double>(t1 - t0).count();
+  if (!converged) return fail(SIPG_ERR_NOT_CONVERGED, "iteration limit reached");
+  return SIPG_OK;
+}
+
+sipg_status sipg_rhs_sines(sipg_problem* p, int level, int n_modes, const double* amps,
+                           const int* pqr, double* b, hipStream_t s) {
+  SIPG_TRY(check_level(p, level));
+  if (n_modes < 1 || n_modes > 64 || !amps || !pqr || !b) return fail(SIPG_ERR_ARG, "bad modes");
+  const int N = p->N, nl = p->n[level];
+  const double h = 1.0 / nl;
+  std::vector<double> nodes = make_tables_1d(p->k).nodes, xq, wq, V;
+  gauss_legendre(p->k + 2, xq, wq);
+  lagrange_eval(nodes, xq, V, nullptr);
+  const int nq = p->k + 2;
+  // coef, bx, by, bz
+  std::vector<double> host((size_t)n_modes * (1 + 3 * nl * N));
+  double* coef = host.data();
+  double* bt[3] = {coef + n_modes, coef + n_modes + (size_t)n_modes * nl * N,
+                   coef + n_modes + 2 * (size_t)n_modes * nl * N};
+  for (int m = 0; m < n_modes; ++m) {
+    const double lam = M_PI * M_PI * ((double)pqr[3 * m] * pqr[3 * m] +
+                                      (double)pqr[3 * m + 1] * pqr[3 * m + 1] +
+                                      (double)pqr[3 * m + 2] * pqr[3 * m + 2]);
+    coef[m] = amps[m] * lam;
+    for (int d = 0; d < 3; ++d)
+      for (int c = 0; c < nl; ++c)
+        for (int i = 0; i < N; ++i) {
+          double acc = 0.0;
+          for (int q = 0; q < nq; ++q)
+            acc += wq[q] * std::sin(pqr[3 * m + d] * M_PI * h * (c + xq[q])) * V[q * N + i];
+          bt[d][((size_t)m * nl + c) * N + i] = h * acc;
+        }
+  }
+  SIPG_TRY(ensure_aux(p, host.size()));
+  SIPG_HIP(hipMemcpyAsync(p->d_aux, host.data(), host.size() * sizeof(double),
+                          hipMemcpyHostToDevice, s));
+  const double* dc = p->d_aux;
+  SIPG_HIP(launch_rhs_sines(N, nl, n_modes, dc, dc + n_modes, dc + n_modes + (size_t)n_modes * nl * N,
+                            dc + n_modes + 2 * (size_t)n_modes * nl * N, b, s));
+  SIPG_HIP(hipStreamSynchronize(s));
+  return SIPG_OK;
+}
+
+sipg_status sipg_l2_error_sines(sipg_problem* p, int level, int n_modes, const double* amps,
+                                const int* pqr, const double* x, double* err, hipStream_t s) {
+  SIPG_TRY(check_level(p, level));
+  if (n_modes < 1 || n_modes > 64 || !amps || !pqr || !x || !err)
+    return fail(SIPG_ERR_ARG, "bad modes");
+  const int N = p->N, nl = p->n[level], nq = p->k + 3;
+  const double h = 1.0 / nl;
+  std::vector<double> nodes = make_tables_1d(p->k).nodes, xq, wq, V;
+  gauss_legendre(nq, xq, wq);
+  lagrange_eval(nodes, xq, V, nullptr);
+  // amps, sx, sy, sz, interp, wq
+  const size_t tab = (size_t)n_modes * nl * nq;
+  std::vector<double> host(n_modes + 3 * tab + (size_t)nq * N + nq);
+  double* a = host.data();
+  double* st[3] = {a + n_modes, a + n_modes + tab, a + n_modes + 2 * tab};
+  double* ip = a + n_modes + 3 * tab;
+  double* w = ip + (size_t)nq * N;
+  for (int m = 0; m < n_modes; ++m) {
+    a[m] = amps[m];
+    for (int d = 0; d < 3; ++d)
+      for (int c = 0; c < nl; ++c)
+        for (int q = 0; q < nq; ++q)
+          st[d][((size_t)m * nl + c) * nq + q] = std::sin(pqr[3 * m + d] * M_PI * h * (c + xq[q]));
+  }
+  for (int i = 0; i < nq * N; ++i) ip[i] = V[i];
+  for (int q = 0; q < nq; ++q) w[q] = wq[q];
+  SIPG_TRY(ensure_aux(p, host.size()));
+  SIPG_HIP(hipMemcpyAsync(p->d_aux, host.data(), host.size() * sizeof(double),
+                          hipMemcpyHostToDevice, s));
+  const double* d = p->d_aux;
+  SIPG_HIP(launch_l2_sines(N, nq, nl, n_modes, d, d + n_modes, d + n_modes + tab,
+                           d + n_modes + 2 * tab, d + n_modes + 3 * tab,
+                           d + n_modes + 3 * tab + (size_t)nq * N, h, x, p->d_partial,
+                           p->d_small + 300, s));
+  double e2 = 0.0;
+  SIPG_HIP(hipMemcpyAsync(&e2, p->d_small + 300, sizeof(double), hipMemcpyDeviceToHost, s));
+  SIPG_HIP(hipStreamSynchronize(s));
+  *err = std::sqrt(e2);
+  return SIPG_OK;
+}
+
+}  // extern "C"

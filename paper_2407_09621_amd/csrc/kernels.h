@@ -1,0 +1,58 @@
+// Launchers of the gfx950 kernels (host side).  Every launcher checks the
+// shapes its grid assumes and returns hipErrorInvalidValue on a mismatch.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "tables.h"
+
+namespace sipg {
+
+struct DevTab {
+  const double* tab = nullptr;  // device copy of build_device_table()
+  TableLayout lay;
+};
+
+// v = h * A_hat u (or r = b - h * A_hat u when b != nullptr); n cells per
+// direction, cell-blocked vectors of n^3 N^3 doubles.
+hipError_t launch_apply_f64(int N, const double* u, double* v, const double* b,
+                            const DevTab& t, int n, double h, hipStream_t s);
+
+// x_P += A_PP^{-1} r_P for all vertex patches of `colour`.
+hipError_t launch_patch_fd_f64(int N, int colour, const double* r, double* x,
+                               const DevTab& t, int n, double h, hipStream_t s);
+
+// x = A_0^{-1} b on the n0^3-cell coarse level (overwrites x).
+hipError_t launch_coarse_fd_f64(int N, int n0, const double* b, double* x,
+                                const DevTab& t, double h, hipStream_t s);
+
+// rc = P^T rf (nc coarse cells per direction) and xf += P ec.
+hipError_t launch_restrict_f64(int N, const double* rf, double* rc, const DevTab& t,
+                               int nc, hipStream_t s);
+hipError_t launch_prolongate_add_f64(int N, const double* ec, double* xf,
+                                     const DevTab& t, int nc, hipStream_t s);
+
+// BLAS-1 helpers (FP64).  `partial` holds at least kDotBlocks * nv doubles.
+constexpr int kDotBlocks = 1024;
+hipError_t launch_mdot(const double* V, int64_t ld, int nv, const double* w, int64_t n,
+                       double* partial, double* out, hipStream_t s);
+// w -= sum_i coef[i] V[i] (coef on the device); if `acc` != nullptr also
+// acc[i] += coef[i]
+hipError_t launch_maxpy(const double* V, int64_t ld, int nv, const double* coef,
+                        double* w, int64_t n, double* acc, double sign, hipStream_t s);
+hipError_t launch_scale_copy(const double* src, double alpha, double* dst, int64_t n,
+                             hipStream_t s);
+hipError_t launch_axpy(double alpha, const double* x, double* y, int64_t n, hipStream_t s);
+hipError_t launch_fill(double* x, double value, int64_t n, hipStream_t s);
+hipError_t launch_finite_check(const double* x, int64_t n, int* flag, hipStream_t s);
+
+// Manufactured right-hand side and L2 error (tables prepared on the host).
+hipError_t launch_rhs_sines(int N, int n, int n_modes, const double* coef,
+                            const double* bx, const double* by, const double* bz,
+                            double* b, hipStream_t s);
+hipError_t launch_l2_sines(int N, int nq, int n, int n_modes, const double* amps,
+                           const double* sx, const double* sy, const double* sz,
+                           const double* interp, const double* wq, double h,
+                           const double* x, double* partial, double* out, hipStream_t s);
+
+}  // namespace sipg

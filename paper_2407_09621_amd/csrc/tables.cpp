@@ -1,0 +1,361 @@
+// Host construction of the 1D data (Sec. 2: Lagrange basis on Gauss-Lobatto
+// points; Sec. 2.1: 1D mass and stiffness matrices, face evaluators S_f,
+// D_f) and of the fast-diagonalization pairs of the vertex-patch and coarse
+// 1D matrices.
+#include "tables.h"
+
+#include <cmath>
+#include <stdexcept>
+
+namespace sipg {
+
+namespace {
+
+// Legendre P_n(t) and P_{n-1}(t) by the three-term recurrence.
+void legendre(int n, double t, double& pn, double& pn1) {
+  double p0 = 1.0, p1 = t;
+  if (n == 0) { pn = 1.0; pn1 = 0.0; return; }
+  for (int m = 2; m <= n; ++m) {
+    double p2 = ((2.0 * m - 1.0) * t * p1 - (m - 1.0) * p0) / m;
+    p0 = p1;
+    p1 = p2;
+  }
+  pn = p1;
+  pn1 = p0;
+}
+
+// Gauss-Lobatto points of degree k on [-1,1]: the endpoints and the roots
+// of P_k', found by Newton's method with P_k'' from Legendre's equation.
+std::vector<double> gll_points_pm1(int k) {
+  std::vector<double> t(k + 1);
+  t[0] = -1.0;
+  t[k] = 1.0;
+  for (int i = 1; i < k; ++i) {
+    double x = -std::cos(M_PI * i / k);
+    for (int it = 0; it < 100; ++it) {
+      double p, pm;
+      legendre(k, x, p, pm);
+      double dp = k * (x * p - pm) / (x * x - 1.0);
+      double d2p = (2.0 * x * dp - k * (k + 1.0) * p) / (1.0 - x * x);
+      double dx = dp / d2p;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    t[i] = x;
+  }
+  return t;
+}
+
+std::vector<double> barycentric_weights(const std::vector<double>& x) {
+  const int n = (int)x.size();
+  std::vector<double> w(n, 1.0);
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b)
+      if (a != b) w[a] /= (x[a] - x[b]);
+  return w;
+}
+
+}  // namespace
+
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double t = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p, pm;
+      legendre(n, t, p, pm);
+      dp = n * (t * p - pm) / (t * t - 1.0);
+      double dt = p / dp;
+      t -= dt;
+      if (std::fabs(dt) < 1e-16) break;
+    }
+    double p, pm;
+    legendre(n, t, p, pm);
+    dp = n * (t * p - pm) / (t * t - 1.0);
+    // map [-1,1] -> [0,1]
+    x[n - 1 - i] = 0.5 * (t + 1.0);
+    w[n - 1 - i] = 1.0 / ((1.0 - t * t) * dp * dp);  // 2/((1-t^2)P'^2) halved
+  }
+}
+
+// Values (and optionally derivatives) of the Lagrange basis of `nodes` at
+// the points x, row-major [x.size() x N].  Values by the barycentric formula,
+// derivatives through the nodal differentiation matrix (phi_a' is a
+// polynomial of degree k-1 and is reproduced by its nodal interpolant).
+void lagrange_eval(const std::vector<double>& nodes, const std::vector<double>& x,
+                   std::vector<double>& val, std::vector<double>* der) {
+  const int N = (int)nodes.size();
+  const int Q = (int)x.size();
+  std::vector<double> bw = barycentric_weights(nodes);
+  val.assign((size_t)Q * N, 0.0);
+  for (int q = 0; q < Q; ++q) {
+    int hit = -1;
+    for (int a = 0; a < N; ++a)
+      if (x[q] == nodes[a]) hit = a;
+    if (hit >= 0) {
+      val[(size_t)q * N + hit] = 1.0;
+      continue;
+    }
+    double den = 0.0;
+    for (int a = 0; a < N; ++a) den += bw[a] / (x[q] - nodes[a]);
+    for (int a = 0; a < N; ++a) val[(size_t)q * N + a] = bw[a] / (x[q] - nodes[a]) / den;
+  }
+  if (der) {
+    // Dn[b][a] = phi_a'(x_b)
+    std::vector<double> Dn((size_t)N * N, 0.0);
+    for (int b = 0; b < N; ++b) {
+      double diag = 0.0;
+      for (int a = 0; a < N; ++a) {
+        if (a == b) continue;
+        double v = (bw[a] / bw[b]) / (nodes[b] - nodes[a]);
+        Dn[(size_t)b * N + a] = v;
+        diag -= v;
+      }
+      Dn[(size_t)b * N + b] = diag;
+    }
+    der->assign((size_t)Q * N, 0.0);
+    for (int q = 0; q < Q; ++q)
+      for (int a = 0; a < N; ++a) {
+        double s = 0.0;
+        for (int b = 0; b < N; ++b) s += val[(size_t)q * N + b] * Dn[(size_t)b * N + a];
+        (*der)[(size_t)q * N + a] = s;
+      }
+  }
+}
+
+Tables1D make_tables_1d(int k) {
+  if (k < 1 || k > kMaxN - 1) throw std::invalid_argument("degree out of range");
+  Tables1D t;
+  t.k = k;
+  const int N = k + 1;
+  t.N = N;
+  std::vector<double> tp = gll_points_pm1(k);
+  t.nodes.resize(N);
+  for (int a = 0; a < N; ++a) t.nodes[a] = 0.5 * (tp[a] + 1.0);
+  t.nodes[0] = 0.0;
+  t.nodes[N - 1] = 1.0;
+
+  std::vector<double> xq, wq, V, D;
+  gauss_legendre(N, xq, wq);
+  lagrange_eval(t.nodes, xq, V, &D);
+  t.mass.assign(N * N, 0.0);
+  t.stiff.assign(N * N, 0.0);
+  for (int a = 0; a < N; ++a)
+    for (int b = 0; b < N; ++b) {
+      double m = 0.0, s = 0.0;
+      for (int q = 0; q < N; ++q) {
+        m += wq[q] * V[q * N + a] * V[q * N + b];
+        s += wq[q] * D[q * N + a] * D[q * N + b];
+      }
+      t.mass[a * N + b] = m;
+      t.stiff[a * N + b] = s;
+    }
+
+  std::vector<double> ends = {0.0, 1.0}, Ve, De;
+  lagrange_eval(t.nodes, ends, Ve, &De);
+  t.d0.assign(De.begin(), De.begin() + N);
+  t.d1.assign(De.begin() + N, De.end());
+  const double g = 2.0 * k * (k + 1);
+  t.gamma_hat = g;
+
+  // 1D face terms (from the SIPG face integral on a point face with jump
+  // u_left - u_right and the average of the two one-sided derivatives;
+  // boundary points use the outward normal).  s0 = e_0, s1 = e_{N-1}.
+  auto e = [&](int a, int b) { return a == b ? 1.0 : 0.0; };
+  const int L = N - 1;
+  std::vector<double> LL(N * N), RR(N * N), B0(N * N), B1(N * N);
+  t.lr.assign(N * N, 0.0);
+  t.rl.assign(N * N, 0.0);
+  for (int a = 0; a < N; ++a)
+    for (int b = 0; b < N; ++b) {
+      double s1a = e(a, L), s1b = e(b, L), s0a = e(a, 0), s0b = e(b, 0);
+      LL[a * N + b] = g * s1a * s1b - 0.5 * (s1a * t.d1[b] + t.d1[a] * s1b);
+      RR[a * N + b] = g * s0a * s0b + 0.5 * (s0a * t.d0[b] + t.d0[a] * s0b);
+      t.lr[a * N + b] = -g * s1a * s0b - 0.5 * s1a * t.d0[b] + 0.5 * t.d1[a] * s0b;
+      t.rl[a * N + b] = -g * s0a * s1b + 0.5 * s0a * t.d1[b] - 0.5 * t.d0[a] * s1b;
+      B0[a * N + b] = g * s0a * s0b + (s0a * t.d0[b] + t.d0[a] * s0b);
+      B1[a * N + b] = g * s1a * s1b - (s1a * t.d1[b] + t.d1[a] * s1b);
+    }
+  for (int v = 0; v < 4; ++v) t.lcell[v] = t.stiff;
+  for (int i = 0; i < N * N; ++i) {
+    t.lcell[0][i] += RR[i] + LL[i];  // interior: left face and right face
+    t.lcell[1][i] += B0[i] + LL[i];  // at x = 0
+    t.lcell[2][i] += RR[i] + B1[i];  // at x = 1
+    t.lcell[3][i] += B0[i] + B1[i];  // single cell
+  }
+  return t;
+}
+
+bool generalized_eig(int n, const std::vector<double>& Lm, const std::vector<double>& Mm,
+                     std::vector<double>& S, std::vector<double>& lam) {
+  // Cholesky M = C C^T
+  std::vector<double> C((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double s = Mm[j * n + j];
+    for (int p = 0; p < j; ++p) s -= C[j * n + p] * C[j * n + p];
+    if (s <= 0.0) return false;
+    C[j * n + j] = std::sqrt(s);
+    for (int i = j + 1; i < n; ++i) {
+      double t = Mm[i * n + j];
+      for (int p = 0; p < j; ++p) t -= C[i * n + p] * C[j * n + p];
+      C[i * n + j] = t / C[j * n + j];
+    }
+  }
+  // Ci = C^{-1} (lower triangular)
+  std::vector<double> Ci((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    Ci[j * n + j] = 1.0 / C[j * n + j];
+    for (int i = j + 1; i < n; ++i) {
+      double s = 0.0;
+      for (int p = j; p < i; ++p) s += C[i * n + p] * Ci[p * n + j];
+      Ci[i * n + j] = -s / C[i * n + i];
+    }
+  }
+  // B = Ci L Ci^T
+  std::vector<double> T((size_t)n * n, 0.0), B((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double s = 0.0;
+      for (int p = 0; p < n; ++p) s += Ci[i * n + p] * Lm[p * n + j];
+      T[i * n + j] = s;
+    }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double s = 0.0;
+      for (int p = 0; p < n; ++p) s += T[i * n + p] * Ci[j * n + p];
+      B[i * n + j] = s;
+    }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j) {
+      double a = 0.5 * (B[i * n + j] + B[j * n + i]);
+      B[i * n + j] = B[j * n + i] = a;
+    }
+  // cyclic Jacobi: B = Q diag Q^T
+  std::vector<double> Q((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) Q[i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        tot += B[i * n + j] * B[i * n + j];
+        if (i != j) off += B[i * n + j] * B[i * n + j];
+      }
+    if (off <= 1e-32 * tot) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        double apq = B[p * n + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        double theta = (B[q * n + q] - B[p * n + p]) / (2.0 * apq);
+        double tt = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        double c = 1.0 / std::sqrt(tt * tt + 1.0), s = tt * c;
+        for (int r = 0; r < n; ++r) {  // B <- B J
+          double bp = B[r * n + p], bq = B[r * n + q];
+          B[r * n + p] = c * bp - s * bq;
+          B[r * n + q] = s * bp + c * bq;
+        }
+        for (int r = 0; r < n; ++r) {  // B <- J^T B
+          double bp = B[p * n + r], bq = B[q * n + r];
+          B[p * n + r] = c * bp - s * bq;
+          B[q * n + r] = s * bp + c * bq;
+        }
+        for (int r = 0; r < n; ++r) {  // Q <- Q J
+          double qp = Q[r * n + p], qq = Q[r * n + q];
+          Q[r * n + p] = c * qp - s * qq;
+          Q[r * n + q] = s * qp + c * qq;
+        }
+      }
+  }
+  lam.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) lam[i] = B[i * n + i];
+  // S = Ci^T Q
+  S.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double s = 0.0;
+      for (int p = 0; p < n; ++p) s += Ci[p * n + i] * Q[p * n + j];
+      S[i * n + j] = s;
+    }
+  return true;
+}
+
+namespace {
+
+// Global 1D stiffness-plus-face matrix of `cells` consecutive cells whose
+// first cell is (or is not) at the low boundary and whose last cell is (or is
+// not) at the high boundary; mass is blockdiag(Mh).
+void line_matrices(const Tables1D& t, int cells, bool low_bdry, bool high_bdry,
+                   std::vector<double>& Lm, std::vector<double>& Mm) {
+  const int N = t.N, G = cells * N;
+  Lm.assign((size_t)G * G, 0.0);
+  Mm.assign((size_t)G * G, 0.0);
+  for (int c = 0; c < cells; ++c) {
+    bool lo = (c == 0) && low_bdry, hi = (c == cells - 1) && high_bdry;
+    int v = (lo ? 1 : 0) + (hi ? 2 : 0);
+    for (int a = 0; a < N; ++a)
+      for (int b = 0; b < N; ++b) {
+        Lm[(size_t)(c * N + a) * G + c * N + b] = t.lcell[v][a * N + b];
+        Mm[(size_t)(c * N + a) * G + c * N + b] = t.mass[a * N + b];
+        if (c + 1 < cells) {
+          Lm[(size_t)(c * N + a) * G + (c + 1) * N + b] = t.lr[a * N + b];
+          Lm[(size_t)((c + 1) * N + a) * G + c * N + b] = t.rl[a * N + b];
+        }
+      }
+  }
+}
+
+}  // namespace
+
+std::vector<double> build_device_table(int k, int n0, TableLayout& lay) {
+  Tables1D t = make_tables_1d(k);
+  const int N = t.N, G = 2 * N, Gc = (n0 >= 1 && n0 <= 3) ? n0 * N : 0;
+  lay = TableLayout();
+  lay.N = N;
+  lay.G = G;
+  lay.Gc = Gc;
+  int off = 0;
+  auto take = [&](int count) { int o = off; off += count; return o; };
+  lay.mass = take(N * N);
+  lay.lcell = take(4 * N * N);
+  lay.d0 = take(N);
+  lay.d1 = take(N);
+  lay.gam = take(2);
+  lay.fd_s = take(4 * G * G);
+  lay.fd_l = take(4 * G);
+  lay.fdc_s = take(Gc * Gc);
+  lay.fdc_l = take(Gc);
+  lay.p1 = take(2 * N * N);
+  lay.total = off;
+  std::vector<double> tab(off, 0.0);
+  for (int i = 0; i < N * N; ++i) tab[lay.mass + i] = t.mass[i];
+  for (int v = 0; v < 4; ++v)
+    for (int i = 0; i < N * N; ++i) tab[lay.lcell + v * N * N + i] = t.lcell[v][i];
+  for (int a = 0; a < N; ++a) {
+    tab[lay.d0 + a] = t.d0[a];
+    tab[lay.d1 + a] = t.d1[a];
+  }
+  tab[lay.gam] = t.gamma_hat;
+  std::vector<double> Lm, Mm, S, lam;
+  for (int type = 0; type < 4; ++type) {
+    line_matrices(t, 2, type & 1, type & 2, Lm, Mm);
+    if (!generalized_eig(G, Lm, Mm, S, lam)) throw std::runtime_error("patch mass not SPD");
+    for (int i = 0; i < G * G; ++i) tab[lay.fd_s + type * G * G + i] = S[i];
+    for (int i = 0; i < G; ++i) tab[lay.fd_l + type * G + i] = lam[i];
+  }
+  if (Gc > 0) {  // exact coarse solve only for 1, 2 or 3 coarse cells per direction
+    line_matrices(t, n0, true, true, Lm, Mm);
+    if (!generalized_eig(Gc, Lm, Mm, S, lam)) throw std::runtime_error("coarse mass not SPD");
+    for (int i = 0; i < Gc * Gc; ++i) tab[lay.fdc_s + i] = S[i];
+    for (int i = 0; i < Gc; ++i) tab[lay.fdc_l + i] = lam[i];
+  }
+  // P1[(c, a), b] = phi_b((x_a + c) / 2): coarse basis at the fine nodes
+  std::vector<double> pts(2 * N), val;
+  for (int c = 0; c < 2; ++c)
+    for (int a = 0; a < N; ++a) pts[c * N + a] = 0.5 * (t.nodes[a] + c);
+  lagrange_eval(t.nodes, pts, val, nullptr);
+  for (int i = 0; i < 2 * N * N; ++i) tab[lay.p1 + i] = val[i];
+  return tab;
+}
+
+}  // namespace sipg

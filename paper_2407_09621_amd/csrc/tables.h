@@ -1,0 +1,61 @@
+// Host-side 1D data of the SIPG discretization and the layout of the
+// per-degree device table that every kernel reads.
+//
+// All tables are h-free: on a uniform Cartesian level with cell size h the
+// operator is A = h * (Mh (x) Mh (x) Lh + Mh (x) Lh (x) Mh + Lh (x) Mh (x) Mh)
+// (Sec. 2.1, eq. tensorproduct_3d, with the 1D mass scaling as h and the 1D
+// stiffness-plus-face matrix as 1/h), so one table serves every level.
+#pragma once
+#include <vector>
+
+namespace sipg {
+
+constexpr int kMaxN = 8;  // degree 7
+
+// Offsets (in doubles) of the pieces of the device table for one degree.
+struct TableLayout {
+  int N = 0;      // nodes per direction, k + 1
+  int G = 0;      // patch size per direction, 2N
+  int Gc = 0;     // coarse-grid size per direction, n0 * N
+  int mass = 0;   // Mh [N x N], row-major
+  int lcell = 0;  // Lh cell blocks [4][N x N]: 0 interior, 1 at x=0, 2 at x=1, 3 both
+  int d0 = 0;     // phi'(0) [N]
+  int d1 = 0;     // phi'(1) [N]
+  int gam = 0;    // h-free penalty 2k(k+1) [1]
+  int fd_s = 0;   // patch eigenvectors S [4][G x G] (types: bit0 lower cell at
+                  // the low boundary, bit1 upper cell at the high boundary)
+  int fd_l = 0;   // patch eigenvalues [4][G]
+  int fdc_s = 0;  // coarse eigenvectors [Gc x Gc]
+  int fdc_l = 0;  // coarse eigenvalues [Gc]
+  int p1 = 0;     // 1D prolongation [2N x N]: row (child c, node a), column b
+  int mass_f = 0; // float copies for the FP32 path start here (same order)
+  int total = 0;
+};
+
+struct Tables1D {
+  int k = 0, N = 0;
+  std::vector<double> nodes;       // GLL points on [0,1]
+  std::vector<double> mass, stiff; // Mh, Kh [N x N]
+  std::vector<double> lcell[4];    // Lh diagonal blocks by boundary type
+  std::vector<double> lr, rl;      // Lh off-diagonal blocks L_{c,c+1}, L_{c+1,c}
+  std::vector<double> d0, d1;
+  double gamma_hat = 0;
+};
+
+Tables1D make_tables_1d(int k);
+
+// Generalized eigenpairs L S = M S diag(lam), S^T M S = I for symmetric L and
+// SPD M of size n (row-major).  Returns false if M is not SPD.
+bool generalized_eig(int n, const std::vector<double>& L, const std::vector<double>& M,
+                     std::vector<double>& S, std::vector<double>& lam);
+
+// 1D Lagrange basis (values / derivatives) of the GLL nodes at points x.
+void lagrange_eval(const std::vector<double>& nodes, const std::vector<double>& x,
+                   std::vector<double>& val, std::vector<double>* der);
+
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
+
+// Full device table for degree k and coarse size n0; fills `layout`.
+std::vector<double> build_device_table(int k, int n0, TableLayout& layout);
+
+}  // namespace sipg

@@ -1,0 +1,242 @@
+"""Thin ctypes binding of the C ABI in include/sipg.h.
+
+Argument marshalling only: every step of the method runs in the HIP library
+(libsipg.so next to this file).  torch supplies device memory and streams;
+vectors are contiguous CUDA (HIP) tensors passed by data pointer.  Loading
+fails loudly when the library is missing - there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsipg.so")
+
+SIPG_OK = 0
+STATUS = {0: "SIPG_OK", 1: "SIPG_ERR_ARG", 2: "SIPG_ERR_UNSUPPORTED", 3: "SIPG_ERR_OOM",
+          4: "SIPG_ERR_HIP", 5: "SIPG_ERR_NOT_CONVERGED", 6: "SIPG_ERR_NONFINITE"}
+PRECISION = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
+
+_lib = None
+
+
+class SipgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int), ("n_cells", ctypes.c_int), ("n_levels", ctypes.c_int),
+                ("mg_precision", ctypes.c_int), ("error_correction", ctypes.c_int),
+                ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("restart", ctypes.c_int), ("max_iters", ctypes.c_int),
+                ("use_learned", ctypes.c_int), ("log_history", ctypes.c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("fell_back", ctypes.c_int),
+                ("rel_res_est", ctypes.c_double), ("rel_res_true", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("history", ctypes.c_double * 128)]
+
+
+def load_library(path=None):
+    """Load libsipg.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    # torch ships its own HIP runtime with the same soname as the system one;
+    # load it first so that the library binds to that single runtime instead
+    # of bringing a second HSA runtime into the process.
+    import torch  # noqa: F401
+    if not os.path.exists(p):
+        raise FileNotFoundError(
+            f"{p} not found: build it with `python -m paper_2407_09621_amd.build`")
+    lib = ctypes.CDLL(p)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "sipg_create": (i32, [ctypes.POINTER(Config), ctypes.POINTER(vp)]),
+        "sipg_destroy": (None, [vp]),
+        "sipg_num_levels": (i32, [vp]),
+        "sipg_level_cells": (i32, [vp, i32]),
+        "sipg_n_dofs": (i64, [vp, i32]),
+        "sipg_apply": (i32, [vp, i32, vp, vp, vp]),
+        "sipg_residual": (i32, [vp, i32, vp, vp, vp, vp]),
+        "sipg_smooth": (i32, [vp, i32, vp, vp, i32, vp]),
+        "sipg_patch_correct": (i32, [vp, i32, i32, vp, vp, vp]),
+        "sipg_restrict": (i32, [vp, i32, vp, vp, vp]),
+        "sipg_prolongate_add": (i32, [vp, i32, vp, vp, vp]),
+        "sipg_coarse_solve": (i32, [vp, vp, vp, vp]),
+        "sipg_vcycle": (i32, [vp, i32, vp, vp, vp]),
+        "sipg_fgmres": (i32, [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp]),
+        "sipg_rhs_sines": (i32, [vp, i32, i32, vp, vp, vp, vp]),
+        "sipg_l2_error_sines": (i32, [vp, i32, i32, vp, vp, vp, ctypes.POINTER(dbl), vp]),
+        "sipg_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != SIPG_OK:
+        raise SipgError(status, _lib.sipg_last_error().decode())
+
+
+def _ptr(t, dtype=None):
+    """Device pointer of a contiguous CUDA tensor."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Problem:
+    """A SIPG Poisson problem on n_cells^3 cells of degree k, with its level
+    hierarchy (level 0 coarsest, level -1 finest)."""
+
+    def __init__(self, k, n_cells, n_levels=0, mg_precision="f64", error_correction=False,
+                 nu_pre=2, nu_post=2):
+        lib = load_library()
+        cfg = Config(k, n_cells, n_levels, PRECISION[mg_precision], int(bool(error_correction)),
+                     nu_pre, nu_post)
+        h = ctypes.c_void_p()
+        _check(lib.sipg_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self.k = k
+        self.N = k + 1
+        self.n_cells = n_cells
+        self.num_levels = lib.sipg_num_levels(h)
+        self.cells = [lib.sipg_level_cells(h, l) for l in range(self.num_levels)]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().sipg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _lvl(self, level):
+        return level % self.num_levels
+
+    def n_dofs(self, level=-1):
+        return int(_lib.sipg_n_dofs(self._h, self._lvl(level)))
+
+    def new_vector(self, level=-1, dtype=None):
+        import torch
+        return torch.zeros(self.n_dofs(level), dtype=dtype or torch.float64, device="cuda")
+
+    def apply(self, u, v=None, level=-1, stream=None):
+        import torch
+        v = torch.empty_like(u) if v is None else v
+        _check(_lib.sipg_apply(self._h, self._lvl(level), _ptr(u, torch.float64),
+                               _ptr(v, torch.float64), _stream(stream)))
+        return v
+
+    def residual(self, b, x, r=None, level=-1, stream=None):
+        import torch
+        r = torch.empty_like(b) if r is None else r
+        _check(_lib.sipg_residual(self._h, self._lvl(level), _ptr(b, torch.float64),
+                                  _ptr(x, torch.float64), _ptr(r, torch.float64), _stream(stream)))
+        return r
+
+    def smooth(self, x, b, sweeps=1, level=-1, stream=None):
+        import torch
+        _check(_lib.sipg_smooth(self._h, self._lvl(level), _ptr(x, torch.float64),
+                                _ptr(b, torch.float64), int(sweeps), _stream(stream)))
+        return x
+
+    def patch_correct(self, colour, r, x, level=-1, stream=None):
+        import torch
+        _check(_lib.sipg_patch_correct(self._h, self._lvl(level), int(colour),
+                                       _ptr(r, torch.float64), _ptr(x, torch.float64),
+                                       _stream(stream)))
+        return x
+
+    def restrict(self, rf, rc=None, level=-1, stream=None):
+        import torch
+        lvl = self._lvl(level)
+        rc = self.new_vector(lvl - 1) if rc is None else rc
+        _check(_lib.sipg_restrict(self._h, lvl, _ptr(rf, torch.float64), _ptr(rc, torch.float64),
+                                  _stream(stream)))
+        return rc
+
+    def prolongate_add(self, ec, xf, level=-1, stream=None):
+        import torch
+        _check(_lib.sipg_prolongate_add(self._h, self._lvl(level), _ptr(ec, torch.float64),
+                                        _ptr(xf, torch.float64), _stream(stream)))
+        return xf
+
+    def coarse_solve(self, b, x=None, stream=None):
+        import torch
+        x = torch.empty_like(b) if x is None else x
+        _check(_lib.sipg_coarse_solve(self._h, _ptr(b, torch.float64), _ptr(x, torch.float64),
+                                      _stream(stream)))
+        return x
+
+    def vcycle(self, x, b, level=-1, stream=None):
+        import torch
+        _check(_lib.sipg_vcycle(self._h, self._lvl(level), _ptr(x, torch.float64),
+                                _ptr(b, torch.float64), _stream(stream)))
+        return x
+
+    def fgmres(self, b, x=None, rtol=1e-10, restart=30, max_iters=200, log_history=True,
+               stream=None, raise_on_nonconvergence=True):
+        import torch
+        x = torch.zeros_like(b) if x is None else x
+        opts = SolveOpts(rtol, restart, max_iters, 0, int(log_history))
+        info = SolveInfo()
+        st = _lib.sipg_fgmres(self._h, _ptr(x, torch.float64), _ptr(b, torch.float64),
+                              ctypes.byref(opts), ctypes.byref(info), _stream(stream))
+        if st != SIPG_OK and (raise_on_nonconvergence or st != 5):
+            _check(st)
+        out = dict(iterations=info.iterations, fell_back=bool(info.fell_back),
+                   rel_res_est=info.rel_res_est, rel_res_true=info.rel_res_true,
+                   seconds=info.seconds, status=STATUS[st],
+                   history=list(info.history[:min(info.iterations + 1, 128)]))
+        return x, out
+
+    def rhs_sines(self, amps, pqr, b=None, level=-1, stream=None):
+        import torch
+        amps = np.ascontiguousarray(amps, dtype=np.float64).reshape(-1)
+        pqr = np.ascontiguousarray(pqr, dtype=np.int32).reshape(-1, 3)
+        b = self.new_vector(level) if b is None else b
+        _check(_lib.sipg_rhs_sines(self._h, self._lvl(level), len(amps),
+                                   amps.ctypes.data_as(ctypes.c_void_p),
+                                   pqr.ctypes.data_as(ctypes.c_void_p),
+                                   _ptr(b, torch.float64), _stream(stream)))
+        return b
+
+    def l2_error_sines(self, amps, pqr, x, level=-1, stream=None):
+        import torch
+        amps = np.ascontiguousarray(amps, dtype=np.float64).reshape(-1)
+        pqr = np.ascontiguousarray(pqr, dtype=np.int32).reshape(-1, 3)
+        err = ctypes.c_double()
+        _check(_lib.sipg_l2_error_sines(self._h, self._lvl(level), len(amps),
+                                        amps.ctypes.data_as(ctypes.c_void_p),
+                                        pqr.ctypes.data_as(ctypes.c_void_p),
+                                        _ptr(x, torch.float64), ctypes.byref(err),
+                                        _stream(stream)))
+        return err.value

@@ -1,0 +1,149 @@
+"""CPU checks of the boundary: the HIP library loads and exports every entry
+point that include/sipg.h declares; the host-side 1D tables (compiled from
+the library's own C++ source with g++, no GPU) agree with the oracle."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sipg.h")
+
+
+def declared_entry_points():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sipg_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_entry_points()
+    for must in ["sipg_create", "sipg_destroy", "sipg_apply", "sipg_smooth", "sipg_vcycle",
+                 "sipg_fgmres", "sipg_last_error"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2407_09621_amd import sipg
+    lib = sipg.load_library()
+    missing = [n for n in declared_entry_points() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert isinstance(lib.sipg_last_error(), bytes)
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    from paper_2407_09621_amd import sipg
+    with pytest.raises(FileNotFoundError):
+        sipg.load_library(str(tmp_path / "missing.so"))
+
+
+SHIM = r"""
+#include "tables.h"
+#include <cstring>
+using namespace sipg;
+extern "C" int shim_layout(int k, int n0, int* lay) {
+  TableLayout L; build_device_table(k, n0, L);
+  int v[] = {L.N, L.G, L.Gc, L.mass, L.lcell, L.d0, L.d1, L.gam, L.fd_s, L.fd_l,
+             L.fdc_s, L.fdc_l, L.p1, L.total};
+  std::memcpy(lay, v, sizeof(v)); return L.total; }
+extern "C" void shim_table(int k, int n0, double* out) {
+  TableLayout L; auto t = build_device_table(k, n0, L);
+  std::memcpy(out, t.data(), t.size() * sizeof(double)); }
+extern "C" void shim_offdiag(int k, double* lr, double* rl) {
+  Tables1D t = make_tables_1d(k);
+  std::memcpy(lr, t.lr.data(), t.lr.size() * 8); std::memcpy(rl, t.rl.data(), t.rl.size() * 8); }
+"""
+
+
+@pytest.fixture(scope="module")
+def host_tables(tmp_path_factory):
+    d = tmp_path_factory.mktemp("shim")
+    src = d / "shim.cpp"
+    src.write_text(SHIM)
+    so = d / "shim.so"
+    csrc = os.path.join(ROOT, "paper_2407_09621_amd", "csrc")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-I", csrc, str(src),
+                    os.path.join(csrc, "tables.cpp"), "-o", str(so)], check=True)
+    lib = ctypes.CDLL(str(so))
+
+    def get(k, n0=2):
+        lay = (ctypes.c_int * 14)()
+        total = lib.shim_layout(k, n0, lay)
+        keys = ["N", "G", "Gc", "mass", "lcell", "d0", "d1", "gam", "fd_s", "fd_l", "fdc_s",
+                "fdc_l", "p1", "total"]
+        L = dict(zip(keys, list(lay)))
+        buf = np.zeros(total)
+        lib.shim_table(k, n0, buf.ctypes.data_as(ctypes.c_void_p))
+        N = k + 1
+        lr = np.zeros(N * N)
+        rl = np.zeros(N * N)
+        lib.shim_offdiag(k, lr.ctypes.data_as(ctypes.c_void_p), rl.ctypes.data_as(ctypes.c_void_p))
+        return L, buf, lr.reshape(N, N), rl.reshape(N, N)
+    return get
+
+
+@pytest.mark.parametrize("k", range(1, 8))
+def test_host_tables_match_oracle(host_tables, k):
+    from oracle import basis1d, sipg as osipg
+    L, t, lr, rl = host_tables(k, 3)
+    N = k + 1
+    Mh, Kh = basis1d.mass_stiffness(k)
+    np.testing.assert_allclose(t[L["mass"]:L["mass"] + N * N].reshape(N, N), Mh, atol=1e-13)
+    s0, s1, d0, d1 = basis1d.end_vectors(k)
+    np.testing.assert_allclose(t[L["d0"]:L["d0"] + N], d0, atol=1e-10 * np.abs(d0).max())
+    np.testing.assert_allclose(t[L["d1"]:L["d1"] + N], d1, atol=1e-10 * np.abs(d1).max())
+    # cell blocks and couplings against the oracle's global 1D matrix (h = 1)
+    for n in (1, 3):
+        M, Lg = osipg.global_1d(n, k)
+        Lg = Lg / n  # h-free
+        blocks = t[L["lcell"]:L["lcell"] + 4 * N * N].reshape(4, N, N)
+        if n == 1:
+            np.testing.assert_allclose(blocks[3], Lg, atol=1e-10 * np.abs(Lg).max())
+        else:
+            sc = np.abs(Lg).max() * 1e-11
+            np.testing.assert_allclose(blocks[1], Lg[:N, :N], atol=sc)
+            np.testing.assert_allclose(blocks[0], Lg[N:2 * N, N:2 * N], atol=sc)
+            np.testing.assert_allclose(blocks[2], Lg[2 * N:, 2 * N:], atol=sc)
+            np.testing.assert_allclose(lr, Lg[:N, N:2 * N], atol=sc)
+            np.testing.assert_allclose(rl, Lg[N:2 * N, :N], atol=sc)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 7])
+def test_host_fast_diagonalization_pairs(host_tables, k):
+    """S^T M_P S = I and S^T L_P S = diag(lam) for the four patch types and
+    the coarse grid, with M_P, L_P from the oracle's global 1D matrices."""
+    from oracle import sipg as osipg
+    for n0 in (1, 2, 3):
+        L, t, _, _ = host_tables(k, n0)
+        N, G, Gc = L["N"], L["G"], L["Gc"]
+        for typ in range(4):
+            # a line of 4 cells; the patch is cells (1,2) with boundary flags
+            n = 2 + (0 if typ & 1 else 1) + (0 if typ & 2 else 1)
+            first = 0 if typ & 1 else 1
+            M, Lg = osipg.global_1d(n, k)
+            sl = slice(first * N, (first + 2) * N)
+            Mp, Lp = M[sl, sl] * n, Lg[sl, sl] / n
+            S = t[L["fd_s"] + typ * G * G:L["fd_s"] + (typ + 1) * G * G].reshape(G, G)
+            lam = t[L["fd_l"] + typ * G:L["fd_l"] + (typ + 1) * G]
+            np.testing.assert_allclose(S.T @ Mp @ S, np.eye(G), atol=1e-9)
+            np.testing.assert_allclose(S.T @ Lp @ S, np.diag(lam), atol=1e-9 * np.abs(lam).max())
+        M, Lg = osipg.global_1d(n0, k)
+        S = t[L["fdc_s"]:L["fdc_s"] + Gc * Gc].reshape(Gc, Gc)
+        lam = t[L["fdc_l"]:L["fdc_l"] + Gc]
+        np.testing.assert_allclose(S.T @ (M * n0) @ S, np.eye(Gc), atol=1e-9)
+        np.testing.assert_allclose(S.T @ (Lg / n0) @ S, np.diag(lam), atol=1e-9 * np.abs(lam).max())
+
+
+@pytest.mark.parametrize("k", [1, 3, 6])
+def test_host_prolongation_table(host_tables, k):
+    from oracle import multigrid
+    L, t, _, _ = host_tables(k)
+    N = k + 1
+    P1 = t[L["p1"]:L["p1"] + 2 * N * N].reshape(2 * N, N)
+    # the 3D embedding of child (0,0,0) is P1[:N] (x) P1[:N] (x) P1[:N]
+    E = multigrid._child_embedding(k, (1, 0, 1))
+    K = np.kron(P1[N:], np.kron(P1[:N], P1[N:]))
+    np.testing.assert_allclose(E, K, atol=1e-12)
