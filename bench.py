@@ -1,0 +1,201 @@
+"""Benchmark of the FP64 SIPG operator apply on one MI355X.
+
+Workload (the paper's operator-apply benchmark, Sec. 4, at the apply
+configuration of this project): the SIPG Laplacian on uniform Cartesian
+meshes of the unit cube, degree 3 on 64^3 cells (16.8 MDoF), degree 5 on
+40^3 (13.8 MDoF) and degree 7 on 32^3 (16.8 MDoF), input vectors seeded
+U[-1, 1] FP64.  One step = one apply at each of the three degrees.  Inputs
+are resident in HBM before timing; each degree rotates over 4 (u, v) pairs
+(>= 1 GB) so the 256 MB last-level cache cannot hold the working set.
+
+Prints one JSON line: value = total DoFs applied / second (GDoF/s) over the
+timed steps, the roofline of the dominant kernel (HIP-event timing of the
+kernel on its own stream), the oracle's CPU rate on a bounded sample, and,
+outside the timed region, the FP64 FGMRES + multigrid solve times.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+CONFIGS = [(3, 64), (5, 40), (7, 32)]
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+BYTES_PER_DOF = 16.0          # read u, write v (FP64)
+ROTATE = 4
+
+
+def flops_per_dof(k):
+    """Model count: 7 sum-factorized N x N products per cell (14 N flop/DoF)
+    plus face traces and expansions (48 flop/DoF)."""
+    return 14 * (k + 1) + 48
+
+
+def cpu_baseline():
+    """The oracle's Kronecker-sum apply (numpy/scipy, FP64) on one apply of
+    each degree at the full sizes."""
+    import numpy as np
+    from oracle import sipg as osipg
+    from paper_2407_09621_amd import inputs
+    total = 0
+    t = 0.0
+    for k, n in CONFIGS:
+        u = inputs.uniform_vector(n ** 3 * (k + 1) ** 3, seed=2 + k)
+        t0 = time.perf_counter()
+        osipg.kron_apply(u, n, k)
+        t += time.perf_counter() - t0
+        total += u.size
+    return {"value": total / t / 1e9, "unit": "GDoF/s", "cores": 1, "kind": "oracle",
+            "sample": "one FP64 apply at each of k=3 (64^3), k=5 (40^3), k=7 (32^3) "
+                      "by the oracle's Kronecker-sum path (scipy.sparse, single-threaded); "
+                      f"{t:.1f} s"}
+
+
+def run_solves(P_cache):
+    """FP64 FGMRES(30) + V(2,2) solves of the sine problem (outside the timed
+    region): time to rtol 1e-10, iterations, L2 error."""
+    import torch
+    from paper_2407_09621_amd import Problem, inputs
+    out = {}
+    amps, pqr = inputs.single_sine_modes()
+    for k, n in [(3, 64), (7, 32)]:
+        P = Problem(k, n)
+        b = P.rhs_sines(amps, pqr)
+        x, info = P.fgmres(b, rtol=1e-10)  # warm-up (allocates the Krylov space)
+        x.zero_()
+        torch.cuda.synchronize()
+        x, info = P.fgmres(b, x=x, rtol=1e-10)
+        err = P.l2_error_sines(amps, pqr, x)
+        out[f"k{k}_n{n}"] = {"seconds": round(info["seconds"], 4), "iterations": info["iterations"],
+                             "rel_res_true": info["rel_res_true"], "l2_error": err,
+                             "mg_precision": "f64"}
+        P.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-solve", action="store_true", help="skip the solve measurements")
+    ap.add_argument("--mode", choices=["bench", "profile"], default="bench",
+                    help="profile: a few applies per degree and a plain copy of a known size "
+                         "(for rocprofv3 kernel traces and HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2407_09621_amd import Problem, inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    probs = []
+    for k, n in CONFIGS:
+        P = Problem(k, n, n_levels=1)
+        nd = P.n_dofs()
+        base = torch.from_numpy(inputs.uniform_vector(nd, seed=2 + k)).to(dev)
+        us = [base.clone() for _ in range(ROTATE)]
+        for i in range(1, ROTATE):
+            us[i].mul_(1.0 - 0.01 * i)
+        vs = [torch.empty_like(base) for _ in range(ROTATE)]
+        probs.append((k, n, P, nd, us, vs))
+    torch.cuda.synchronize()
+
+    if args.mode == "profile":
+        for k, n, P, nd, us, vs in probs:
+            for i in range(5):
+                P.apply(us[i % ROTATE], vs[i % ROTATE], stream=stream)
+            torch.cuda.synchronize()
+            print(f"profiled apply k={k} n={n}: 5 launches, {nd} DoFs", flush=True)
+        # calibration: a plain device copy of exactly 2^27 bytes (read) + 2^27 (write)
+        a = torch.empty(1 << 24, dtype=torch.float64, device=dev).uniform_()
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print("profiled copy: 5 launches of 134217728 bytes", flush=True)
+        return
+
+    # warm-up
+    for _ in range(args.warmup):
+        for k, n, P, nd, us, vs in probs:
+            P.apply(us[0], vs[0], stream=stream)
+    torch.cuda.synchronize()
+
+    # per-degree kernel timing with events on the launch stream
+    per_k = {}
+    for k, n, P, nd, us, vs in probs:
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps = max(args.steps, 1)
+        e0.record(stream)
+        for i in range(reps):
+            P.apply(us[i % ROTATE], vs[i % ROTATE], stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        gdofs = nd / (ms * 1e-3) / 1e9
+        per_k[f"k{k}_n{n}"] = {
+            "ms_per_apply": round(ms, 5), "gdof_s": round(gdofs, 2),
+            "hbm_gb_s": round(gdofs * BYTES_PER_DOF, 1),
+            "hbm_frac": round(gdofs * BYTES_PER_DOF / HBM_PEAK_GBS, 4),
+            "fp64_tflops_model": round(gdofs * flops_per_dof(k) / 1e3, 2),
+            "fp64_frac_model": round(gdofs * flops_per_dof(k) / 1e3 / FP64_PEAK_TFLOPS, 4),
+            "n_dofs": nd}
+
+    # the timed region: K steps, each one apply per degree
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        for k, n, P, nd, us, vs in probs:
+            P.apply(us[s % ROTATE], vs[s % ROTATE], stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    total_dofs = sum(p[3] for p in probs) * args.steps
+    seconds = t1 - t0
+    value = total_dofs / seconds / 1e9
+
+    # dominant kernel = the degree with the largest share of the step
+    dom = max(per_k.items(), key=lambda kv: kv[1]["ms_per_apply"])
+    dk = dom[1]
+    roofline = {"bound": "hbm", "achieved": dk["hbm_gb_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(dk["hbm_gb_s"] / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": f"apply_f64_kernel ({dom[0]})",
+                "bytes_per_launch": int(dk["n_dofs"] * BYTES_PER_DOF)}
+
+    for k, n, P, nd, us, vs in probs:
+        P.close()
+    del probs
+    torch.cuda.empty_cache()
+
+    solves = None if args.no_solve else run_solves(None)
+    cpu = None if args.no_cpu else cpu_baseline()
+
+    line = {
+        "metric": "SIPG apply GDoF/s (FP64/FP16 MFMA); FGMRES-MG solve time at equal L2 error",
+        "value": round(value, 3), "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(seconds / max(args.steps, 1) * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "FP64 SIPG operator apply, unit cube, uniform Cartesian: "
+                               "k=3 on 64^3 cells, k=5 on 40^3, k=7 on 32^3; u ~ U[-1,1] seeded; "
+                               "one step = one apply per degree",
+                   "parallelism": "single GPU"},
+        "per_k": per_k, "roofline": roofline, "cpu_baseline": cpu, "solves_fp64": solves,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()
