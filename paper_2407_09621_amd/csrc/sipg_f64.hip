@@ -90,128 +90,196 @@ __device__ __forceinline__ int bdry_variant(int coord, int n) {
   return (coord == 0 ? 1 : 0) | (coord == n - 1 ? 2 : 0);
 }
 
+// The diagonal block of a cell at a boundary differs from the interior one
+// by a rank-2 term: at x = 0 the boundary face adds (s0 d0^T + d0 s0^T)/2
+// more than an interior face, at x = 1 it adds -(s1 d1^T + d1 s1^T)/2.
+// Applied to the line x (before any face term is added to t).
+template <int N>
+__device__ __forceinline__ void add_boundary_correction(double (&t)[N], const double (&x)[N],
+                                                        bool lo, bool hi,
+                                                        const double* __restrict__ d0,
+                                                        const double* __restrict__ d1) {
+  if (lo) {
+    double g = 0.0;
+#pragma unroll
+    for (int a = 0; a < N; ++a) g = fma(d0[a], x[a], g);
+    t[0] += 0.5 * g;
+#pragma unroll
+    for (int a = 0; a < N; ++a) t[a] = fma(0.5 * d0[a], x[0], t[a]);
+  }
+  if (hi) {
+    double g = 0.0;
+#pragma unroll
+    for (int a = 0; a < N; ++a) g = fma(d1[a], x[a], g);
+    t[N - 1] -= 0.5 * g;
+#pragma unroll
+    for (int a = 0; a < N; ++a) t[a] = fma(-0.5 * d1[a], x[N - 1], t[a]);
+  }
+}
+
 // ---------------------------------------------------------------------------
-// Operator apply: CPB cells per workgroup, one thread per 1D line per stage.
+// Operator apply.  A workgroup owns a tile of TX consecutive cells along x
+// (TX <= CPB divides n); one thread per 1D line per stage.  Tiles are
+// ordered so that a cell's six face neighbours are processed close in time
+// on the same XCD: x-tiles fastest, then z and y in 8 x 8 blocks.
 // ---------------------------------------------------------------------------
+struct TileMap {
+  int n, tx, ntx, blk;  // blk = 8 when n % 8 == 0 (blocked order), else 1
+};
+
+__device__ __forceinline__ int tile_first_cell(const TileMap& m, int t) {
+  const int txi = t % m.ntx;
+  int r = t / m.ntx;
+  int cy, cz;
+  if (m.blk > 1) {
+    const int zi = r % m.blk;
+    r /= m.blk;
+    const int yi = r % m.blk;
+    r /= m.blk;
+    const int nb = m.n / m.blk;
+    const int zb = r % nb, yb = r / nb;
+    cz = zb * m.blk + zi;
+    cy = yb * m.blk + yi;
+  } else {
+    cy = r % m.n;
+    cz = r / m.n;
+  }
+  return (cz * m.n + cy) * m.n + txi * m.tx;
+}
+
 template <int N, bool RES>
 __global__ __launch_bounds__(kThreads) void apply_f64_kernel(
     const double* __restrict__ u, double* __restrict__ v, const double* __restrict__ bvec,
-    const double* __restrict__ tab, TableLayout lay, int n, double h, int ncells) {
+    const double* __restrict__ tab, TableLayout lay, TileMap tm, double h) {
   constexpr int N2 = N * N, N3 = N2 * N, CPB = kThreads / N2;
-  __shared__ double s_M[N2];
-  __shared__ double s_L[4 * N2];
-  __shared__ double s_d0[N], s_d1[N];
-  __shared__ double s_u[CPB * N3];
   __shared__ double s_t1[CPB * N3];
   __shared__ double s_t2[CPB * N3];
-  __shared__ double s_tr[CPB * 12 * N2];  // [cell][face 0..5][value, derivative][N2]
+  // per cell: y-face traces [face 0,1][value, derivative][i + N l] and
+  // z-face traces [face 0,1][value, derivative][i + N j], raw then after Mx
+  __shared__ double s_ty[CPB * 4 * N2];
+  __shared__ double s_tz[CPB * 4 * N2];
+  __shared__ double s_tzm[CPB * 4 * N2];
 
   const int tid = threadIdx.x;
-  const int c0 = xcd_remap(blockIdx.x, gridDim.x) * CPB;
-  const int nc = min(CPB, ncells - c0);
-  if (nc <= 0) return;
-  for (int i = tid; i < N2; i += kThreads) s_M[i] = tab[lay.mass + i];
-  for (int i = tid; i < 4 * N2; i += kThreads) s_L[i] = tab[lay.lcell + i];
-  if (tid < N) {
-    s_d0[tid] = tab[lay.d0 + tid];
-    s_d1[tid] = tab[lay.d1 + tid];
-  }
-  const double gam = tab[lay.gam];
-  const double* ug = u + (size_t)c0 * N3;
-  for (int i = tid; i < nc * N3; i += kThreads) s_u[i] = ug[i];
-  __syncthreads();
+  const int n = tm.n, nn = n * n, nc = tm.tx;
+  const int c0 = tile_first_cell(tm, xcd_remap(blockIdx.x, gridDim.x));
+  const int cy = (c0 / n) % n, cz = c0 / nn, cx0 = c0 % n;
+  const bool act = tid < nc * N2;
+  const int cl = act ? tid / N2 : 0, ln = tid - cl * N2;
+  const int c = c0 + cl, cx = cx0 + cl;
+  // this thread owns x-line (j, l) = (ln % N, ln / N) of cell c and the
+  // y-/z-face trace lines at (i, l) = (ln % N, ln / N) and (i, j) = ln.
+  const int lp = ln % N, lq = ln / N;
 
-  // Face traces of the six neighbours: value on the shared face and the
-  // normal derivative there (reference coordinates).
-  const int nn = n * n;
-  for (int w = tid; w < nc * 6 * N2; w += kThreads) {
-    const int cl = w / (6 * N2), r = w - cl * 6 * N2;
-    const int face = r / N2, pq = r - face * N2;
-    const int p = pq % N, q = pq / N;
-    const int c = c0 + cl;
-    const int d = face >> 1, upper = face & 1;
-    const int coord = d == 0 ? c % n : (d == 1 ? (c / n) % n : c / nn);
-    const bool has = upper ? (coord < n - 1) : (coord > 0);
-    double f = 0.0, g = 0.0;
-    if (has) {
-      const int sc = d == 0 ? 1 : (d == 1 ? n : nn);
-      const int cn = upper ? c + sc : c - sc;
-      const double* src = (cn >= c0 && cn < c0 + nc) ? s_u + (cn - c0) * N3 : u + (size_t)cn * N3;
-      const int sn = d == 0 ? 1 : (d == 1 ? N : N2);
-      const int base = d == 0 ? (p * N + q * N2) : (d == 1 ? (p + q * N2) : (p + q * N));
-      const double* dv = upper ? s_d0 : s_d1;
-      f = src[base + (upper ? 0 : (N - 1) * sn)];
-#pragma unroll
-      for (int a = 0; a < N; ++a) g = fma(dv[a], src[base + a * sn], g);
-    }
-    s_tr[(cl * 12 + face * 2 + 0) * N2 + pq] = f;
-    s_tr[(cl * 12 + face * 2 + 1) * N2 + pq] = g;
-  }
-  __syncthreads();
-  // Mass along x on the y- and z-face traces (index p).
-  for (int w = tid; w < nc * 8 * N; w += kThreads) {
-    const int cl = w / (8 * N), r = w - cl * 8 * N, fa = r / N, q = r - fa * N;
-    double* t = s_tr + (cl * 12 + 4 + fa) * N2 + q * N;
-    double x[N], y[N];
-#pragma unroll
-    for (int a = 0; a < N; ++a) x[a] = t[a];
-    matvec<N>(s_M, x, y);
-#pragma unroll
-    for (int a = 0; a < N; ++a) t[a] = y[a];
-  }
-  __syncthreads();
-  // Mass along y on the z-face traces (index q).
-  for (int w = tid; w < nc * 4 * N; w += kThreads) {
-    const int cl = w / (4 * N), r = w - cl * 4 * N, fa = r / N, p = r - fa * N;
-    double* t = s_tr + (cl * 12 + 8 + fa) * N2 + p;
-    double x[N], y[N];
-#pragma unroll
-    for (int a = 0; a < N; ++a) x[a] = t[a * N];
-    matvec<N>(s_M, x, y);
-#pragma unroll
-    for (int a = 0; a < N; ++a) t[a * N] = y[a];
-  }
-  __syncthreads();
-
-  // x stage: lines (j, l)
-  if (tid < nc * N2) {
-    const int cl = tid / N2, jl = tid - cl * N2;
-    const int cx = (c0 + cl) % n;
-    double x[N], t1[N], t2[N];
-    const double* src = s_u + cl * N3 + jl * N;
-#pragma unroll
-    for (int a = 0; a < N; ++a) x[a] = src[a];
-    matvec<N>(s_L + bdry_variant(cx, n) * N2, x, t1);
-    matvec<N>(s_M, x, t2);
-    const double* tr = s_tr + cl * 12 * N2;
-    if (cx > 0) add_lower_face<N>(t1, tr[0 * N2 + jl], tr[1 * N2 + jl], gam, s_d0);
-    if (cx < n - 1) add_upper_face<N>(t1, tr[2 * N2 + jl], tr[3 * N2 + jl], gam, s_d1);
+  // ---- all global loads of the tile are issued first
+  double own[N], xlo[N], xhi[N], ylo[N], yhi[N], zlo[N], zhi[N];
+  const bool hx0 = act && cx > 0, hx1 = act && cx < n - 1;
+  const bool hy0 = act && cy > 0, hy1 = act && cy < n - 1;
+  const bool hz0 = act && cz > 0, hz1 = act && cz < n - 1;
+  {
+    const double* pc = u + (size_t)c * N3;
+    const double* pxl = pc - N3 + ln * N;
+    const double* pxh = pc + N3 + ln * N;
+    const double* pyl = pc - (size_t)n * N3 + lp + lq * N2;
+    const double* pyh = pc + (size_t)n * N3 + lp + lq * N2;
+    const double* pzl = pc - (size_t)nn * N3 + ln;
+    const double* pzh = pc + (size_t)nn * N3 + ln;
 #pragma unroll
     for (int a = 0; a < N; ++a) {
-      s_t1[cl * N3 + jl * N + a] = t1[a];
-      s_t2[cl * N3 + jl * N + a] = t2[a];
+      own[a] = act ? pc[ln * N + a] : 0.0;
+      xlo[a] = hx0 ? pxl[a] : 0.0;
+      xhi[a] = hx1 ? pxh[a] : 0.0;
+      ylo[a] = hy0 ? pyl[a * N] : 0.0;
+      yhi[a] = hy1 ? pyh[a * N] : 0.0;
+      zlo[a] = hz0 ? pzl[a * N2] : 0.0;
+      zhi[a] = hz1 ? pzh[a * N2] : 0.0;
     }
+  }
+  // 1D tables are uniform over the workgroup: read through the scalar path
+  const double* __restrict__ s_M = tab + lay.mass;
+  const double* __restrict__ s_L = tab + lay.lcell;  // interior block (variant 0)
+  const double* __restrict__ s_d0 = tab + lay.d0;
+  const double* __restrict__ s_d1 = tab + lay.d1;
+  const double gam = tab[lay.gam];
+
+  // ---- x stage in registers, traces of the y/z neighbours to LDS
+  if (act) {
+    double t1[N], t2[N];
+    matvec<N>(s_L, own, t1);
+    add_boundary_correction<N>(t1, own, cx == 0, cx == n - 1, s_d0, s_d1);
+    matvec<N>(s_M, own, t2);
+    if (hx0) {
+      double g = 0.0;
+#pragma unroll
+      for (int a = 0; a < N; ++a) g = fma(s_d1[a], xlo[a], g);
+      add_lower_face<N>(t1, xlo[N - 1], g, gam, s_d0);
+    }
+    if (hx1) {
+      double g = 0.0;
+#pragma unroll
+      for (int a = 0; a < N; ++a) g = fma(s_d0[a], xhi[a], g);
+      add_upper_face<N>(t1, xhi[0], g, gam, s_d1);
+    }
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      s_t1[cl * N3 + ln * N + a] = t1[a];
+      s_t2[cl * N3 + ln * N + a] = t2[a];
+    }
+    double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      g0 = fma(s_d1[a], ylo[a], g0);
+      g1 = fma(s_d0[a], yhi[a], g1);
+      g2 = fma(s_d1[a], zlo[a], g2);
+      g3 = fma(s_d0[a], zhi[a], g3);
+    }
+    double* ty = s_ty + cl * 4 * N2;
+    double* tz = s_tz + cl * 4 * N2;
+    ty[0 * N2 + ln] = ylo[N - 1];
+    ty[1 * N2 + ln] = g0;
+    ty[2 * N2 + ln] = yhi[0];
+    ty[3 * N2 + ln] = g1;
+    tz[0 * N2 + ln] = zlo[N - 1];
+    tz[1 * N2 + ln] = g2;
+    tz[2 * N2 + ln] = zhi[0];
+    tz[3 * N2 + ln] = g3;
   }
   __syncthreads();
 
-  // y stage: lines (i, l)
-  if (tid < nc * N2) {
-    const int cl = tid / N2, il = tid - cl * N2;
-    const int i = il % N, l = il / N;
-    const int cy = ((c0 + cl) / n) % n;
+  // ---- y stage: lines (i, l) = (lp, lq); also Mx on the z traces at (i, j)
+  if (act) {
     double a1[N], a2[N], cc[N], e[N];
-    const int base = cl * N3 + i + l * N2;
+    const int base = cl * N3 + lp + lq * N2;
 #pragma unroll
     for (int b = 0; b < N; ++b) {
       a1[b] = s_t1[base + b * N];
       a2[b] = s_t2[base + b * N];
     }
     matvec<N>(s_M, a1, cc);
-    matvec_acc<N>(s_L + bdry_variant(cy, n) * N2, a2, cc);
+    matvec_acc<N>(s_L, a2, cc);
+    add_boundary_correction<N>(cc, a2, cy == 0, cy == n - 1, s_d0, s_d1);
     matvec<N>(s_M, a2, e);
-    const double* tr = s_tr + cl * 12 * N2;
-    if (cy > 0) add_lower_face<N>(cc, tr[4 * N2 + il], tr[5 * N2 + il], gam, s_d0);
-    if (cy < n - 1) add_upper_face<N>(cc, tr[6 * N2 + il], tr[7 * N2 + il], gam, s_d1);
+    const double* ty = s_ty + cl * 4 * N2 + lq * N;
+    const double* Mrow = s_M + lp * N;
+    double f0 = 0.0, q0 = 0.0, f1 = 0.0, q1 = 0.0;
+#pragma unroll
+    for (int b = 0; b < N; ++b) {  // (Mx trace)(i, l) = sum_i' M[i][i'] trace(i', l)
+      f0 = fma(Mrow[b], ty[0 * N2 + b], f0);
+      q0 = fma(Mrow[b], ty[1 * N2 + b], q0);
+      f1 = fma(Mrow[b], ty[2 * N2 + b], f1);
+      q1 = fma(Mrow[b], ty[3 * N2 + b], q1);
+    }
+    if (hy0) add_lower_face<N>(cc, f0, q0, gam, s_d0);
+    if (hy1) add_upper_face<N>(cc, f1, q1, gam, s_d1);
+    const double* tz = s_tz + cl * 4 * N2 + lq * N;
+    double* tzm = s_tzm + cl * 4 * N2 + lq * N + lp;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double acc = 0.0;
+#pragma unroll
+      for (int b = 0; b < N; ++b) acc = fma(Mrow[b], tz[r * N2 + b], acc);
+      tzm[r * N2] = acc;
+    }
 #pragma unroll
     for (int b = 0; b < N; ++b) {
       s_t1[base + b * N] = cc[b];
@@ -220,26 +288,34 @@ __global__ __launch_bounds__(kThreads) void apply_f64_kernel(
   }
   __syncthreads();
 
-  // z stage: lines (i, j), written straight to global memory
-  if (tid < nc * N2) {
-    const int cl = tid / N2, ij = tid - cl * N2;
-    const int c = c0 + cl;
-    const int cz = c / nn;
+  // ---- z stage: lines (i, j) = ln, written straight to global memory
+  if (act) {
     double a1[N], a2[N], o[N];
-    const int base = cl * N3 + ij;
+    const int base = cl * N3 + ln;
 #pragma unroll
     for (int b = 0; b < N; ++b) {
       a1[b] = s_t1[base + b * N2];
       a2[b] = s_t2[base + b * N2];
     }
     matvec<N>(s_M, a1, o);
-    matvec_acc<N>(s_L + bdry_variant(cz, n) * N2, a2, o);
-    const double* tr = s_tr + cl * 12 * N2;
-    if (cz > 0) add_lower_face<N>(o, tr[8 * N2 + ij], tr[9 * N2 + ij], gam, s_d0);
-    if (cz < n - 1) add_upper_face<N>(o, tr[10 * N2 + ij], tr[11 * N2 + ij], gam, s_d1);
-    double* dst = v + (size_t)c * N3 + ij;
+    matvec_acc<N>(s_L, a2, o);
+    add_boundary_correction<N>(o, a2, cz == 0, cz == n - 1, s_d0, s_d1);
+    // (My Mx trace)(i, j) = sum_j' M[j][j'] (Mx trace)(i, j')
+    const double* tzm = s_tzm + cl * 4 * N2 + lp;
+    const double* Mrow = s_M + lq * N;
+    double f0 = 0.0, q0 = 0.0, f1 = 0.0, q1 = 0.0;
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      f0 = fma(Mrow[b], tzm[0 * N2 + b * N], f0);
+      q0 = fma(Mrow[b], tzm[1 * N2 + b * N], q0);
+      f1 = fma(Mrow[b], tzm[2 * N2 + b * N], f1);
+      q1 = fma(Mrow[b], tzm[3 * N2 + b * N], q1);
+    }
+    if (hz0) add_lower_face<N>(o, f0, q0, gam, s_d0);
+    if (hz1) add_upper_face<N>(o, f1, q1, gam, s_d1);
+    double* dst = v + (size_t)c * N3 + ln;
     if (RES) {
-      const double* bs = bvec + (size_t)c * N3 + ij;
+      const double* bs = bvec + (size_t)c * N3 + ln;
 #pragma unroll
       for (int a = 0; a < N; ++a) dst[a * N2] = bs[a * N2] - h * o[a];
     } else {
@@ -589,15 +665,22 @@ template <int N>
 hipError_t apply_impl(const double* u, double* v, const double* b, const DevTab& t, int n,
                       double h, hipStream_t s) {
   constexpr int CPB = kThreads / (N * N);
-  const int64_t ncells = (int64_t)n * n * n;
-  if (ncells <= 0 || ncells > (int64_t)1 << 30) return hipErrorInvalidValue;
-  const int grid = (int)((ncells + CPB - 1) / CPB);
+  if (n < 1 || n > 1024) return hipErrorInvalidValue;
+  TileMap tm;
+  tm.n = n;
+  tm.tx = 1;
+  for (int d = 1; d <= CPB && d <= n; ++d)
+    if (n % d == 0) tm.tx = d;  // largest divisor of n that fits the workgroup
+  tm.ntx = n / tm.tx;
+  tm.blk = (n % 8 == 0) ? 8 : 1;
+  const int64_t tiles = (int64_t)tm.ntx * n * n;
+  if (tiles > ((int64_t)1 << 31) - 1) return hipErrorInvalidValue;
   if (b)
-    hipLaunchKernelGGL((apply_f64_kernel<N, true>), dim3(grid), dim3(kThreads), 0, s, u, v, b,
-                       t.tab, t.lay, n, h, (int)ncells);
+    hipLaunchKernelGGL((apply_f64_kernel<N, true>), dim3((int)tiles), dim3(kThreads), 0, s, u, v,
+                       b, t.tab, t.lay, tm, h);
   else
-    hipLaunchKernelGGL((apply_f64_kernel<N, false>), dim3(grid), dim3(kThreads), 0, s, u, v,
-                       nullptr, t.tab, t.lay, n, h, (int)ncells);
+    hipLaunchKernelGGL((apply_f64_kernel<N, false>), dim3((int)tiles), dim3(kThreads), 0, s, u,
+                       v, nullptr, t.tab, t.lay, tm, h);
   return hipGetLastError();
 }
 
