@@ -118,13 +118,15 @@ __device__ __forceinline__ void add_boundary_correction(double (&t)[N], const do
 }
 
 // ---------------------------------------------------------------------------
-// Operator apply.  A workgroup owns a tile of TX consecutive cells along x
-// (TX <= CPB divides n); one thread per 1D line per stage.  Tiles are
-// ordered so that a cell's six face neighbours are processed close in time
-// on the same XCD: x-tiles fastest, then z and y in 8 x 8 blocks.
+// Operator apply.  A wave owns a tile of TX consecutive cells along x (TX
+// divides n, TX * N^2 <= 64 lanes), one lane per 1D line per stage; waves
+// run independently (cells never straddle a wave).  Tiles are ordered so
+// that a cell's six face neighbours are processed close in time on the same
+// XCD: x-tiles fastest, then z and y in 8 x 8 blocks.
 // ---------------------------------------------------------------------------
 struct TileMap {
   int n, tx, ntx, blk;  // blk = 8 when n % 8 == 0 (blocked order), else 1
+  int ngroups;          // number of tiles (wave-level variant)
 };
 
 __device__ __forceinline__ int tile_first_cell(const TileMap& m, int t) {
@@ -147,22 +149,37 @@ __device__ __forceinline__ int tile_first_cell(const TileMap& m, int t) {
   return (cz * m.n + cy) * m.n + txi * m.tx;
 }
 
+// Order LDS traffic between the lanes of one wave: LDS instructions of a
+// wave execute in order; the wait and the memory clobber keep the compiler
+// from moving accesses across this point.
+__device__ __forceinline__ void wave_lds_sync() {
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
 template <int N, bool RES>
-__global__ __launch_bounds__(kThreads) void apply_f64_kernel(
+__global__ __launch_bounds__(kThreads) void apply_f64_wave_kernel(
     const double* __restrict__ u, double* __restrict__ v, const double* __restrict__ bvec,
     const double* __restrict__ tab, TableLayout lay, TileMap tm, double h) {
-  constexpr int N2 = N * N, N3 = N2 * N, CPB = kThreads / N2;
-  __shared__ double s_t1[CPB * N3];
-  __shared__ double s_t2[CPB * N3];
+  constexpr int N2 = N * N, N3 = N2 * N, CPB = (64 / N2) > 0 ? 64 / N2 : 1;
+  constexpr int WAVES = kThreads / 64;
+  __shared__ double s_t1_all[WAVES * CPB * N3];
+  __shared__ double s_t2_all[WAVES * CPB * N3];
   // per cell: y-face traces [face 0,1][value, derivative][i + N l] and
   // z-face traces [face 0,1][value, derivative][i + N j], raw then after Mx
-  __shared__ double s_ty[CPB * 4 * N2];
-  __shared__ double s_tz[CPB * 4 * N2];
-  __shared__ double s_tzm[CPB * 4 * N2];
+  __shared__ double s_ty_all[WAVES * CPB * 4 * N2];
+  __shared__ double s_tz_all[WAVES * CPB * 4 * N2];
+  __shared__ double s_tzm_all[WAVES * CPB * 4 * N2];
 
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int grp = xcd_remap(blockIdx.x, gridDim.x) * WAVES + wave;
+  if (grp >= tm.ngroups) return;  // wave-uniform; no workgroup barriers below
+  double* s_t1 = s_t1_all + wave * (CPB * N3);
+  double* s_t2 = s_t2_all + wave * (CPB * N3);
+  double* s_ty = s_ty_all + wave * (CPB * 4 * N2);
+  double* s_tz = s_tz_all + wave * (CPB * 4 * N2);
+  double* s_tzm = s_tzm_all + wave * (CPB * 4 * N2);
   const int n = tm.n, nn = n * n, nc = tm.tx;
-  const int c0 = tile_first_cell(tm, xcd_remap(blockIdx.x, gridDim.x));
+  const int c0 = tile_first_cell(tm, grp);
   const int cy = (c0 / n) % n, cz = c0 / nn, cx0 = c0 % n;
   const bool act = tid < nc * N2;
   const int cl = act ? tid / N2 : 0, ln = tid - cl * N2;
@@ -244,7 +261,7 @@ __global__ __launch_bounds__(kThreads) void apply_f64_kernel(
     tz[2 * N2 + ln] = zhi[0];
     tz[3 * N2 + ln] = g3;
   }
-  __syncthreads();
+  wave_lds_sync();
 
   // ---- y stage: lines (i, l) = (lp, lq); also Mx on the z traces at (i, j)
   if (act) {
@@ -286,7 +303,7 @@ __global__ __launch_bounds__(kThreads) void apply_f64_kernel(
       s_t2[base + b * N] = e[b];
     }
   }
-  __syncthreads();
+  wave_lds_sync();
 
   // ---- z stage: lines (i, j) = ln, written straight to global memory
   if (act) {
@@ -664,22 +681,27 @@ __global__ __launch_bounds__(kThreads) void prolongate_add_f64_kernel(
 template <int N>
 hipError_t apply_impl(const double* u, double* v, const double* b, const DevTab& t, int n,
                       double h, hipStream_t s) {
-  constexpr int CPB = kThreads / (N * N);
+  // one tile = consecutive cells along x handled by one wave (cells never
+  // straddle a wave, so waves run independently)
+  constexpr int CPW = (64 / (N * N)) > 0 ? 64 / (N * N) : 1;
   if (n < 1 || n > 1024) return hipErrorInvalidValue;
   TileMap tm;
   tm.n = n;
   tm.tx = 1;
-  for (int d = 1; d <= CPB && d <= n; ++d)
-    if (n % d == 0) tm.tx = d;  // largest divisor of n that fits the workgroup
+  for (int d = 1; d <= CPW && d <= n; ++d)
+    if (n % d == 0) tm.tx = d;  // largest divisor of n that fits a wave
   tm.ntx = n / tm.tx;
   tm.blk = (n % 8 == 0) ? 8 : 1;
   const int64_t tiles = (int64_t)tm.ntx * n * n;
-  if (tiles > ((int64_t)1 << 31) - 1) return hipErrorInvalidValue;
+  if (tiles > ((int64_t)1 << 30)) return hipErrorInvalidValue;
+  tm.ngroups = (int)tiles;
+  const int waves = kThreads / 64;
+  const int grid = (int)((tiles + waves - 1) / waves);
   if (b)
-    hipLaunchKernelGGL((apply_f64_kernel<N, true>), dim3((int)tiles), dim3(kThreads), 0, s, u, v,
+    hipLaunchKernelGGL((apply_f64_wave_kernel<N, true>), dim3(grid), dim3(kThreads), 0, s, u, v,
                        b, t.tab, t.lay, tm, h);
   else
-    hipLaunchKernelGGL((apply_f64_kernel<N, false>), dim3((int)tiles), dim3(kThreads), 0, s, u,
+    hipLaunchKernelGGL((apply_f64_wave_kernel<N, false>), dim3(grid), dim3(kThreads), 0, s, u,
                        v, nullptr, t.tab, t.lay, tm, h);
   return hipGetLastError();
 }
