@@ -85,6 +85,15 @@ int64_t sipg_n_dofs(const sipg_problem* p, int level);
 sipg_status sipg_apply(sipg_problem* p, int level, const double* u, double* v,
                        hipStream_t stream);
 
+/* v = A_l u with FP32 vectors in a reduced-precision arithmetic (Sec. 5,
+ * Sec. 7.1): precision SIPG_F32 (FP32 throughout), SIPG_F16 or SIPG_BF16
+ * (1D contractions on the matrix cores with FP16/BF16 operands and FP32
+ * accumulation; FP16 lines are scaled by powers of two into range).  ec = 1
+ * adds the split-operand error correction of Alg. matmul (ignored for F32).
+ * u, v: n_dofs(level) floats, must not overlap. */
+sipg_status sipg_apply_lp(sipg_problem* p, int level, const float* u, float* v,
+                          int precision, int ec, hipStream_t stream);
+
 /* r = b - A_l x in FP64.  r must not overlap x or b. */
 sipg_status sipg_residual(sipg_problem* p, int level, const double* b,
                           const double* x, double* r, hipStream_t stream);
@@ -118,8 +127,11 @@ sipg_status sipg_coarse_solve(sipg_problem* p, const double* b, double* x,
                               hipStream_t stream);
 
 /* x <- V-cycle_l(x, b) with nu_pre/nu_post sweeps (Alg. v_cycle), in the
- * handle's mg_precision (FP64 vectors in and out; converted internally).
- * x and b must not overlap. */
+ * handle's mg_precision (FP64 vectors in and out).  For mg_precision other
+ * than SIPG_F64 the cycle runs on FP32 copies made at entry and converted
+ * back at exit; residuals and patch solves then use the reduced-precision
+ * kernels of sipg_apply_lp (with the handle's error_correction), transfers
+ * and the coarse solve run in FP32.  x and b must not overlap. */
 sipg_status sipg_vcycle(sipg_problem* p, int level, double* x, const double* b,
                         hipStream_t stream);
 

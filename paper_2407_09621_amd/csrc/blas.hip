@@ -103,6 +103,23 @@ __global__ __launch_bounds__(kT) void finite_kernel(const double* __restrict__ x
   if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
 }
 
+__global__ __launch_bounds__(kT) void to_f32_kernel(const double* __restrict__ src,
+                                                    float* __restrict__ dst, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x; e < n; e += (int64_t)gridDim.x * kT)
+    dst[e] = (float)src[e];
+}
+
+__global__ __launch_bounds__(kT) void to_f64_kernel(const float* __restrict__ src,
+                                                    double* __restrict__ dst, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x; e < n; e += (int64_t)gridDim.x * kT)
+    dst[e] = (double)src[e];
+}
+
+__global__ __launch_bounds__(kT) void fill_f32_kernel(float* __restrict__ x, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x; e < n; e += (int64_t)gridDim.x * kT)
+    x[e] = 0.0f;
+}
+
 int grid_for(int64_t n) {
   int64_t g = (n + kT - 1) / kT;
   return (int)(g < 8192 ? (g < 1 ? 1 : g) : 8192);
@@ -139,6 +156,21 @@ hipError_t launch_axpy(double alpha, const double* x, double* y, int64_t n, hipS
 
 hipError_t launch_fill(double* x, double value, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(kT), 0, s, x, value, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(to_f32_kernel, dim3(grid_for(n)), dim3(kT), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_f64(const float* src, double* dst, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(to_f64_kernel, dim3(grid_for(n)), dim3(kT), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_f32(float* x, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(fill_f32_kernel, dim3(grid_for(n)), dim3(kT), 0, s, x, n);
   return hipGetLastError();
 }
 

@@ -55,6 +55,11 @@ struct sipg_problem {
   int* d_flag = nullptr;
   double* d_aux = nullptr;          // tables for rhs / l2 (grown on demand)
   size_t aux_size = 0;
+  // low-precision V-cycle (mg_precision != F64): FP32 level vectors
+  int prec = SIPG_F64;
+  bool ec = false;
+  float* d_tabf = nullptr;
+  std::vector<float*> fx, fb, fr;
 };
 
 namespace {
@@ -93,6 +98,62 @@ sipg_status smooth(sipg_problem* p, int l, double* x, const double* b, int sweep
       SIPG_TRY(residual(p, l, b, x, p->wr[l], s));
       SIPG_HIP(launch_patch_fd_f64(p->N, colour, p->wr[l], x, p->tab, p->n[l], level_h(p, l), s));
     }
+  return SIPG_OK;
+}
+
+// ---- low-precision V-cycle on FP32 vectors
+sipg_status residual_lp(sipg_problem* p, int l, const float* b, const float* x, float* r,
+                        hipStream_t s) {
+  if (p->prec == SIPG_F32)
+    SIPG_HIP(launch_apply_f32(p->N, x, r, b, p->tab, p->n[l], level_h(p, l), s));
+  else
+    SIPG_HIP(launch_apply_lp(p->N, p->prec == SIPG_BF16, p->ec, x, r, b, p->tab, p->n[l],
+                             level_h(p, l), s));
+  return SIPG_OK;
+}
+
+sipg_status smooth_lp(sipg_problem* p, int l, float* x, const float* b, int sweeps,
+                      hipStream_t s) {
+  if (p->n[l] < 2) return SIPG_OK;
+  for (int sw = 0; sw < sweeps; ++sw)
+    for (int colour = 0; colour < 8; ++colour) {
+      SIPG_TRY(residual_lp(p, l, b, x, p->fr[l], s));
+      if (p->prec == SIPG_F32)
+        SIPG_HIP(launch_patch_fd_f32(p->N, colour, p->fr[l], x, p->tab, p->n[l], level_h(p, l), s));
+      else
+        SIPG_HIP(launch_patch_fd_lp(p->N, p->prec == SIPG_BF16, p->ec, colour, p->fr[l], x,
+                                    p->tab, p->n[l], level_h(p, l), s));
+    }
+  return SIPG_OK;
+}
+
+sipg_status vcycle_lp(sipg_problem* p, int l, float* x, const float* b, hipStream_t s) {
+  if (l == 0) {
+    if (p->n0 > 3) return fail(SIPG_ERR_UNSUPPORTED, "coarsest level above 3 cells per direction");
+    SIPG_HIP(launch_coarse_fd_f32(p->N, p->n0, b, x, p->tab, level_h(p, 0), s));
+    return SIPG_OK;
+  }
+  SIPG_TRY(smooth_lp(p, l, x, b, p->cfg.nu_pre, s));
+  SIPG_TRY(residual_lp(p, l, b, x, p->fr[l], s));
+  SIPG_HIP(launch_restrict_f32(p->N, p->fr[l], p->fb[l - 1], p->tab, p->n[l - 1], s));
+  if (l - 1 > 0) SIPG_HIP(launch_zero_f32(p->fx[l - 1], p->ndofs[l - 1], s));
+  SIPG_TRY(vcycle_lp(p, l - 1, p->fx[l - 1], p->fb[l - 1], s));
+  SIPG_HIP(launch_prolongate_add_f32(p->N, p->fx[l - 1], x, p->tab, p->n[l - 1], s));
+  SIPG_TRY(smooth_lp(p, l, x, b, p->cfg.nu_post, s));
+  return SIPG_OK;
+}
+
+sipg_status vcycle(sipg_problem* p, int l, double* x, const double* b, hipStream_t s);
+
+// x <- V-cycle(x, b) in the handle's precision; FP64 in and out.  The
+// low-precision cycle runs on FP32 copies (the format is converted at entry
+// and exit of the V-cycle, Sec. 7.1).
+sipg_status vcycle_any(sipg_problem* p, int l, double* x, const double* b, hipStream_t s) {
+  if (p->prec == SIPG_F64) return vcycle(p, l, x, b, s);
+  SIPG_HIP(launch_to_f32(b, p->fb[l], p->ndofs[l], s));
+  SIPG_HIP(launch_to_f32(x, p->fx[l], p->ndofs[l], s));
+  SIPG_TRY(vcycle_lp(p, l, p->fx[l], p->fb[l], s));
+  SIPG_HIP(launch_to_f64(p->fx[l], x, p->ndofs[l], s));
   return SIPG_OK;
 }
 
@@ -146,8 +207,8 @@ sipg_status sipg_create(const sipg_config* cfg, sipg_problem** out) {
   if (cfg->n_cells < 1 || cfg->n_cells > 1024) return fail(SIPG_ERR_ARG, "n_cells must be in 1..1024");
   if (cfg->nu_pre < 0 || cfg->nu_post < 0 || cfg->nu_pre > 16 || cfg->nu_post > 16)
     return fail(SIPG_ERR_ARG, "smoothing steps must be in 0..16");
-  if (cfg->mg_precision != SIPG_F64)
-    return fail(SIPG_ERR_UNSUPPORTED, "only the FP64 V-cycle is available in this build");
+  if (cfg->mg_precision < SIPG_F64 || cfg->mg_precision > SIPG_BF16)
+    return fail(SIPG_ERR_ARG, "mg_precision must be a sipg_precision");
   if (cfg->error_correction != 0 && cfg->error_correction != 1)
     return fail(SIPG_ERR_ARG, "error_correction must be 0 or 1");
   // level sizes: halve while even and above 3
@@ -195,6 +256,25 @@ sipg_status sipg_create(const sipg_config* cfg, sipg_problem** out) {
     if (st == SIPG_OK && l < p->L - 1) st = dev_alloc(&p->wx[l], p->ndofs[l]);
     if (st == SIPG_OK && l < p->L - 1) st = dev_alloc(&p->wb[l], p->ndofs[l]);
   }
+  p->prec = cfg->mg_precision;
+  p->ec = cfg->error_correction != 0;
+  {  // FP32 copy of the tables (FP32 / FP16 / BF16 kernels read it)
+    std::vector<float> tf(tab.begin(), tab.end());
+    if (st == SIPG_OK) st = dev_alloc(&p->d_tabf, tf.size());
+    if (st == SIPG_OK && hipMemcpy(p->d_tabf, tf.data(), tf.size() * sizeof(float),
+                                   hipMemcpyHostToDevice) != hipSuccess)
+      st = fail(SIPG_ERR_HIP, "table upload failed");
+    p->tab.tabf = p->d_tabf;
+  }
+  p->fx.assign(p->L, nullptr);
+  p->fb.assign(p->L, nullptr);
+  p->fr.assign(p->L, nullptr);
+  if (p->prec != SIPG_F64)
+    for (int l = 0; l < p->L && st == SIPG_OK; ++l) {
+      st = dev_alloc(&p->fx[l], p->ndofs[l]);
+      if (st == SIPG_OK) st = dev_alloc(&p->fb[l], p->ndofs[l]);
+      if (st == SIPG_OK) st = dev_alloc(&p->fr[l], p->ndofs[l]);
+    }
   if (st == SIPG_OK) st = dev_alloc(&p->d_partial, (size_t)kDotBlocks * 65);
   if (st == SIPG_OK) st = dev_alloc(&p->d_small, 512);
   if (st == SIPG_OK) st = dev_alloc(&p->d_flag, 1);
@@ -221,6 +301,10 @@ void sipg_destroy(sipg_problem* p) {
   fr(p->d_small);
   fr(p->d_flag);
   fr(p->d_aux);
+  fr(p->d_tabf);
+  for (auto q : p->fx) fr(q);
+  for (auto q : p->fb) fr(q);
+  for (auto q : p->fr) fr(q);
   delete p;
 }
 
@@ -303,7 +387,23 @@ sipg_status sipg_vcycle(sipg_problem* p, int level, double* x, const double* b, 
   SIPG_TRY(check_level(p, level));
   if (!x || !b) return fail(SIPG_ERR_ARG, "NULL vector");
   if (x == b) return fail(SIPG_ERR_ARG, "x and b must not alias");
-  return vcycle(p, level, x, b, s);
+  return vcycle_any(p, level, x, b, s);
+}
+
+sipg_status sipg_apply_lp(sipg_problem* p, int level, const float* u, float* v, int precision,
+                          int ec, hipStream_t s) {
+  SIPG_TRY(check_level(p, level));
+  if (!u || !v) return fail(SIPG_ERR_ARG, "NULL vector");
+  if (u == v) return fail(SIPG_ERR_ARG, "u and v must not alias");
+  if (precision == SIPG_F32) {
+    SIPG_HIP(launch_apply_f32(p->N, u, v, nullptr, p->tab, p->n[level], level_h(p, level), s));
+  } else if (precision == SIPG_F16 || precision == SIPG_BF16) {
+    SIPG_HIP(launch_apply_lp(p->N, precision == SIPG_BF16, ec != 0, u, v, nullptr, p->tab,
+                             p->n[level], level_h(p, level), s));
+  } else {
+    return fail(SIPG_ERR_ARG, "precision must be SIPG_F32, SIPG_F16 or SIPG_BF16");
+  }
+  return SIPG_OK;
 }
 
 sipg_status sipg_fgmres(sipg_problem* p, double* x, const double* b, const sipg_solve_opts* o,
@@ -372,7 +472,7 @@ sipg_status sipg_fgmres(sipg_problem* p, double* x, const double* b, const sipg_
       double* Zj = p->Z + (size_t)j * n;
       double* w = p->V + (size_t)(j + 1) * n;
       SIPG_HIP(launch_fill(Zj, 0.0, n, s));
-      SIPG_TRY(vcycle(p, L, Zj, Vj, s));
+      SIPG_TRY(vcycle_any(p, L, Zj, Vj, s));
       SIPG_HIP(hipMemsetAsync(p->d_flag, 0, sizeof(int), s));
       SIPG_HIP(launch_finite_check(Zj, n, p->d_flag, s));
       int flag = 0;

@@ -10,6 +10,7 @@ namespace sipg {
 
 struct DevTab {
   const double* tab = nullptr;  // device copy of build_device_table()
+  const float* tabf = nullptr;  // the same table rounded to FP32
   TableLayout lay;
 };
 
@@ -18,19 +19,32 @@ struct DevTab {
 hipError_t launch_apply_f64(int N, const double* u, double* v, const double* b,
                             const DevTab& t, int n, double h, hipStream_t s);
 
+hipError_t launch_apply_f32(int N, const float* u, float* v, const float* b, const DevTab& t,
+                            int n, double h, hipStream_t s);
+
 // x_P += A_PP^{-1} r_P for all vertex patches of `colour`.
 hipError_t launch_patch_fd_f64(int N, int colour, const double* r, double* x,
                                const DevTab& t, int n, double h, hipStream_t s);
 
+hipError_t launch_patch_fd_f32(int N, int colour, const float* r, float* x, const DevTab& t,
+                               int n, double h, hipStream_t s);
+
 // x = A_0^{-1} b on the n0^3-cell coarse level (overwrites x).
 hipError_t launch_coarse_fd_f64(int N, int n0, const double* b, double* x,
                                 const DevTab& t, double h, hipStream_t s);
+
+hipError_t launch_coarse_fd_f32(int N, int n0, const float* b, float* x, const DevTab& t,
+                                double h, hipStream_t s);
 
 // rc = P^T rf (nc coarse cells per direction) and xf += P ec.
 hipError_t launch_restrict_f64(int N, const double* rf, double* rc, const DevTab& t,
                                int nc, hipStream_t s);
 hipError_t launch_prolongate_add_f64(int N, const double* ec, double* xf,
                                      const DevTab& t, int nc, hipStream_t s);
+hipError_t launch_restrict_f32(int N, const float* rf, float* rc, const DevTab& t, int nc,
+                               hipStream_t s);
+hipError_t launch_prolongate_add_f32(int N, const float* ec, float* xf, const DevTab& t, int nc,
+                                     hipStream_t s);
 
 // BLAS-1 helpers (FP64).  `partial` holds at least kDotBlocks * nv doubles.
 constexpr int kDotBlocks = 1024;
@@ -45,6 +59,16 @@ hipError_t launch_scale_copy(const double* src, double alpha, double* dst, int64
 hipError_t launch_axpy(double alpha, const double* x, double* y, int64_t n, hipStream_t s);
 hipError_t launch_fill(double* x, double value, int64_t n, hipStream_t s);
 hipError_t launch_finite_check(const double* x, int64_t n, int* flag, hipStream_t s);
+hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
+hipError_t launch_to_f64(const float* src, double* dst, int64_t n, hipStream_t s);
+hipError_t launch_zero_f32(float* x, int64_t n, hipStream_t s);
+
+// Low-precision kernels: FP32 storage, FP16 (bf16 = false) or BF16 products
+// on the matrix cores with FP32 accumulation, optional error correction.
+hipError_t launch_apply_lp(int N, bool bf16, bool ec, const float* u, float* v, const float* b,
+                           const DevTab& t, int n, double h, hipStream_t s);
+hipError_t launch_patch_fd_lp(int N, bool bf16, bool ec, int colour, const float* r, float* x,
+                              const DevTab& t, int n, double h, hipStream_t s);
 
 // Manufactured right-hand side and L2 error (tables prepared on the host).
 hipError_t launch_rhs_sines(int N, int n, int n_modes, const double* coef,

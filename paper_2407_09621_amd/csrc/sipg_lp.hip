@@ -1,0 +1,643 @@
+// Low-precision kernels of the V-cycle (Sec. 7.1 mixed precision): FP32
+// storage, 1D contractions on FP16 or BF16 matrix cores with FP32
+// accumulation, optional split-operand error correction (Sec. 5.2,
+// Alg. matmul).
+//
+// Building block: v_mfma_f32_4x4x4{f16,bf16_1k} on gfx950 computes 16
+// independent 4x4x4 products.  Lane 4b + j supplies column j of block b of
+// the B operand (its four K values) and receives column j of block b of the
+// result in its four accumulator registers; lane 4b + i supplies row i of
+// block b of the A operand.  With the same matrix in every block this is a
+// "line per lane" matrix-vector product for 64 lines at once, the layout of
+// the VALU kernels.  Lines longer than 4 are split into 4 x 4 sub-blocks
+// (lengths padded to a multiple of 4 with zeros).
+//
+// FP16 range: every line is scaled by a power of two so that its largest
+// entry lies in [0.5, 1) before rounding, and the product is scaled back in
+// FP32 (exact).  BF16 has the FP32 exponent range and is not scaled.
+// Error correction (both operands refined, as the paper's Alg. matmul):
+// x = x_hi + 2^-s x_lo with x_lo = round((x - x_hi) 2^s), s = 11 for FP16
+// and 8 for BF16; S x ~ S_hi x_hi + 2^-s (S_lo x_hi + S_hi x_lo), the
+// correction accumulated in its own FP32 accumulator.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace sipg {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
+  return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
+// ---- operand rounding -----------------------------------------------------
+template <bool BF>
+struct Lp;
+
+template <>
+struct Lp<false> {  // FP16
+  typedef h4 vec;
+  static constexpr float kSplit = 2048.0f;  // 2^11
+  static __device__ __forceinline__ float round(float x) { return (float)(_Float16)x; }
+  static __device__ __forceinline__ vec pack(float a, float b, float c, float d) {
+    vec v = {(_Float16)a, (_Float16)b, (_Float16)c, (_Float16)d};
+    return v;
+  }
+  static __device__ __forceinline__ f4 mfma(vec a, vec b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_4x4x4f16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <>
+struct Lp<true> {  // BF16
+  typedef s4 vec;
+  static constexpr float kSplit = 256.0f;  // 2^8
+  static __device__ __forceinline__ short bits(float x) {
+    __bf16 b = (__bf16)x;  // round to nearest even
+    return __builtin_bit_cast(short, b);
+  }
+  static __device__ __forceinline__ float round(float x) { return (float)(__bf16)x; }
+  static __device__ __forceinline__ vec pack(float a, float b, float c, float d) {
+    vec v = {bits(a), bits(b), bits(c), bits(d)};
+    return v;
+  }
+  static __device__ __forceinline__ f4 mfma(vec a, vec b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(a, b, c, 0, 0, 0);
+  }
+};
+
+// y = S x for the line held by every lane (all 64 lanes must call).  NP is
+// the padded line length (multiple of 4); S is n x n (n <= NP), row-major,
+// possibly different per group of 4 lanes.
+template <int NP, bool BF, bool EC>
+struct LineMV {
+  typedef Lp<BF> L;
+  static constexpr int C = NP / 4;
+  typename L::vec hi[C][C];
+  typename L::vec lo[C][C];
+
+  // lane's row of S for block rows: row 4 rc + (lane % 4)
+  __device__ __forceinline__ void load(const float* __restrict__ S, int n, bool transpose) {
+    const int r = threadIdx.x & 3;
+#pragma unroll
+    for (int rc = 0; rc < C; ++rc)
+#pragma unroll
+      for (int kc = 0; kc < C; ++kc) {
+        float v[4], w[4];
+        const int row = 4 * rc + r;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int col = 4 * kc + q;
+          float s = 0.0f;
+          if (row < n && col < n) s = transpose ? S[col * n + row] : S[row * n + col];
+          v[q] = L::round(s);
+          w[q] = (s - v[q]) * L::kSplit;
+        }
+        hi[rc][kc] = L::pack(v[0], v[1], v[2], v[3]);
+        if (EC) lo[rc][kc] = L::pack(w[0], w[1], w[2], w[3]);
+      }
+  }
+
+  __device__ __forceinline__ void apply(const float (&x)[NP], float (&y)[NP]) const {
+    float s = 1.0f, inv = 1.0f;
+    if (!BF) {  // per-line power-of-two scale into [0.5, 1)
+      float m = 0.0f;
+#pragma unroll
+      for (int a = 0; a < NP; ++a) m = fmaxf(m, fabsf(x[a]));
+      if (m > 0.0f) {
+        int e;
+        frexpf(m, &e);
+        s = ldexpf(1.0f, -e);
+        inv = ldexpf(1.0f, e);
+      }
+    }
+    typename L::vec xh[C], xl[C];
+#pragma unroll
+    for (int kc = 0; kc < C; ++kc) {
+      float v[4], w[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float t = x[4 * kc + q] * s;
+        v[q] = L::round(t);
+        w[q] = (t - v[q]) * L::kSplit;
+      }
+      xh[kc] = L::pack(v[0], v[1], v[2], v[3]);
+      if (EC) xl[kc] = L::pack(w[0], w[1], w[2], w[3]);
+    }
+#pragma unroll
+    for (int rc = 0; rc < C; ++rc) {
+      f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int kc = 0; kc < C; ++kc) acc = L::mfma(hi[rc][kc], xh[kc], acc);
+      if (EC) {
+        f4 cor = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int kc = 0; kc < C; ++kc) {
+          cor = L::mfma(lo[rc][kc], xh[kc], cor);
+          cor = L::mfma(hi[rc][kc], xl[kc], cor);
+        }
+        acc += cor * (1.0f / L::kSplit);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) y[4 * rc + i] = acc[i] * inv;
+    }
+  }
+};
+
+template <int N>
+struct Pad {
+  static constexpr int value = (N + 3) / 4 * 4;
+};
+
+template <int N>
+__device__ __forceinline__ void add_lower_face(float (&t)[N], float f, float g, float gam,
+                                               const float* __restrict__ d0) {
+  t[0] += -gam * f + 0.5f * g;
+#pragma unroll
+  for (int a = 0; a < N; ++a) t[a] = fmaf(-0.5f * d0[a], f, t[a]);
+}
+template <int N>
+__device__ __forceinline__ void add_upper_face(float (&t)[N], float f, float g, float gam,
+                                               const float* __restrict__ d1) {
+  t[N - 1] += -gam * f - 0.5f * g;
+#pragma unroll
+  for (int a = 0; a < N; ++a) t[a] = fmaf(0.5f * d1[a], f, t[a]);
+}
+template <int N>
+__device__ __forceinline__ void add_boundary_correction(float (&t)[N], const float (&x)[N],
+                                                        bool lo, bool hi,
+                                                        const float* __restrict__ d0,
+                                                        const float* __restrict__ d1) {
+  if (lo) {
+    float g = 0.0f;
+#pragma unroll
+    for (int a = 0; a < N; ++a) g = fmaf(d0[a], x[a], g);
+    t[0] += 0.5f * g;
+#pragma unroll
+    for (int a = 0; a < N; ++a) t[a] = fmaf(0.5f * d0[a], x[0], t[a]);
+  }
+  if (hi) {
+    float g = 0.0f;
+#pragma unroll
+    for (int a = 0; a < N; ++a) g = fmaf(d1[a], x[a], g);
+    t[N - 1] -= 0.5f * g;
+#pragma unroll
+    for (int a = 0; a < N; ++a) t[a] = fmaf(-0.5f * d1[a], x[N - 1], t[a]);
+  }
+}
+
+// line of length N inside a padded register array
+template <int N, int NP, bool BF, bool EC>
+__device__ __forceinline__ void line_mv(const LineMV<NP, BF, EC>& m, const float (&x)[N],
+                                        float (&y)[N]) {
+  float xp[NP], yp[NP];
+#pragma unroll
+  for (int a = 0; a < NP; ++a) xp[a] = a < N ? x[a] : 0.0f;
+  m.apply(xp, yp);
+#pragma unroll
+  for (int a = 0; a < N; ++a) y[a] = yp[a];
+}
+template <int N, int NP, bool BF, bool EC>
+__device__ __forceinline__ void line_mv_acc(const LineMV<NP, BF, EC>& m, const float (&x)[N],
+                                            float (&y)[N]) {
+  float t[N];
+  line_mv<N>(m, x, t);
+#pragma unroll
+  for (int a = 0; a < N; ++a) y[a] += t[a];
+}
+
+struct TileMapLp {
+  int n, tx, ntx, blk, ngroups;
+};
+
+__device__ __forceinline__ int tile_first_cell(const TileMapLp& m, int t) {
+  const int txi = t % m.ntx;
+  int r = t / m.ntx;
+  int cy, cz;
+  if (m.blk > 1) {
+    const int zi = r % m.blk;
+    r /= m.blk;
+    const int yi = r % m.blk;
+    r /= m.blk;
+    const int nb = m.n / m.blk;
+    const int zb = r % nb, yb = r / nb;
+    cz = zb * m.blk + zi;
+    cy = yb * m.blk + yi;
+  } else {
+    cy = r % m.n;
+    cz = r / m.n;
+  }
+  return (cz * m.n + cy) * m.n + txi * m.tx;
+}
+
+// ---------------------------------------------------------------------------
+// Operator apply / residual, FP32 storage, contractions on the matrix cores.
+// Same decomposition as the VALU kernel (a wave owns TX cells of an x-row,
+// one lane per 1D line); the N x N products of the three stages run as
+// LineMV calls of all 64 lanes, face traces and rank-2 terms in FP32.
+// ---------------------------------------------------------------------------
+template <int N, bool BF, bool EC, bool RES>
+__global__ __launch_bounds__(kThreads) void apply_lp_kernel(
+    const float* __restrict__ u, float* __restrict__ v, const float* __restrict__ bvec,
+    const float* __restrict__ tab, TableLayout lay, TileMapLp tm, float h) {
+  constexpr int N2 = N * N, N3 = N2 * N, CPB = (64 / N2) > 0 ? 64 / N2 : 1;
+  constexpr int NP = Pad<N>::value;
+  constexpr int WAVES = kThreads / 64;
+  __shared__ float s_t1_all[WAVES * CPB * N3];
+  __shared__ float s_t2_all[WAVES * CPB * N3];
+  __shared__ float s_ty_all[WAVES * CPB * 4 * N2];
+  __shared__ float s_tz_all[WAVES * CPB * 4 * N2];
+  __shared__ float s_tzm_all[WAVES * CPB * 4 * N2];
+
+  const int tid = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int grp = xcd_remap(blockIdx.x, gridDim.x) * WAVES + wave;
+  if (grp >= tm.ngroups) return;  // wave-uniform
+  float* s_t1 = s_t1_all + wave * (CPB * N3);
+  float* s_t2 = s_t2_all + wave * (CPB * N3);
+  float* s_ty = s_ty_all + wave * (CPB * 4 * N2);
+  float* s_tz = s_tz_all + wave * (CPB * 4 * N2);
+  float* s_tzm = s_tzm_all + wave * (CPB * 4 * N2);
+  const int n = tm.n, nn = n * n, nc = tm.tx;
+  const int c0 = tile_first_cell(tm, grp);
+  const int cy = (c0 / n) % n, cz = c0 / nn, cx0 = c0 % n;
+  const bool act = tid < nc * N2;
+  const int cl = act ? tid / N2 : 0, ln = tid - cl * N2;
+  const int c = c0 + cl, cx = cx0 + cl;
+  const int lp = ln % N, lq = ln / N;
+
+  const float* __restrict__ gM = tab + lay.mass;
+  const float* __restrict__ gL = tab + lay.lcell;
+  const float* __restrict__ d0 = tab + lay.d0;
+  const float* __restrict__ d1 = tab + lay.d1;
+  const float gam = tab[lay.gam];
+  LineMV<NP, BF, EC> mvM, mvL;
+  mvM.load(gM, N, false);
+  mvL.load(gL, N, false);
+
+  float own[N], xlo[N], xhi[N], ylo[N], yhi[N], zlo[N], zhi[N];
+  const bool hx0 = act && cx > 0, hx1 = act && cx < n - 1;
+  const bool hy0 = act && cy > 0, hy1 = act && cy < n - 1;
+  const bool hz0 = act && cz > 0, hz1 = act && cz < n - 1;
+  {
+    const float* pc = u + (size_t)c * N3;
+    const float* pxl = pc - N3 + ln * N;
+    const float* pxh = pc + N3 + ln * N;
+    const float* pyl = pc - (size_t)n * N3 + lp + lq * N2;
+    const float* pyh = pc + (size_t)n * N3 + lp + lq * N2;
+    const float* pzl = pc - (size_t)nn * N3 + ln;
+    const float* pzh = pc + (size_t)nn * N3 + ln;
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      own[a] = act ? pc[ln * N + a] : 0.0f;
+      xlo[a] = hx0 ? pxl[a] : 0.0f;
+      xhi[a] = hx1 ? pxh[a] : 0.0f;
+      ylo[a] = hy0 ? pyl[a * N] : 0.0f;
+      yhi[a] = hy1 ? pyh[a * N] : 0.0f;
+      zlo[a] = hz0 ? pzl[a * N2] : 0.0f;
+      zhi[a] = hz1 ? pzh[a * N2] : 0.0f;
+    }
+  }
+
+  // ---- x stage
+  {
+    float t1[N], t2[N];
+    line_mv<N>(mvL, own, t1);
+    line_mv<N>(mvM, own, t2);
+    if (act) {
+      add_boundary_correction<N>(t1, own, cx == 0, cx == n - 1, d0, d1);
+      if (hx0) {
+        float g = 0.0f;
+#pragma unroll
+        for (int a = 0; a < N; ++a) g = fmaf(d1[a], xlo[a], g);
+        add_lower_face<N>(t1, xlo[N - 1], g, gam, d0);
+      }
+      if (hx1) {
+        float g = 0.0f;
+#pragma unroll
+        for (int a = 0; a < N; ++a) g = fmaf(d0[a], xhi[a], g);
+        add_upper_face<N>(t1, xhi[0], g, gam, d1);
+      }
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        s_t1[cl * N3 + ln * N + a] = t1[a];
+        s_t2[cl * N3 + ln * N + a] = t2[a];
+      }
+      float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, g3 = 0.0f;
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        g0 = fmaf(d1[a], ylo[a], g0);
+        g1 = fmaf(d0[a], yhi[a], g1);
+        g2 = fmaf(d1[a], zlo[a], g2);
+        g3 = fmaf(d0[a], zhi[a], g3);
+      }
+      float* ty = s_ty + cl * 4 * N2;
+      float* tz = s_tz + cl * 4 * N2;
+      ty[0 * N2 + ln] = ylo[N - 1];
+      ty[1 * N2 + ln] = g0;
+      ty[2 * N2 + ln] = yhi[0];
+      ty[3 * N2 + ln] = g1;
+      tz[0 * N2 + ln] = zlo[N - 1];
+      tz[1 * N2 + ln] = g2;
+      tz[2 * N2 + ln] = zhi[0];
+      tz[3 * N2 + ln] = g3;
+    }
+  }
+  wave_lds_sync();
+
+  // ---- y stage: lines (i, l) = (lp, lq); Mx on the z traces at (i, j)
+  {
+    float a1[N], a2[N], cc[N], e[N];
+    const int base = cl * N3 + lp + lq * N2;
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      a1[b] = act ? s_t1[base + b * N] : 0.0f;
+      a2[b] = act ? s_t2[base + b * N] : 0.0f;
+    }
+    line_mv<N>(mvM, a1, cc);
+    line_mv_acc<N>(mvL, a2, cc);
+    line_mv<N>(mvM, a2, e);
+    if (act) {
+      add_boundary_correction<N>(cc, a2, cy == 0, cy == n - 1, d0, d1);
+      const float* ty = s_ty + cl * 4 * N2 + lq * N;
+      const float* Mrow = gM + lp * N;
+      float f0 = 0.0f, q0 = 0.0f, f1 = 0.0f, q1 = 0.0f;
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        f0 = fmaf(Mrow[b], ty[0 * N2 + b], f0);
+        q0 = fmaf(Mrow[b], ty[1 * N2 + b], q0);
+        f1 = fmaf(Mrow[b], ty[2 * N2 + b], f1);
+        q1 = fmaf(Mrow[b], ty[3 * N2 + b], q1);
+      }
+      if (hy0) add_lower_face<N>(cc, f0, q0, gam, d0);
+      if (hy1) add_upper_face<N>(cc, f1, q1, gam, d1);
+      const float* tz = s_tz + cl * 4 * N2 + lq * N;
+      float* tzm = s_tzm + cl * 4 * N2 + lq * N + lp;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int b = 0; b < N; ++b) acc = fmaf(Mrow[b], tz[r * N2 + b], acc);
+        tzm[r * N2] = acc;
+      }
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        s_t1[base + b * N] = cc[b];
+        s_t2[base + b * N] = e[b];
+      }
+    }
+  }
+  wave_lds_sync();
+
+  // ---- z stage: lines (i, j) = ln
+  {
+    float a1[N], a2[N], o[N];
+    const int base = cl * N3 + ln;
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      a1[b] = act ? s_t1[base + b * N2] : 0.0f;
+      a2[b] = act ? s_t2[base + b * N2] : 0.0f;
+    }
+    line_mv<N>(mvM, a1, o);
+    line_mv_acc<N>(mvL, a2, o);
+    if (act) {
+      add_boundary_correction<N>(o, a2, cz == 0, cz == n - 1, d0, d1);
+      const float* tzm = s_tzm + cl * 4 * N2 + lp;
+      const float* Mrow = gM + lq * N;
+      float f0 = 0.0f, q0 = 0.0f, f1 = 0.0f, q1 = 0.0f;
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        f0 = fmaf(Mrow[b], tzm[0 * N2 + b * N], f0);
+        q0 = fmaf(Mrow[b], tzm[1 * N2 + b * N], q0);
+        f1 = fmaf(Mrow[b], tzm[2 * N2 + b * N], f1);
+        q1 = fmaf(Mrow[b], tzm[3 * N2 + b * N], q1);
+      }
+      if (hz0) add_lower_face<N>(o, f0, q0, gam, d0);
+      if (hz1) add_upper_face<N>(o, f1, q1, gam, d1);
+      float* dst = v + (size_t)c * N3 + ln;
+      if (RES) {
+        const float* bs = bvec + (size_t)c * N3 + ln;
+#pragma unroll
+        for (int a = 0; a < N; ++a) dst[a * N2] = bs[a * N2] - h * o[a];
+      } else {
+#pragma unroll
+        for (int a = 0; a < N; ++a) dst[a * N2] = h * o[a];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fast-diagonalization patch correction, FP32 storage, the six 2N x 2N
+// contractions on the matrix cores.  Lines of one patch are consecutive
+// lanes, so every group of 4 lanes shares the patch (and its 1D type).
+// ---------------------------------------------------------------------------
+template <int N, bool BF, bool EC>
+__global__ __launch_bounds__(kThreads) void patch_fd_lp_kernel(
+    const float* __restrict__ r, float* __restrict__ x, const float* __restrict__ tab,
+    TableLayout lay, int n, float h, int bx, int by, int bz, int npx, int npy, int npatch) {
+  constexpr int G = 2 * N, G2 = G * G, G3 = G2 * G, N2 = N * N, N3 = N2 * N;
+  constexpr int PPB = (kThreads / G2) > 0 ? kThreads / G2 : 1;
+  constexpr int GP = Pad<G>::value;
+  __shared__ float s_l[4 * G];
+  __shared__ float s_X[PPB * G3];
+  const int tid = threadIdx.x;
+  const int p0 = xcd_remap(blockIdx.x, gridDim.x) * PPB;
+  const int np = min(PPB, npatch - p0);
+  if (np <= 0) return;
+  for (int i = tid; i < 4 * G; i += kThreads) s_l[i] = tab[lay.fd_l + i];
+  auto vertex = [&](int pl, int& vx, int& vy, int& vz) {
+    const int p = p0 + pl;
+    const int px = p % npx, py = (p / npx) % npy, pz = p / (npx * npy);
+    vx = 2 * px + (bx ? 1 : 2);
+    vy = 2 * py + (by ? 1 : 2);
+    vz = 2 * pz + (bz ? 1 : 2);
+  };
+  const int nn = n * n;
+  for (int w = tid; w < np * G3; w += kThreads) {
+    const int pl = w / G3, rr = w - pl * G3;
+    int vx, vy, vz;
+    vertex(pl, vx, vy, vz);
+    const int cell8 = rr / N3, loc = rr - cell8 * N3;
+    const int dx = cell8 & 1, dy = (cell8 >> 1) & 1, dz = cell8 >> 2;
+    const int i = loc % N, j = (loc / N) % N, l = loc / N2;
+    const int c = (vx - 1 + dx) + n * (vy - 1 + dy) + nn * (vz - 1 + dz);
+    s_X[pl * G3 + (dx * N + i) + G * (dy * N + j) + G2 * (dz * N + l)] = r[(size_t)c * N3 + loc];
+  }
+  __syncthreads();
+
+  const bool act = tid < np * G2;
+  const int pl = act ? tid / G2 : 0, ln = tid - pl * G2;
+  int vx = 1, vy = 1, vz = 1;
+  if (act) vertex(pl, vx, vy, vz);
+  const int tx = (vx == 1 ? 1 : 0) | (vx == n - 1 ? 2 : 0);
+  const int ty = (vy == 1 ? 1 : 0) | (vy == n - 1 ? 2 : 0);
+  const int tz = (vz == 1 ? 1 : 0) | (vz == n - 1 ? 2 : 0);
+  float* X = s_X + pl * G3;
+  const int la = ln % G, lb = ln / G;
+  const int o0 = la * G + lb * G2, o1 = la + lb * G2, o2 = la + lb * G;
+  const float* S = tab + lay.fd_s;
+  float in[G], out[G];
+  {
+    LineMV<GP, BF, EC> m;
+    m.load(S + tx * G2, G, true);
+#pragma unroll
+    for (int a = 0; a < G; ++a) in[a] = act ? X[o0 + a] : 0.0f;
+    line_mv<G>(m, in, out);
+    if (act)
+#pragma unroll
+      for (int a = 0; a < G; ++a) X[o0 + a] = out[a];
+  }
+  __syncthreads();
+  {
+    LineMV<GP, BF, EC> m;
+    m.load(S + ty * G2, G, true);
+#pragma unroll
+    for (int a = 0; a < G; ++a) in[a] = act ? X[o1 + a * G] : 0.0f;
+    line_mv<G>(m, in, out);
+    if (act)
+#pragma unroll
+      for (int a = 0; a < G; ++a) X[o1 + a * G] = out[a];
+  }
+  __syncthreads();
+  {
+    LineMV<GP, BF, EC> mt, mf;
+    mt.load(S + tz * G2, G, true);
+    mf.load(S + tz * G2, G, false);
+#pragma unroll
+    for (int a = 0; a < G; ++a) in[a] = act ? X[o2 + a * G2] : 0.0f;
+    line_mv<G>(mt, in, out);
+    const float lij = act ? s_l[tx * G + la] + s_l[ty * G + lb] : 1.0f;
+#pragma unroll
+    for (int a = 0; a < G; ++a) in[a] = act ? out[a] / (h * (lij + s_l[tz * G + a])) : 0.0f;
+    line_mv<G>(mf, in, out);
+    if (act)
+#pragma unroll
+      for (int a = 0; a < G; ++a) X[o2 + a * G2] = out[a];
+  }
+  __syncthreads();
+  {
+    LineMV<GP, BF, EC> m;
+    m.load(S + ty * G2, G, false);
+#pragma unroll
+    for (int a = 0; a < G; ++a) in[a] = act ? X[o1 + a * G] : 0.0f;
+    line_mv<G>(m, in, out);
+    if (act)
+#pragma unroll
+      for (int a = 0; a < G; ++a) X[o1 + a * G] = out[a];
+  }
+  __syncthreads();
+  {
+    LineMV<GP, BF, EC> m;
+    m.load(S + tx * G2, G, false);
+#pragma unroll
+    for (int a = 0; a < G; ++a) in[a] = act ? X[o0 + a] : 0.0f;
+    line_mv<G>(m, in, out);
+    if (act)
+#pragma unroll
+      for (int a = 0; a < G; ++a) X[o0 + a] = out[a];
+  }
+  __syncthreads();
+  for (int w = tid; w < np * G3; w += kThreads) {
+    const int q = w / G3, rr = w - q * G3;
+    int ux, uy, uz;
+    vertex(q, ux, uy, uz);
+    const int cell8 = rr / N3, loc = rr - cell8 * N3;
+    const int dx = cell8 & 1, dy = (cell8 >> 1) & 1, dz = cell8 >> 2;
+    const int i = loc % N, j = (loc / N) % N, l = loc / N2;
+    const int c = (ux - 1 + dx) + n * (uy - 1 + dy) + nn * (uz - 1 + dz);
+    x[(size_t)c * N3 + loc] += s_X[q * G3 + (dx * N + i) + G * (dy * N + j) + G2 * (dz * N + l)];
+  }
+}
+
+template <int N, bool BF, bool EC>
+hipError_t apply_lp_impl(const float* u, float* v, const float* b, const DevTab& t, int n,
+                         double h, hipStream_t s) {
+  constexpr int CPW = (64 / (N * N)) > 0 ? 64 / (N * N) : 1;
+  if (n < 1 || n > 1024) return hipErrorInvalidValue;
+  TileMapLp tm;
+  tm.n = n;
+  tm.tx = 1;
+  for (int d = 1; d <= CPW && d <= n; ++d)
+    if (n % d == 0) tm.tx = d;
+  tm.ntx = n / tm.tx;
+  tm.blk = (n % 8 == 0) ? 8 : 1;
+  const int64_t tiles = (int64_t)tm.ntx * n * n;
+  if (tiles > ((int64_t)1 << 30)) return hipErrorInvalidValue;
+  tm.ngroups = (int)tiles;
+  const int waves = kThreads / 64;
+  const int grid = (int)((tiles + waves - 1) / waves);
+  if (b)
+    hipLaunchKernelGGL((apply_lp_kernel<N, BF, EC, true>), dim3(grid), dim3(kThreads), 0, s, u,
+                       v, b, t.tabf, t.lay, tm, (float)h);
+  else
+    hipLaunchKernelGGL((apply_lp_kernel<N, BF, EC, false>), dim3(grid), dim3(kThreads), 0, s,
+                       u, v, nullptr, t.tabf, t.lay, tm, (float)h);
+  return hipGetLastError();
+}
+
+template <int N, bool BF, bool EC>
+hipError_t patch_lp_impl(int colour, const float* r, float* x, const DevTab& t, int n,
+                         double h, hipStream_t s) {
+  constexpr int G2 = 4 * N * N;
+  constexpr int PPB = (kThreads / G2) > 0 ? kThreads / G2 : 1;
+  const int bx = colour & 1, by = (colour >> 1) & 1, bz = (colour >> 2) & 1;
+  auto count = [&](int bit) { return bit ? n / 2 : (n - 1) / 2; };
+  const int npx = count(bx), npy = count(by), npz = count(bz);
+  const int64_t np = (int64_t)npx * npy * npz;
+  if (np == 0) return hipSuccess;
+  const int grid = (int)((np + PPB - 1) / PPB);
+  hipLaunchKernelGGL((patch_fd_lp_kernel<N, BF, EC>), dim3(grid), dim3(kThreads), 0, s, r, x,
+                     t.tabf, t.lay, n, (float)h, bx, by, bz, npx, npy, (int)np);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+#define SIPG_LP_DISPATCH(N, BF, EC, CALL)                         \
+  switch (N) {                                                    \
+    case 2: return EC ? (BF ? CALL(2, true, true) : CALL(2, false, true)) \
+                      : (BF ? CALL(2, true, false) : CALL(2, false, false)); \
+    case 3: return EC ? (BF ? CALL(3, true, true) : CALL(3, false, true)) \
+                      : (BF ? CALL(3, true, false) : CALL(3, false, false)); \
+    case 4: return EC ? (BF ? CALL(4, true, true) : CALL(4, false, true)) \
+                      : (BF ? CALL(4, true, false) : CALL(4, false, false)); \
+    case 5: return EC ? (BF ? CALL(5, true, true) : CALL(5, false, true)) \
+                      : (BF ? CALL(5, true, false) : CALL(5, false, false)); \
+    case 6: return EC ? (BF ? CALL(6, true, true) : CALL(6, false, true)) \
+                      : (BF ? CALL(6, true, false) : CALL(6, false, false)); \
+    case 7: return EC ? (BF ? CALL(7, true, true) : CALL(7, false, true)) \
+                      : (BF ? CALL(7, true, false) : CALL(7, false, false)); \
+    case 8: return EC ? (BF ? CALL(8, true, true) : CALL(8, false, true)) \
+                      : (BF ? CALL(8, true, false) : CALL(8, false, false)); \
+    default: return hipErrorInvalidValue;                         \
+  }
+
+hipError_t launch_apply_lp(int N, bool bf16, bool ec, const float* u, float* v, const float* b,
+                           const DevTab& t, int n, double h, hipStream_t s) {
+  if (t.lay.N != N) return hipErrorInvalidValue;
+#define CALL(NN, BB, EE) apply_lp_impl<NN, BB, EE>(u, v, b, t, n, h, s)
+  SIPG_LP_DISPATCH(N, bf16, ec, CALL)
+#undef CALL
+}
+
+hipError_t launch_patch_fd_lp(int N, bool bf16, bool ec, int colour, const float* r, float* x,
+                              const DevTab& t, int n, double h, hipStream_t s) {
+  if (t.lay.N != N || colour < 0 || colour > 7 || n < 2) return hipErrorInvalidValue;
+#define CALL(NN, BB, EE) patch_lp_impl<NN, BB, EE>(colour, r, x, t, n, h, s)
+  SIPG_LP_DISPATCH(N, bf16, ec, CALL)
+#undef CALL
+}
+
+}  // namespace sipg

@@ -1,4 +1,4 @@
-// FP64 kernels of the SIPG operator, the vertex-patch fast-diagonalization
+// VALU kernels (FP64 and FP32 instantiations) of the SIPG operator, the vertex-patch fast-diagonalization
 // smoother, the exact coarse solve and the level transfers on gfx950.
 //
 // Operator (Sec. 2.1, eq. tensorproduct_3d): on a uniform Cartesian level
@@ -32,24 +32,22 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
-template <int N>
-__device__ __forceinline__ void matvec(const double* __restrict__ A, const double (&x)[N],
-                                       double (&y)[N]) {
+template <int N, typename T>
+__device__ __forceinline__ void matvec(const T* __restrict__ A, const T (&x)[N], T (&y)[N]) {
 #pragma unroll
   for (int a = 0; a < N; ++a) {
-    double s = 0.0;
+    T s = 0;
 #pragma unroll
     for (int b = 0; b < N; ++b) s = fma(A[a * N + b], x[b], s);
     y[a] = s;
   }
 }
 
-template <int N>
-__device__ __forceinline__ void matvec_acc(const double* __restrict__ A, const double (&x)[N],
-                                           double (&y)[N]) {
+template <int N, typename T>
+__device__ __forceinline__ void matvec_acc(const T* __restrict__ A, const T (&x)[N], T (&y)[N]) {
 #pragma unroll
   for (int a = 0; a < N; ++a) {
-    double s = y[a];
+    T s = y[a];
 #pragma unroll
     for (int b = 0; b < N; ++b) s = fma(A[a * N + b], x[b], s);
     y[a] = s;
@@ -57,12 +55,11 @@ __device__ __forceinline__ void matvec_acc(const double* __restrict__ A, const d
 }
 
 // y = A^T x
-template <int N>
-__device__ __forceinline__ void matvec_t(const double* __restrict__ A, const double (&x)[N],
-                                         double (&y)[N]) {
+template <int N, typename T>
+__device__ __forceinline__ void matvec_t(const T* __restrict__ A, const T (&x)[N], T (&y)[N]) {
 #pragma unroll
   for (int a = 0; a < N; ++a) {
-    double s = 0.0;
+    T s = 0;
 #pragma unroll
     for (int b = 0; b < N; ++b) s = fma(A[b * N + a], x[b], s);
     y[a] = s;
@@ -71,19 +68,19 @@ __device__ __forceinline__ void matvec_t(const double* __restrict__ A, const dou
 
 // Face coupling to the lower neighbour (its high-end value f and derivative
 // g = d1 . u) and to the upper neighbour (low-end value f, g = d0 . u).
-template <int N>
-__device__ __forceinline__ void add_lower_face(double (&t)[N], double f, double g, double gam,
-                                               const double* __restrict__ d0) {
-  t[0] += -gam * f + 0.5 * g;
+template <int N, typename T>
+__device__ __forceinline__ void add_lower_face(T (&t)[N], T f, T g, T gam,
+                                               const T* __restrict__ d0) {
+  t[0] += -gam * f + T(0.5) * g;
 #pragma unroll
-  for (int a = 0; a < N; ++a) t[a] = fma(-0.5 * d0[a], f, t[a]);
+  for (int a = 0; a < N; ++a) t[a] = fma(T(-0.5) * d0[a], f, t[a]);
 }
-template <int N>
-__device__ __forceinline__ void add_upper_face(double (&t)[N], double f, double g, double gam,
-                                               const double* __restrict__ d1) {
-  t[N - 1] += -gam * f - 0.5 * g;
+template <int N, typename T>
+__device__ __forceinline__ void add_upper_face(T (&t)[N], T f, T g, T gam,
+                                               const T* __restrict__ d1) {
+  t[N - 1] += -gam * f - T(0.5) * g;
 #pragma unroll
-  for (int a = 0; a < N; ++a) t[a] = fma(0.5 * d1[a], f, t[a]);
+  for (int a = 0; a < N; ++a) t[a] = fma(T(0.5) * d1[a], f, t[a]);
 }
 
 __device__ __forceinline__ int bdry_variant(int coord, int n) {
@@ -94,26 +91,25 @@ __device__ __forceinline__ int bdry_variant(int coord, int n) {
 // by a rank-2 term: at x = 0 the boundary face adds (s0 d0^T + d0 s0^T)/2
 // more than an interior face, at x = 1 it adds -(s1 d1^T + d1 s1^T)/2.
 // Applied to the line x (before any face term is added to t).
-template <int N>
-__device__ __forceinline__ void add_boundary_correction(double (&t)[N], const double (&x)[N],
-                                                        bool lo, bool hi,
-                                                        const double* __restrict__ d0,
-                                                        const double* __restrict__ d1) {
+template <int N, typename T>
+__device__ __forceinline__ void add_boundary_correction(T (&t)[N], const T (&x)[N], bool lo,
+                                                        bool hi, const T* __restrict__ d0,
+                                                        const T* __restrict__ d1) {
   if (lo) {
-    double g = 0.0;
+    T g = 0;
 #pragma unroll
     for (int a = 0; a < N; ++a) g = fma(d0[a], x[a], g);
-    t[0] += 0.5 * g;
+    t[0] += T(0.5) * g;
 #pragma unroll
-    for (int a = 0; a < N; ++a) t[a] = fma(0.5 * d0[a], x[0], t[a]);
+    for (int a = 0; a < N; ++a) t[a] = fma(T(0.5) * d0[a], x[0], t[a]);
   }
   if (hi) {
-    double g = 0.0;
+    T g = 0;
 #pragma unroll
     for (int a = 0; a < N; ++a) g = fma(d1[a], x[a], g);
-    t[N - 1] -= 0.5 * g;
+    t[N - 1] -= T(0.5) * g;
 #pragma unroll
-    for (int a = 0; a < N; ++a) t[a] = fma(-0.5 * d1[a], x[N - 1], t[a]);
+    for (int a = 0; a < N; ++a) t[a] = fma(T(-0.5) * d1[a], x[N - 1], t[a]);
   }
 }
 
@@ -156,28 +152,28 @@ __device__ __forceinline__ void wave_lds_sync() {
   asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 }
 
-template <int N, bool RES>
-__global__ __launch_bounds__(kThreads) void apply_f64_wave_kernel(
-    const double* __restrict__ u, double* __restrict__ v, const double* __restrict__ bvec,
-    const double* __restrict__ tab, TableLayout lay, TileMap tm, double h) {
+template <typename T, int N, bool RES>
+__global__ __launch_bounds__(kThreads) void apply_wave_kernel(
+    const T* __restrict__ u, T* __restrict__ v, const T* __restrict__ bvec,
+    const T* __restrict__ tab, TableLayout lay, TileMap tm, T h) {
   constexpr int N2 = N * N, N3 = N2 * N, CPB = (64 / N2) > 0 ? 64 / N2 : 1;
   constexpr int WAVES = kThreads / 64;
-  __shared__ double s_t1_all[WAVES * CPB * N3];
-  __shared__ double s_t2_all[WAVES * CPB * N3];
+  __shared__ T s_t1_all[WAVES * CPB * N3];
+  __shared__ T s_t2_all[WAVES * CPB * N3];
   // per cell: y-face traces [face 0,1][value, derivative][i + N l] and
   // z-face traces [face 0,1][value, derivative][i + N j], raw then after Mx
-  __shared__ double s_ty_all[WAVES * CPB * 4 * N2];
-  __shared__ double s_tz_all[WAVES * CPB * 4 * N2];
-  __shared__ double s_tzm_all[WAVES * CPB * 4 * N2];
+  __shared__ T s_ty_all[WAVES * CPB * 4 * N2];
+  __shared__ T s_tz_all[WAVES * CPB * 4 * N2];
+  __shared__ T s_tzm_all[WAVES * CPB * 4 * N2];
 
   const int tid = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int grp = xcd_remap(blockIdx.x, gridDim.x) * WAVES + wave;
   if (grp >= tm.ngroups) return;  // wave-uniform; no workgroup barriers below
-  double* s_t1 = s_t1_all + wave * (CPB * N3);
-  double* s_t2 = s_t2_all + wave * (CPB * N3);
-  double* s_ty = s_ty_all + wave * (CPB * 4 * N2);
-  double* s_tz = s_tz_all + wave * (CPB * 4 * N2);
-  double* s_tzm = s_tzm_all + wave * (CPB * 4 * N2);
+  T* s_t1 = s_t1_all + wave * (CPB * N3);
+  T* s_t2 = s_t2_all + wave * (CPB * N3);
+  T* s_ty = s_ty_all + wave * (CPB * 4 * N2);
+  T* s_tz = s_tz_all + wave * (CPB * 4 * N2);
+  T* s_tzm = s_tzm_all + wave * (CPB * 4 * N2);
   const int n = tm.n, nn = n * n, nc = tm.tx;
   const int c0 = tile_first_cell(tm, grp);
   const int cy = (c0 / n) % n, cz = c0 / nn, cx0 = c0 % n;
@@ -189,18 +185,18 @@ __global__ __launch_bounds__(kThreads) void apply_f64_wave_kernel(
   const int lp = ln % N, lq = ln / N;
 
   // ---- all global loads of the tile are issued first
-  double own[N], xlo[N], xhi[N], ylo[N], yhi[N], zlo[N], zhi[N];
+  T own[N], xlo[N], xhi[N], ylo[N], yhi[N], zlo[N], zhi[N];
   const bool hx0 = act && cx > 0, hx1 = act && cx < n - 1;
   const bool hy0 = act && cy > 0, hy1 = act && cy < n - 1;
   const bool hz0 = act && cz > 0, hz1 = act && cz < n - 1;
   {
-    const double* pc = u + (size_t)c * N3;
-    const double* pxl = pc - N3 + ln * N;
-    const double* pxh = pc + N3 + ln * N;
-    const double* pyl = pc - (size_t)n * N3 + lp + lq * N2;
-    const double* pyh = pc + (size_t)n * N3 + lp + lq * N2;
-    const double* pzl = pc - (size_t)nn * N3 + ln;
-    const double* pzh = pc + (size_t)nn * N3 + ln;
+    const T* pc = u + (size_t)c * N3;
+    const T* pxl = pc - N3 + ln * N;
+    const T* pxh = pc + N3 + ln * N;
+    const T* pyl = pc - (size_t)n * N3 + lp + lq * N2;
+    const T* pyh = pc + (size_t)n * N3 + lp + lq * N2;
+    const T* pzl = pc - (size_t)nn * N3 + ln;
+    const T* pzh = pc + (size_t)nn * N3 + ln;
 #pragma unroll
     for (int a = 0; a < N; ++a) {
       own[a] = act ? pc[ln * N + a] : 0.0;
@@ -213,26 +209,26 @@ __global__ __launch_bounds__(kThreads) void apply_f64_wave_kernel(
     }
   }
   // 1D tables are uniform over the workgroup: read through the scalar path
-  const double* __restrict__ s_M = tab + lay.mass;
-  const double* __restrict__ s_L = tab + lay.lcell;  // interior block (variant 0)
-  const double* __restrict__ s_d0 = tab + lay.d0;
-  const double* __restrict__ s_d1 = tab + lay.d1;
-  const double gam = tab[lay.gam];
+  const T* __restrict__ s_M = tab + lay.mass;
+  const T* __restrict__ s_L = tab + lay.lcell;  // interior block (variant 0)
+  const T* __restrict__ s_d0 = tab + lay.d0;
+  const T* __restrict__ s_d1 = tab + lay.d1;
+  const T gam = tab[lay.gam];
 
   // ---- x stage in registers, traces of the y/z neighbours to LDS
   if (act) {
-    double t1[N], t2[N];
+    T t1[N], t2[N];
     matvec<N>(s_L, own, t1);
     add_boundary_correction<N>(t1, own, cx == 0, cx == n - 1, s_d0, s_d1);
     matvec<N>(s_M, own, t2);
     if (hx0) {
-      double g = 0.0;
+      T g = 0.0;
 #pragma unroll
       for (int a = 0; a < N; ++a) g = fma(s_d1[a], xlo[a], g);
       add_lower_face<N>(t1, xlo[N - 1], g, gam, s_d0);
     }
     if (hx1) {
-      double g = 0.0;
+      T g = 0.0;
 #pragma unroll
       for (int a = 0; a < N; ++a) g = fma(s_d0[a], xhi[a], g);
       add_upper_face<N>(t1, xhi[0], g, gam, s_d1);
@@ -242,7 +238,7 @@ __global__ __launch_bounds__(kThreads) void apply_f64_wave_kernel(
       s_t1[cl * N3 + ln * N + a] = t1[a];
       s_t2[cl * N3 + ln * N + a] = t2[a];
     }
-    double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
+    T g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
 #pragma unroll
     for (int a = 0; a < N; ++a) {
       g0 = fma(s_d1[a], ylo[a], g0);
@@ -250,8 +246,8 @@ __global__ __launch_bounds__(kThreads) void apply_f64_wave_kernel(
       g2 = fma(s_d1[a], zlo[a], g2);
       g3 = fma(s_d0[a], zhi[a], g3);
     }
-    double* ty = s_ty + cl * 4 * N2;
-    double* tz = s_tz + cl * 4 * N2;
+    T* ty = s_ty + cl * 4 * N2;
+    T* tz = s_tz + cl * 4 * N2;
     ty[0 * N2 + ln] = ylo[N - 1];
     ty[1 * N2 + ln] = g0;
     ty[2 * N2 + ln] = yhi[0];
@@ -265,7 +261,7 @@ __global__ __launch_bounds__(kThreads) void apply_f64_wave_kernel(
 
   // ---- y stage: lines (i, l) = (lp, lq); also Mx on the z traces at (i, j)
   if (act) {
-    double a1[N], a2[N], cc[N], e[N];
+    T a1[N], a2[N], cc[N], e[N];
     const int base = cl * N3 + lp + lq * N2;
 #pragma unroll
     for (int b = 0; b < N; ++b) {
@@ -276,9 +272,9 @@ __global__ __launch_bounds__(kThreads) void apply_f64_wave_kernel(
     matvec_acc<N>(s_L, a2, cc);
     add_boundary_correction<N>(cc, a2, cy == 0, cy == n - 1, s_d0, s_d1);
     matvec<N>(s_M, a2, e);
-    const double* ty = s_ty + cl * 4 * N2 + lq * N;
-    const double* Mrow = s_M + lp * N;
-    double f0 = 0.0, q0 = 0.0, f1 = 0.0, q1 = 0.0;
+    const T* ty = s_ty + cl * 4 * N2 + lq * N;
+    const T* Mrow = s_M + lp * N;
+    T f0 = 0.0, q0 = 0.0, f1 = 0.0, q1 = 0.0;
 #pragma unroll
     for (int b = 0; b < N; ++b) {  // (Mx trace)(i, l) = sum_i' M[i][i'] trace(i', l)
       f0 = fma(Mrow[b], ty[0 * N2 + b], f0);
@@ -288,11 +284,11 @@ __global__ __launch_bounds__(kThreads) void apply_f64_wave_kernel(
     }
     if (hy0) add_lower_face<N>(cc, f0, q0, gam, s_d0);
     if (hy1) add_upper_face<N>(cc, f1, q1, gam, s_d1);
-    const double* tz = s_tz + cl * 4 * N2 + lq * N;
-    double* tzm = s_tzm + cl * 4 * N2 + lq * N + lp;
+    const T* tz = s_tz + cl * 4 * N2 + lq * N;
+    T* tzm = s_tzm + cl * 4 * N2 + lq * N + lp;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      double acc = 0.0;
+      T acc = 0.0;
 #pragma unroll
       for (int b = 0; b < N; ++b) acc = fma(Mrow[b], tz[r * N2 + b], acc);
       tzm[r * N2] = acc;
@@ -307,7 +303,7 @@ __global__ __launch_bounds__(kThreads) void apply_f64_wave_kernel(
 
   // ---- z stage: lines (i, j) = ln, written straight to global memory
   if (act) {
-    double a1[N], a2[N], o[N];
+    T a1[N], a2[N], o[N];
     const int base = cl * N3 + ln;
 #pragma unroll
     for (int b = 0; b < N; ++b) {
@@ -318,9 +314,9 @@ __global__ __launch_bounds__(kThreads) void apply_f64_wave_kernel(
     matvec_acc<N>(s_L, a2, o);
     add_boundary_correction<N>(o, a2, cz == 0, cz == n - 1, s_d0, s_d1);
     // (My Mx trace)(i, j) = sum_j' M[j][j'] (Mx trace)(i, j')
-    const double* tzm = s_tzm + cl * 4 * N2 + lp;
-    const double* Mrow = s_M + lq * N;
-    double f0 = 0.0, q0 = 0.0, f1 = 0.0, q1 = 0.0;
+    const T* tzm = s_tzm + cl * 4 * N2 + lp;
+    const T* Mrow = s_M + lq * N;
+    T f0 = 0.0, q0 = 0.0, f1 = 0.0, q1 = 0.0;
 #pragma unroll
     for (int b = 0; b < N; ++b) {
       f0 = fma(Mrow[b], tzm[0 * N2 + b * N], f0);
@@ -330,9 +326,9 @@ __global__ __launch_bounds__(kThreads) void apply_f64_wave_kernel(
     }
     if (hz0) add_lower_face<N>(o, f0, q0, gam, s_d0);
     if (hz1) add_upper_face<N>(o, f1, q1, gam, s_d1);
-    double* dst = v + (size_t)c * N3 + ln;
+    T* dst = v + (size_t)c * N3 + ln;
     if (RES) {
-      const double* bs = bvec + (size_t)c * N3 + ln;
+      const T* bs = bvec + (size_t)c * N3 + ln;
 #pragma unroll
       for (int a = 0; a < N; ++a) dst[a * N2] = bs[a * N2] - h * o[a];
     } else {
@@ -349,15 +345,15 @@ __global__ __launch_bounds__(kThreads) void apply_f64_wave_kernel(
 // (Lh_P S = Mh_P S diag(l), S^T Mh_P S = I).  Patch layout in LDS:
 // i' + G j' + G^2 l' with i' = dx N + i over the two cells of each direction.
 // ---------------------------------------------------------------------------
-template <int N>
-__global__ __launch_bounds__(kThreads) void patch_fd_f64_kernel(
-    const double* __restrict__ r, double* __restrict__ x, const double* __restrict__ tab,
-    TableLayout lay, int n, double h, int bx, int by, int bz, int npx, int npy, int npatch) {
+template <typename T, int N>
+__global__ __launch_bounds__(kThreads) void patch_fd_kernel(
+    const T* __restrict__ r, T* __restrict__ x, const T* __restrict__ tab,
+    TableLayout lay, int n, T h, int bx, int by, int bz, int npx, int npy, int npatch) {
   constexpr int G = 2 * N, G2 = G * G, G3 = G2 * G, N2 = N * N, N3 = N2 * N;
   constexpr int PPB = (kThreads / G2) > 0 ? kThreads / G2 : 1;
-  __shared__ double s_S[4 * G2];
-  __shared__ double s_l[4 * G];
-  __shared__ double s_X[PPB * G3];
+  __shared__ T s_S[4 * G2];
+  __shared__ T s_l[4 * G];
+  __shared__ T s_X[PPB * G3];
   const int tid = threadIdx.x;
   const int p0 = xcd_remap(blockIdx.x, gridDim.x) * PPB;
   const int np = min(PPB, npatch - p0);
@@ -394,11 +390,11 @@ __global__ __launch_bounds__(kThreads) void patch_fd_f64_kernel(
   const int tx = (vx == 1 ? 1 : 0) | (vx == n - 1 ? 2 : 0);
   const int ty = (vy == 1 ? 1 : 0) | (vy == n - 1 ? 2 : 0);
   const int tz = (vz == 1 ? 1 : 0) | (vz == n - 1 ? 2 : 0);
-  double* X = s_X + pl * G3;
+  T* X = s_X + pl * G3;
   const int la = ln % G, lb = ln / G;
   // offsets of line ln in direction d: start and stride
   const int o0 = la * G + lb * G2, o1 = la + lb * G2, o2 = la + lb * G;
-  double in[G], out[G];
+  T in[G], out[G];
   // forward: S^T along x, y, z
   if (act) {
 #pragma unroll
@@ -421,7 +417,7 @@ __global__ __launch_bounds__(kThreads) void patch_fd_f64_kernel(
     for (int a = 0; a < G; ++a) in[a] = X[o2 + a * G2];
     matvec_t<G>(s_S + tz * G2, in, out);
     // eigenvalue scaling: line (la, lb) = (i', j'), running over l'
-    const double lij = s_l[tx * G + la] + s_l[ty * G + lb];
+    const T lij = s_l[tx * G + la] + s_l[ty * G + lb];
 #pragma unroll
     for (int a = 0; a < G; ++a) in[a] = out[a] / (h * (lij + s_l[tz * G + a]));
     matvec<G>(s_S + tz * G2, in, out);
@@ -462,16 +458,17 @@ __global__ __launch_bounds__(kThreads) void patch_fd_f64_kernel(
 // Exact coarse solve by fast diagonalization of the whole n0^3-cell level
 // (one workgroup; G = n0 N <= 3N).
 // ---------------------------------------------------------------------------
-template <int N>
-__global__ __launch_bounds__(kThreads) void coarse_fd_f64_kernel(
-    const double* __restrict__ b, double* __restrict__ x, const double* __restrict__ tab,
-    TableLayout lay, int n0, double h) {
+template <typename T, int N>
+__global__ __launch_bounds__(kThreads) void coarse_fd_kernel(
+    const T* __restrict__ b, T* __restrict__ x, const T* __restrict__ tab,
+    TableLayout lay, int n0, T h) {
   constexpr int GM = 3 * N, N2 = N * N, N3 = N2 * N;
-  extern __shared__ double s_dyn[];
+  extern __shared__ __align__(16) unsigned char s_raw[];
+  T* s_dyn = reinterpret_cast<T*>(s_raw);
   const int G = n0 * N, G2 = G * G, G3 = G2 * G;
-  double* s_S = s_dyn;
-  double* s_l = s_S + G2;
-  double* X = s_l + G;
+  T* s_S = s_dyn;
+  T* s_l = s_S + G2;
+  T* X = s_l + G;
   const int tid = threadIdx.x;
   for (int i = tid; i < G2; i += kThreads) s_S[i] = tab[lay.fdc_s + i];
   for (int i = tid; i < G; i += kThreads) s_l[i] = tab[lay.fdc_l + i];
@@ -483,7 +480,7 @@ __global__ __launch_bounds__(kThreads) void coarse_fd_f64_kernel(
     X[(cx * N + i) + G * (cy * N + j) + G2 * (cz * N + l)] = b[w];
   }
   __syncthreads();
-  double in[GM], out[GM];
+  T in[GM], out[GM];
   for (int pass = 0; pass < 6; ++pass) {
     const int d = pass < 3 ? pass : 5 - pass;
     const int sd = d == 0 ? 1 : (d == 1 ? G : G2);
@@ -492,7 +489,7 @@ __global__ __launch_bounds__(kThreads) void coarse_fd_f64_kernel(
       const int o = d == 0 ? la * G + lb * G2 : (d == 1 ? la + lb * G2 : la + lb * G);
       for (int a = 0; a < G; ++a) in[a] = X[o + a * sd];
       for (int a = 0; a < G; ++a) {
-        double s = 0.0;
+        T s = 0.0;
         if (pass < 3)
           for (int c = 0; c < G; ++c) s = fma(s_S[c * G + a], in[c], s);
         else
@@ -518,14 +515,14 @@ __global__ __launch_bounds__(kThreads) void coarse_fd_f64_kernel(
 // (child c, node a) from coarse node b.  Restriction applies P1^T along x,
 // y, z to the 8 children (2N)^3 -> N^3; prolongation applies P1.
 // ---------------------------------------------------------------------------
-template <int N>
-__global__ __launch_bounds__(kThreads) void restrict_f64_kernel(
-    const double* __restrict__ rf, double* __restrict__ rc, const double* __restrict__ tab,
+template <typename T, int N>
+__global__ __launch_bounds__(kThreads) void restrict_kernel(
+    const T* __restrict__ rf, T* __restrict__ rc, const T* __restrict__ tab,
     TableLayout lay, int nc) {
   constexpr int G = 2 * N, G2 = G * G, G3 = G2 * G, N2 = N * N, N3 = N2 * N;
   constexpr int CPB = (kThreads / G2) > 0 ? kThreads / G2 : 1;
-  __shared__ double s_P[G * N];
-  __shared__ double s_X[CPB * G3];
+  __shared__ T s_P[G * N];
+  __shared__ T s_X[CPB * G3];
   const int tid = threadIdx.x;
   const int ncells = nc * nc * nc;
   const int c0 = xcd_remap(blockIdx.x, gridDim.x) * CPB;
@@ -547,13 +544,13 @@ __global__ __launch_bounds__(kThreads) void restrict_f64_kernel(
   // x: lines (j', l') of length G -> N values, stored in place at stride 1
   for (int w = tid; w < cnt * G2; w += kThreads) {
     const int cl = w / G2, ln = w - cl * G2;
-    double* X = s_X + cl * G3 + ln * G;
-    double in[G];
+    T* X = s_X + cl * G3 + ln * G;
+    T in[G];
 #pragma unroll
     for (int a = 0; a < G; ++a) in[a] = X[a];
 #pragma unroll
     for (int b = 0; b < N; ++b) {
-      double s = 0.0;
+      T s = 0.0;
 #pragma unroll
       for (int a = 0; a < G; ++a) s = fma(s_P[a * N + b], in[a], s);
       X[b] = s;
@@ -564,13 +561,13 @@ __global__ __launch_bounds__(kThreads) void restrict_f64_kernel(
   for (int w = tid; w < cnt * N * G; w += kThreads) {
     const int cl = w / (N * G), ln = w - cl * N * G;
     const int bx = ln % N, lz = ln / N;
-    double* X = s_X + cl * G3 + bx + lz * G2;
-    double in[G];
+    T* X = s_X + cl * G3 + bx + lz * G2;
+    T in[G];
 #pragma unroll
     for (int a = 0; a < G; ++a) in[a] = X[a * G];
 #pragma unroll
     for (int b = 0; b < N; ++b) {
-      double s = 0.0;
+      T s = 0.0;
 #pragma unroll
       for (int a = 0; a < G; ++a) s = fma(s_P[a * N + b], in[a], s);
       X[b * G] = s;
@@ -581,14 +578,14 @@ __global__ __launch_bounds__(kThreads) void restrict_f64_kernel(
   for (int w = tid; w < cnt * N2; w += kThreads) {
     const int cl = w / N2, ln = w - cl * N2;
     const int bx = ln % N, by = ln / N;
-    const double* X = s_X + cl * G3 + bx + by * G;
-    double in[G];
+    const T* X = s_X + cl * G3 + bx + by * G;
+    T in[G];
 #pragma unroll
     for (int a = 0; a < G; ++a) in[a] = X[a * G2];
-    double* dst = rc + (size_t)(c0 + cl) * N3 + bx + by * N;
+    T* dst = rc + (size_t)(c0 + cl) * N3 + bx + by * N;
 #pragma unroll
     for (int b = 0; b < N; ++b) {
-      double s = 0.0;
+      T s = 0.0;
 #pragma unroll
       for (int a = 0; a < G; ++a) s = fma(s_P[a * N + b], in[a], s);
       dst[b * N2] = s;
@@ -596,14 +593,14 @@ __global__ __launch_bounds__(kThreads) void restrict_f64_kernel(
   }
 }
 
-template <int N>
-__global__ __launch_bounds__(kThreads) void prolongate_add_f64_kernel(
-    const double* __restrict__ ec, double* __restrict__ xf, const double* __restrict__ tab,
+template <typename T, int N>
+__global__ __launch_bounds__(kThreads) void prolongate_add_kernel(
+    const T* __restrict__ ec, T* __restrict__ xf, const T* __restrict__ tab,
     TableLayout lay, int nc) {
   constexpr int G = 2 * N, G2 = G * G, G3 = G2 * G, N2 = N * N, N3 = N2 * N;
   constexpr int CPB = (kThreads / G2) > 0 ? kThreads / G2 : 1;
-  __shared__ double s_P[G * N];
-  __shared__ double s_X[CPB * G3];
+  __shared__ T s_P[G * N];
+  __shared__ T s_X[CPB * G3];
   const int tid = threadIdx.x;
   const int ncells = nc * nc * nc;
   const int c0 = xcd_remap(blockIdx.x, gridDim.x) * CPB;
@@ -620,13 +617,13 @@ __global__ __launch_bounds__(kThreads) void prolongate_add_f64_kernel(
   // z first: lines (b, b') over l: N -> G
   for (int w = tid; w < cnt * N2; w += kThreads) {
     const int cl = w / N2, ln = w - cl * N2;
-    double* X = s_X + cl * G3 + (ln % N) + (ln / N) * G;
-    double in[N];
+    T* X = s_X + cl * G3 + (ln % N) + (ln / N) * G;
+    T in[N];
 #pragma unroll
     for (int b = 0; b < N; ++b) in[b] = X[b * G2];
 #pragma unroll
     for (int a = 0; a < G; ++a) {
-      double s = 0.0;
+      T s = 0.0;
 #pragma unroll
       for (int b = 0; b < N; ++b) s = fma(s_P[a * N + b], in[b], s);
       X[a * G2] = s;
@@ -636,13 +633,13 @@ __global__ __launch_bounds__(kThreads) void prolongate_add_f64_kernel(
   // y: lines (b, l') over j: N -> G
   for (int w = tid; w < cnt * N * G; w += kThreads) {
     const int cl = w / (N * G), ln = w - cl * N * G;
-    double* X = s_X + cl * G3 + (ln % N) + (ln / N) * G2;
-    double in[N];
+    T* X = s_X + cl * G3 + (ln % N) + (ln / N) * G2;
+    T in[N];
 #pragma unroll
     for (int b = 0; b < N; ++b) in[b] = X[b * G];
 #pragma unroll
     for (int a = 0; a < G; ++a) {
-      double s = 0.0;
+      T s = 0.0;
 #pragma unroll
       for (int b = 0; b < N; ++b) s = fma(s_P[a * N + b], in[b], s);
       X[a * G] = s;
@@ -652,13 +649,13 @@ __global__ __launch_bounds__(kThreads) void prolongate_add_f64_kernel(
   // x: lines (j', l') over i: N -> G
   for (int w = tid; w < cnt * G2; w += kThreads) {
     const int cl = w / G2, ln = w - cl * G2;
-    double* X = s_X + cl * G3 + ln * G;
-    double in[N];
+    T* X = s_X + cl * G3 + ln * G;
+    T in[N];
 #pragma unroll
     for (int b = 0; b < N; ++b) in[b] = X[b];
 #pragma unroll
     for (int a = 0; a < G; ++a) {
-      double s = 0.0;
+      T s = 0.0;
 #pragma unroll
       for (int b = 0; b < N; ++b) s = fma(s_P[a * N + b], in[b], s);
       X[a] = s;
@@ -678,11 +675,16 @@ __global__ __launch_bounds__(kThreads) void prolongate_add_f64_kernel(
   }
 }
 
-template <int N>
-hipError_t apply_impl(const double* u, double* v, const double* b, const DevTab& t, int n,
-                      double h, hipStream_t s) {
-  // one tile = consecutive cells along x handled by one wave (cells never
-  // straddle a wave, so waves run independently)
+template <typename T>
+const T* tab_of(const DevTab& t);
+template <>
+const double* tab_of<double>(const DevTab& t) { return t.tab; }
+template <>
+const float* tab_of<float>(const DevTab& t) { return t.tabf; }
+
+template <typename T, int N>
+hipError_t apply_impl(const T* u, T* v, const T* b, const DevTab& t, int n, double h,
+                      hipStream_t s) {
   constexpr int CPW = (64 / (N * N)) > 0 ? 64 / (N * N) : 1;
   if (n < 1 || n > 1024) return hipErrorInvalidValue;
   TileMap tm;
@@ -698,16 +700,16 @@ hipError_t apply_impl(const double* u, double* v, const double* b, const DevTab&
   const int waves = kThreads / 64;
   const int grid = (int)((tiles + waves - 1) / waves);
   if (b)
-    hipLaunchKernelGGL((apply_f64_wave_kernel<N, true>), dim3(grid), dim3(kThreads), 0, s, u, v,
-                       b, t.tab, t.lay, tm, h);
+    hipLaunchKernelGGL((apply_wave_kernel<T, N, true>), dim3(grid), dim3(kThreads), 0, s, u,
+                       v, b, tab_of<T>(t), t.lay, tm, (T)h);
   else
-    hipLaunchKernelGGL((apply_f64_wave_kernel<N, false>), dim3(grid), dim3(kThreads), 0, s, u,
-                       v, nullptr, t.tab, t.lay, tm, h);
+    hipLaunchKernelGGL((apply_wave_kernel<T, N, false>), dim3(grid), dim3(kThreads), 0, s, u,
+                       v, nullptr, tab_of<T>(t), t.lay, tm, (T)h);
   return hipGetLastError();
 }
 
-template <int N>
-hipError_t patch_impl(int colour, const double* r, double* x, const DevTab& t, int n, double h,
+template <typename T, int N>
+hipError_t patch_impl(int colour, const T* r, T* x, const DevTab& t, int n, double h,
                       hipStream_t s) {
   constexpr int G2 = 4 * N * N;
   constexpr int PPB = (kThreads / G2) > 0 ? kThreads / G2 : 1;
@@ -718,40 +720,39 @@ hipError_t patch_impl(int colour, const double* r, double* x, const DevTab& t, i
   const int64_t np = (int64_t)npx * npy * npz;
   if (np == 0) return hipSuccess;
   const int grid = (int)((np + PPB - 1) / PPB);
-  hipLaunchKernelGGL((patch_fd_f64_kernel<N>), dim3(grid), dim3(kThreads), 0, s, r, x, t.tab,
-                     t.lay, n, h, bx, by, bz, npx, npy, (int)np);
+  hipLaunchKernelGGL((patch_fd_kernel<T, N>), dim3(grid), dim3(kThreads), 0, s, r, x,
+                     tab_of<T>(t), t.lay, n, (T)h, bx, by, bz, npx, npy, (int)np);
   return hipGetLastError();
 }
 
-template <int N>
-hipError_t coarse_impl(int n0, const double* b, double* x, const DevTab& t, double h,
-                       hipStream_t s) {
+template <typename T, int N>
+hipError_t coarse_impl(int n0, const T* b, T* x, const DevTab& t, double h, hipStream_t s) {
   if (n0 < 1 || n0 > 3 || t.lay.Gc != n0 * N) return hipErrorInvalidValue;
   const int G = n0 * N;
-  const size_t shm = sizeof(double) * ((size_t)G * G + G + (size_t)G * G * G);
+  const size_t shm = sizeof(T) * ((size_t)G * G + G + (size_t)G * G * G);
   if (shm > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)coarse_fd_f64_kernel<N>,
+    hipError_t e = hipFuncSetAttribute((const void*)coarse_fd_kernel<T, N>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((coarse_fd_f64_kernel<N>), dim3(1), dim3(kThreads), shm, s, b, x, t.tab,
-                     t.lay, n0, h);
+  hipLaunchKernelGGL((coarse_fd_kernel<T, N>), dim3(1), dim3(kThreads), shm, s, b, x,
+                     tab_of<T>(t), t.lay, n0, (T)h);
   return hipGetLastError();
 }
 
-template <int N>
-hipError_t transfer_impl(bool restr, const double* in, double* out, const DevTab& t, int nc,
+template <typename T, int N>
+hipError_t transfer_impl(bool restr, const T* in, T* out, const DevTab& t, int nc,
                          hipStream_t s) {
   constexpr int G2 = 4 * N * N;
   constexpr int CPB = (kThreads / G2) > 0 ? kThreads / G2 : 1;
   const int64_t ncells = (int64_t)nc * nc * nc;
   const int grid = (int)((ncells + CPB - 1) / CPB);
   if (restr)
-    hipLaunchKernelGGL((restrict_f64_kernel<N>), dim3(grid), dim3(kThreads), 0, s, in, out,
-                       t.tab, t.lay, nc);
+    hipLaunchKernelGGL((restrict_kernel<T, N>), dim3(grid), dim3(kThreads), 0, s, in, out,
+                       tab_of<T>(t), t.lay, nc);
   else
-    hipLaunchKernelGGL((prolongate_add_f64_kernel<N>), dim3(grid), dim3(kThreads), 0, s, in,
-                       out, t.tab, t.lay, nc);
+    hipLaunchKernelGGL((prolongate_add_kernel<T, N>), dim3(grid), dim3(kThreads), 0, s, in,
+                       out, tab_of<T>(t), t.lay, nc);
   return hipGetLastError();
 }
 
@@ -769,44 +770,80 @@ hipError_t transfer_impl(bool restr, const double* in, double* out, const DevTab
     default: return hipErrorInvalidValue;       \
   }
 
-hipError_t launch_apply_f64(int N, const double* u, double* v, const double* b, const DevTab& t,
-                            int n, double h, hipStream_t s) {
+
+
+template <typename T>
+static hipError_t apply_any(int N, const T* u, T* v, const T* b, const DevTab& t, int n,
+                            double h, hipStream_t s) {
   if (t.lay.N != N) return hipErrorInvalidValue;
-#define CALL(NN) apply_impl<NN>(u, v, b, t, n, h, s)
+#define CALL(NN) apply_impl<T, NN>(u, v, b, t, n, h, s)
   SIPG_DISPATCH_N(N, CALL)
 #undef CALL
 }
-
-hipError_t launch_patch_fd_f64(int N, int colour, const double* r, double* x, const DevTab& t,
-                               int n, double h, hipStream_t s) {
+template <typename T>
+static hipError_t patch_any(int N, int colour, const T* r, T* x, const DevTab& t, int n,
+                            double h, hipStream_t s) {
   if (t.lay.N != N || colour < 0 || colour > 7 || n < 2) return hipErrorInvalidValue;
-#define CALL(NN) patch_impl<NN>(colour, r, x, t, n, h, s)
+#define CALL(NN) patch_impl<T, NN>(colour, r, x, t, n, h, s)
   SIPG_DISPATCH_N(N, CALL)
 #undef CALL
 }
-
-hipError_t launch_coarse_fd_f64(int N, int n0, const double* b, double* x, const DevTab& t,
-                                double h, hipStream_t s) {
+template <typename T>
+static hipError_t coarse_any(int N, int n0, const T* b, T* x, const DevTab& t, double h,
+                             hipStream_t s) {
   if (t.lay.N != N) return hipErrorInvalidValue;
-#define CALL(NN) coarse_impl<NN>(n0, b, x, t, h, s)
+#define CALL(NN) coarse_impl<T, NN>(n0, b, x, t, h, s)
   SIPG_DISPATCH_N(N, CALL)
 #undef CALL
 }
-
-hipError_t launch_restrict_f64(int N, const double* rf, double* rc, const DevTab& t, int nc,
+template <typename T>
+static hipError_t transfer_any(int N, bool restr, const T* in, T* out, const DevTab& t, int nc,
                                hipStream_t s) {
   if (t.lay.N != N || nc < 1) return hipErrorInvalidValue;
-#define CALL(NN) transfer_impl<NN>(true, rf, rc, t, nc, s)
+#define CALL(NN) transfer_impl<T, NN>(restr, in, out, t, nc, s)
   SIPG_DISPATCH_N(N, CALL)
 #undef CALL
 }
 
+hipError_t launch_apply_f64(int N, const double* u, double* v, const double* b, const DevTab& t,
+                            int n, double h, hipStream_t s) {
+  return apply_any<double>(N, u, v, b, t, n, h, s);
+}
+hipError_t launch_apply_f32(int N, const float* u, float* v, const float* b, const DevTab& t,
+                            int n, double h, hipStream_t s) {
+  return apply_any<float>(N, u, v, b, t, n, h, s);
+}
+hipError_t launch_patch_fd_f64(int N, int colour, const double* r, double* x, const DevTab& t,
+                               int n, double h, hipStream_t s) {
+  return patch_any<double>(N, colour, r, x, t, n, h, s);
+}
+hipError_t launch_patch_fd_f32(int N, int colour, const float* r, float* x, const DevTab& t,
+                               int n, double h, hipStream_t s) {
+  return patch_any<float>(N, colour, r, x, t, n, h, s);
+}
+hipError_t launch_coarse_fd_f64(int N, int n0, const double* b, double* x, const DevTab& t,
+                                double h, hipStream_t s) {
+  return coarse_any<double>(N, n0, b, x, t, h, s);
+}
+hipError_t launch_coarse_fd_f32(int N, int n0, const float* b, float* x, const DevTab& t,
+                                double h, hipStream_t s) {
+  return coarse_any<float>(N, n0, b, x, t, h, s);
+}
+hipError_t launch_restrict_f64(int N, const double* rf, double* rc, const DevTab& t, int nc,
+                               hipStream_t s) {
+  return transfer_any<double>(N, true, rf, rc, t, nc, s);
+}
+hipError_t launch_restrict_f32(int N, const float* rf, float* rc, const DevTab& t, int nc,
+                               hipStream_t s) {
+  return transfer_any<float>(N, true, rf, rc, t, nc, s);
+}
 hipError_t launch_prolongate_add_f64(int N, const double* ec, double* xf, const DevTab& t, int nc,
                                      hipStream_t s) {
-  if (t.lay.N != N || nc < 1) return hipErrorInvalidValue;
-#define CALL(NN) transfer_impl<NN>(false, ec, xf, t, nc, s)
-  SIPG_DISPATCH_N(N, CALL)
-#undef CALL
+  return transfer_any<double>(N, false, ec, xf, t, nc, s);
+}
+hipError_t launch_prolongate_add_f32(int N, const float* ec, float* xf, const DevTab& t, int nc,
+                                     hipStream_t s) {
+  return transfer_any<float>(N, false, ec, xf, t, nc, s);
 }
 
 }  // namespace sipg

@@ -67,6 +67,7 @@ def load_library(path=None):
         "sipg_n_dofs": (i64, [vp, i32]),
         "sipg_apply": (i32, [vp, i32, vp, vp, vp]),
         "sipg_residual": (i32, [vp, i32, vp, vp, vp, vp]),
+        "sipg_apply_lp": (i32, [vp, i32, vp, vp, i32, i32, vp]),
         "sipg_smooth": (i32, [vp, i32, vp, vp, i32, vp]),
         "sipg_patch_correct": (i32, [vp, i32, i32, vp, vp, vp]),
         "sipg_restrict": (i32, [vp, i32, vp, vp, vp]),
@@ -153,6 +154,15 @@ class Problem:
         v = torch.empty_like(u) if v is None else v
         _check(_lib.sipg_apply(self._h, self._lvl(level), _ptr(u, torch.float64),
                                _ptr(v, torch.float64), _stream(stream)))
+        return v
+
+    def apply_lp(self, u, v=None, precision="f16", ec=False, level=-1, stream=None):
+        """v = A u on FP32 vectors in reduced precision ("f32", "f16", "bf16")."""
+        import torch
+        v = torch.empty_like(u) if v is None else v
+        _check(_lib.sipg_apply_lp(self._h, self._lvl(level), _ptr(u, torch.float32),
+                                  _ptr(v, torch.float32), PRECISION[precision], int(bool(ec)),
+                                  _stream(stream)))
         return v
 
     def residual(self, b, x, r=None, level=-1, stream=None):

@@ -1,0 +1,110 @@
+"""GPU checks of the reduced-precision path (Sec. 5 and Sec. 7.1): the FP32
+and FP16/BF16 matrix-core operator applies against the oracle's FP64 apply
+(relative l2 error as in Sec. 5.2), and FGMRES with a low-precision V-cycle
+against the FP64 solve.
+
+Tolerances derive from the unit roundoff u of the operand format: one
+rounding of each operand and FP32 accumulation give a relative error of a
+few u (measured ~0.8-2 u).  Bounds: FP32 8 u32; FP16 4 u16; FP16 with error
+correction (both operands split, Alg. matmul) ~FP32 level, 8 u32 + 4 u16^2;
+BF16 4 u_bf; BF16 with error correction 4 (2^-8 u_bf) + 8 u32."""
+import numpy as np
+import pytest
+
+from gpu_util import announce, rel_l2
+from oracle import sipg
+from paper_2407_09621_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+U32, U16, UBF = 2.0 ** -24, 2.0 ** -11, 2.0 ** -8
+BOUND = {("f32", 0): 8 * U32, ("f16", 0): 4 * U16, ("f16", 1): 8 * U32 + 4 * U16 ** 2,
+         ("bf16", 0): 4 * UBF, ("bf16", 1): 4 * UBF * 2.0 ** -8 + 8 * U32}
+MODES = list(BOUND)
+
+
+def _apply_lp(P, u, prec, ec):
+    import torch
+    ug = torch.from_numpy(u.astype(np.float32)).to("cuda")
+    return P.apply_lp(ug, precision=prec, ec=ec).double().cpu().numpy()
+
+
+@pytest.mark.parametrize("k,n", [(1, 3), (2, 5), (3, 4), (4, 3), (5, 3), (6, 2), (7, 2)])
+def test_lowprec_apply_error_bounds(k, n):
+    from paper_2407_09621_amd import Problem
+    announce("apply lp", k, n)
+    P = Problem(k, n, n_levels=1)
+    A = sipg.assemble(n, k)
+    for dist in ("normal", "uniform"):
+        u = (inputs.normal_vector(P.n_dofs(), 300 + k) if dist == "normal"
+             else inputs.uniform_vector(P.n_dofs(), 300 + k))
+        # the oracle sees the FP32-rounded input, so only the arithmetic differs
+        u32 = u.astype(np.float32).astype(np.float64)
+        ref = A @ u32
+        for prec, ec in MODES:
+            err = rel_l2(_apply_lp(P, u, prec, ec), ref)
+            assert err < BOUND[(prec, ec)], (dist, prec, ec, err)
+
+
+def test_error_correction_recovers_fp32_accuracy():
+    """The paper's observation (Sec. 5.2): error-corrected FP16 reaches the
+    accuracy of FP32."""
+    from paper_2407_09621_amd import Problem
+    announce("ec ~ fp32")
+    k, n = 3, 6
+    P = Problem(k, n, n_levels=1)
+    u = inputs.normal_vector(P.n_dofs(), 7)
+    ref = sipg.kron_apply(u.astype(np.float32).astype(np.float64), n, k)
+    e32 = rel_l2(_apply_lp(P, u, "f32", 0), ref)
+    e16 = rel_l2(_apply_lp(P, u, "f16", 0), ref)
+    e16ec = rel_l2(_apply_lp(P, u, "f16", 1), ref)
+    assert e16ec < 4 * e32 and e16 > 100 * e16ec
+
+
+@pytest.mark.parametrize("k,n", [(3, 64), (7, 32)])
+def test_lowprec_apply_full_size(k, n):
+    from paper_2407_09621_amd import Problem
+    announce("apply lp full", k, n)
+    P = Problem(k, n, n_levels=1)
+    u = inputs.uniform_vector(P.n_dofs(), 2 + k)
+    ref = sipg.kron_apply(u.astype(np.float32).astype(np.float64), n, k)
+    for prec, ec in [("f16", 1), ("bf16", 1), ("f16", 0)]:
+        assert rel_l2(_apply_lp(P, u, prec, ec), ref) < BOUND[(prec, ec)]
+
+
+@pytest.mark.parametrize("prec,ec", [("f32", 0), ("f16", 0), ("f16", 1), ("bf16", 0), ("bf16", 1)])
+def test_fgmres_with_lowprec_vcycle(prec, ec):
+    """FP64 FGMRES with a reduced-precision V(2,2) preconditioner reaches the
+    same FP64 true residual and the same solution as the FP64 solve;
+    error correction keeps the FP64 iteration count (+1)."""
+    from paper_2407_09621_amd import Problem
+    announce("fgmres lp", prec, ec)
+    k, n = 3, 8
+    amps, pqr = inputs.single_sine_modes()
+    P64 = Problem(k, n)
+    b = P64.rhs_sines(amps, pqr)
+    x64, i64 = P64.fgmres(b, rtol=1e-10)
+    P = Problem(k, n, mg_precision=prec, error_correction=bool(ec))
+    x, info = P.fgmres(b, rtol=1e-10, max_iters=100)
+    assert info["rel_res_true"] < 1e-10
+    assert rel_l2(x.cpu().numpy(), x64.cpu().numpy()) < 1e-8
+    e, e64 = P.l2_error_sines(amps, pqr, x), P64.l2_error_sines(amps, pqr, x64)
+    assert abs(e - e64) < 1e-3 * e64
+    if ec or prec == "f32":
+        assert info["iterations"] <= i64["iterations"] + 1
+    else:
+        assert info["iterations"] <= 40
+
+
+def test_lowprec_vcycle_close_to_fp64_vcycle():
+    from paper_2407_09621_amd import Problem
+    announce("vcycle lp vs f64")
+    import torch
+    k, n = 2, 8
+    b = torch.from_numpy(inputs.uniform_vector(Problem(k, n).n_dofs(), 9)).to("cuda")
+    x64 = torch.zeros_like(b)
+    Problem(k, n).vcycle(x64, b)
+    for prec, ec, tol in [("f32", 0, 1e-5), ("f16", 1, 1e-5), ("bf16", 1, 1e-4), ("f16", 0, 1e-2)]:
+        x = torch.zeros_like(b)
+        Problem(k, n, mg_precision=prec, error_correction=bool(ec)).vcycle(x, b)
+        assert rel_l2(x.cpu().numpy(), x64.cpu().numpy()) < tol, (prec, ec)
