@@ -56,25 +56,67 @@ def cpu_baseline():
                       f"{t:.1f} s"}
 
 
-def run_solves(P_cache):
-    """FP64 FGMRES(30) + V(2,2) solves of the sine problem (outside the timed
-    region): time to rtol 1e-10, iterations, L2 error."""
+SOLVE_CONFIGS = [(3, 64), (5, 32), (7, 32)]
+SOLVE_CONFIGS_ALL = [(k, n) for k in (3, 5, 7) for n in (16, 32, 64)]
+SOLVE_VARIANTS = [("f64", 0), ("f32", 0), ("f16", 0), ("f16", 1), ("bf16", 0), ("bf16", 1)]
+
+
+def run_solves(configs):
+    """FP64 FGMRES(30) + V(2,2) solves of the sine problem with the V-cycle in
+    FP64, FP32, FP16 and BF16 (the latter two with and without error
+    correction), outside the timed apply region: time to rtol 1e-10
+    (after one warm-up solve that allocates the Krylov space), iterations,
+    true residual, L2 error and the speed multiple over the FP64 solve."""
     import torch
     from paper_2407_09621_amd import Problem, inputs
     out = {}
     amps, pqr = inputs.single_sine_modes()
-    for k, n in [(3, 64), (7, 32)]:
-        P = Problem(k, n)
-        b = P.rhs_sines(amps, pqr)
-        x, info = P.fgmres(b, rtol=1e-10)  # warm-up (allocates the Krylov space)
-        x.zero_()
-        torch.cuda.synchronize()
-        x, info = P.fgmres(b, x=x, rtol=1e-10)
-        err = P.l2_error_sines(amps, pqr, x)
-        out[f"k{k}_n{n}"] = {"seconds": round(info["seconds"], 4), "iterations": info["iterations"],
-                             "rel_res_true": info["rel_res_true"], "l2_error": err,
-                             "mg_precision": "f64"}
-        P.close()
+    for k, n in configs:
+        row = {}
+        for prec, ec in SOLVE_VARIANTS:
+            P = Problem(k, n, mg_precision=prec, error_correction=bool(ec))
+            b = P.rhs_sines(amps, pqr)
+            x, info = P.fgmres(b, rtol=1e-10, max_iters=200, raise_on_nonconvergence=False)
+            x.zero_()
+            torch.cuda.synchronize()
+            x, info = P.fgmres(b, x=x, rtol=1e-10, max_iters=200, raise_on_nonconvergence=False)
+            err = P.l2_error_sines(amps, pqr, x)
+            row[prec + ("_ec" if ec else "")] = {
+                "seconds": round(info["seconds"], 5), "iterations": info["iterations"],
+                "rel_res_true": info["rel_res_true"], "l2_error": err, "status": info["status"]}
+            P.close()
+            del x, b
+        base = row["f64"]
+        for v in row.values():
+            v["speedup_vs_f64"] = round(base["seconds"] / v["seconds"], 3)
+            v["l2_within_1pct_of_f64"] = abs(v["l2_error"] - base["l2_error"]) <= 0.01 * base["l2_error"]
+        out[f"k{k}_n{n}"] = row
+        torch.cuda.empty_cache()
+    return out
+
+
+def lp_apply_rates(probs, stream, reps):
+    """Reduced-precision applies (FP32 storage, 8 B/DoF) at the apply sizes."""
+    import torch
+    out = {}
+    for k, n, P, nd, us, vs in probs:
+        u32 = [u.float() for u in us[:2]]
+        v32 = [torch.empty_like(u32[0]) for _ in range(2)]
+        for prec, ec in [("f32", 0), ("f16", 0), ("f16", 1), ("bf16", 0), ("bf16", 1)]:
+            P.apply_lp(u32[0], v32[0], precision=prec, ec=ec, stream=stream)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for i in range(reps):
+                P.apply_lp(u32[i % 2], v32[i % 2], precision=prec, ec=ec, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            g = nd / (ms * 1e-3) / 1e9
+            out[f"k{k}_n{n}_{prec}{'_ec' if ec else ''}"] = {
+                "ms_per_apply": round(ms, 5), "gdof_s": round(g, 2),
+                "hbm_frac": round(g * 8.0 / HBM_PEAK_GBS, 4)}
+        del u32, v32
     return out
 
 
@@ -85,6 +127,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-solve", action="store_true", help="skip the solve measurements")
+    ap.add_argument("--all-solves", action="store_true",
+                    help="solve every degree 3/5/7 x 16^3/32^3/64^3 configuration")
     ap.add_argument("--mode", choices=["bench", "profile"], default="bench",
                     help="profile: a few applies per degree and a plain copy of a known size "
                          "(for rocprofv3 kernel traces and HBM counters)")
@@ -118,6 +162,14 @@ def main():
                 P.apply(us[i % ROTATE], vs[i % ROTATE], stream=stream)
             torch.cuda.synchronize()
             print(f"profiled apply k={k} n={n}: 5 launches, {nd} DoFs", flush=True)
+            u32 = us[0].float()
+            v32 = torch.empty_like(u32)
+            for prec, ec in [("f16", 1), ("bf16", 1)]:
+                for i in range(3):
+                    P.apply_lp(u32, v32, precision=prec, ec=ec, stream=stream)
+            torch.cuda.synchronize()
+            del u32, v32
+            print(f"profiled low-precision apply k={k} n={n}: 3 launches each", flush=True)
         # calibration: a plain device copy of exactly 2^27 bytes (read) + 2^27 (write)
         a = torch.empty(1 << 24, dtype=torch.float64, device=dev).uniform_()
         b = torch.empty_like(a)
@@ -174,12 +226,14 @@ def main():
                 "kernel": f"apply_f64_kernel ({dom[0]})",
                 "bytes_per_launch": int(dk["n_dofs"] * BYTES_PER_DOF)}
 
+    lp_rates = lp_apply_rates(probs, stream, max(10, args.steps // 4))
     for k, n, P, nd, us, vs in probs:
         P.close()
     del probs
     torch.cuda.empty_cache()
 
-    solves = None if args.no_solve else run_solves(None)
+    solves = None if args.no_solve else run_solves(SOLVE_CONFIGS_ALL if args.all_solves
+                                                   else SOLVE_CONFIGS)
     cpu = None if args.no_cpu else cpu_baseline()
 
     line = {
@@ -192,7 +246,8 @@ def main():
                                "k=3 on 64^3 cells, k=5 on 40^3, k=7 on 32^3; u ~ U[-1,1] seeded; "
                                "one step = one apply per degree",
                    "parallelism": "single GPU"},
-        "per_k": per_k, "roofline": roofline, "cpu_baseline": cpu, "solves_fp64": solves,
+        "per_k": per_k, "roofline": roofline, "cpu_baseline": cpu,
+        "lowprec_apply": lp_rates, "solves": solves,
     }
     print(json.dumps(line))
 

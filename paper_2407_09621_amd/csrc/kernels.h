@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "batch.h"
 #include "tables.h"
 
 namespace sipg {
@@ -46,6 +47,17 @@ hipError_t launch_restrict_f32(int N, const float* rf, float* rc, const DevTab& 
 hipError_t launch_prolongate_add_f32(int N, const float* ec, float* xf, const DevTab& t, int nc,
                                      hipStream_t s);
 
+// Batched forms: up to kMaxBatch problems of one degree per launch.
+// prec 0 = FP64 vectors, 1 = FP32 vectors (VALU arithmetic).
+hipError_t launch_apply_batch(int prec, int N, const ApplyJob* jobs, int count, const DevTab& t,
+                              hipStream_t s);
+hipError_t launch_patch_fd_batch(int prec, int N, int colour, const PatchJob* jobs, int count,
+                                 const DevTab& t, hipStream_t s);
+hipError_t launch_coarse_fd_batch(int prec, int N, const CoarseJob* jobs, int count,
+                                  const DevTab& t, hipStream_t s);
+hipError_t launch_transfer_batch(int prec, int N, bool restr, const TransferJob* jobs, int count,
+                                 const DevTab& t, hipStream_t s);
+
 // BLAS-1 helpers (FP64).  `partial` holds at least kDotBlocks * nv doubles.
 constexpr int kDotBlocks = 1024;
 hipError_t launch_mdot(const double* V, int64_t ld, int nv, const double* w, int64_t n,
@@ -69,6 +81,10 @@ hipError_t launch_apply_lp(int N, bool bf16, bool ec, const float* u, float* v, 
                            const DevTab& t, int n, double h, hipStream_t s);
 hipError_t launch_patch_fd_lp(int N, bool bf16, bool ec, int colour, const float* r, float* x,
                               const DevTab& t, int n, double h, hipStream_t s);
+hipError_t launch_apply_lp_batch(int N, bool bf16, bool ec, const ApplyJob* jobs, int count,
+                                 const DevTab& t, hipStream_t s);
+hipError_t launch_patch_fd_lp_batch(int N, bool bf16, bool ec, int colour, const PatchJob* jobs,
+                                    int count, const DevTab& t, hipStream_t s);
 
 // Manufactured right-hand side and L2 error (tables prepared on the host).
 hipError_t launch_rhs_sines(int N, int n, int n_modes, const double* coef,

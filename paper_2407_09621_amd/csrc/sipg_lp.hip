@@ -21,6 +21,7 @@
 // correction accumulated in its own FP32 accumulator.
 #include <hip/hip_runtime.h>
 
+#include "batch.h"
 #include "kernels.h"
 
 namespace sipg {
@@ -250,8 +251,7 @@ __device__ __forceinline__ int tile_first_cell(const TileMapLp& m, int t) {
 // ---------------------------------------------------------------------------
 template <int N, bool BF, bool EC, bool RES>
 __global__ __launch_bounds__(kThreads) void apply_lp_kernel(
-    const float* __restrict__ u, float* __restrict__ v, const float* __restrict__ bvec,
-    const float* __restrict__ tab, TableLayout lay, TileMapLp tm, float h) {
+    Batch<float> B, const float* __restrict__ tab, TableLayout lay) {
   constexpr int N2 = N * N, N3 = N2 * N, CPB = (64 / N2) > 0 ? 64 / N2 : 1;
   constexpr int NP = Pad<N>::value;
   constexpr int WAVES = kThreads / 64;
@@ -262,8 +262,20 @@ __global__ __launch_bounds__(kThreads) void apply_lp_kernel(
   __shared__ float s_tzm_all[WAVES * CPB * 4 * N2];
 
   const int tid = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int grp = xcd_remap(blockIdx.x, gridDim.x) * WAVES + wave;
-  if (grp >= tm.ngroups) return;  // wave-uniform
+  const int gi = xcd_remap(blockIdx.x, gridDim.x) * WAVES + wave;
+  if (gi >= B.start[B.count]) return;  // wave-uniform
+  const int pb = batch_find(B, gi);
+  const int grp = gi - B.start[pb];
+  const float* __restrict__ u = B.d[pb].in;
+  float* __restrict__ v = B.d[pb].out;
+  const float* __restrict__ bvec = B.d[pb].aux;
+  const float h = B.d[pb].h;
+  TileMapLp tm;
+  tm.n = B.d[pb].n;
+  tm.tx = B.d[pb].a0;
+  tm.ntx = B.d[pb].a1;
+  tm.blk = B.d[pb].a2;
+  tm.ngroups = B.start[pb + 1] - B.start[pb];
   float* s_t1 = s_t1_all + wave * (CPB * N3);
   float* s_t2 = s_t2_all + wave * (CPB * N3);
   float* s_ty = s_ty_all + wave * (CPB * 4 * N2);
@@ -445,15 +457,21 @@ __global__ __launch_bounds__(kThreads) void apply_lp_kernel(
 // ---------------------------------------------------------------------------
 template <int N, bool BF, bool EC>
 __global__ __launch_bounds__(kThreads) void patch_fd_lp_kernel(
-    const float* __restrict__ r, float* __restrict__ x, const float* __restrict__ tab,
-    TableLayout lay, int n, float h, int bx, int by, int bz, int npx, int npy, int npatch) {
+    Batch<float> B, const float* __restrict__ tab, TableLayout lay, int bx, int by, int bz) {
   constexpr int G = 2 * N, G2 = G * G, G3 = G2 * G, N2 = N * N, N3 = N2 * N;
   constexpr int PPB = (kThreads / G2) > 0 ? kThreads / G2 : 1;
   constexpr int GP = Pad<G>::value;
   __shared__ float s_l[4 * G];
   __shared__ float s_X[PPB * G3];
   const int tid = threadIdx.x;
-  const int p0 = xcd_remap(blockIdx.x, gridDim.x) * PPB;
+  const int bi = xcd_remap(blockIdx.x, gridDim.x);
+  if (bi >= B.start[B.count]) return;
+  const int pb = batch_find(B, bi);
+  const float* __restrict__ r = B.d[pb].in;
+  float* __restrict__ x = B.d[pb].out;
+  const int n = B.d[pb].n, npx = B.d[pb].a0, npy = B.d[pb].a1, npatch = B.d[pb].a2;
+  const float h = B.d[pb].h;
+  const int p0 = (bi - B.start[pb]) * PPB;
   const int np = min(PPB, npatch - p0);
   if (np <= 0) return;
   for (int i = tid; i < 4 * G; i += kThreads) s_l[i] = tab[lay.fd_l + i];
@@ -562,44 +580,74 @@ __global__ __launch_bounds__(kThreads) void patch_fd_lp_kernel(
 }
 
 template <int N, bool BF, bool EC>
-hipError_t apply_lp_impl(const float* u, float* v, const float* b, const DevTab& t, int n,
-                         double h, hipStream_t s) {
+hipError_t apply_lp_impl(const ApplyJob* jobs, int count, const DevTab& t, hipStream_t s) {
   constexpr int CPW = (64 / (N * N)) > 0 ? 64 / (N * N) : 1;
-  if (n < 1 || n > 1024) return hipErrorInvalidValue;
-  TileMapLp tm;
-  tm.n = n;
-  tm.tx = 1;
-  for (int d = 1; d <= CPW && d <= n; ++d)
-    if (n % d == 0) tm.tx = d;
-  tm.ntx = n / tm.tx;
-  tm.blk = (n % 8 == 0) ? 8 : 1;
-  const int64_t tiles = (int64_t)tm.ntx * n * n;
-  if (tiles > ((int64_t)1 << 30)) return hipErrorInvalidValue;
-  tm.ngroups = (int)tiles;
+  if (count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
+  Batch<float> B;
+  const bool residual = jobs[0].b != nullptr;
+  B.count = count;
+  B.start[0] = 0;
+  for (int i = 0; i < count; ++i) {
+    const ApplyJob& j = jobs[i];
+    if (j.n < 1 || j.n > 1024 || !j.u || !j.v || (j.b != nullptr) != residual)
+      return hipErrorInvalidValue;
+    int tx = 1;
+    for (int q = 1; q <= CPW && q <= j.n; ++q)
+      if (j.n % q == 0) tx = q;
+    Desc<float>& d = B.d[i];
+    d.in = (const float*)j.u;
+    d.out = (float*)j.v;
+    d.aux = (const float*)j.b;
+    d.h = (float)j.h;
+    d.n = j.n;
+    d.a0 = tx;
+    d.a1 = j.n / tx;
+    d.a2 = (j.n % 8 == 0) ? 8 : 1;
+    const int64_t items = (int64_t)d.a1 * j.n * j.n;
+    if (B.start[i] + items > ((int64_t)1 << 30)) return hipErrorInvalidValue;
+    B.start[i + 1] = B.start[i] + (int)items;
+  }
+  for (int i = count; i < kMaxBatch; ++i) B.start[i + 1] = B.start[count];
   const int waves = kThreads / 64;
-  const int grid = (int)((tiles + waves - 1) / waves);
-  if (b)
-    hipLaunchKernelGGL((apply_lp_kernel<N, BF, EC, true>), dim3(grid), dim3(kThreads), 0, s, u,
-                       v, b, t.tabf, t.lay, tm, (float)h);
+  const int grid = (B.start[count] + waves - 1) / waves;
+  if (residual)
+    hipLaunchKernelGGL((apply_lp_kernel<N, BF, EC, true>), dim3(grid), dim3(kThreads), 0, s, B,
+                       t.tabf, t.lay);
   else
     hipLaunchKernelGGL((apply_lp_kernel<N, BF, EC, false>), dim3(grid), dim3(kThreads), 0, s,
-                       u, v, nullptr, t.tabf, t.lay, tm, (float)h);
+                       B, t.tabf, t.lay);
   return hipGetLastError();
 }
 
 template <int N, bool BF, bool EC>
-hipError_t patch_lp_impl(int colour, const float* r, float* x, const DevTab& t, int n,
-                         double h, hipStream_t s) {
+hipError_t patch_lp_impl(int colour, const PatchJob* jobs, int count, const DevTab& t,
+                         hipStream_t s) {
   constexpr int G2 = 4 * N * N;
   constexpr int PPB = (kThreads / G2) > 0 ? kThreads / G2 : 1;
+  if (count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
   const int bx = colour & 1, by = (colour >> 1) & 1, bz = (colour >> 2) & 1;
-  auto count = [&](int bit) { return bit ? n / 2 : (n - 1) / 2; };
-  const int npx = count(bx), npy = count(by), npz = count(bz);
-  const int64_t np = (int64_t)npx * npy * npz;
-  if (np == 0) return hipSuccess;
-  const int grid = (int)((np + PPB - 1) / PPB);
-  hipLaunchKernelGGL((patch_fd_lp_kernel<N, BF, EC>), dim3(grid), dim3(kThreads), 0, s, r, x,
-                     t.tabf, t.lay, n, (float)h, bx, by, bz, npx, npy, (int)np);
+  Batch<float> B;
+  B.count = count;
+  B.start[0] = 0;
+  for (int i = 0; i < count; ++i) {
+    const PatchJob& j = jobs[i];
+    if (j.n < 2 || j.n > 1024 || !j.r || !j.x) return hipErrorInvalidValue;
+    auto cnt = [&](int bit) { return bit ? j.n / 2 : (j.n - 1) / 2; };
+    Desc<float>& d = B.d[i];
+    d.in = (const float*)j.r;
+    d.out = (float*)j.x;
+    d.aux = nullptr;
+    d.h = (float)j.h;
+    d.n = j.n;
+    d.a0 = cnt(bx);
+    d.a1 = cnt(by);
+    d.a2 = d.a0 * d.a1 * cnt(bz);
+    B.start[i + 1] = B.start[i] + (d.a2 + PPB - 1) / PPB;
+  }
+  for (int i = count; i < kMaxBatch; ++i) B.start[i + 1] = B.start[count];
+  if (B.start[count] == 0) return hipSuccess;
+  hipLaunchKernelGGL((patch_fd_lp_kernel<N, BF, EC>), dim3(B.start[count]), dim3(kThreads), 0, s,
+                     B, t.tabf, t.lay, bx, by, bz);
   return hipGetLastError();
 }
 
@@ -624,20 +672,32 @@ hipError_t patch_lp_impl(int colour, const float* r, float* x, const DevTab& t, 
     default: return hipErrorInvalidValue;                         \
   }
 
-hipError_t launch_apply_lp(int N, bool bf16, bool ec, const float* u, float* v, const float* b,
-                           const DevTab& t, int n, double h, hipStream_t s) {
+hipError_t launch_apply_lp_batch(int N, bool bf16, bool ec, const ApplyJob* jobs, int count,
+                                 const DevTab& t, hipStream_t s) {
   if (t.lay.N != N) return hipErrorInvalidValue;
-#define CALL(NN, BB, EE) apply_lp_impl<NN, BB, EE>(u, v, b, t, n, h, s)
+#define CALL(NN, BB, EE) apply_lp_impl<NN, BB, EE>(jobs, count, t, s)
   SIPG_LP_DISPATCH(N, bf16, ec, CALL)
 #undef CALL
 }
 
-hipError_t launch_patch_fd_lp(int N, bool bf16, bool ec, int colour, const float* r, float* x,
-                              const DevTab& t, int n, double h, hipStream_t s) {
-  if (t.lay.N != N || colour < 0 || colour > 7 || n < 2) return hipErrorInvalidValue;
-#define CALL(NN, BB, EE) patch_lp_impl<NN, BB, EE>(colour, r, x, t, n, h, s)
+hipError_t launch_patch_fd_lp_batch(int N, bool bf16, bool ec, int colour, const PatchJob* jobs,
+                                    int count, const DevTab& t, hipStream_t s) {
+  if (t.lay.N != N || colour < 0 || colour > 7) return hipErrorInvalidValue;
+#define CALL(NN, BB, EE) patch_lp_impl<NN, BB, EE>(colour, jobs, count, t, s)
   SIPG_LP_DISPATCH(N, bf16, ec, CALL)
 #undef CALL
+}
+
+hipError_t launch_apply_lp(int N, bool bf16, bool ec, const float* u, float* v, const float* b,
+                           const DevTab& t, int n, double h, hipStream_t s) {
+  ApplyJob j{u, v, b, n, h};
+  return launch_apply_lp_batch(N, bf16, ec, &j, 1, t, s);
+}
+
+hipError_t launch_patch_fd_lp(int N, bool bf16, bool ec, int colour, const float* r, float* x,
+                              const DevTab& t, int n, double h, hipStream_t s) {
+  PatchJob j{r, x, n, h};
+  return launch_patch_fd_lp_batch(N, bf16, ec, colour, &j, 1, t, s);
 }
 
 }  // namespace sipg

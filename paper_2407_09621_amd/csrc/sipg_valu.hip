@@ -17,6 +17,7 @@
 // so that consecutive cells (and their face neighbours) share an L2.
 #include <hip/hip_runtime.h>
 
+#include "batch.h"
 #include "kernels.h"
 
 namespace sipg {
@@ -154,8 +155,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 template <typename T, int N, bool RES>
 __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
-    const T* __restrict__ u, T* __restrict__ v, const T* __restrict__ bvec,
-    const T* __restrict__ tab, TableLayout lay, TileMap tm, T h) {
+    Batch<T> B, const T* __restrict__ tab, TableLayout lay) {
   constexpr int N2 = N * N, N3 = N2 * N, CPB = (64 / N2) > 0 ? 64 / N2 : 1;
   constexpr int WAVES = kThreads / 64;
   __shared__ T s_t1_all[WAVES * CPB * N3];
@@ -167,8 +167,20 @@ __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
   __shared__ T s_tzm_all[WAVES * CPB * 4 * N2];
 
   const int tid = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int grp = xcd_remap(blockIdx.x, gridDim.x) * WAVES + wave;
-  if (grp >= tm.ngroups) return;  // wave-uniform; no workgroup barriers below
+  const int gi = xcd_remap(blockIdx.x, gridDim.x) * WAVES + wave;
+  if (gi >= B.start[B.count]) return;  // wave-uniform; no workgroup barriers below
+  const int pb = batch_find(B, gi);
+  const int grp = gi - B.start[pb];
+  const T* __restrict__ u = B.d[pb].in;
+  T* __restrict__ v = B.d[pb].out;
+  const T* __restrict__ bvec = B.d[pb].aux;
+  const T h = B.d[pb].h;
+  TileMap tm;
+  tm.n = B.d[pb].n;
+  tm.tx = B.d[pb].a0;
+  tm.ntx = B.d[pb].a1;
+  tm.blk = B.d[pb].a2;
+  tm.ngroups = B.start[pb + 1] - B.start[pb];
   T* s_t1 = s_t1_all + wave * (CPB * N3);
   T* s_t2 = s_t2_all + wave * (CPB * N3);
   T* s_ty = s_ty_all + wave * (CPB * 4 * N2);
@@ -347,15 +359,21 @@ __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
 // ---------------------------------------------------------------------------
 template <typename T, int N>
 __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
-    const T* __restrict__ r, T* __restrict__ x, const T* __restrict__ tab,
-    TableLayout lay, int n, T h, int bx, int by, int bz, int npx, int npy, int npatch) {
+    Batch<T> B, const T* __restrict__ tab, TableLayout lay, int bx, int by, int bz) {
   constexpr int G = 2 * N, G2 = G * G, G3 = G2 * G, N2 = N * N, N3 = N2 * N;
   constexpr int PPB = (kThreads / G2) > 0 ? kThreads / G2 : 1;
   __shared__ T s_S[4 * G2];
   __shared__ T s_l[4 * G];
   __shared__ T s_X[PPB * G3];
   const int tid = threadIdx.x;
-  const int p0 = xcd_remap(blockIdx.x, gridDim.x) * PPB;
+  const int bi = xcd_remap(blockIdx.x, gridDim.x);
+  if (bi >= B.start[B.count]) return;
+  const int pb = batch_find(B, bi);
+  const T* __restrict__ r = B.d[pb].in;
+  T* __restrict__ x = B.d[pb].out;
+  const int n = B.d[pb].n, npx = B.d[pb].a0, npy = B.d[pb].a1, npatch = B.d[pb].a2;
+  const T h = B.d[pb].h;
+  const int p0 = (bi - B.start[pb]) * PPB;
   const int np = min(PPB, npatch - p0);
   if (np <= 0) return;
   for (int i = tid; i < 4 * G2; i += kThreads) s_S[i] = tab[lay.fd_s + i];
@@ -460,8 +478,11 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
 // ---------------------------------------------------------------------------
 template <typename T, int N>
 __global__ __launch_bounds__(kThreads) void coarse_fd_kernel(
-    const T* __restrict__ b, T* __restrict__ x, const T* __restrict__ tab,
-    TableLayout lay, int n0, T h) {
+    Batch<T> B, const T* __restrict__ tab, TableLayout lay) {
+  const T* __restrict__ b = B.d[blockIdx.x].in;
+  T* __restrict__ x = B.d[blockIdx.x].out;
+  const int n0 = B.d[blockIdx.x].n;
+  const T h = B.d[blockIdx.x].h;
   constexpr int GM = 3 * N, N2 = N * N, N3 = N2 * N;
   extern __shared__ __align__(16) unsigned char s_raw[];
   T* s_dyn = reinterpret_cast<T*>(s_raw);
@@ -517,17 +538,22 @@ __global__ __launch_bounds__(kThreads) void coarse_fd_kernel(
 // ---------------------------------------------------------------------------
 template <typename T, int N>
 __global__ __launch_bounds__(kThreads) void restrict_kernel(
-    const T* __restrict__ rf, T* __restrict__ rc, const T* __restrict__ tab,
-    TableLayout lay, int nc) {
+    Batch<T> B, const T* __restrict__ tab, TableLayout lay) {
   constexpr int G = 2 * N, G2 = G * G, G3 = G2 * G, N2 = N * N, N3 = N2 * N;
   constexpr int CPB = (kThreads / G2) > 0 ? kThreads / G2 : 1;
   __shared__ T s_P[G * N];
   __shared__ T s_X[CPB * G3];
   const int tid = threadIdx.x;
+  const int bi = xcd_remap(blockIdx.x, gridDim.x);
+  if (bi >= B.start[B.count]) return;
+  const int pb = batch_find(B, bi);
+  const int nc = B.d[pb].n;
   const int ncells = nc * nc * nc;
-  const int c0 = xcd_remap(blockIdx.x, gridDim.x) * CPB;
+  const int c0 = (bi - B.start[pb]) * CPB;
   const int cnt = min(CPB, ncells - c0);
   if (cnt <= 0) return;
+  const T* __restrict__ src_in = B.d[pb].in;
+  T* __restrict__ dst_out = B.d[pb].out;
   for (int i = tid; i < G * N; i += kThreads) s_P[i] = tab[lay.p1 + i];
   const int nf = 2 * nc;
   for (int w = tid; w < cnt * G3; w += kThreads) {
@@ -538,7 +564,7 @@ __global__ __launch_bounds__(kThreads) void restrict_kernel(
     const int ox = child & 1, oy = (child >> 1) & 1, oz = child >> 2;
     const int i = loc % N, j = (loc / N) % N, l = loc / N2;
     const int f = (2 * cx + ox) + nf * (2 * cy + oy) + nf * nf * (2 * cz + oz);
-    s_X[cl * G3 + (ox * N + i) + G * (oy * N + j) + G2 * (oz * N + l)] = rf[(size_t)f * N3 + loc];
+    s_X[cl * G3 + (ox * N + i) + G * (oy * N + j) + G2 * (oz * N + l)] = src_in[(size_t)f * N3 + loc];
   }
   __syncthreads();
   // x: lines (j', l') of length G -> N values, stored in place at stride 1
@@ -582,7 +608,7 @@ __global__ __launch_bounds__(kThreads) void restrict_kernel(
     T in[G];
 #pragma unroll
     for (int a = 0; a < G; ++a) in[a] = X[a * G2];
-    T* dst = rc + (size_t)(c0 + cl) * N3 + bx + by * N;
+    T* dst = dst_out + (size_t)(c0 + cl) * N3 + bx + by * N;
 #pragma unroll
     for (int b = 0; b < N; ++b) {
       T s = 0.0;
@@ -595,23 +621,28 @@ __global__ __launch_bounds__(kThreads) void restrict_kernel(
 
 template <typename T, int N>
 __global__ __launch_bounds__(kThreads) void prolongate_add_kernel(
-    const T* __restrict__ ec, T* __restrict__ xf, const T* __restrict__ tab,
-    TableLayout lay, int nc) {
+    Batch<T> B, const T* __restrict__ tab, TableLayout lay) {
   constexpr int G = 2 * N, G2 = G * G, G3 = G2 * G, N2 = N * N, N3 = N2 * N;
   constexpr int CPB = (kThreads / G2) > 0 ? kThreads / G2 : 1;
   __shared__ T s_P[G * N];
   __shared__ T s_X[CPB * G3];
   const int tid = threadIdx.x;
+  const int bi = xcd_remap(blockIdx.x, gridDim.x);
+  if (bi >= B.start[B.count]) return;
+  const int pb = batch_find(B, bi);
+  const int nc = B.d[pb].n;
   const int ncells = nc * nc * nc;
-  const int c0 = xcd_remap(blockIdx.x, gridDim.x) * CPB;
+  const int c0 = (bi - B.start[pb]) * CPB;
   const int cnt = min(CPB, ncells - c0);
   if (cnt <= 0) return;
+  const T* __restrict__ src_in = B.d[pb].in;
+  T* __restrict__ dst_out = B.d[pb].out;
   for (int i = tid; i < G * N; i += kThreads) s_P[i] = tab[lay.p1 + i];
   // coarse values at X[b + G b' + G^2 b''] (the low corner of the box)
   for (int w = tid; w < cnt * N3; w += kThreads) {
     const int cl = w / N3, loc = w - cl * N3;
     const int i = loc % N, j = (loc / N) % N, l = loc / N2;
-    s_X[cl * G3 + i + G * j + G2 * l] = ec[(size_t)(c0 + cl) * N3 + loc];
+    s_X[cl * G3 + i + G * j + G2 * l] = src_in[(size_t)(c0 + cl) * N3 + loc];
   }
   __syncthreads();
   // z first: lines (b, b') over l: N -> G
@@ -671,7 +702,7 @@ __global__ __launch_bounds__(kThreads) void prolongate_add_kernel(
     const int ox = child & 1, oy = (child >> 1) & 1, oz = child >> 2;
     const int i = loc % N, j = (loc / N) % N, l = loc / N2;
     const int f = (2 * cx + ox) + nf * (2 * cy + oy) + nf * nf * (2 * cz + oz);
-    xf[(size_t)f * N3 + loc] += s_X[cl * G3 + (ox * N + i) + G * (oy * N + j) + G2 * (oz * N + l)];
+    dst_out[(size_t)f * N3 + loc] += s_X[cl * G3 + (ox * N + i) + G * (oy * N + j) + G2 * (oz * N + l)];
   }
 }
 
@@ -682,77 +713,144 @@ const double* tab_of<double>(const DevTab& t) { return t.tab; }
 template <>
 const float* tab_of<float>(const DevTab& t) { return t.tabf; }
 
+// Fill the work ranges of a batch; `items(i)` = work items of job i.
+template <typename T, typename F>
+hipError_t make_batch(Batch<T>& B, int count, F&& fill) {
+  if (count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
+  B.count = count;
+  B.start[0] = 0;
+  for (int i = 0; i < count; ++i) {
+    int64_t items = 0;
+    hipError_t e = fill(i, B.d[i], items);
+    if (e != hipSuccess) return e;
+    if ((int64_t)B.start[i] + items > ((int64_t)1 << 30)) return hipErrorInvalidValue;
+    B.start[i + 1] = B.start[i] + (int)items;
+  }
+  for (int i = count; i < kMaxBatch; ++i) B.start[i + 1] = B.start[count];
+  return hipSuccess;
+}
+
 template <typename T, int N>
-hipError_t apply_impl(const T* u, T* v, const T* b, const DevTab& t, int n, double h,
-                      hipStream_t s) {
+hipError_t apply_impl(const ApplyJob* jobs, int count, const DevTab& t, hipStream_t s) {
   constexpr int CPW = (64 / (N * N)) > 0 ? 64 / (N * N) : 1;
-  if (n < 1 || n > 1024) return hipErrorInvalidValue;
-  TileMap tm;
-  tm.n = n;
-  tm.tx = 1;
-  for (int d = 1; d <= CPW && d <= n; ++d)
-    if (n % d == 0) tm.tx = d;  // largest divisor of n that fits a wave
-  tm.ntx = n / tm.tx;
-  tm.blk = (n % 8 == 0) ? 8 : 1;
-  const int64_t tiles = (int64_t)tm.ntx * n * n;
-  if (tiles > ((int64_t)1 << 30)) return hipErrorInvalidValue;
-  tm.ngroups = (int)tiles;
+  Batch<T> B;
+  bool residual = jobs[0].b != nullptr;
+  hipError_t e = make_batch(B, count, [&](int i, Desc<T>& d, int64_t& items) {
+    const ApplyJob& j = jobs[i];
+    if (j.n < 1 || j.n > 1024 || !j.u || !j.v || (j.b != nullptr) != residual)
+      return hipErrorInvalidValue;
+    int tx = 1;
+    for (int q = 1; q <= CPW && q <= j.n; ++q)
+      if (j.n % q == 0) tx = q;  // largest divisor of n that fits a wave
+    d.in = (const T*)j.u;
+    d.out = (T*)j.v;
+    d.aux = (const T*)j.b;
+    d.h = (T)j.h;
+    d.n = j.n;
+    d.a0 = tx;
+    d.a1 = j.n / tx;
+    d.a2 = (j.n % 8 == 0) ? 8 : 1;
+    items = (int64_t)d.a1 * j.n * j.n;
+    return hipSuccess;
+  });
+  if (e != hipSuccess) return e;
   const int waves = kThreads / 64;
-  const int grid = (int)((tiles + waves - 1) / waves);
-  if (b)
-    hipLaunchKernelGGL((apply_wave_kernel<T, N, true>), dim3(grid), dim3(kThreads), 0, s, u,
-                       v, b, tab_of<T>(t), t.lay, tm, (T)h);
+  const int grid = (B.start[count] + waves - 1) / waves;
+  if (grid == 0) return hipSuccess;
+  if (residual)
+    hipLaunchKernelGGL((apply_wave_kernel<T, N, true>), dim3(grid), dim3(kThreads), 0, s, B,
+                       tab_of<T>(t), t.lay);
   else
-    hipLaunchKernelGGL((apply_wave_kernel<T, N, false>), dim3(grid), dim3(kThreads), 0, s, u,
-                       v, nullptr, tab_of<T>(t), t.lay, tm, (T)h);
+    hipLaunchKernelGGL((apply_wave_kernel<T, N, false>), dim3(grid), dim3(kThreads), 0, s, B,
+                       tab_of<T>(t), t.lay);
   return hipGetLastError();
 }
 
 template <typename T, int N>
-hipError_t patch_impl(int colour, const T* r, T* x, const DevTab& t, int n, double h,
+hipError_t patch_impl(int colour, const PatchJob* jobs, int count, const DevTab& t,
                       hipStream_t s) {
   constexpr int G2 = 4 * N * N;
   constexpr int PPB = (kThreads / G2) > 0 ? kThreads / G2 : 1;
   const int bx = colour & 1, by = (colour >> 1) & 1, bz = (colour >> 2) & 1;
-  // vertices v in [1, n-1]: odd ones 1,3,..; even ones 2,4,..
-  auto count = [&](int bit) { return bit ? n / 2 : (n - 1) / 2; };
-  const int npx = count(bx), npy = count(by), npz = count(bz);
-  const int64_t np = (int64_t)npx * npy * npz;
-  if (np == 0) return hipSuccess;
-  const int grid = (int)((np + PPB - 1) / PPB);
-  hipLaunchKernelGGL((patch_fd_kernel<T, N>), dim3(grid), dim3(kThreads), 0, s, r, x,
-                     tab_of<T>(t), t.lay, n, (T)h, bx, by, bz, npx, npy, (int)np);
+  Batch<T> B;
+  hipError_t e = make_batch(B, count, [&](int i, Desc<T>& d, int64_t& items) {
+    const PatchJob& j = jobs[i];
+    if (j.n < 2 || j.n > 1024 || !j.r || !j.x) return hipErrorInvalidValue;
+    // vertices v in [1, n-1]: odd ones 1,3,..; even ones 2,4,..
+    auto cnt = [&](int bit) { return bit ? j.n / 2 : (j.n - 1) / 2; };
+    d.in = (const T*)j.r;
+    d.out = (T*)j.x;
+    d.aux = nullptr;
+    d.h = (T)j.h;
+    d.n = j.n;
+    d.a0 = cnt(bx);
+    d.a1 = cnt(by);
+    d.a2 = d.a0 * d.a1 * cnt(bz);
+    items = (d.a2 + PPB - 1) / PPB;
+    return hipSuccess;
+  });
+  if (e != hipSuccess) return e;
+  if (B.start[count] == 0) return hipSuccess;
+  hipLaunchKernelGGL((patch_fd_kernel<T, N>), dim3(B.start[count]), dim3(kThreads), 0, s, B,
+                     tab_of<T>(t), t.lay, bx, by, bz);
   return hipGetLastError();
 }
 
 template <typename T, int N>
-hipError_t coarse_impl(int n0, const T* b, T* x, const DevTab& t, double h, hipStream_t s) {
-  if (n0 < 1 || n0 > 3 || t.lay.Gc != n0 * N) return hipErrorInvalidValue;
-  const int G = n0 * N;
+hipError_t coarse_impl(const CoarseJob* jobs, int count, const DevTab& t, hipStream_t s) {
+  Batch<T> B;
+  int gmax = 0;
+  hipError_t e = make_batch(B, count, [&](int i, Desc<T>& d, int64_t& items) {
+    const CoarseJob& j = jobs[i];
+    if (j.n0 < 1 || j.n0 > 3 || t.lay.Gc != j.n0 * N || !j.b || !j.x) return hipErrorInvalidValue;
+    d.in = (const T*)j.b;
+    d.out = (T*)j.x;
+    d.aux = nullptr;
+    d.h = (T)j.h;
+    d.n = j.n0;
+    d.a0 = d.a1 = d.a2 = 0;
+    gmax = gmax > j.n0 * N ? gmax : j.n0 * N;
+    items = 1;
+    return hipSuccess;
+  });
+  if (e != hipSuccess) return e;
+  const int G = gmax;
   const size_t shm = sizeof(T) * ((size_t)G * G + G + (size_t)G * G * G);
   if (shm > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)coarse_fd_kernel<T, N>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
+    hipError_t e2 = hipFuncSetAttribute((const void*)coarse_fd_kernel<T, N>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e2 != hipSuccess) return e2;
   }
-  hipLaunchKernelGGL((coarse_fd_kernel<T, N>), dim3(1), dim3(kThreads), shm, s, b, x,
-                     tab_of<T>(t), t.lay, n0, (T)h);
+  hipLaunchKernelGGL((coarse_fd_kernel<T, N>), dim3(count), dim3(kThreads), shm, s, B,
+                     tab_of<T>(t), t.lay);
   return hipGetLastError();
 }
 
 template <typename T, int N>
-hipError_t transfer_impl(bool restr, const T* in, T* out, const DevTab& t, int nc,
+hipError_t transfer_impl(bool restr, const TransferJob* jobs, int count, const DevTab& t,
                          hipStream_t s) {
   constexpr int G2 = 4 * N * N;
   constexpr int CPB = (kThreads / G2) > 0 ? kThreads / G2 : 1;
-  const int64_t ncells = (int64_t)nc * nc * nc;
-  const int grid = (int)((ncells + CPB - 1) / CPB);
+  Batch<T> B;
+  hipError_t e = make_batch(B, count, [&](int i, Desc<T>& d, int64_t& items) {
+    const TransferJob& j = jobs[i];
+    if (j.nc < 1 || j.nc > 512 || !j.in || !j.out) return hipErrorInvalidValue;
+    d.in = (const T*)j.in;
+    d.out = (T*)j.out;
+    d.aux = nullptr;
+    d.h = (T)0;
+    d.n = j.nc;
+    d.a0 = d.a1 = d.a2 = 0;
+    items = ((int64_t)j.nc * j.nc * j.nc + CPB - 1) / CPB;
+    return hipSuccess;
+  });
+  if (e != hipSuccess) return e;
   if (restr)
-    hipLaunchKernelGGL((restrict_kernel<T, N>), dim3(grid), dim3(kThreads), 0, s, in, out,
-                       tab_of<T>(t), t.lay, nc);
+    hipLaunchKernelGGL((restrict_kernel<T, N>), dim3(B.start[count]), dim3(kThreads), 0, s, B,
+                       tab_of<T>(t), t.lay);
   else
-    hipLaunchKernelGGL((prolongate_add_kernel<T, N>), dim3(grid), dim3(kThreads), 0, s, in,
-                       out, tab_of<T>(t), t.lay, nc);
+    hipLaunchKernelGGL((prolongate_add_kernel<T, N>), dim3(B.start[count]), dim3(kThreads), 0,
+                       s, B, tab_of<T>(t), t.lay);
   return hipGetLastError();
 }
 
@@ -770,80 +868,108 @@ hipError_t transfer_impl(bool restr, const T* in, T* out, const DevTab& t, int n
     default: return hipErrorInvalidValue;       \
   }
 
-
-
-template <typename T>
-static hipError_t apply_any(int N, const T* u, T* v, const T* b, const DevTab& t, int n,
-                            double h, hipStream_t s) {
+hipError_t launch_apply_batch(int prec, int N, const ApplyJob* jobs, int count, const DevTab& t,
+                              hipStream_t s) {
   if (t.lay.N != N) return hipErrorInvalidValue;
-#define CALL(NN) apply_impl<T, NN>(u, v, b, t, n, h, s)
-  SIPG_DISPATCH_N(N, CALL)
+  if (prec == 0) {
+#define CALL(NN) apply_impl<double, NN>(jobs, count, t, s)
+    SIPG_DISPATCH_N(N, CALL)
 #undef CALL
-}
-template <typename T>
-static hipError_t patch_any(int N, int colour, const T* r, T* x, const DevTab& t, int n,
-                            double h, hipStream_t s) {
-  if (t.lay.N != N || colour < 0 || colour > 7 || n < 2) return hipErrorInvalidValue;
-#define CALL(NN) patch_impl<T, NN>(colour, r, x, t, n, h, s)
-  SIPG_DISPATCH_N(N, CALL)
-#undef CALL
-}
-template <typename T>
-static hipError_t coarse_any(int N, int n0, const T* b, T* x, const DevTab& t, double h,
-                             hipStream_t s) {
-  if (t.lay.N != N) return hipErrorInvalidValue;
-#define CALL(NN) coarse_impl<T, NN>(n0, b, x, t, h, s)
-  SIPG_DISPATCH_N(N, CALL)
-#undef CALL
-}
-template <typename T>
-static hipError_t transfer_any(int N, bool restr, const T* in, T* out, const DevTab& t, int nc,
-                               hipStream_t s) {
-  if (t.lay.N != N || nc < 1) return hipErrorInvalidValue;
-#define CALL(NN) transfer_impl<T, NN>(restr, in, out, t, nc, s)
+  }
+#define CALL(NN) apply_impl<float, NN>(jobs, count, t, s)
   SIPG_DISPATCH_N(N, CALL)
 #undef CALL
 }
 
+hipError_t launch_patch_fd_batch(int prec, int N, int colour, const PatchJob* jobs, int count,
+                                 const DevTab& t, hipStream_t s) {
+  if (t.lay.N != N || colour < 0 || colour > 7) return hipErrorInvalidValue;
+  if (prec == 0) {
+#define CALL(NN) patch_impl<double, NN>(colour, jobs, count, t, s)
+    SIPG_DISPATCH_N(N, CALL)
+#undef CALL
+  }
+#define CALL(NN) patch_impl<float, NN>(colour, jobs, count, t, s)
+  SIPG_DISPATCH_N(N, CALL)
+#undef CALL
+}
+
+hipError_t launch_coarse_fd_batch(int prec, int N, const CoarseJob* jobs, int count,
+                                  const DevTab& t, hipStream_t s) {
+  if (t.lay.N != N) return hipErrorInvalidValue;
+  if (prec == 0) {
+#define CALL(NN) coarse_impl<double, NN>(jobs, count, t, s)
+    SIPG_DISPATCH_N(N, CALL)
+#undef CALL
+  }
+#define CALL(NN) coarse_impl<float, NN>(jobs, count, t, s)
+  SIPG_DISPATCH_N(N, CALL)
+#undef CALL
+}
+
+hipError_t launch_transfer_batch(int prec, int N, bool restr, const TransferJob* jobs, int count,
+                                 const DevTab& t, hipStream_t s) {
+  if (t.lay.N != N) return hipErrorInvalidValue;
+  if (prec == 0) {
+#define CALL(NN) transfer_impl<double, NN>(restr, jobs, count, t, s)
+    SIPG_DISPATCH_N(N, CALL)
+#undef CALL
+  }
+#define CALL(NN) transfer_impl<float, NN>(restr, jobs, count, t, s)
+  SIPG_DISPATCH_N(N, CALL)
+#undef CALL
+}
+
+// single-problem forms
 hipError_t launch_apply_f64(int N, const double* u, double* v, const double* b, const DevTab& t,
                             int n, double h, hipStream_t s) {
-  return apply_any<double>(N, u, v, b, t, n, h, s);
+  ApplyJob j{u, v, b, n, h};
+  return launch_apply_batch(0, N, &j, 1, t, s);
 }
 hipError_t launch_apply_f32(int N, const float* u, float* v, const float* b, const DevTab& t,
                             int n, double h, hipStream_t s) {
-  return apply_any<float>(N, u, v, b, t, n, h, s);
+  ApplyJob j{u, v, b, n, h};
+  return launch_apply_batch(1, N, &j, 1, t, s);
 }
 hipError_t launch_patch_fd_f64(int N, int colour, const double* r, double* x, const DevTab& t,
                                int n, double h, hipStream_t s) {
-  return patch_any<double>(N, colour, r, x, t, n, h, s);
+  PatchJob j{r, x, n, h};
+  return launch_patch_fd_batch(0, N, colour, &j, 1, t, s);
 }
 hipError_t launch_patch_fd_f32(int N, int colour, const float* r, float* x, const DevTab& t,
                                int n, double h, hipStream_t s) {
-  return patch_any<float>(N, colour, r, x, t, n, h, s);
+  PatchJob j{r, x, n, h};
+  return launch_patch_fd_batch(1, N, colour, &j, 1, t, s);
 }
 hipError_t launch_coarse_fd_f64(int N, int n0, const double* b, double* x, const DevTab& t,
                                 double h, hipStream_t s) {
-  return coarse_any<double>(N, n0, b, x, t, h, s);
+  CoarseJob j{b, x, n0, h};
+  return launch_coarse_fd_batch(0, N, &j, 1, t, s);
 }
 hipError_t launch_coarse_fd_f32(int N, int n0, const float* b, float* x, const DevTab& t,
                                 double h, hipStream_t s) {
-  return coarse_any<float>(N, n0, b, x, t, h, s);
+  CoarseJob j{b, x, n0, h};
+  return launch_coarse_fd_batch(1, N, &j, 1, t, s);
 }
 hipError_t launch_restrict_f64(int N, const double* rf, double* rc, const DevTab& t, int nc,
                                hipStream_t s) {
-  return transfer_any<double>(N, true, rf, rc, t, nc, s);
+  TransferJob j{rf, rc, nc};
+  return launch_transfer_batch(0, N, true, &j, 1, t, s);
 }
 hipError_t launch_restrict_f32(int N, const float* rf, float* rc, const DevTab& t, int nc,
                                hipStream_t s) {
-  return transfer_any<float>(N, true, rf, rc, t, nc, s);
+  TransferJob j{rf, rc, nc};
+  return launch_transfer_batch(1, N, true, &j, 1, t, s);
 }
 hipError_t launch_prolongate_add_f64(int N, const double* ec, double* xf, const DevTab& t, int nc,
                                      hipStream_t s) {
-  return transfer_any<double>(N, false, ec, xf, t, nc, s);
+  TransferJob j{ec, xf, nc};
+  return launch_transfer_batch(0, N, false, &j, 1, t, s);
 }
 hipError_t launch_prolongate_add_f32(int N, const float* ec, float* xf, const DevTab& t, int nc,
                                      hipStream_t s) {
-  return transfer_any<float>(N, false, ec, xf, t, nc, s);
+  TransferJob j{ec, xf, nc};
+  return launch_transfer_batch(1, N, false, &j, 1, t, s);
 }
 
 }  // namespace sipg
