@@ -11,7 +11,8 @@ are resident in HBM before timing; each degree rotates over 4 (u, v) pairs
 Prints one JSON line: value = total DoFs applied / second (GDoF/s) over the
 timed steps, the roofline of the dominant kernel (HIP-event timing of the
 kernel on its own stream), the oracle's CPU rate on a bounded sample, and,
-outside the timed region, the FP64 FGMRES + multigrid solve times.
+outside the timed region, the FP64 / mixed-precision FGMRES + multigrid
+solve times and the batched uneven solves.
 """
 import argparse
 import json
@@ -95,6 +96,64 @@ def run_solves(configs):
     return out
 
 
+BATCH_SEED, BATCH_COUNT, BATCH_RESTART = 4, 64, 6
+SMALL_EDGES = (4, 6, 8, 12)
+
+
+def run_batch(count=BATCH_COUNT, seed=BATCH_SEED, restart=BATCH_RESTART,
+              edges=(16, 24, 32, 48, 64)):
+    """Batched uneven solves: `count` seeded problems (mesh edge in
+    {16,24,32,48,64}, k in 2..7), right-hand sides from 4 seeded sine modes,
+    FGMRES(restart) + FP64 V(2,2) to rtol 1e-10.  Times one batched solve
+    with captured V-cycle graphs (after a warm-up solve that captures them),
+    one batched solve without graphs, and the one-problem-at-a-time loop on
+    the same handles.  Aggregate rate = sum over problems of DoFs x
+    iterations / wall time.  The Krylov space holds restart + 1 and restart
+    vectors per problem, sized so the whole batch fits in HBM (the sine
+    right-hand sides converge in <= 3 iterations, so no restart occurs).
+    The same measurement on small meshes (edges 4..12) shows the launch-bound
+    regime that batching and graph capture target."""
+    import torch
+    from paper_2407_09621_amd import Batch, inputs
+    pairs = [(k, n) for n, k in inputs.batch_problems(seed, count, edges=edges)]
+    B = Batch(pairs)
+    B.autotune()
+    modes = [inputs.sine_modes(1000 * seed + i) for i in range(count)]
+    bs = [B.rhs_sines(i, *modes[i]) for i in range(count)]
+    torch.cuda.synchronize()
+    res = {}
+    for name, kw in [("warmup", dict(use_graph=True)), ("graph", dict(use_graph=True)),
+                     ("eager", dict(use_graph=False)), ("sequential", dict(sequential=True))]:
+        xs = [torch.zeros_like(b) for b in bs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xs, infos = B.solve(bs, xs=xs, rtol=1e-10, restart=restart, max_iters=100, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        its = [i["iterations"] for i in infos]
+        work = sum(m * it for m, it in zip(B.sizes, its))
+        res[name] = {"seconds": round(dt, 4), "gdof_s": round(work / dt / 1e9, 3),
+                     "iterations_total": sum(its), "iterations_max": max(its),
+                     "max_rel_res_true": max(i["rel_res_true"] for i in infos),
+                     "converged": all(i["status"] == "SIPG_OK" for i in infos)}
+        if name in ("graph", "sequential"):
+            res[name]["l2_errors"] = [B.l2_error_sines(i, *modes[i], xs[i]) for i in range(count)]
+        del xs
+        torch.cuda.empty_cache()
+    eg, es = res["graph"].pop("l2_errors"), res["sequential"].pop("l2_errors")
+    out = {"problems": count, "seed": seed, "restart": restart,
+           "total_dofs": int(sum(B.sizes)),
+           "degrees": sorted({k for k, _ in pairs}), "edges": sorted({n for _, n in pairs}),
+           "l2_max_rel_diff_vs_sequential": max(abs(a - b) / b for a, b in zip(eg, es)),
+           "speedup_graph_vs_sequential": round(res["sequential"]["seconds"] / res["graph"]["seconds"], 3),
+           "speedup_graph_vs_eager": round(res["eager"]["seconds"] / res["graph"]["seconds"], 3)}
+    out.update({k: v for k, v in res.items() if k != "warmup"})
+    B.close()
+    del bs
+    torch.cuda.empty_cache()
+    return out
+
+
 def lp_apply_rates(probs, stream, reps):
     """Reduced-precision applies (FP32 storage, 8 B/DoF) at the apply sizes."""
     import torch
@@ -129,6 +188,9 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the solve measurements")
     ap.add_argument("--all-solves", action="store_true",
                     help="solve every degree 3/5/7 x 16^3/32^3/64^3 configuration")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-solve measurement")
+    ap.add_argument("--batch-count", type=int, default=BATCH_COUNT,
+                    help="problems in the batched-solve measurement")
     ap.add_argument("--mode", choices=["bench", "profile"], default="bench",
                     help="profile: a few applies per degree and a plain copy of a known size "
                          "(for rocprofv3 kernel traces and HBM counters)")
@@ -234,6 +296,10 @@ def main():
 
     solves = None if args.no_solve else run_solves(SOLVE_CONFIGS_ALL if args.all_solves
                                                    else SOLVE_CONFIGS)
+    batch = None
+    if not args.no_batch:
+        batch = {"large": run_batch(count=args.batch_count),
+                 "small": run_batch(count=args.batch_count, edges=SMALL_EDGES)}
     cpu = None if args.no_cpu else cpu_baseline()
 
     line = {
@@ -247,7 +313,7 @@ def main():
                                "one step = one apply per degree",
                    "parallelism": "single GPU"},
         "per_k": per_k, "roofline": roofline, "cpu_baseline": cpu,
-        "lowprec_apply": lp_rates, "solves": solves,
+        "lowprec_apply": lp_rates, "solves": solves, "batch": batch,
     }
     print(json.dumps(line))
 

@@ -175,6 +175,53 @@ sipg_status sipg_l2_error_sines(sipg_problem* p, int level, int n_modes,
                                 const double* x, double* err,
                                 hipStream_t stream);
 
+/* Tile-order autotuner of the operator apply: times the apply on `level`
+ * with each admissible tile-order block (1, 2, 4, 8 cells, dividing n) and
+ * keeps the fastest for all later applies, residuals and smoother sweeps of
+ * that level.  u, v: two distinct scratch vectors of the level (contents
+ * irrelevant; v is overwritten).  *best (HOST, may be NULL) receives the
+ * chosen block.  Synchronizes the stream. */
+sipg_status sipg_autotune(sipg_problem* p, int level, const double* u, double* v,
+                          int* best, hipStream_t stream);
+
+/* ---- batches of independent problems (uneven sizes and degrees) ---------
+ * A batch owns one problem handle per configuration.  All configurations
+ * must share mg_precision, error_correction, nu_pre and nu_post, and reach
+ * a coarsest level of 1, 2 or 3 cells.  Vector arguments are HOST arrays of
+ * `count` DEVICE pointers (problem i uses sipg_n_dofs of its finest level).
+ * Every stage of the batched V-cycle and FGMRES iteration is issued as
+ * launches that each cover up to 16 problems of one degree. */
+typedef struct sipg_batch sipg_batch;
+
+sipg_status sipg_batch_create(const sipg_config* cfgs, int count, sipg_batch** out);
+void sipg_batch_destroy(sipg_batch* b);
+int sipg_batch_count(const sipg_batch* b);
+/* Borrowed handle of problem i (owned by the batch; do not destroy). */
+sipg_problem* sipg_batch_problem(sipg_batch* b, int i);
+/* Run sipg_autotune on every level of one problem per (k, n) class and share
+ * the result with the class.  Synchronizes. */
+sipg_status sipg_batch_autotune(sipg_batch* b, hipStream_t stream);
+/* v_i = A_i u_i on the finest levels (FP64). */
+sipg_status sipg_batch_apply(sipg_batch* b, const double* const* u, double* const* v,
+                             hipStream_t stream);
+/* x_i <- V-cycle(x_i, b_i) on the finest levels, levels aligned by depth. */
+sipg_status sipg_batch_vcycle(sipg_batch* b, double* const* x, const double* const* bvec,
+                              hipStream_t stream);
+/* FGMRES for all problems in lockstep (one host synchronization per Krylov
+ * step for the whole batch), each with its own Hessenberg system, stopping
+ * test and restarts.  use_graph = 1 captures the batched V-cycle of Krylov
+ * step j as a HIP graph on an internal stream at its first use and replays
+ * it.  infos[count] (HOST) receive per-problem results; `seconds` is the
+ * batch wall time.  Blocks until done. */
+sipg_status sipg_batch_solve(sipg_batch* b, double* const* x, const double* const* bvec,
+                             const sipg_solve_opts* opts, sipg_solve_info* infos,
+                             int use_graph, hipStream_t stream);
+/* Reference: sipg_fgmres on each problem in turn. */
+sipg_status sipg_batch_solve_sequential(sipg_batch* b, double* const* x,
+                                        const double* const* bvec,
+                                        const sipg_solve_opts* opts,
+                                        sipg_solve_info* infos, hipStream_t stream);
+
 /* Thread-local text of the last error ("" if none). */
 const char* sipg_last_error(void);
 

@@ -40,6 +40,7 @@ struct ApplyJob {
   const void* b;  // nullptr: v = A u; else v = b - A u
   int n;
   double h;
+  int order = 0;  // tile order block (divides n); 0 = default (8 if it divides n, else 1)
 };
 struct PatchJob {
   const void* r;

@@ -9,58 +9,13 @@
 #include <string>
 #include <vector>
 
-#include "../../include/sipg.h"
-#include "kernels.h"
-#include "tables.h"
+#include "problem.h"
 
 using namespace sipg;
 
-namespace {
-
+namespace sipg {
 thread_local std::string g_err;
-
-sipg_status fail(sipg_status s, const std::string& msg) {
-  g_err = msg;
-  return s;
-}
-
-#define SIPG_HIP(expr)                                                               \
-  do {                                                                               \
-    hipError_t e_ = (expr);                                                          \
-    if (e_ != hipSuccess)                                                            \
-      return fail(SIPG_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-  } while (0)
-
-#define SIPG_TRY(expr)                \
-  do {                                \
-    sipg_status s_ = (expr);          \
-    if (s_ != SIPG_OK) return s_;     \
-  } while (0)
-
-}  // namespace
-
-struct sipg_problem {
-  sipg_config cfg{};
-  int k = 0, N = 0, L = 0, n0 = 0;
-  std::vector<int> n;
-  std::vector<int64_t> ndofs;
-  DevTab tab;
-  double* d_tab = nullptr;
-  std::vector<double*> wx, wb, wr;  // per-level V-cycle vectors
-  double* V = nullptr;              // Krylov basis, (restart + 1) vectors
-  double* Z = nullptr;              // preconditioned vectors, restart vectors
-  int restart_alloc = 0;
-  double* d_partial = nullptr;      // kDotBlocks * 65 doubles
-  double* d_small = nullptr;        // 512 doubles of scalars
-  int* d_flag = nullptr;
-  double* d_aux = nullptr;          // tables for rhs / l2 (grown on demand)
-  size_t aux_size = 0;
-  // low-precision V-cycle (mg_precision != F64): FP32 level vectors
-  int prec = SIPG_F64;
-  bool ec = false;
-  float* d_tabf = nullptr;
-  std::vector<float*> fx, fb, fr;
-};
+}  // namespace sipg
 
 namespace {
 
@@ -70,23 +25,14 @@ sipg_status check_level(const sipg_problem* p, int level) {
   return SIPG_OK;
 }
 
-template <typename T>
-sipg_status dev_alloc(T** ptr, size_t count) {
-  *ptr = nullptr;
-  if (count == 0) return SIPG_OK;
-  hipError_t e = hipMalloc((void**)ptr, count * sizeof(T));
-  if (e != hipSuccess) {
-    *ptr = nullptr;
-    return fail(SIPG_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
-  }
-  return SIPG_OK;
+int tile_order(const sipg_problem* p, int l) {
+  return (l < (int)p->order.size()) ? p->order[l] : 0;
 }
-
-double level_h(const sipg_problem* p, int l) { return 1.0 / p->n[l]; }
 
 sipg_status residual(sipg_problem* p, int l, const double* b, const double* x, double* r,
                      hipStream_t s) {
-  SIPG_HIP(launch_apply_f64(p->N, x, r, b, p->tab, p->n[l], level_h(p, l), s));
+  ApplyJob j{x, r, b, p->n[l], level_h(p, l), tile_order(p, l)};
+  SIPG_HIP(launch_apply_batch(0, p->N, &j, 1, p->tab, s));
   return SIPG_OK;
 }
 
@@ -195,6 +141,21 @@ sipg_status ensure_aux(sipg_problem* p, size_t count) {
 }
 
 }  // namespace
+
+namespace sipg {
+sipg_status ensure_krylov(sipg_problem* p, int m) {
+  if (m <= p->restart_alloc) return SIPG_OK;
+  const int64_t n = p->ndofs[p->L - 1];
+  if (p->V) hipFree(p->V);
+  if (p->Z) hipFree(p->Z);
+  p->V = p->Z = nullptr;
+  p->restart_alloc = 0;
+  SIPG_TRY(dev_alloc(&p->V, (size_t)(m + 1) * n));
+  SIPG_TRY(dev_alloc(&p->Z, (size_t)m * n));
+  p->restart_alloc = m;
+  return SIPG_OK;
+}
+}  // namespace sipg
 
 extern "C" {
 
@@ -324,7 +285,8 @@ sipg_status sipg_apply(sipg_problem* p, int level, const double* u, double* v, h
   SIPG_TRY(check_level(p, level));
   if (!u || !v) return fail(SIPG_ERR_ARG, "NULL vector");
   if (u == v) return fail(SIPG_ERR_ARG, "u and v must not alias");
-  SIPG_HIP(launch_apply_f64(p->N, u, v, nullptr, p->tab, p->n[level], level_h(p, level), s));
+  ApplyJob j{u, v, nullptr, p->n[level], level_h(p, level), tile_order(p, level)};
+  SIPG_HIP(launch_apply_batch(0, p->N, &j, 1, p->tab, s));
   return SIPG_OK;
 }
 
@@ -390,6 +352,40 @@ sipg_status sipg_vcycle(sipg_problem* p, int level, double* x, const double* b, 
   return vcycle_any(p, level, x, b, s);
 }
 
+sipg_status sipg_autotune(sipg_problem* p, int level, const double* u, double* v, int* best,
+                          hipStream_t s) {
+  SIPG_TRY(check_level(p, level));
+  if (!u || !v || u == v) return fail(SIPG_ERR_ARG, "need two distinct vectors");
+  const int nl = p->n[level];
+  const int cand[4] = {1, 2, 4, 8};
+  hipEvent_t e0, e1;
+  SIPG_HIP(hipEventCreate(&e0));
+  SIPG_HIP(hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  int best_o = 0;
+  for (int c : cand) {
+    if (nl % c) continue;
+    ApplyJob j{u, v, nullptr, nl, level_h(p, level), c};
+    SIPG_HIP(launch_apply_batch(0, p->N, &j, 1, p->tab, s));  // warm-up
+    SIPG_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < 5; ++r) SIPG_HIP(launch_apply_batch(0, p->N, &j, 1, p->tab, s));
+    SIPG_HIP(hipEventRecord(e1, s));
+    SIPG_HIP(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    SIPG_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best_o = c;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if ((int)p->order.size() < p->L) p->order.assign(p->L, 0);
+  p->order[level] = best_o;
+  if (best) *best = best_o;
+  return SIPG_OK;
+}
+
 sipg_status sipg_apply_lp(sipg_problem* p, int level, const float* u, float* v, int precision,
                           int ec, hipStream_t s) {
   SIPG_TRY(check_level(p, level));
@@ -418,15 +414,7 @@ sipg_status sipg_fgmres(sipg_problem* p, double* x, const double* b, const sipg_
   const int m = o->restart;
   const int L = p->L - 1;
   const int64_t n = p->ndofs[L];
-  if (m > p->restart_alloc) {
-    if (p->V) hipFree(p->V);
-    if (p->Z) hipFree(p->Z);
-    p->V = p->Z = nullptr;
-    p->restart_alloc = 0;
-    SIPG_TRY(dev_alloc(&p->V, (size_t)(m + 1) * n));
-    SIPG_TRY(dev_alloc(&p->Z, (size_t)m * n));
-    p->restart_alloc = m;
-  }
+  SIPG_TRY(ensure_krylov(p, m));
   SIPG_HIP(hipStreamSynchronize(s));
   const auto t0 = std::chrono::steady_clock::now();
   double* d_h = p->d_small;        // [0, 65)
@@ -482,7 +470,10 @@ sipg_status sipg_fgmres(sipg_problem* p, double* x, const double* b, const sipg_
         SIPG_HIP(launch_scale_copy(Vj, 1.0, Zj, n, s));
         info->fell_back = 1;
       }
-      SIPG_HIP(launch_apply_f64(p->N, Zj, w, nullptr, p->tab, p->n[L], level_h(p, L), s));
+      {
+        ApplyJob aj{Zj, w, nullptr, p->n[L], level_h(p, L), tile_order(p, L)};
+        SIPG_HIP(launch_apply_batch(0, p->N, &aj, 1, p->tab, s));
+      }
       // classical Gram-Schmidt, twice
       SIPG_HIP(launch_mdot(p->V, n, j + 1, w, n, p->d_partial, d_h, s));
       SIPG_HIP(launch_maxpy(p->V, n, j + 1, d_h, w, n, nullptr, 1.0, s));

@@ -1,0 +1,76 @@
+// Internal state of a problem handle and helpers shared by the C-ABI
+// translation units (not part of the public interface).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/sipg.h"
+#include "kernels.h"
+#include "tables.h"
+
+namespace sipg {
+
+extern thread_local std::string g_err;
+
+inline sipg_status fail(sipg_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+template <typename T>
+sipg_status dev_alloc(T** ptr, size_t count) {
+  *ptr = nullptr;
+  if (count == 0) return SIPG_OK;
+  hipError_t e = hipMalloc((void**)ptr, count * sizeof(T));
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    return fail(SIPG_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  return SIPG_OK;
+}
+
+}  // namespace sipg
+
+#define SIPG_HIP(expr)                                                                     \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return ::sipg::fail(SIPG_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define SIPG_TRY(expr)            \
+  do {                            \
+    sipg_status s_ = (expr);      \
+    if (s_ != SIPG_OK) return s_; \
+  } while (0)
+
+struct sipg_problem {
+  sipg_config cfg{};
+  int k = 0, N = 0, L = 0, n0 = 0;
+  std::vector<int> n;
+  std::vector<int64_t> ndofs;
+  sipg::DevTab tab;
+  double* d_tab = nullptr;
+  std::vector<double*> wx, wb, wr;  // per-level V-cycle vectors
+  double* V = nullptr;              // Krylov basis, (restart + 1) vectors
+  double* Z = nullptr;              // preconditioned vectors, restart vectors
+  int restart_alloc = 0;
+  double* d_partial = nullptr;      // kDotBlocks * 65 doubles
+  double* d_small = nullptr;        // 512 doubles of scalars
+  int* d_flag = nullptr;
+  double* d_aux = nullptr;          // tables for rhs / l2 (grown on demand)
+  size_t aux_size = 0;
+  // low-precision V-cycle (mg_precision != F64): FP32 level vectors
+  int prec = SIPG_F64;
+  bool ec = false;
+  float* d_tabf = nullptr;
+  std::vector<float*> fx, fb, fr;
+  std::vector<int> order;  // tile order of the apply per level (autotuned; 0 = default)
+};
+
+namespace sipg {
+inline double level_h(const sipg_problem* p, int l) { return 1.0 / p->n[l]; }
+sipg_status ensure_krylov(sipg_problem* p, int m);
+}  // namespace sipg

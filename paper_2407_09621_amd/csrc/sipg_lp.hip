@@ -602,7 +602,7 @@ hipError_t apply_lp_impl(const ApplyJob* jobs, int count, const DevTab& t, hipSt
     d.n = j.n;
     d.a0 = tx;
     d.a1 = j.n / tx;
-    d.a2 = (j.n % 8 == 0) ? 8 : 1;
+    d.a2 = (j.order > 0 && j.n % j.order == 0) ? j.order : ((j.n % 8 == 0) ? 8 : 1);
     const int64_t items = (int64_t)d.a1 * j.n * j.n;
     if (B.start[i] + items > ((int64_t)1 << 30)) return hipErrorInvalidValue;
     B.start[i + 1] = B.start[i] + (int)items;

@@ -749,7 +749,7 @@ hipError_t apply_impl(const ApplyJob* jobs, int count, const DevTab& t, hipStrea
     d.n = j.n;
     d.a0 = tx;
     d.a1 = j.n / tx;
-    d.a2 = (j.n % 8 == 0) ? 8 : 1;
+    d.a2 = (j.order > 0 && j.n % j.order == 0) ? j.order : ((j.n % 8 == 0) ? 8 : 1);
     items = (int64_t)d.a1 * j.n * j.n;
     return hipSuccess;
   });

@@ -78,6 +78,16 @@ def load_library(path=None):
         "sipg_rhs_sines": (i32, [vp, i32, i32, vp, vp, vp, vp]),
         "sipg_l2_error_sines": (i32, [vp, i32, i32, vp, vp, vp, ctypes.POINTER(dbl), vp]),
         "sipg_last_error": (ctypes.c_char_p, []),
+        "sipg_autotune": (i32, [vp, i32, vp, vp, ctypes.POINTER(i32), vp]),
+        "sipg_batch_create": (i32, [ctypes.POINTER(Config), i32, ctypes.POINTER(vp)]),
+        "sipg_batch_destroy": (None, [vp]),
+        "sipg_batch_count": (i32, [vp]),
+        "sipg_batch_problem": (vp, [vp, i32]),
+        "sipg_batch_autotune": (i32, [vp, vp]),
+        "sipg_batch_apply": (i32, [vp, vp, vp, vp]),
+        "sipg_batch_vcycle": (i32, [vp, vp, vp, vp]),
+        "sipg_batch_solve": (i32, [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), i32, vp]),
+        "sipg_batch_solve_sequential": (i32, [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -165,6 +175,15 @@ class Problem:
                                   _stream(stream)))
         return v
 
+    def autotune(self, level=-1, stream=None):
+        """Tile-order autotuner of the apply on `level`; returns the chosen block."""
+        u = self.new_vector(level)
+        v = self.new_vector(level)
+        best = ctypes.c_int()
+        _check(_lib.sipg_autotune(self._h, self._lvl(level), _ptr(u), _ptr(v), ctypes.byref(best),
+                                  _stream(stream)))
+        return best.value
+
     def residual(self, b, x, r=None, level=-1, stream=None):
         import torch
         r = torch.empty_like(b) if r is None else r
@@ -250,3 +269,115 @@ class Problem:
                                         _ptr(x, torch.float64), ctypes.byref(err),
                                         _stream(stream)))
         return err.value
+
+
+def _ptr_array(ts, dtype, sizes):
+    """Host array of device pointers, one vector per problem of the batch."""
+    if len(ts) != len(sizes):
+        raise ValueError(f"expected {len(sizes)} vectors, got {len(ts)}")
+    arr = (ctypes.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        if t.numel() != sizes[i]:
+            raise ValueError(f"vector {i} has {t.numel()} entries, problem needs {sizes[i]}")
+        arr[i] = _ptr(t, dtype).value
+    return arr
+
+
+def _info_dict(info, status):
+    return dict(iterations=info.iterations, fell_back=bool(info.fell_back),
+                rel_res_est=info.rel_res_est, rel_res_true=info.rel_res_true,
+                seconds=info.seconds, status=STATUS[status],
+                history=list(info.history[:min(info.iterations + 1, 128)]))
+
+
+class Batch:
+    """Independent problems of uneven degree and size solved together
+    (vectors are lists of CUDA tensors, one per problem)."""
+
+    def __init__(self, problems, mg_precision="f64", error_correction=False, nu_pre=2, nu_post=2):
+        lib = load_library()
+        cfgs = (Config * len(problems))()
+        for i, (k, n) in enumerate(problems):
+            cfgs[i] = Config(k, n, 0, PRECISION[mg_precision], int(bool(error_correction)),
+                             nu_pre, nu_post)
+        h = ctypes.c_void_p()
+        _check(lib.sipg_batch_create(cfgs, len(problems), ctypes.byref(h)))
+        self._h = h
+        self.problems = list(problems)
+        self.sizes = []
+        for i in range(len(problems)):
+            ph = lib.sipg_batch_problem(h, i)
+            L = lib.sipg_num_levels(ph)
+            self.sizes.append(int(lib.sipg_n_dofs(ph, L - 1)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().sipg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def new_vectors(self):
+        import torch
+        return [torch.zeros(m, dtype=torch.float64, device="cuda") for m in self.sizes]
+
+    def autotune(self, stream=None):
+        _check(_lib.sipg_batch_autotune(self._h, _stream(stream)))
+
+    def apply(self, us, vs=None, stream=None):
+        import torch
+        vs = [torch.empty_like(u) for u in us] if vs is None else vs
+        _check(_lib.sipg_batch_apply(self._h, _ptr_array(us, torch.float64, self.sizes),
+                                     _ptr_array(vs, torch.float64, self.sizes), _stream(stream)))
+        return vs
+
+    def vcycle(self, xs, bs, stream=None):
+        import torch
+        _check(_lib.sipg_batch_vcycle(self._h, _ptr_array(xs, torch.float64, self.sizes),
+                                      _ptr_array(bs, torch.float64, self.sizes), _stream(stream)))
+        return xs
+
+    def solve(self, bs, xs=None, rtol=1e-10, restart=30, max_iters=200, use_graph=True,
+              sequential=False, stream=None):
+        import torch
+        xs = [torch.zeros_like(b) for b in bs] if xs is None else xs
+        opts = SolveOpts(rtol, restart, max_iters, 0, 1)
+        infos = (SolveInfo * len(bs))()
+        if sequential:
+            st = _lib.sipg_batch_solve_sequential(self._h, _ptr_array(xs, torch.float64, self.sizes),
+                                                  _ptr_array(bs, torch.float64, self.sizes), ctypes.byref(opts),
+                                                  infos, _stream(stream))
+        else:
+            st = _lib.sipg_batch_solve(self._h, _ptr_array(xs, torch.float64, self.sizes),
+                                       _ptr_array(bs, torch.float64, self.sizes), ctypes.byref(opts), infos,
+                                       int(bool(use_graph)), _stream(stream))
+        if st not in (SIPG_OK, 5):
+            _check(st)
+        return xs, [_info_dict(infos[i], st) for i in range(len(bs))]
+
+    def rhs_sines(self, i, amps, pqr):
+        """Right-hand side of problem i (through its borrowed handle)."""
+        return _BorrowedProblem(self, i).rhs_sines(amps, pqr)
+
+    def l2_error_sines(self, i, amps, pqr, x):
+        return _BorrowedProblem(self, i).l2_error_sines(amps, pqr, x)
+
+
+class _BorrowedProblem(Problem):
+    """View of a problem owned by a Batch (never destroyed by Python)."""
+
+    def __init__(self, batch, i):
+        lib = load_library()
+        self._batch = batch
+        self._h = ctypes.c_void_p(lib.sipg_batch_problem(batch._h, i))
+        self.k, self.n_cells = batch.problems[i]
+        self.N = self.k + 1
+        self.num_levels = lib.sipg_num_levels(self._h)
+        self.cells = [lib.sipg_level_cells(self._h, l) for l in range(self.num_levels)]
+
+    def close(self):
+        self._h = None

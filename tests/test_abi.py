@@ -147,3 +147,17 @@ def test_host_prolongation_table(host_tables, k):
     E = multigrid._child_embedding(k, (1, 0, 1))
     K = np.kron(P1[N:], np.kron(P1[:N], P1[N:]))
     np.testing.assert_allclose(E, K, atol=1e-12)
+
+
+def test_batch_rejects_mixed_precision_before_allocating():
+    """A batch shares one V-cycle precision; the check runs before any
+    device call, so it holds without a GPU."""
+    from paper_2407_09621_amd import SipgError
+    from paper_2407_09621_amd import sipg as binding
+    cfgs = (binding.Config * 2)()
+    cfgs[0] = binding.Config(2, 4, 0, binding.PRECISION["f64"], 0, 2, 2)
+    cfgs[1] = binding.Config(2, 4, 0, binding.PRECISION["f16"], 1, 2, 2)
+    h = ctypes.c_void_p()
+    with pytest.raises(SipgError, match="share precision"):
+        binding._check(binding.load_library().sipg_batch_create(cfgs, 2, ctypes.byref(h)))
+    assert not h.value

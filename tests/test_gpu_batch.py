@@ -1,0 +1,198 @@
+"""GPU checks of batched solves over problems of uneven size and degree:
+every batched stage (operator apply, V-cycle, FGMRES with Sec. 7.1's
+multigrid preconditioner) gives each problem the result it gets when solved
+alone, and the solves agree with the oracle.  The batched launches run the
+same per-problem arithmetic in the same order as the one-problem calls, so
+the comparisons with those are at rounding level (tolerance 1e-12 relative,
+equality expected); captured-graph replays are checked against eager runs
+with other GPU work and synchronisations between the replays."""
+import numpy as np
+import pytest
+
+from gpu_util import announce, rel_l2, to_cpu, to_gpu
+from oracle import fgmres as ofg
+from oracle import multigrid, sipg
+from paper_2407_09621_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+# (k, n): several degrees (two problems each of N = 3 and 4), meshes from 2
+# to 24 cells, depths 1..4, single-level problems of 2 and 3 cells
+MIXED = [(2, 4), (3, 6), (2, 24), (5, 3), (3, 8), (1, 12), (7, 2), (3, 3), (2, 16)]
+
+
+def _vectors(B, seed):
+    return [to_gpu(inputs.uniform_vector(m, seed + i)) for i, m in enumerate(B.sizes)]
+
+
+def test_batch_shapes_and_rejections():
+    from paper_2407_09621_amd import Batch, SipgError
+    announce("batch shapes")
+    B = Batch(MIXED)
+    assert B.sizes == [n ** 3 * (k + 1) ** 3 for k, n in MIXED]
+    with pytest.raises(SipgError, match="coarsest"):
+        Batch([(2, 4), (2, 5)])  # 5 cells cannot be halved to a coarse grid of <= 3
+    with pytest.raises(ValueError):
+        B.apply(_vectors(B, 1)[:-1])
+
+
+def test_batch_apply_matches_single_and_oracle():
+    from paper_2407_09621_amd import Batch, Problem
+    announce("batch apply")
+    B = Batch(MIXED)
+    us = _vectors(B, 10)
+    vs = B.apply(us)
+    for (k, n), u, v in zip(MIXED, us, vs):
+        ref = Problem(k, n, n_levels=1).apply(u)
+        assert rel_l2(to_cpu(v), to_cpu(ref)) < 1e-12, (k, n)
+        assert rel_l2(to_cpu(v), sipg.kron_apply(to_cpu(u), n, k)) < 1e-13, (k, n)
+
+
+def test_batch_apply_more_than_one_launch_per_degree():
+    """20 problems of one degree: two launches of at most 16 problems."""
+    from paper_2407_09621_amd import Batch
+    announce("batch apply 20")
+    probs = [(2, (2, 3, 4, 6)[i % 4]) for i in range(20)]
+    B = Batch(probs)
+    us = _vectors(B, 40)
+    vs = B.apply(us)
+    for (k, n), u, v in zip(probs, us, vs):
+        assert rel_l2(to_cpu(v), sipg.kron_apply(to_cpu(u), n, k)) < 1e-13
+
+
+@pytest.mark.parametrize("prec,ec", [("f64", 0), ("f32", 0), ("f16", 1)])
+def test_batch_vcycle_matches_single(prec, ec):
+    from paper_2407_09621_amd import Batch, Problem
+    announce("batch vcycle", prec, ec)
+    import torch
+    B = Batch(MIXED, mg_precision=prec, error_correction=bool(ec))
+    bs = _vectors(B, 60)
+    xs = [torch.zeros_like(b) for b in bs]
+    B.vcycle(xs, bs)
+    for (k, n), b, x in zip(MIXED, bs, xs):
+        P = Problem(k, n, mg_precision=prec, error_correction=bool(ec))
+        x1 = torch.zeros_like(b)
+        P.vcycle(x1, b)
+        assert rel_l2(to_cpu(x), to_cpu(x1)) < 1e-12, (k, n)
+
+
+def test_batch_vcycle_matches_oracle():
+    from paper_2407_09621_amd import Batch
+    announce("batch vcycle oracle")
+    import torch
+    probs = [(2, 4), (3, 6), (1, 8)]
+    B = Batch(probs)
+    bs = _vectors(B, 70)
+    xs = [torch.zeros_like(b) for b in bs]
+    B.vcycle(xs, bs)
+    for (k, n), b, x in zip(probs, bs, xs):
+        H = multigrid.Hierarchy(n, k)
+        assert rel_l2(to_cpu(x), H.precondition(to_cpu(b))) < 1e-12, (k, n)
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_solve_matches_sequential(use_graph):
+    from paper_2407_09621_amd import Batch
+    announce("batch solve", use_graph)
+    B = Batch(MIXED)
+    bs = _vectors(B, 80)
+    xs, infos = B.solve(bs, rtol=1e-10, use_graph=use_graph)
+    xq, iq = B.solve(bs, rtol=1e-10, sequential=True)
+    for i, (k, n) in enumerate(MIXED):
+        assert infos[i]["rel_res_true"] < 1e-10, (k, n, infos[i])
+        assert infos[i]["iterations"] == iq[i]["iterations"], (k, n)
+        assert rel_l2(to_cpu(xs[i]), to_cpu(xq[i])) < 1e-12, (k, n)
+        h, hq = np.array(infos[i]["history"]), np.array(iq[i]["history"])
+        assert len(h) == len(hq)
+        np.testing.assert_allclose(h, hq, rtol=1e-9, atol=1e-14)
+
+
+def test_batch_solve_matches_oracle():
+    from paper_2407_09621_amd import Batch
+    announce("batch solve oracle")
+    probs = [(2, 4), (3, 4), (1, 6)]
+    B = Batch(probs)
+    bs = _vectors(B, 90)
+    xs, infos = B.solve(bs, rtol=1e-10)
+    for i, (k, n) in enumerate(probs):
+        H = multigrid.Hierarchy(n, k)
+        A = H.levels[-1].A
+        xo, io = ofg.fgmres(lambda v: A @ v, to_cpu(bs[i]), H.precondition, rtol=1e-10)
+        assert abs(infos[i]["iterations"] - io["iterations"]) <= 1
+        assert rel_l2(to_cpu(xs[i]), xo) < 1e-8
+
+
+def test_batch_graph_replays_match_eager():
+    """Four solves: the first captures one graph per Krylov step, the next
+    ones replay them; GPU work of another kind and host synchronisations
+    run between the replays.  Every replayed solve equals the eager solve of
+    the same right-hand side."""
+    from paper_2407_09621_amd import Batch
+    announce("batch graph replays")
+    import torch
+    probs = [(2, 8), (3, 4), (5, 2), (2, 6)]
+    Bg, Be = Batch(probs), Batch(probs)
+    for rep in range(4):
+        bs = _vectors(Bg, 100 + 10 * rep)
+        xg, ig = Bg.solve(bs, rtol=1e-9, restart=8, use_graph=True)
+        junk = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
+        (junk * 2.0).sum().item()
+        torch.cuda.synchronize()
+        xe, ie = Be.solve(bs, rtol=1e-9, restart=8, use_graph=False)
+        for i in range(len(probs)):
+            assert ig[i]["iterations"] == ie[i]["iterations"], (rep, i)
+            assert rel_l2(to_cpu(xg[i]), to_cpu(xe[i])) < 1e-12, (rep, i)
+            assert ig[i]["rel_res_true"] < 1e-9
+
+
+def test_batch_solve_lowprec():
+    """FP16 V-cycle with error correction inside the batched FGMRES: FP64
+    accuracy and the FP64 batch's iteration counts (+1)."""
+    from paper_2407_09621_amd import Batch
+    announce("batch solve f16 ec")
+    probs = [(3, 8), (2, 12), (5, 4), (7, 2)]
+    B64, B16 = Batch(probs), Batch(probs, mg_precision="f16", error_correction=True)
+    bs = _vectors(B64, 120)
+    x64, i64 = B64.solve(bs, rtol=1e-10)
+    x16, i16 = B16.solve(bs, rtol=1e-10)
+    for i in range(len(probs)):
+        assert i16[i]["rel_res_true"] < 1e-10
+        assert i16[i]["iterations"] <= i64[i]["iterations"] + 1
+        assert rel_l2(to_cpu(x16[i]), to_cpu(x64[i])) < 1e-8
+
+
+def test_batch_zero_rhs_and_restart_growth():
+    """A zero right-hand side converges at once with x = 0; growing the
+    restart length reallocates the Krylov space and drops stale graphs."""
+    from paper_2407_09621_amd import Batch
+    announce("batch zero rhs")
+    import torch
+    probs = [(2, 4), (3, 4)]
+    B = Batch(probs)
+    bs = _vectors(B, 130)
+    bs[0].zero_()
+    xs = [torch.ones_like(b) for b in bs]
+    for restart in (4, 12, 4):
+        xs = [torch.ones_like(b) for b in bs]
+        xs, infos = B.solve(bs, xs=xs, rtol=1e-10, restart=restart)
+        assert infos[0]["iterations"] == 0 and float(xs[0].abs().max()) == 0.0
+        assert infos[1]["rel_res_true"] < 1e-10
+
+
+def test_autotune_keeps_results():
+    from paper_2407_09621_amd import Batch, Problem
+    announce("autotune")
+    P = Problem(3, 16, n_levels=1)
+    u = to_gpu(inputs.uniform_vector(P.n_dofs(), 5))
+    v0 = to_cpu(P.apply(u))
+    best = P.autotune()
+    assert best in (1, 2, 4, 8)
+    assert np.array_equal(to_cpu(P.apply(u)), v0)
+    B = Batch([(3, 16), (2, 16), (3, 16)])
+    bs = _vectors(B, 140)
+    x0, i0 = B.solve(bs, rtol=1e-10)
+    B.autotune()
+    x1, i1 = B.solve(bs, rtol=1e-10)
+    for i in range(3):
+        assert i0[i]["iterations"] == i1[i]["iterations"]
+        assert rel_l2(to_cpu(x0[i]), to_cpu(x1[i])) < 1e-12
