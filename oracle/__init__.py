@@ -22,9 +22,11 @@ Tensor-Product Operations with Tensor Cores", arXiv 2407.09621, it follows):
                   patch solves, coarse solve, V-cycle (Sec. 7.1, Alg. v_cycle).
 * ``fgmres``    - right-preconditioned flexible GMRES with modified
                   Gram-Schmidt (Sec. 7.1, 7.2).
-* ``lowprec``   - the error-corrected half-precision product (Sec. 5.2,
-                  Alg. matmul) written out on arrays, for pins of the rounding
-                  model.
+* ``learned``   - the learned correction stage of this project (not in the
+                  paper): grid mapping of DG coefficients, 3D convolutions,
+                  ReLU, masked MSE and their exact gradients, Adam, the
+                  solver-generated training pairs and the learned
+                  preconditioner with its fallback rule.
 
 Readings of passages the paper leaves open are listed in each function's
 docstring.  Parity pins for each function live in ``tests/test_oracle_*.py``.

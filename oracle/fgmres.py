@@ -10,12 +10,14 @@ import numpy as np
 
 
 def fgmres(apply_A, b, precond, rtol=1e-10, restart=30, max_iters=300, x0=None,
-           on_iteration=None):
+           on_iteration=None, on_estimate=None):
     """Solve A x = b.  ``precond(v)`` may change from step to step (flexible).
 
     Returns (x, info) with info = dict(iterations, rel_res_est, rel_res_true,
     history, converged).  ``on_iteration(j, z)`` may inspect (and replace) the
-    preconditioned vector; used for failure-injection tests."""
+    preconditioned vector; used for failure-injection tests.  ``on_estimate(
+    history)`` sees the residual history after every Arnoldi step (the learned
+    stage's fallback rule reads it)."""
     b = np.asarray(b, dtype=np.float64)
     nb = float(np.linalg.norm(b))
     x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
@@ -69,6 +71,8 @@ def fgmres(apply_A, b, precond, rtol=1e-10, restart=30, max_iters=300, x0=None,
             it += 1
             j_done = j + 1
             history.append(abs(g[j + 1]) / nb)
+            if on_estimate is not None:
+                on_estimate(history)
             if abs(g[j + 1]) <= tol or it >= max_iters or H[j, j] == 0.0:
                 break
         y = np.zeros(j_done)
