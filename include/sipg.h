@@ -139,13 +139,15 @@ typedef struct {
   double rtol;        /* stop when |Arnoldi residual| <= rtol * ||b||_2 */
   int restart;        /* Krylov dimension before restart (<= 64) */
   int max_iters;      /* total iteration limit */
-  int use_learned;    /* reserved, must be 0 */
+  int use_learned;    /* 1: apply the attached network after each V-cycle */
   int log_history;    /* 1: record the residual estimate of every iteration */
 } sipg_solve_opts;
 
 typedef struct {
   int iterations;
-  int fell_back;           /* 1 if a non-finite preconditioner output was replaced */
+  int fell_back;           /* 1 if the learned stage was switched off during the
+                              solve, or a non-finite preconditioner output was
+                              replaced */
   double rel_res_est;      /* last Arnoldi estimate / ||b|| */
   double rel_res_true;     /* ||b - A x||_2 / ||b||_2, recomputed in FP64 */
   double seconds;          /* wall time of the solve */
@@ -224,6 +226,87 @@ sipg_status sipg_batch_solve_sequential(sipg_batch* b, double* const* x,
 
 /* Thread-local text of the last error ("" if none). */
 const char* sipg_last_error(void);
+
+/* ---- learned correction stage (a project extension, not in the paper) ----
+ * A 3D convolutional network 1 -> 32 -> 32 -> 32 -> 1 channels, 3x3x3
+ * kernels, zero padding, ReLU between layers, FP16 weights and activations
+ * with FP32 accumulation, on the G^3 grid of DG coefficients: node (i, j, l)
+ * of cell (cx, cy, cz) sits at grid point (N cx + i, N cy + j, N cz + l),
+ * G = n N, N = k + 1.  Grids are dense FP32 device arrays indexed
+ * gx + G (gy + G gz), one after another for a batch; G must be a multiple of
+ * 16.  The parameter vector (SIPG_CNN_PARAMS floats) is w1[32][27] b1[32]
+ * w2[32][32][27] b2[32] w3[32][32][27] b3[32] w4[32][27] b4 with weights
+ * indexed [c_out][c_in][9 (dz+1) + 3 (dy+1) + dx + 1] (cross-correlation).
+ * The network output is multiplied by a power of two sigma (the output
+ * scale, chosen from the first training pair when 0).
+ * Stage: after the V-cycle z = V(v) the preconditioner adds
+ * s sigma net((v - A z) / s), s = 2^ceil(log2 max|v - A z|), on the finest
+ * level.  sipg_fgmres (use_learned = 1) switches the stage off for the rest
+ * of a solve once an iteration reduces the residual estimate by less than a
+ * factor 0.9 or the corrected vector is not finite (that iteration then
+ * uses the plain V-cycle); info->fell_back reports it.
+ * A handle is used by one stream at a time. */
+#define SIPG_CNN_PARAMS 57121
+typedef struct sipg_cnn sipg_cnn;
+int sipg_cnn_num_params(void);
+/* All parameters zero, sigma 0 (no correction until trained or set). */
+sipg_status sipg_cnn_create(sipg_cnn** out);
+void sipg_cnn_destroy(sipg_cnn* c);
+/* He-uniform weights from a splitmix64 stream seeded with `seed` (last
+ * layer scaled by 0.1), zero biases, sigma 0, Adam state reset. */
+sipg_status sipg_cnn_init(sipg_cnn* c, uint64_t seed);
+/* HOST arrays of SIPG_CNN_PARAMS floats.  set resets the Adam state. */
+sipg_status sipg_cnn_set_params(sipg_cnn* c, const float* params, float sigma);
+sipg_status sipg_cnn_get_params(const sipg_cnn* c, float* params, float* sigma);
+/* out = sigma * net(in) on `batch` device grids of side G (in is rounded
+ * to FP16). */
+sipg_status sipg_cnn_forward(sipg_cnn* c, int G, int batch, const float* in, float* out,
+                             hipStream_t stream);
+/* grad (device, SIPG_CNN_PARAMS floats) = gradient of the masked loss
+ * L = sum m (sigma net(in) - target)^2 / sum m over the batch; *loss
+ * (device float, may be NULL) = L.  mask m >= 0 per grid point. */
+sipg_status sipg_cnn_gradient(sipg_cnn* c, int G, int batch, const float* in,
+                              const float* target, const float* mask, float* grad,
+                              float* loss, hipStream_t stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with the
+ * device gradient `grad`. */
+sipg_status sipg_cnn_adam_step(sipg_cnn* c, const float* grad, float lr, hipStream_t stream);
+/* Training pairs generated by the solver on the finest level: starting
+ * from x = x0 (device, not modified), each pair computes r = A x,
+ * z = V-cycle(0, r), e = x - z, rho = r - A z, s = 2^ceil(log2 max|rho|),
+ * writes grid(rho / s) and grid(e / s) into the next G^3 slot of rho_grids
+ * and e_grids (device, count * G^3 floats each) and s into scales[j]
+ * (HOST, may be NULL), then continues the chain with
+ * x = e / 2^ceil(log2 max|e|).  Synchronizes the stream. */
+sipg_status sipg_cnn_make_pairs(sipg_problem* p, const double* x0, int count,
+                                float* rho_grids, float* e_grids, double* scales,
+                                hipStream_t stream);
+typedef struct {
+  int n_chains;        /* right-hand sides (4 sine modes, a ~ U[-1,1], p,q,r ~ U{1..4}) */
+  int chain_length;    /* pairs per right-hand side (one Adam step each) */
+  int crops_per_pair;  /* random crops of side `crop` per step (1..16) */
+  int crop;            /* crop side, a multiple of 16, <= G */
+  float lr;            /* Adam learning rate */
+  int log_every;       /* read the loss back every this many steps (0: first/last) */
+  uint64_t seed;       /* seed of the draws (modes, crop offsets) */
+} sipg_cnn_train_opts;
+typedef struct {
+  int steps;
+  float loss_first, loss_last;  /* masked MSE of the first and last step */
+  float sigma;                  /* output scale in use */
+  double seconds;               /* wall time of the training run */
+  double seconds_pairs;         /* part spent generating pairs */
+} sipg_cnn_train_info;
+/* Train on the GPU with pairs made by the problem's own solver: per
+ * right-hand side, x0 from three V-cycles on b, then chain_length pairs
+ * (as in sipg_cnn_make_pairs), each giving one Adam step on crops_per_pair
+ * random crops (loss masked to points at least 4 points from crop faces
+ * inside the grid).  Runs on an internal stream; blocks until done. */
+sipg_status sipg_cnn_train(sipg_problem* p, sipg_cnn* c, const sipg_cnn_train_opts* o,
+                           sipg_cnn_train_info* info);
+/* Use `c` as the problem's learned stage (NULL detaches).  The problem
+ * borrows the handle: keep it alive while attached. */
+sipg_status sipg_cnn_attach(sipg_problem* p, sipg_cnn* c);
 
 #ifdef __cplusplus
 }

@@ -96,8 +96,8 @@ def conv3d(x, w, b):
     for a in range(3):
         for bb in range(3):
             for c in range(3):
-                y += np.einsum("oi,izyx->ozyx", w[:, :, a, bb, c],
-                               xp[:, a:a + G, bb:bb + G, c:c + G])
+                sl = xp[:, a:a + G, bb:bb + G, c:c + G].reshape(cin, -1)
+                y += (w[:, :, a, bb, c] @ sl).reshape(y.shape)
     return y
 
 
@@ -107,12 +107,13 @@ def conv3d_backward(x, w, gy):
     xp = np.pad(x, ((0, 0), (1, 1), (1, 1), (1, 1)))
     gxp = np.zeros_like(xp)
     gw = np.zeros_like(w)
+    gy2 = gy.reshape(gy.shape[0], -1)
     for a in range(3):
         for bb in range(3):
             for c in range(3):
                 sl = (slice(None), slice(a, a + G), slice(bb, bb + G), slice(c, c + G))
-                gw[:, :, a, bb, c] = np.einsum("ozyx,izyx->oi", gy, xp[sl])
-                gxp[sl] += np.einsum("oi,ozyx->izyx", w[:, :, a, bb, c], gy)
+                gw[:, :, a, bb, c] = gy2 @ xp[sl].reshape(xp.shape[0], -1).T
+                gxp[sl] += (w[:, :, a, bb, c].T @ gy2).reshape((w.shape[1],) + gy.shape[1:])
     return gxp[:, 1:-1, 1:-1, 1:-1], gw, gy.sum(axis=(1, 2, 3))
 
 

@@ -7,4 +7,4 @@ The compute lives in the HIP library ``libsipg.so`` (C ABI: include/sipg.h);
 ``sipg`` is its ctypes binding.  Build with
 ``python -m paper_2407_09621_amd.build``.
 """
-from .sipg import Batch, Problem, SipgError, load_library, LIB_PATH  # noqa: F401
+from .sipg import Batch, Network, Problem, SipgError, load_library, LIB_PATH  # noqa: F401

@@ -130,6 +130,19 @@ sipg_status mdot_host(sipg_problem* p, const double* V, int64_t ld, int nv, cons
   return SIPG_OK;
 }
 
+// flag = 1 if x holds a NaN or Inf (synchronizes the stream)
+sipg_status nonfinite(sipg_problem* p, const double* x, int64_t n, int* flag, hipStream_t s) {
+  SIPG_HIP(hipMemsetAsync(p->d_flag, 0, sizeof(int), s));
+  SIPG_HIP(launch_finite_check(x, n, p->d_flag, s));
+  SIPG_HIP(hipMemcpyAsync(flag, p->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  SIPG_HIP(hipStreamSynchronize(s));
+  return SIPG_OK;
+}
+
+// An iteration whose residual estimate falls by less than this factor ends
+// the learned stage for the rest of the solve.
+constexpr double kStagnation = 0.9;
+
 sipg_status ensure_aux(sipg_problem* p, size_t count) {
   if (count <= p->aux_size) return SIPG_OK;
   if (p->d_aux) hipFree(p->d_aux);
@@ -409,8 +422,9 @@ sipg_status sipg_fgmres(sipg_problem* p, double* x, const double* b, const sipg_
   if (o->restart < 1 || o->restart > 64) return fail(SIPG_ERR_ARG, "restart must be in 1..64");
   if (o->max_iters < 1) return fail(SIPG_ERR_ARG, "max_iters must be >= 1");
   if (!(o->rtol > 0.0)) return fail(SIPG_ERR_ARG, "rtol must be > 0");
-  if (o->use_learned) return fail(SIPG_ERR_UNSUPPORTED, "learned stage not available in this build");
+  if (o->use_learned && !p->cnn) return fail(SIPG_ERR_ARG, "use_learned set but no network attached");
   std::memset(info, 0, sizeof(*info));
+  bool learned = o->use_learned != 0;
   const int m = o->restart;
   const int L = p->L - 1;
   const int64_t n = p->ndofs[L];
@@ -434,8 +448,9 @@ sipg_status sipg_fgmres(sipg_problem* p, double* x, const double* b, const sipg_
   auto Hm = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
   int it = 0, hist = 0;
   bool converged = false;
-  double est = 1.0;
+  double est = 1.0, prev_est = 1.0;
   auto record = [&](double v) {
+    prev_est = est;
     est = v;
     if (o->log_history && hist < 128) info->history[hist] = v;
     ++hist;
@@ -461,11 +476,16 @@ sipg_status sipg_fgmres(sipg_problem* p, double* x, const double* b, const sipg_
       double* w = p->V + (size_t)(j + 1) * n;
       SIPG_HIP(launch_fill(Zj, 0.0, n, s));
       SIPG_TRY(vcycle_any(p, L, Zj, Vj, s));
-      SIPG_HIP(hipMemsetAsync(p->d_flag, 0, sizeof(int), s));
-      SIPG_HIP(launch_finite_check(Zj, n, p->d_flag, s));
+      if (learned) SIPG_TRY(cnn_stage(p, Vj, Zj, s));
       int flag = 0;
-      SIPG_HIP(hipMemcpyAsync(&flag, p->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
-      SIPG_HIP(hipStreamSynchronize(s));
+      SIPG_TRY(nonfinite(p, Zj, n, &flag, s));
+      if (flag && learned) {  // the learned stage failed: plain V-cycle from here on
+        learned = false;
+        info->fell_back = 1;
+        SIPG_HIP(launch_fill(Zj, 0.0, n, s));
+        SIPG_TRY(vcycle_any(p, L, Zj, Vj, s));
+        SIPG_TRY(nonfinite(p, Zj, n, &flag, s));
+      }
       if (flag) {  // preconditioner broke down: fall back to the identity
         SIPG_HIP(launch_scale_copy(Vj, 1.0, Zj, n, s));
         info->fell_back = 1;
@@ -502,6 +522,10 @@ sipg_status sipg_fgmres(sipg_problem* p, double* x, const double* b, const sipg_
       ++it;
       jd = j + 1;
       record(std::fabs(g[j + 1]) / nb);
+      if (learned && !(est <= kStagnation * prev_est)) {  // stagnation: drop the learned stage
+        learned = false;
+        info->fell_back = 1;
+      }
       if (std::fabs(g[j + 1]) <= tol || it >= o->max_iters || den == 0.0) break;
     }
     for (int i = jd - 1; i >= 0; --i) {

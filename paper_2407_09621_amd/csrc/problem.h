@@ -68,9 +68,12 @@ struct sipg_problem {
   float* d_tabf = nullptr;
   std::vector<float*> fx, fb, fr;
   std::vector<int> order;  // tile order of the apply per level (autotuned; 0 = default)
+  sipg_cnn* cnn = nullptr;  // learned correction stage (borrowed; see sipg_cnn_attach)
 };
 
 namespace sipg {
 inline double level_h(const sipg_problem* p, int l) { return 1.0 / p->n[l]; }
 sipg_status ensure_krylov(sipg_problem* p, int m);
+// z += learned correction of the residual v - A z on the finest level
+sipg_status cnn_stage(sipg_problem* p, const double* v, double* z, hipStream_t s);
 }  // namespace sipg

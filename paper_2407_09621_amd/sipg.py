@@ -44,6 +44,18 @@ class SolveInfo(ctypes.Structure):
                 ("seconds", ctypes.c_double), ("history", ctypes.c_double * 128)]
 
 
+class CnnTrainOpts(ctypes.Structure):
+    _fields_ = [("n_chains", ctypes.c_int), ("chain_length", ctypes.c_int),
+                ("crops_per_pair", ctypes.c_int), ("crop", ctypes.c_int), ("lr", ctypes.c_float),
+                ("log_every", ctypes.c_int), ("seed", ctypes.c_uint64)]
+
+
+class CnnTrainInfo(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int), ("loss_first", ctypes.c_float),
+                ("loss_last", ctypes.c_float), ("sigma", ctypes.c_float),
+                ("seconds", ctypes.c_double), ("seconds_pairs", ctypes.c_double)]
+
+
 def load_library(path=None):
     """Load libsipg.so (raises if it is not built)."""
     global _lib
@@ -79,6 +91,18 @@ def load_library(path=None):
         "sipg_l2_error_sines": (i32, [vp, i32, i32, vp, vp, vp, ctypes.POINTER(dbl), vp]),
         "sipg_last_error": (ctypes.c_char_p, []),
         "sipg_autotune": (i32, [vp, i32, vp, vp, ctypes.POINTER(i32), vp]),
+        "sipg_cnn_num_params": (i32, []),
+        "sipg_cnn_create": (i32, [ctypes.POINTER(vp)]),
+        "sipg_cnn_destroy": (None, [vp]),
+        "sipg_cnn_init": (i32, [vp, ctypes.c_uint64]),
+        "sipg_cnn_set_params": (i32, [vp, vp, ctypes.c_float]),
+        "sipg_cnn_get_params": (i32, [vp, vp, ctypes.POINTER(ctypes.c_float)]),
+        "sipg_cnn_forward": (i32, [vp, i32, i32, vp, vp, vp]),
+        "sipg_cnn_gradient": (i32, [vp, i32, i32, vp, vp, vp, vp, vp, vp]),
+        "sipg_cnn_adam_step": (i32, [vp, vp, ctypes.c_float, vp]),
+        "sipg_cnn_make_pairs": (i32, [vp, vp, i32, vp, vp, vp, vp]),
+        "sipg_cnn_train": (i32, [vp, vp, ctypes.POINTER(CnnTrainOpts), ctypes.POINTER(CnnTrainInfo)]),
+        "sipg_cnn_attach": (i32, [vp, vp]),
         "sipg_batch_create": (i32, [ctypes.POINTER(Config), i32, ctypes.POINTER(vp)]),
         "sipg_batch_destroy": (None, [vp]),
         "sipg_batch_count": (i32, [vp]),
@@ -231,11 +255,16 @@ class Problem:
                                 _ptr(b, torch.float64), _stream(stream)))
         return x
 
+    def attach(self, network):
+        """Use a trained Network as the learned stage (None detaches)."""
+        _check(_lib.sipg_cnn_attach(self._h, network._h if network is not None else None))
+        self._network = network
+
     def fgmres(self, b, x=None, rtol=1e-10, restart=30, max_iters=200, log_history=True,
-               stream=None, raise_on_nonconvergence=True):
+               stream=None, raise_on_nonconvergence=True, use_learned=False):
         import torch
         x = torch.zeros_like(b) if x is None else x
-        opts = SolveOpts(rtol, restart, max_iters, 0, int(log_history))
+        opts = SolveOpts(rtol, restart, max_iters, int(bool(use_learned)), int(log_history))
         info = SolveInfo()
         st = _lib.sipg_fgmres(self._h, _ptr(x, torch.float64), _ptr(b, torch.float64),
                               ctypes.byref(opts), ctypes.byref(info), _stream(stream))
@@ -381,3 +410,121 @@ class _BorrowedProblem(Problem):
 
     def close(self):
         self._h = None
+
+
+class Network:
+    """The learned correction stage's network (1 -> 32 -> 32 -> 32 -> 1
+    channels, 3x3x3 convolutions, ReLU), FP16 weights and activations with
+    FP32 accumulation on the GPU.  Grids are CUDA float32 tensors of shape
+    [batch, G, G, G] (indexed [z, y, x]), G a multiple of 16."""
+
+    def __init__(self, seed=None):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.sipg_cnn_create(ctypes.byref(h)))
+        self._h = h
+        self.n_params = lib.sipg_cnn_num_params()
+        if seed is not None:
+            _check(lib.sipg_cnn_init(h, ctypes.c_uint64(seed)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().sipg_cnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        p = np.zeros(self.n_params, dtype=np.float32)
+        sig = ctypes.c_float()
+        _check(_lib.sipg_cnn_get_params(self._h, p.ctypes.data_as(ctypes.c_void_p), ctypes.byref(sig)))
+        return p, float(sig.value)
+
+    def set_params(self, params, sigma):
+        p = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+        if p.size != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters")
+        _check(_lib.sipg_cnn_set_params(self._h, p.ctypes.data_as(ctypes.c_void_p), float(sigma)))
+
+    @staticmethod
+    def _grids(t):
+        import torch
+        if t.dtype != torch.float32 or t.dim() != 4 or not (t.shape[1] == t.shape[2] == t.shape[3]):
+            raise ValueError("expected a float32 tensor [batch, G, G, G]")
+        return int(t.shape[1]), int(t.shape[0])
+
+    def forward(self, grids, stream=None):
+        import torch
+        G, nb = self._grids(grids)
+        out = torch.empty_like(grids)
+        _check(_lib.sipg_cnn_forward(self._h, G, nb, _ptr(grids, torch.float32),
+                                     _ptr(out, torch.float32), _stream(stream)))
+        return out
+
+    def gradient(self, grids, targets, masks, stream=None):
+        """(gradient tensor [n_params], loss) of the masked MSE."""
+        import torch
+        G, nb = self._grids(grids)
+        for t in (targets, masks):
+            if t.shape != grids.shape:
+                raise ValueError("targets and masks must match the input grids")
+        grad = torch.empty(self.n_params, dtype=torch.float32, device=grids.device)
+        loss = torch.empty(1, dtype=torch.float32, device=grids.device)
+        _check(_lib.sipg_cnn_gradient(self._h, G, nb, _ptr(grids, torch.float32),
+                                      _ptr(targets, torch.float32), _ptr(masks, torch.float32),
+                                      _ptr(grad, torch.float32), _ptr(loss, torch.float32),
+                                      _stream(stream)))
+        return grad, loss
+
+    def adam_step(self, grad, lr, stream=None):
+        import torch
+        if grad.numel() != self.n_params:
+            raise ValueError("gradient has the wrong length")
+        _check(_lib.sipg_cnn_adam_step(self._h, _ptr(grad, torch.float32), float(lr),
+                                       _stream(stream)))
+
+    @staticmethod
+    def make_pairs(problem, x0, count, stream=None):
+        """Solver-generated (rho / s, e / s) grids and the scales s."""
+        import torch
+        G = problem.cells[-1] * problem.N
+        rho = torch.empty((count, G, G, G), dtype=torch.float32, device=x0.device)
+        err = torch.empty_like(rho)
+        sc = np.zeros(count, dtype=np.float64)
+        _check(_lib.sipg_cnn_make_pairs(problem._h, _ptr(x0, torch.float64), count,
+                                        _ptr(rho, torch.float32), _ptr(err, torch.float32),
+                                        sc.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+        return rho, err, sc
+
+    def train(self, problem, n_chains, chain_length=4, crops_per_pair=8, crop=32, lr=1e-3,
+              seed=0, log_every=0):
+        o = CnnTrainOpts(n_chains, chain_length, crops_per_pair, crop, lr, log_every, seed)
+        info = CnnTrainInfo()
+        _check(_lib.sipg_cnn_train(problem._h, self._h, ctypes.byref(o), ctypes.byref(info)))
+        return dict(steps=info.steps, loss_first=info.loss_first, loss_last=info.loss_last,
+                    sigma=info.sigma, seconds=info.seconds, seconds_pairs=info.seconds_pairs)
+
+    def save(self, path):
+        """Weights as raw little-endian float32 (`path`.bin) plus JSON meta."""
+        import json
+        p, sig = self.get_params()
+        p.astype("<f4").tofile(path + ".bin")
+        with open(path + ".json", "w") as f:
+            json.dump({"architecture": "conv3d 1-32-32-32-1, 3x3x3, zero padding, ReLU",
+                       "n_params": int(p.size), "sigma": sig, "dtype": "float32"}, f)
+
+    @classmethod
+    def load(cls, path):
+        import json
+        with open(path + ".json") as f:
+            meta = json.load(f)
+        p = np.fromfile(path + ".bin", dtype="<f4")
+        net = cls()
+        if p.size != meta["n_params"] or p.size != net.n_params:
+            raise ValueError("weight file does not match the network")
+        net.set_params(p, meta["sigma"])
+        return net

@@ -1,0 +1,234 @@
+"""GPU checks of the learned correction stage against the oracle
+(oracle/learned.py): the network forward, the masked-MSE gradient of every
+parameter, Adam, the solver-generated training pairs, the stage inside the
+flexible GMRES preconditioner with its fallback rule, training, and the
+trained stage's effect on held-out solves.
+
+Tolerances: the GPU network rounds weights and activations to FP16 and
+accumulates in FP32, so a layer output carries a relative error of a few
+units of 2^-11; over four layers the outputs and gradients agree with the
+FP64 oracle to ~1e-3 (bound 1e-2, relative l2).  Adam runs in FP32 (1e-5).
+Pair grids are FP32 copies of FP64 vectors (1e-6)."""
+import numpy as np
+import pytest
+
+from gpu_util import announce, rel_l2, to_cpu, to_gpu
+from oracle import learned as OL
+from oracle import multigrid, rhs
+from paper_2407_09621_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _params(seed, C=32, wscale=1.0):
+    rng = np.random.default_rng(seed)
+    p = {}
+    for name, shp in OL.param_shapes(C).items():
+        if name.startswith("w"):
+            fan_in = shp[1] * 27
+            p[name] = rng.standard_normal(shp) * np.sqrt(2.0 / fan_in) * wscale
+        else:
+            p[name] = rng.uniform(-0.05, 0.05, shp)
+    return p
+
+
+def _net(params, sigma):
+    from paper_2407_09621_amd import Network
+    net = Network()
+    net.set_params(OL.flatten(params).astype(np.float32), sigma)
+    return net
+
+
+def _grids(arrs):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(np.array(arrs, dtype=np.float32))).to("cuda")
+
+
+def test_forward_matches_oracle():
+    announce("cnn forward")
+    params, sigma = _params(1), 0.5
+    net = _net(params, sigma)
+    rng = np.random.default_rng(2)
+    xs = [rng.uniform(-1, 1, (16, 16, 16)), rng.standard_normal((16, 16, 16)) * 0.5]
+    y = to_cpu(net.forward(_grids(xs)))
+    for i, x in enumerate(xs):
+        ref = sigma * OL.forward(params, x)[0]
+        assert rel_l2(y[i], ref) < 1e-2, i
+    # a second grid size, larger than one tile in every direction
+    x = rng.uniform(-1, 1, (32, 32, 32))
+    assert rel_l2(to_cpu(net.forward(_grids([x])))[0], sigma * OL.forward(params, x)[0]) < 1e-2
+
+
+def test_gradient_matches_oracle():
+    announce("cnn gradient")
+    params, sigma = _params(3), 0.25
+    net = _net(params, sigma)
+    rng = np.random.default_rng(4)
+    xs = [rng.uniform(-1, 1, (16, 16, 16)) for _ in range(2)]
+    ts = [rng.standard_normal((16, 16, 16)) * 0.1 for _ in range(2)]
+    ms = [(rng.uniform(0, 1, (16, 16, 16)) > 0.3).astype(float) for _ in range(2)]
+    grad, loss = net.gradient(_grids(xs), _grids(ts), _grids(ms))
+    g = to_cpu(grad).astype(np.float64)
+    lref, gref = OL.loss_and_grads(params, sigma, xs, ts, ms)
+    assert abs(float(to_cpu(loss)[0]) - lref) < 1e-2 * lref
+    flat = OL.flatten(gref)
+    o = 0
+    for name in OL.PARAM_NAMES:
+        m = gref[name].size
+        assert rel_l2(g[o:o + m], flat[o:o + m]) < 2e-2, name
+        o += m
+
+
+def test_adam_matches_oracle():
+    announce("cnn adam")
+    import torch
+    params = _params(5)
+    net = _net(params, 1.0)
+    theta = OL.flatten(params).astype(np.float32).astype(np.float64)
+    opt = OL.Adam(theta.size, lr=1e-3)
+    rng = np.random.default_rng(6)
+    for step in range(3):
+        g = rng.standard_normal(theta.size).astype(np.float32)
+        net.adam_step(torch.from_numpy(g).to("cuda"), 1e-3)
+        theta = opt.step(theta, g.astype(np.float64))
+        got, _ = net.get_params()
+        assert np.allclose(got, theta, rtol=1e-5, atol=1e-7), step
+
+
+def test_make_pairs_match_oracle():
+    from paper_2407_09621_amd import Network, Problem
+    announce("cnn pairs")
+    k, n = 3, 4
+    P = Problem(k, n)
+    H = multigrid.Hierarchy(n, k)
+    A = H.levels[-1].A
+    amps, pqr = inputs.sine_modes(21)
+    x0 = rhs.interpolate(rhs.SineModes(amps, pqr), n, k)
+    rho, err, sc = Network.make_pairs(P, to_gpu(x0), 3)
+    ref = OL.make_pairs(A, H.precondition, x0, 3, n, k)
+    for j, (rg, eg, s) in enumerate(ref):
+        assert sc[j] == s, j
+        assert rel_l2(to_cpu(rho[j]), rg) < 1e-6, j
+        assert rel_l2(to_cpu(err[j]), eg) < 1e-6, j
+
+
+def test_zero_network_leaves_the_solve_unchanged():
+    from paper_2407_09621_amd import Network, Problem
+    announce("cnn zero net")
+    k, n = 3, 4
+    P = Problem(k, n)
+    b = P.rhs_sines(*inputs.sine_modes(22))
+    x0, i0 = P.fgmres(b, rtol=1e-10)
+    net = Network()                     # all-zero parameters, sigma 0
+    P.attach(net)
+    x1, i1 = P.fgmres(b, rtol=1e-10, use_learned=True)
+    assert i1["iterations"] == i0["iterations"] and not i1["fell_back"]
+    assert rel_l2(to_cpu(x1), to_cpu(x0)) < 1e-14
+
+
+def test_stage_direction_matches_oracle():
+    """One FGMRES step without restarts returns x = y0 z0 with z0 the
+    preconditioned b / ||b||: the learned z0's direction equals the oracle's."""
+    from paper_2407_09621_amd import Problem
+    announce("cnn stage")
+    k, n = 3, 4
+    P = Problem(k, n)
+    params, sigma = _params(7, wscale=0.5), 2.0 ** 20  # correction ~1e-2 of z here
+    net = _net(params, sigma)
+    P.attach(net)
+    amps, pqr = inputs.sine_modes(23)
+    b = P.rhs_sines(amps, pqr)
+    x, info = P.fgmres(b, rtol=1e-14, restart=1, max_iters=1, use_learned=True,
+                       raise_on_nonconvergence=False)
+    H = multigrid.Hierarchy(n, k)
+    A = H.levels[-1].A
+    bo = to_cpu(b)
+    stage = OL.learned_precondition(A, H.precondition, OL.network_fn(params, sigma), n, k)
+    z = stage(bo / np.linalg.norm(bo))
+    plain = H.precondition(bo / np.linalg.norm(bo))
+    xs = to_cpu(x)
+    u, v = xs / np.linalg.norm(xs), z / np.linalg.norm(z)
+    assert rel_l2(u * np.sign(u @ v), v) < 1e-3
+    # and the correction is not negligible, so the check sees the network
+    assert rel_l2(z, plain) > 1e-2
+
+
+def test_learned_solve_matches_oracle():
+    from paper_2407_09621_amd import Problem
+    announce("cnn solve")
+    k, n = 3, 4
+    P = Problem(k, n)
+    params, sigma = _params(8, wscale=0.5), 2.0 ** 12
+    net = _net(params, sigma)
+    P.attach(net)
+    amps, pqr = inputs.sine_modes(24)
+    b = P.rhs_sines(amps, pqr)
+    x, info = P.fgmres(b, rtol=1e-10, use_learned=True)
+    H = multigrid.Hierarchy(n, k)
+    A = H.levels[-1].A
+    xo, io = OL.solve(A, to_cpu(b), H.precondition, OL.network_fn(params, sigma), n, k, rtol=1e-10)
+    assert info["rel_res_true"] < 1e-10
+    assert abs(info["iterations"] - io["iterations"]) <= 1
+    assert rel_l2(to_cpu(x), xo) < 1e-8
+
+
+def test_fallback_on_non_finite_and_on_stagnation():
+    from paper_2407_09621_amd import Problem
+    announce("cnn fallback")
+    k, n = 3, 4
+    P = Problem(k, n)
+    b = P.rhs_sines(*inputs.sine_modes(25))
+    x0, i0 = P.fgmres(b, rtol=1e-10)
+    params = _params(9)
+    flat = OL.flatten(params).astype(np.float32)
+    flat[OL.flatten(params).size - 1] = np.nan          # b4 = NaN: every output is NaN
+    net = _net(params, 1.0)
+    net.set_params(flat, 1.0)
+    P.attach(net)
+    x, info = P.fgmres(b, rtol=1e-10, use_learned=True)
+    assert info["fell_back"] and info["rel_res_true"] < 1e-10
+    assert info["iterations"] == i0["iterations"]   # every iteration used the plain V-cycle
+    # a huge output swamps the V-cycle: stagnation switches the stage off
+    net2 = _net(_params(10), 2.0 ** 30)
+    P.attach(net2)
+    x, info = P.fgmres(b, rtol=1e-10, use_learned=True, max_iters=60)
+    assert info["fell_back"] and info["rel_res_true"] < 1e-10
+
+
+def test_save_load_roundtrip(tmp_path):
+    from paper_2407_09621_amd import Network
+    announce("cnn save/load")
+    params = _params(11)
+    net = _net(params, 0.125)
+    path = str(tmp_path / "net")
+    net.save(path)
+    back = Network.load(path)
+    p0, s0 = net.get_params()
+    p1, s1 = back.get_params()
+    assert np.array_equal(p0, p1) and s0 == s1 == 0.125
+
+
+def test_training_reduces_loss_and_the_stage_keeps_fp64_accuracy():
+    """Train on solver-made pairs (k = 3, 8^3 cells, G = 32), then solve
+    held-out right-hand sides with and without the stage: both reach the
+    FP64 residual and the same L2 error; the iteration counts are printed
+    (the gain at this training budget is measured, not assumed)."""
+    from paper_2407_09621_amd import Network, Problem
+    announce("cnn train")
+    k, n = 3, 8
+    P = Problem(k, n)
+    net = Network(seed=1)
+    info = net.train(P, n_chains=40, chain_length=4, crops_per_pair=4, crop=32, lr=1e-3, seed=2)
+    assert info["steps"] == 160 and info["loss_last"] < info["loss_first"]
+    P.attach(net)
+    rows = []
+    for seed in (100000, 100001, 100002):
+        amps, pqr = inputs.sine_modes(seed)
+        b = P.rhs_sines(amps, pqr)
+        x0, i0 = P.fgmres(b, rtol=1e-10)
+        x1, i1 = P.fgmres(b, rtol=1e-10, use_learned=True)
+        assert i1["rel_res_true"] < 1e-10
+        e0, e1 = P.l2_error_sines(amps, pqr, x0), P.l2_error_sines(amps, pqr, x1)
+        assert abs(e1 - e0) <= 1e-2 * e0
+        rows.append((i0["iterations"], i1["iterations"], i1["fell_back"]))
+    print("plain / learned iterations, fell back:", rows, "training", info)
