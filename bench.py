@@ -12,7 +12,7 @@ Prints one JSON line: value = total DoFs applied / second (GDoF/s) over the
 timed steps, the roofline of the dominant kernel (HIP-event timing of the
 kernel on its own stream), the oracle's CPU rate on a bounded sample, and,
 outside the timed region, the FP64 / mixed-precision FGMRES + multigrid
-solve times and the batched uneven solves.
+solve times, the batched uneven solves and the learned correction stage.
 """
 import argparse
 import json
@@ -27,6 +27,7 @@ if ROOT not in sys.path:
 CONFIGS = [(3, 64), (5, 40), (7, 32)]
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP16_PEAK_TFLOPS = 2500.0     # dense FP16 matrix-core peak
 BYTES_PER_DOF = 16.0          # read u, write v (FP64)
 ROTATE = 4
 
@@ -154,6 +155,60 @@ def run_batch(count=BATCH_COUNT, seed=BATCH_SEED, restart=BATCH_RESTART,
     return out
 
 
+CNN_CHAINS = 500
+
+
+def run_learned(chains=CNN_CHAINS):
+    """Learned correction stage at k = 3 on 32^3 cells (128^3 grid): train
+    on the GPU with 4 solver-made pairs per right-hand side (one Adam step on
+    8 random 32^3 crops per pair), then solve held-out right-hand sides
+    (4 sine modes, seeds 100000..100003) to rtol 1e-10 with and without the
+    stage.  Also times the network forward on the full grid (FP16 matrix
+    cores; 2 x 32 x 32 x 27 x 2 flop per point in each 32 -> 32 layer)."""
+    import torch
+    from paper_2407_09621_amd import Network, Problem, inputs
+    k, n = 3, 32
+    P = Problem(k, n)
+    net = Network(seed=1)
+    tr = net.train(P, n_chains=chains, chain_length=4, crops_per_pair=8, crop=32, lr=1e-3, seed=2)
+    P.attach(net)
+    rows = []
+    for seed in range(100000, 100004):
+        amps, pqr = inputs.sine_modes(seed)
+        b = P.rhs_sines(amps, pqr)
+        P.fgmres(b, rtol=1e-10)                      # warm-up (Krylov space)
+        res = {}
+        for name, ul in (("plain", False), ("learned", True)):
+            x, info = P.fgmres(b, rtol=1e-10, use_learned=ul)
+            res[name] = {"iterations": info["iterations"], "seconds": round(info["seconds"], 5),
+                         "rel_res_true": info["rel_res_true"], "fell_back": info["fell_back"],
+                         "l2_error": P.l2_error_sines(amps, pqr, x)}
+        rows.append({"seed": seed, **res})
+    G = n * (k + 1)
+    g = torch.rand((1, G, G, G), device="cuda", dtype=torch.float32) * 2 - 1
+    net.forward(g)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        net.forward(g)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / 20
+    mid_flop = 2 * 32 * 32 * 27 * G ** 3
+    fwd_flop = 2 * mid_flop + 2 * 2 * 27 * 32 * G ** 3
+    tp = sum(r["plain"]["seconds"] for r in rows)
+    tl = sum(r["learned"]["seconds"] for r in rows)
+    return {"workload": "k=3, 32^3 cells (128^3 grid), 2,097,152 DoFs",
+            "training": {"pairs": tr["steps"], "crops_per_step": 8, "crop": 32, **tr},
+            "solves": rows,
+            "iterations_plain": [r["plain"]["iterations"] for r in rows],
+            "iterations_learned": [r["learned"]["iterations"] for r in rows],
+            "speedup_learned_vs_plain": round(tp / tl, 3),
+            "forward_ms": round(ms, 4), "forward_tflops": round(fwd_flop / ms / 1e9, 1),
+            "forward_frac_fp16_peak": round(fwd_flop / ms / 1e9 / FP16_PEAK_TFLOPS, 4)}
+
+
 def lp_apply_rates(probs, stream, reps):
     """Reduced-precision applies (FP32 storage, 8 B/DoF) at the apply sizes."""
     import torch
@@ -191,6 +246,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-solve measurement")
     ap.add_argument("--batch-count", type=int, default=BATCH_COUNT,
                     help="problems in the batched-solve measurement")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-stage measurement")
+    ap.add_argument("--cnn-chains", type=int, default=CNN_CHAINS,
+                    help="right-hand sides for the learned stage's training (4 pairs each)")
     ap.add_argument("--mode", choices=["bench", "profile"], default="bench",
                     help="profile: a few applies per degree and a plain copy of a known size "
                          "(for rocprofv3 kernel traces and HBM counters)")
@@ -232,6 +290,22 @@ def main():
             torch.cuda.synchronize()
             del u32, v32
             print(f"profiled low-precision apply k={k} n={n}: 3 launches each", flush=True)
+        for prec, ec in (("f64", 0), ("f16", 1)):
+            Ps = Problem(3, 32, mg_precision=prec, error_correction=bool(ec))
+            amps, pqr = inputs.single_sine_modes()
+            x, info = Ps.fgmres(Ps.rhs_sines(amps, pqr), rtol=1e-10)
+            print(f"profiled solve k=3 n=32 {prec}{'_ec' if ec else ''}: "
+                  f"{info['iterations']} iterations", flush=True)
+            Ps.close()
+        from paper_2407_09621_amd import Network
+        net = Network(seed=1)
+        net.set_params(net.get_params()[0], 1.0)
+        g = torch.rand((1, 128, 128, 128), device=dev, dtype=torch.float32)
+        for _ in range(3):
+            net.forward(g)
+        torch.cuda.synchronize()
+        print("profiled network forward: 3 x 128^3 grid", flush=True)
+        del net, g
         # calibration: a plain device copy of exactly 2^27 bytes (read) + 2^27 (write)
         a = torch.empty(1 << 24, dtype=torch.float64, device=dev).uniform_()
         b = torch.empty_like(a)
@@ -300,6 +374,7 @@ def main():
     if not args.no_batch:
         batch = {"large": run_batch(count=args.batch_count),
                  "small": run_batch(count=args.batch_count, edges=SMALL_EDGES)}
+    learned = None if args.no_learned else run_learned(args.cnn_chains)
     cpu = None if args.no_cpu else cpu_baseline()
 
     line = {
@@ -313,7 +388,7 @@ def main():
                                "one step = one apply per degree",
                    "parallelism": "single GPU"},
         "per_k": per_k, "roofline": roofline, "cpu_baseline": cpu,
-        "lowprec_apply": lp_rates, "solves": solves, "batch": batch,
+        "lowprec_apply": lp_rates, "solves": solves, "batch": batch, "learned": learned,
     }
     print(json.dumps(line))
 

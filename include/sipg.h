@@ -141,6 +141,8 @@ typedef struct {
   int max_iters;      /* total iteration limit */
   int use_learned;    /* 1: apply the attached network after each V-cycle */
   int log_history;    /* 1: record the residual estimate of every iteration */
+  double stagnation;  /* learned stage: switch it off after an iteration whose
+                         estimate falls by less than this factor (0: 0.9) */
 } sipg_solve_opts;
 
 typedef struct {
@@ -239,9 +241,10 @@ const char* sipg_last_error(void);
  * indexed [c_out][c_in][9 (dz+1) + 3 (dy+1) + dx + 1] (cross-correlation).
  * The network output is multiplied by a power of two sigma (the output
  * scale, chosen from the first training pair when 0).
- * Stage: after the V-cycle z = V(v) the preconditioner adds
- * s sigma net((v - A z) / s), s = 2^ceil(log2 max|v - A z|), on the finest
- * level.  sipg_fgmres (use_learned = 1) switches the stage off for the rest
+ * Stage: after the V-cycle z = V(v) the preconditioner forms the
+ * correction c = s sigma net((v - A z) / s), s = 2^ceil(log2 max|v - A z|),
+ * and adds alpha c with alpha = (rho . A c) / (A c . A c), rho = v - A z,
+ * the factor minimising ||v - A (z + alpha c)||_2 (finest level).  sipg_fgmres (use_learned = 1) switches the stage off for the rest
  * of a solve once an iteration reduces the residual estimate by less than a
  * factor 0.9 or the corrected vector is not finite (that iteration then
  * uses the plain V-cycle); info->fell_back reports it.

@@ -14,9 +14,12 @@ What is computed, in order (readings of this project, not the paper's):
   network output is multiplied by a fixed power of two sigma that is chosen
   once from training data (so targets and outputs have similar size).
 * Stage.  For a Krylov vector v: z = V(v) (the multigrid V-cycle); the
-  residual rho = v - A z; s = 2^ceil(log2 max|rho|); the corrected
-  z + s * sigma * net(grid(rho / s)) (mapped back to cells).  If rho = 0 the
-  correction is zero.
+  residual rho = v - A z; s = 2^ceil(log2 max|rho|); the correction
+  c = s * sigma * net(grid(rho / s)) (mapped back to cells); q = A c; the
+  corrected z + alpha c with alpha = (rho . q) / (q . q), the factor that
+  minimises ||v - A (z + alpha c)||_2 (alpha = 0 if q = 0).  If rho = 0 the
+  correction is zero.  (The factor keeps a correction whose error is rich
+  in high frequencies, which A amplifies, from raising the residual.)
 * Fallback.  The solve switches to the plain V-cycle for all later
   iterations as soon as one iteration reduces the residual estimate by a
   factor worse than 0.9, or a corrected vector is not finite (that
@@ -232,7 +235,11 @@ def learned_precondition(A, precondition, net, n, k):
         if mx == 0.0:
             return z
         s = pow2_ceil(mx)
-        return z + s * grid_to_cells(net(cells_to_grid(rho / s, n, k)), n, k)
+        c = s * grid_to_cells(net(cells_to_grid(rho / s, n, k)), n, k)
+        q = A @ c
+        qq = float(q @ q)
+        alpha = float(rho @ q) / qq if qq > 0.0 else 0.0
+        return z + alpha * c
     return apply
 
 

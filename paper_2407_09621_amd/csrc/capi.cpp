@@ -279,6 +279,8 @@ void sipg_destroy(sipg_problem* p) {
   for (auto q : p->fx) fr(q);
   for (auto q : p->fb) fr(q);
   for (auto q : p->fr) fr(q);
+  fr(p->stage_c);
+  fr(p->stage_q);
   delete p;
 }
 
@@ -425,6 +427,7 @@ sipg_status sipg_fgmres(sipg_problem* p, double* x, const double* b, const sipg_
   if (o->use_learned && !p->cnn) return fail(SIPG_ERR_ARG, "use_learned set but no network attached");
   std::memset(info, 0, sizeof(*info));
   bool learned = o->use_learned != 0;
+  const double stagnation = o->stagnation > 0.0 ? o->stagnation : kStagnation;
   const int m = o->restart;
   const int L = p->L - 1;
   const int64_t n = p->ndofs[L];
@@ -522,7 +525,7 @@ sipg_status sipg_fgmres(sipg_problem* p, double* x, const double* b, const sipg_
       ++it;
       jd = j + 1;
       record(std::fabs(g[j + 1]) / nb);
-      if (learned && !(est <= kStagnation * prev_est)) {  // stagnation: drop the learned stage
+      if (learned && !(est <= stagnation * prev_est)) {  // stagnation: drop the learned stage
         learned = false;
         info->fell_back = 1;
       }

@@ -58,6 +58,9 @@ hipError_t launch_gather_f16(const double* v, int n, int N, const double* scale,
 hipError_t launch_gather_f32(const double* v, int n, int N, const double* scale, float* g,
                              hipStream_t s);
 hipError_t launch_f32_to_f16(const float* a, _Float16* b, int64_t n, hipStream_t s);
+// y += (num[0] / den[0]) x (nothing if den[0] = 0); scalars on the device
+hipError_t launch_axpy_ratio(const double* num, const double* den, const double* x, double* y,
+                             int64_t n, hipStream_t s);
 
 // ---- training -----------------------------------------------------------------
 // Loss L = sum m (sigma y - t)^2 / sum m.  g4 = 2 m (y - t / sigma), which is

@@ -308,6 +308,16 @@ __global__ __launch_bounds__(kT) void gather32_kernel(const double* __restrict__
   g[gp] = s > 0.0 ? (float)(u / s) : 0.0f;
 }
 
+__global__ __launch_bounds__(kT) void axpy_ratio_kernel(const double* __restrict__ num,
+                                                        const double* __restrict__ den,
+                                                        const double* __restrict__ x,
+                                                        double* __restrict__ y, int64_t n) {
+  const double d = den[0];
+  const double a = d > 0.0 ? num[0] / d : 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x; e < n; e += (int64_t)gridDim.x * kT)
+    y[e] = fma(a, x[e], y[e]);
+}
+
 __global__ __launch_bounds__(kT) void f32_to_f16_kernel(const float* __restrict__ a,
                                                         _Float16* __restrict__ b, int64_t n) {
   for (int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x; e < n; e += (int64_t)gridDim.x * kT)
@@ -602,6 +612,14 @@ hipError_t launch_gather_f32(const double* v, int n, int N, const double* scale,
                              hipStream_t s) {
   const int64_t G = (int64_t)n * N;
   hipLaunchKernelGGL(gather32_kernel, dim3(blocks_for(G * G * G)), dim3(kT), 0, s, v, n, N, scale, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_ratio(const double* num, const double* den, const double* x, double* y,
+                             int64_t n, hipStream_t s) {
+  int64_t g = (n + kT - 1) / kT;
+  hipLaunchKernelGGL(axpy_ratio_kernel, dim3((unsigned)(g < 8192 ? (g < 1 ? 1 : g) : 8192)),
+                     dim3(kT), 0, s, num, den, x, y, n);
   return hipGetLastError();
 }
 

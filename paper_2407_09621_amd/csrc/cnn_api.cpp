@@ -190,21 +190,31 @@ sipg_status check_problem_grid(const sipg_problem* p) {
 
 namespace sipg {
 
-// z += s sigma net(rho / s), rho = v - A z, s = 2^ceil(log2 max|rho|): the
-// learned stage applied after the V-cycle inside the preconditioner.
+// The learned stage applied after the V-cycle inside the preconditioner:
+// rho = v - A z, s = 2^ceil(log2 max|rho|), c = s sigma net(rho / s),
+// q = A c and z += alpha c with alpha = (rho . q) / (q . q), the factor that
+// minimises ||v - A (z + alpha c)||_2 (0 when q = 0).
 sipg_status cnn_stage(sipg_problem* p, const double* v, double* z, hipStream_t s) {
   sipg_cnn* c = p->cnn;
   const int L = p->L - 1;
   const int n = p->n[L], N = p->N, G = n * N;
   const int64_t nd = p->ndofs[L];
   SIPG_TRY(ensure_ws(c, (int64_t)G * G * G, false));
+  if (!p->stage_c) SIPG_TRY(dev_alloc(&p->stage_c, nd));
+  if (!p->stage_q) SIPG_TRY(dev_alloc(&p->stage_q, nd));
   double* rho = p->wr[L];
   double* scale = p->d_small + 400;
+  double* dots = p->d_small + 408;  // [rho . q, q . q]
   SIPG_TRY(sipg_residual(p, L, v, z, rho, s));
   SIPG_HIP(C::launch_pow2_absmax(rho, nd, p->d_partial, scale, s));
   SIPG_HIP(C::launch_gather_f16(rho, n, N, scale, c->x16, s));
   SIPG_TRY(forward(c, G, 1, nullptr, 0.0f, s));
-  SIPG_HIP(C::launch_out_scatter(c->a3, n, N, c->prm, c->sigma, scale, z, s));
+  SIPG_HIP(launch_fill(p->stage_c, 0.0, nd, s));
+  SIPG_HIP(C::launch_out_scatter(c->a3, n, N, c->prm, c->sigma, scale, p->stage_c, s));
+  SIPG_TRY(sipg_apply(p, L, p->stage_c, p->stage_q, s));
+  SIPG_HIP(launch_mdot(rho, nd, 1, p->stage_q, nd, p->d_partial, dots, s));
+  SIPG_HIP(launch_mdot(p->stage_q, nd, 1, p->stage_q, nd, p->d_partial, dots + 1, s));
+  SIPG_HIP(C::launch_axpy_ratio(dots, dots + 1, p->stage_c, z, nd, s));
   return SIPG_OK;
 }
 

@@ -69,6 +69,8 @@ struct sipg_problem {
   std::vector<float*> fx, fb, fr;
   std::vector<int> order;  // tile order of the apply per level (autotuned; 0 = default)
   sipg_cnn* cnn = nullptr;  // learned correction stage (borrowed; see sipg_cnn_attach)
+  double* stage_c = nullptr;  // the stage's correction and its image under A (finest level)
+  double* stage_q = nullptr;
 };
 
 namespace sipg {

@@ -35,7 +35,8 @@ class Config(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("restart", ctypes.c_int), ("max_iters", ctypes.c_int),
-                ("use_learned", ctypes.c_int), ("log_history", ctypes.c_int)]
+                ("use_learned", ctypes.c_int), ("log_history", ctypes.c_int),
+                ("stagnation", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -261,10 +262,11 @@ class Problem:
         self._network = network
 
     def fgmres(self, b, x=None, rtol=1e-10, restart=30, max_iters=200, log_history=True,
-               stream=None, raise_on_nonconvergence=True, use_learned=False):
+               stream=None, raise_on_nonconvergence=True, use_learned=False, stagnation=0.0):
         import torch
         x = torch.zeros_like(b) if x is None else x
-        opts = SolveOpts(rtol, restart, max_iters, int(bool(use_learned)), int(log_history))
+        opts = SolveOpts(rtol, restart, max_iters, int(bool(use_learned)), int(log_history),
+                         stagnation)
         info = SolveInfo()
         st = _lib.sipg_fgmres(self._h, _ptr(x, torch.float64), _ptr(b, torch.float64),
                               ctypes.byref(opts), ctypes.byref(info), _stream(stream))
@@ -374,7 +376,7 @@ class Batch:
               sequential=False, stream=None):
         import torch
         xs = [torch.zeros_like(b) for b in bs] if xs is None else xs
-        opts = SolveOpts(rtol, restart, max_iters, 0, 1)
+        opts = SolveOpts(rtol, restart, max_iters, 0, 1, 0.0)
         infos = (SolveInfo * len(bs))()
         if sequential:
             st = _lib.sipg_batch_solve_sequential(self._h, _ptr_array(xs, torch.float64, self.sizes),

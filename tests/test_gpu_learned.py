@@ -126,14 +126,37 @@ def test_zero_network_leaves_the_solve_unchanged():
     assert rel_l2(to_cpu(x1), to_cpu(x0)) < 1e-14
 
 
-def test_stage_direction_matches_oracle():
-    """One FGMRES step without restarts returns x = y0 z0 with z0 the
-    preconditioned b / ||b||: the learned z0's direction equals the oracle's."""
+def _identity_params(C=32):
+    """Weights for which the network is the identity map: channel 0 carries
+    ReLU(x), channel 1 ReLU(-x), the last layer returns their difference."""
+    p = {name: np.zeros(shp) for name, shp in OL.param_shapes(C).items()}
+    c = (1, 1, 1)
+    p["w1"][(0, 0) + c], p["w1"][(1, 0) + c] = 1.0, -1.0
+    for w in ("w2", "w3"):
+        p[w][(0, 0) + c] = p[w][(1, 1) + c] = 1.0
+    p["w4"][(0, 0) + c], p["w4"][(0, 1) + c] = 1.0, -1.0
+    return p
+
+
+def test_identity_network():
+    announce("cnn identity")
+    net = _net(_identity_params(), 1.0)
+    x = np.random.default_rng(12).uniform(-1, 1, (1, 32, 32, 32))
+    x16 = x.astype(np.float32).astype(np.float16).astype(np.float64)  # FP32 grid, FP16 input
+    assert np.array_equal(to_cpu(net.forward(_grids(x))).astype(np.float64), x16)
+
+
+def test_stage_matches_oracle():
+    """One FGMRES step without restarts: the residual estimate after it is
+    min_y ||v - y A z0|| for z0 the preconditioned v = b / ||b||, and x is a
+    multiple of z0.  With the identity network the stage adds a
+    residual-minimising Richardson step, which lowers that estimate by ~20%
+    here, so the comparison sees the network."""
     from paper_2407_09621_amd import Problem
     announce("cnn stage")
     k, n = 3, 4
     P = Problem(k, n)
-    params, sigma = _params(7, wscale=0.5), 2.0 ** 20  # correction ~1e-2 of z here
+    params, sigma = _identity_params(), 1.0
     net = _net(params, sigma)
     P.attach(net)
     amps, pqr = inputs.sine_modes(23)
@@ -143,14 +166,20 @@ def test_stage_direction_matches_oracle():
     H = multigrid.Hierarchy(n, k)
     A = H.levels[-1].A
     bo = to_cpu(b)
+    v = bo / np.linalg.norm(bo)
     stage = OL.learned_precondition(A, H.precondition, OL.network_fn(params, sigma), n, k)
-    z = stage(bo / np.linalg.norm(bo))
-    plain = H.precondition(bo / np.linalg.norm(bo))
+
+    def estimate(z):
+        q = A @ z
+        return np.sqrt(max(0.0, 1.0 - (v @ q) ** 2 / (q @ q)))
+
+    z, zp = stage(v), H.precondition(v)
+    e_learned, e_plain = estimate(z), estimate(zp)
+    assert abs(e_plain - e_learned) > 0.1 * e_learned
+    assert abs(info["history"][1] - e_learned) < 0.02 * e_learned
     xs = to_cpu(x)
-    u, v = xs / np.linalg.norm(xs), z / np.linalg.norm(z)
-    assert rel_l2(u * np.sign(u @ v), v) < 1e-3
-    # and the correction is not negligible, so the check sees the network
-    assert rel_l2(z, plain) > 1e-2
+    u, w = xs / np.linalg.norm(xs), z / np.linalg.norm(z)
+    assert rel_l2(u * np.sign(u @ w), w) < 1e-6
 
 
 def test_learned_solve_matches_oracle():
@@ -188,10 +217,15 @@ def test_fallback_on_non_finite_and_on_stagnation():
     x, info = P.fgmres(b, rtol=1e-10, use_learned=True)
     assert info["fell_back"] and info["rel_res_true"] < 1e-10
     assert info["iterations"] == i0["iterations"]   # every iteration used the plain V-cycle
-    # a huge output swamps the V-cycle: stagnation switches the stage off
+    # a huge output would swamp the V-cycle; the residual-minimising factor
+    # keeps it harmless, and a threshold no iteration meets forces the
+    # stagnation switch (same rule as the oracle's)
     net2 = _net(_params(10), 2.0 ** 30)
     P.attach(net2)
     x, info = P.fgmres(b, rtol=1e-10, use_learned=True, max_iters=60)
+    assert not info["fell_back"] and info["rel_res_true"] < 1e-10
+    assert info["iterations"] <= i0["iterations"] + 1
+    x, info = P.fgmres(b, rtol=1e-10, use_learned=True, max_iters=60, stagnation=1e-12)
     assert info["fell_back"] and info["rel_res_true"] < 1e-10
 
 

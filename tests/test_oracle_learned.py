@@ -229,8 +229,14 @@ def test_fallback_on_stagnation_and_non_finite():
     amps, pqr = inputs.sine_modes(13)
     b = rhs.rhs(rhs.SineModes(amps, pqr), n, k)
     rng = np.random.default_rng(14)
-    noisy = lambda g: 1e9 * rng.standard_normal(g.shape)        # swamps the V-cycle result
+    noisy = lambda g: 1e9 * rng.standard_normal(g.shape)
+    # the residual-minimising factor keeps even a useless correction harmless
     x, info = L.solve(A, b, H.precondition, noisy, n, k, rtol=1e-10)
+    assert not info["fell_back"] and info["rel_res_true"] < 1e-9
+    xp, ip = L.solve(A, b, H.precondition, lambda g: np.zeros_like(g), n, k, rtol=1e-10)
+    assert info["iterations"] <= ip["iterations"] + 1
+    # a threshold no iteration can meet forces the stagnation switch
+    x, info = L.solve(A, b, H.precondition, noisy, n, k, rtol=1e-10, stagnation=1e-12)
     assert info["fell_back"] and info["rel_res_true"] < 1e-9
     bad = lambda g: np.full(g.shape, np.nan)
     x, info = L.solve(A, b, H.precondition, bad, n, k, rtol=1e-10)
