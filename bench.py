@@ -29,6 +29,10 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP16_PEAK_TFLOPS = 2500.0     # dense FP16 matrix-core peak
 BYTES_PER_DOF = 16.0          # read u, write v (FP64)
+# HBM bytes per launch of the apply kernel as profiled (FETCH_SIZE x 2 +
+# WRITE_SIZE x 1, profiles/apply_f64_wave_k3n64_k5n40_k7n32.md); set an entry
+# to None when the kernel changes until it is profiled again.
+PROFILED_TRAFFIC = {"k3_n64": 313.7e6, "k5_n40": 273.4e6, "k7_n32": 396.5e6}
 ROTATE = 4
 
 
@@ -358,7 +362,8 @@ def main():
     dom = max(per_k.items(), key=lambda kv: kv[1]["ms_per_apply"])
     dk = dom[1]
     roofline = {"bound": "hbm", "achieved": dk["hbm_gb_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(dk["hbm_gb_s"] / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(dk["hbm_gb_s"] / HBM_PEAK_GBS, 4),
+                "traffic": PROFILED_TRAFFIC.get(dom[0]),
                 "kernel": f"apply_f64_kernel ({dom[0]})",
                 "bytes_per_launch": int(dk["n_dofs"] * BYTES_PER_DOF)}
 
