@@ -153,17 +153,28 @@ __device__ __forceinline__ void wave_lds_sync() {
   asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 }
 
+// Global loads: for N >= 5 every cell the tile touches (its own and the six
+// face neighbours) is read in the coalesced z-line pattern -- lane (p, q)
+// reads nodes (p, q, a), a = 0..N-1, so consecutive lanes read consecutive
+// doubles -- and transposed into x- or y-lines through the wave's LDS
+// slice.  The staging slice is reused for the face traces once consumed
+// (8 N^2 <= 2 N^3 for N >= 4).  For N <= 4 the lanes read their lines
+// directly (measured faster at N = 4, where a line is 32 bytes).  Both
+// paths feed identical values to identical arithmetic.  (Also measured:
+// persistent waves that prefetch the next tile during the y and z stages
+// lose more to the lower occupancy than they gain.)
 template <typename T, int N, bool RES>
 __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
     Batch<T> B, const T* __restrict__ tab, TableLayout lay) {
   constexpr int N2 = N * N, N3 = N2 * N, CPB = (64 / N2) > 0 ? 64 / N2 : 1;
   constexpr int WAVES = kThreads / 64;
+  constexpr bool COAL = N >= 5;
+  constexpr int NBUF = COAL ? 2 * N3 : 8 * N2;  // per cell: staging, or ty + tz
   __shared__ T s_t1_all[WAVES * CPB * N3];
   __shared__ T s_t2_all[WAVES * CPB * N3];
   // per cell: y-face traces [face 0,1][value, derivative][i + N l] and
   // z-face traces [face 0,1][value, derivative][i + N j], raw then after Mx
-  __shared__ T s_ty_all[WAVES * CPB * 4 * N2];
-  __shared__ T s_tz_all[WAVES * CPB * 4 * N2];
+  __shared__ T s_n_all[WAVES * CPB * NBUF];
   __shared__ T s_tzm_all[WAVES * CPB * 4 * N2];
 
   const int tid = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -183,9 +194,11 @@ __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
   tm.ngroups = B.start[pb + 1] - B.start[pb];
   T* s_t1 = s_t1_all + wave * (CPB * N3);
   T* s_t2 = s_t2_all + wave * (CPB * N3);
-  T* s_ty = s_ty_all + wave * (CPB * 4 * N2);
-  T* s_tz = s_tz_all + wave * (CPB * 4 * N2);
+  T* s_ty = s_n_all + wave * (CPB * NBUF);
+  T* s_tz = s_ty + CPB * 4 * N2;
   T* s_tzm = s_tzm_all + wave * (CPB * 4 * N2);
+  T* s_n0 = s_ty;             // staging (COAL): lower neighbour, then traces
+  T* s_n1 = s_ty + CPB * N3;  //                 upper neighbour
   const int n = tm.n, nn = n * n, nc = tm.tx;
   const int c0 = tile_first_cell(tm, grp);
   const int cy = (c0 / n) % n, cz = c0 / nn, cx0 = c0 % n;
@@ -201,7 +214,59 @@ __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
   const bool hx0 = act && cx > 0, hx1 = act && cx < n - 1;
   const bool hy0 = act && cy > 0, hy1 = act && cy < n - 1;
   const bool hz0 = act && cz > 0, hz1 = act && cz < n - 1;
-  {
+  if constexpr (COAL) {
+    const T* pc = u + (size_t)c * N3 + ln;
+    const ptrdiff_t sx = N3, sy = (ptrdiff_t)n * N3, sz = (ptrdiff_t)nn * N3;
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      own[a] = act ? pc[a * N2] : 0.0;
+      xlo[a] = hx0 ? pc[a * N2 - sx] : 0.0;
+      xhi[a] = hx1 ? pc[a * N2 + sx] : 0.0;
+      ylo[a] = hy0 ? pc[a * N2 - sy] : 0.0;
+      yhi[a] = hy1 ? pc[a * N2 + sy] : 0.0;
+      zlo[a] = hz0 ? pc[a * N2 - sz] : 0.0;
+      zhi[a] = hz1 ? pc[a * N2 + sz] : 0.0;
+    }
+    // own and x-neighbours: z-lines -> x-lines (j, l) = (lp, lq)
+    const int w = cl * N3 + ln;
+    if (act) {
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        s_t1[w + a * N2] = own[a];
+        s_n0[w + a * N2] = xlo[a];
+        s_n1[w + a * N2] = xhi[a];
+      }
+    }
+    wave_lds_sync();
+    const int rx = cl * N3 + ln * N;
+    if (act) {
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        own[a] = s_t1[rx + a];
+        xlo[a] = s_n0[rx + a];
+        xhi[a] = s_n1[rx + a];
+      }
+    }
+    wave_lds_sync();
+    // y-neighbours: z-lines -> y-lines (i, l) = (lp, lq)
+    if (act) {
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        s_n0[w + a * N2] = ylo[a];
+        s_n1[w + a * N2] = yhi[a];
+      }
+    }
+    wave_lds_sync();
+    const int ry = cl * N3 + lp + lq * N2;
+    if (act) {
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        ylo[a] = s_n0[ry + a * N];
+        yhi[a] = s_n1[ry + a * N];
+      }
+    }
+    wave_lds_sync();  // the staging slice becomes the trace buffers below
+  } else {
     const T* pc = u + (size_t)c * N3;
     const T* pxl = pc - N3 + ln * N;
     const T* pxh = pc + N3 + ln * N;
