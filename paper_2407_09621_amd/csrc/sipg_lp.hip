@@ -475,6 +475,18 @@ __global__ __launch_bounds__(kThreads) void patch_fd_lp_kernel(
   const int np = min(PPB, npatch - p0);
   if (np <= 0) return;
   for (int i = tid; i < 4 * G; i += kThreads) s_l[i] = tab[lay.fd_l + i];
+  // A patch of G^2 <= 64 lines that divides 64 lives inside one wave: its
+  // waves then synchronise only with themselves after the table load.
+  constexpr bool WL = (G2 <= 64) && (64 % G2 == 0);
+  const int lane = tid & 63, wv = tid >> 6;
+  __syncthreads();
+  auto psync = [&]() {
+    if constexpr (WL) wave_lds_sync();
+    else __syncthreads();
+  };
+  const int w_lo = WL ? wv * (G2 <= 64 ? 64 / G2 : 1) * G3 : 0;
+  const int w_hi = WL ? min(np * G3, w_lo + (G2 <= 64 ? 64 / G2 : 1) * G3) : np * G3;
+  const int w_first = WL ? w_lo + lane : tid, w_step = WL ? 64 : kThreads;
   auto vertex = [&](int pl, int& vx, int& vy, int& vz) {
     const int p = p0 + pl;
     const int px = p % npx, py = (p / npx) % npy, pz = p / (npx * npy);
@@ -483,7 +495,7 @@ __global__ __launch_bounds__(kThreads) void patch_fd_lp_kernel(
     vz = 2 * pz + (bz ? 1 : 2);
   };
   const int nn = n * n;
-  for (int w = tid; w < np * G3; w += kThreads) {
+  for (int w = w_first; w < w_hi; w += w_step) {
     const int pl = w / G3, rr = w - pl * G3;
     int vx, vy, vz;
     vertex(pl, vx, vy, vz);
@@ -493,7 +505,7 @@ __global__ __launch_bounds__(kThreads) void patch_fd_lp_kernel(
     const int c = (vx - 1 + dx) + n * (vy - 1 + dy) + nn * (vz - 1 + dz);
     s_X[pl * G3 + (dx * N + i) + G * (dy * N + j) + G2 * (dz * N + l)] = r[(size_t)c * N3 + loc];
   }
-  __syncthreads();
+  psync();
 
   const bool act = tid < np * G2;
   const int pl = act ? tid / G2 : 0, ln = tid - pl * G2;
@@ -517,7 +529,7 @@ __global__ __launch_bounds__(kThreads) void patch_fd_lp_kernel(
 #pragma unroll
       for (int a = 0; a < G; ++a) X[o0 + a] = out[a];
   }
-  __syncthreads();
+  psync();
   {
     LineMV<GP, BF, EC> m;
     m.load(S + ty * G2, G, true);
@@ -528,7 +540,7 @@ __global__ __launch_bounds__(kThreads) void patch_fd_lp_kernel(
 #pragma unroll
       for (int a = 0; a < G; ++a) X[o1 + a * G] = out[a];
   }
-  __syncthreads();
+  psync();
   {
     LineMV<GP, BF, EC> mt, mf;
     mt.load(S + tz * G2, G, true);
@@ -544,7 +556,7 @@ __global__ __launch_bounds__(kThreads) void patch_fd_lp_kernel(
 #pragma unroll
       for (int a = 0; a < G; ++a) X[o2 + a * G2] = out[a];
   }
-  __syncthreads();
+  psync();
   {
     LineMV<GP, BF, EC> m;
     m.load(S + ty * G2, G, false);
@@ -555,7 +567,7 @@ __global__ __launch_bounds__(kThreads) void patch_fd_lp_kernel(
 #pragma unroll
       for (int a = 0; a < G; ++a) X[o1 + a * G] = out[a];
   }
-  __syncthreads();
+  psync();
   {
     LineMV<GP, BF, EC> m;
     m.load(S + tx * G2, G, false);
@@ -566,8 +578,8 @@ __global__ __launch_bounds__(kThreads) void patch_fd_lp_kernel(
 #pragma unroll
       for (int a = 0; a < G; ++a) X[o0 + a] = out[a];
   }
-  __syncthreads();
-  for (int w = tid; w < np * G3; w += kThreads) {
+  psync();
+  for (int w = w_first; w < w_hi; w += w_step) {
     const int q = w / G3, rr = w - q * G3;
     int ux, uy, uz;
     vertex(q, ux, uy, uz);

@@ -169,13 +169,14 @@ __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
   constexpr int N2 = N * N, N3 = N2 * N, CPB = (64 / N2) > 0 ? 64 / N2 : 1;
   constexpr int WAVES = kThreads / 64;
   constexpr bool COAL = N >= 5;
-  constexpr int NBUF = COAL ? 2 * N3 : 8 * N2;  // per cell: staging, or ty + tz
+  // per cell: t1, t2 and a region holding first (COAL) one staged neighbour
+  // cell, then the y-face traces [face 0,1][value, derivative][i + N l] and
+  // z-face traces [face 0,1][value, derivative][i + N j]; the z-traces after
+  // Mx overwrite the y-traces once those are read
+  constexpr int NR = (COAL && N3 > 8 * N2) ? N3 : 8 * N2;
   __shared__ T s_t1_all[WAVES * CPB * N3];
   __shared__ T s_t2_all[WAVES * CPB * N3];
-  // per cell: y-face traces [face 0,1][value, derivative][i + N l] and
-  // z-face traces [face 0,1][value, derivative][i + N j], raw then after Mx
-  __shared__ T s_n_all[WAVES * CPB * NBUF];
-  __shared__ T s_tzm_all[WAVES * CPB * 4 * N2];
+  __shared__ T s_r_all[WAVES * CPB * NR];
 
   const int tid = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int gi = xcd_remap(blockIdx.x, gridDim.x) * WAVES + wave;
@@ -194,11 +195,12 @@ __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
   tm.ngroups = B.start[pb + 1] - B.start[pb];
   T* s_t1 = s_t1_all + wave * (CPB * N3);
   T* s_t2 = s_t2_all + wave * (CPB * N3);
-  T* s_ty = s_n_all + wave * (CPB * NBUF);
+  T* s_ty = s_r_all + wave * (CPB * NR);
   T* s_tz = s_ty + CPB * 4 * N2;
-  T* s_tzm = s_tzm_all + wave * (CPB * 4 * N2);
-  T* s_n0 = s_ty;             // staging (COAL): lower neighbour, then traces
-  T* s_n1 = s_ty + CPB * N3;  //                 upper neighbour
+  T* s_tzm = s_ty;
+  // staging (COAL): t1 and t2 are free until the x stage writes them
+  T* s_n0 = s_t2;
+  T* s_n1 = s_ty;
   const int n = tm.n, nn = n * n, nc = tm.tx;
   const int c0 = tile_first_cell(tm, grp);
   const int cy = (c0 / n) % n, cz = c0 / nn, cx0 = c0 % n;
@@ -363,6 +365,7 @@ __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
     if (hy1) add_upper_face<N>(cc, f1, q1, gam, s_d1);
     const T* tz = s_tz + cl * 4 * N2 + lq * N;
     T* tzm = s_tzm + cl * 4 * N2 + lq * N + lp;
+    wave_lds_sync();  // every lane has read its y-traces before they are overwritten
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       T acc = 0.0;
@@ -443,6 +446,18 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
   if (np <= 0) return;
   for (int i = tid; i < 4 * G2; i += kThreads) s_S[i] = tab[lay.fd_s + i];
   for (int i = tid; i < 4 * G; i += kThreads) s_l[i] = tab[lay.fd_l + i];
+  // A patch of G^2 <= 64 lines that divides 64 lives inside one wave: its
+  // waves then synchronise only with themselves after the table load.
+  constexpr bool WL = (G2 <= 64) && (64 % G2 == 0);
+  const int lane = tid & 63, wv = tid >> 6;
+  __syncthreads();
+  auto psync = [&]() {
+    if constexpr (WL) wave_lds_sync();
+    else __syncthreads();
+  };
+  const int w_lo = WL ? wv * (G2 <= 64 ? 64 / G2 : 1) * G3 : 0;
+  const int w_hi = WL ? min(np * G3, w_lo + (G2 <= 64 ? 64 / G2 : 1) * G3) : np * G3;
+  const int w_first = WL ? w_lo + lane : tid, w_step = WL ? 64 : kThreads;
 
   // vertex of a patch and its first cell
   auto vertex = [&](int pl, int& vx, int& vy, int& vz) {
@@ -454,7 +469,7 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
   };
   const int nn = n * n;
   // gather r_P
-  for (int w = tid; w < np * G3; w += kThreads) {
+  for (int w = w_first; w < w_hi; w += w_step) {
     const int pl = w / G3, rr = w - pl * G3;
     int vx, vy, vz;
     vertex(pl, vx, vy, vz);
@@ -464,7 +479,7 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
     const int c = (vx - 1 + dx) + n * (vy - 1 + dy) + nn * (vz - 1 + dz);
     s_X[pl * G3 + (dx * N + i) + G * (dy * N + j) + G2 * (dz * N + l)] = r[(size_t)c * N3 + loc];
   }
-  __syncthreads();
+  psync();
 
   const bool act = tid < np * G2;
   const int pl = act ? tid / G2 : 0, ln = tid - pl * G2;
@@ -486,7 +501,7 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
 #pragma unroll
     for (int a = 0; a < G; ++a) X[o0 + a] = out[a];
   }
-  __syncthreads();
+  psync();
   if (act) {
 #pragma unroll
     for (int a = 0; a < G; ++a) in[a] = X[o1 + a * G];
@@ -494,7 +509,7 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
 #pragma unroll
     for (int a = 0; a < G; ++a) X[o1 + a * G] = out[a];
   }
-  __syncthreads();
+  psync();
   if (act) {
 #pragma unroll
     for (int a = 0; a < G; ++a) in[a] = X[o2 + a * G2];
@@ -507,7 +522,7 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
 #pragma unroll
     for (int a = 0; a < G; ++a) X[o2 + a * G2] = out[a];
   }
-  __syncthreads();
+  psync();
   if (act) {
 #pragma unroll
     for (int a = 0; a < G; ++a) in[a] = X[o1 + a * G];
@@ -515,7 +530,7 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
 #pragma unroll
     for (int a = 0; a < G; ++a) X[o1 + a * G] = out[a];
   }
-  __syncthreads();
+  psync();
   if (act) {
 #pragma unroll
     for (int a = 0; a < G; ++a) in[a] = X[o0 + a];
@@ -523,9 +538,9 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
 #pragma unroll
     for (int a = 0; a < G; ++a) X[o0 + a] = out[a];
   }
-  __syncthreads();
+  psync();
   // scatter-add into x
-  for (int w = tid; w < np * G3; w += kThreads) {
+  for (int w = w_first; w < w_hi; w += w_step) {
     const int q = w / G3, rr = w - q * G3;
     int ux, uy, uz;
     vertex(q, ux, uy, uz);
