@@ -47,6 +47,11 @@ hipError_t launch_restrict_f32(int N, const float* rf, float* rc, const DevTab& 
 hipError_t launch_prolongate_add_f32(int N, const float* ec, float* xf, const DevTab& t, int nc,
                                      hipStream_t s);
 
+// FP64 apply of degree 3 on the matrix cores (one wave per cell); same
+// contract as launch_apply_batch with prec 0 and N = 4.
+hipError_t launch_apply_mfma4_batch(const ApplyJob* jobs, int count, const DevTab& t,
+                                    hipStream_t s);
+
 // Batched forms: up to kMaxBatch problems of one degree per launch.
 // prec 0 = FP64 vectors, 1 = FP32 vectors (VALU arithmetic).
 hipError_t launch_apply_batch(int prec, int N, const ApplyJob* jobs, int count, const DevTab& t,

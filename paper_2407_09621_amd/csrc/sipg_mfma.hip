@@ -1,0 +1,213 @@
+// FP64 SIPG operator apply on the matrix cores for degree 3 (N = 4).
+//
+// A cell of degree 3 holds 64 coefficients: one per lane of a wave, in the
+// natural order i + 4 j + 16 l.  v_mfma_f64_4x4x4f64 computes four 4x4x4
+// products at once; its operands put the contraction index k at lane bits
+// 4-5 (A[b][i][k] at lane 16k + 4b + i, B[b][k][j] at lane 16k + 4b + j) and
+// its result D[b][i][j] at lane 16i + 4b + j.  So a 1D matrix Q applied
+// along the direction stored in lane bits 4-5 is ONE instruction whose
+// output keeps the layout, with the contracted index replaced by the row
+// index.  Three layouts put each direction at bits 4-5:
+//   Z (natural): x at bits 0-1, y at 2-3, z at 4-5
+//   X          : z at bits 0-1, y at 2-3, x at 4-5
+//   Y          : x at bits 0-1, z at 2-3, y at 4-5
+// and one ds_bpermute per 32-bit half moves a value between them.
+//
+// The operator (Sec. 2.1, eq. tensorproduct_3d) with the block-tridiagonal
+// 1D matrices written out per cell:
+//   v = h [ Mz My Lx~ u + Mz Mx Ly~ u + My Mx Lz~ u ],
+//   Ld~ u = Lcc u_c + Lrl u_{c-e_d} + Llr u_{c+e_d}
+// where Lcc is the cell block (by boundary type) and Lrl, Llr are the
+// rank-2 couplings to the lower and upper face neighbour (Sec. 2.1's face
+// evaluators folded into 4x4 blocks).  Every term is a 4x4 contraction:
+// 9 products for the three Ld~ (own cell and two neighbours each), 5 for
+// the mass factors; about 14 permutations.  Loads and stores are coalesced
+// 512-byte lines, one per cell.
+#include <hip/hip_runtime.h>
+
+#include "batch.h"
+#include "kernels.h"
+
+namespace sipg {
+
+namespace {
+
+constexpr int kT = 256;  // 4 waves, one cell each
+
+__device__ __forceinline__ double mma(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
+
+// value of `v` held by lane `src`
+__device__ __forceinline__ double gather(double v, int src) {
+  const int addr = src << 2;
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+// A operand of a 4x4 matrix Q (row-major at q): lane 16k + 4b + i holds Q[i][k]
+__device__ __forceinline__ double a_operand(const double* __restrict__ q, int lane) {
+  return q[(lane & 3) * 4 + (lane >> 4)];
+}
+
+__device__ __forceinline__ int xcd_remap4(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
+  return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// cell index of work item t: x fastest, then (z, y) in blk x blk blocks
+__device__ __forceinline__ int cell_of(int t, int n, int blk) {
+  const int cx = t % n;
+  int r = t / n, cy, cz;
+  if (blk > 1) {
+    const int zi = r % blk;
+    r /= blk;
+    const int yi = r % blk;
+    r /= blk;
+    const int nb = n / blk;
+    cz = (r % nb) * blk + zi;
+    cy = (r / nb) * blk + yi;
+  } else {
+    cy = r % n;
+    cz = r / n;
+  }
+  return (cz * n + cy) * n + cx;
+}
+
+// One wave owns CPW consecutive cells of an x-row: their dependency chains
+// (load, permute, product, permute, ...) are independent and interleave,
+// and the x-neighbours inside the row come from registers.
+template <bool RES, int CPW>
+__global__ __launch_bounds__(kT) void apply_mfma4_kernel(Batch<double> B,
+                                                         const double* __restrict__ tab,
+                                                         TableLayout lay) {
+  const int lane = threadIdx.x & 63;
+  const int gi = xcd_remap4(blockIdx.x, gridDim.x) * (kT / 64) + (threadIdx.x >> 6);
+  if (gi >= B.start[B.count]) return;  // wave-uniform; no barriers in this kernel
+  const int pb = batch_find(B, gi);
+  const double* __restrict__ u = B.d[pb].in;
+  double* __restrict__ v = B.d[pb].out;
+  const double* __restrict__ bv = B.d[pb].aux;
+  const double h = B.d[pb].h;
+  const int n = B.d[pb].n, nn = n * n;
+  // tile t covers cells c0 .. c0 + CPW - 1 along x
+  const int t = gi - B.start[pb];
+  const int ntx = n / CPW;
+  const int c0 = cell_of(t / ntx * n + (t % ntx) * CPW, n, B.d[pb].a2);
+  const int cx0 = c0 % n, cy = (c0 / n) % n, cz = c0 / nn;
+
+  // ---- loads (natural layout): the row's cells, the two row ends' outer
+  // x-neighbours, and each cell's y and z neighbours
+  const double* pc = u + (size_t)c0 * 64 + lane;
+  double u0[CPW], uym[CPW], uyp[CPW], uzm[CPW], uzp[CPW], b0[CPW];
+#pragma unroll
+  for (int q = 0; q < CPW; ++q) {
+    u0[q] = pc[q * 64];
+    uym[q] = cy > 0 ? pc[q * 64 - (ptrdiff_t)n * 64] : 0.0;
+    uyp[q] = cy < n - 1 ? pc[q * 64 + (ptrdiff_t)n * 64] : 0.0;
+    uzm[q] = cz > 0 ? pc[q * 64 - (ptrdiff_t)nn * 64] : 0.0;
+    uzp[q] = cz < n - 1 ? pc[q * 64 + (ptrdiff_t)nn * 64] : 0.0;
+    b0[q] = RES ? bv[(size_t)(c0 + q) * 64 + lane] : 0.0;
+  }
+  const double uxm0 = cx0 > 0 ? pc[-64] : 0.0;
+  const double uxpE = cx0 + CPW < n ? pc[CPW * 64] : 0.0;
+
+  // ---- A operands (uniform tables)
+  auto var = [&](int q) { return (q == 0 ? 1 : 0) | (q == n - 1 ? 2 : 0); };
+  const double aM = a_operand(tab + lay.mass, lane);
+  const double aLy = a_operand(tab + lay.lcell + var(cy) * 16, lane);
+  const double aLz = a_operand(tab + lay.lcell + var(cz) * 16, lane);
+  const double aRL = a_operand(tab + lay.rl, lane);  // coupling to the lower neighbour
+  const double aLR = a_operand(tab + lay.lr, lane);  // coupling to the upper neighbour
+  const double aLi = a_operand(tab + lay.lcell, lane);             // interior x block
+  const double aL0 = a_operand(tab + lay.lcell + var(cx0) * 16, lane);
+  const double aL1 = a_operand(tab + lay.lcell + var(cx0 + CPW - 1) * 16, lane);
+
+  // lane sources of the layout changes (all are permutations of bit pairs)
+  const int p0 = lane & 3, p1 = (lane >> 2) & 3, p2 = lane >> 4;
+  const int sZX = p2 | (p1 << 2) | (p0 << 4);  // Z <-> X (swap pairs 0 and 2)
+  const int sZY = p0 | (p2 << 2) | (p1 << 4);  // Z <-> Y (swap pairs 1 and 2)
+  const int sXY = p1 | (p2 << 2) | (p0 << 4);  // X -> Y
+  const int sYX = p2 | (p0 << 2) | (p1 << 4);  // Y -> X
+
+  double ux[CPW + 2];  // the row in X layout with its outer neighbours
+  ux[0] = gather(uxm0, sZX);
+#pragma unroll
+  for (int q = 0; q < CPW; ++q) ux[q + 1] = gather(u0[q], sZX);
+  ux[CPW + 1] = gather(uxpE, sZX);
+
+#pragma unroll
+  for (int q = 0; q < CPW; ++q) {
+    // Lz~ u in Z, then Mx (in X), then My (in Y), back to Z
+    double z1 = mma(aLz, u0[q], 0.0);
+    z1 = mma(aRL, uzm[q], z1);
+    z1 = mma(aLR, uzp[q], z1);
+    double t3 = mma(aM, gather(z1, sZX), 0.0);
+    t3 = mma(aM, gather(t3, sXY), 0.0);
+    t3 = gather(t3, sZY);
+    // Lx~ u in X, then My in Y
+    const double aLx = (q == 0) ? aL0 : ((q == CPW - 1) ? aL1 : aLi);
+    double x1 = mma(aLx, ux[q + 1], 0.0);
+    x1 = mma(aRL, ux[q], x1);
+    x1 = mma(aLR, ux[q + 2], x1);
+    const double s1 = mma(aM, gather(x1, sXY), 0.0);
+    // Ly~ u in Y, then Mx in X
+    double y1 = mma(aLy, gather(u0[q], sZY), 0.0);
+    y1 = mma(aRL, gather(uym[q], sZY), y1);
+    y1 = mma(aLR, gather(uyp[q], sZY), y1);
+    const double s2 = mma(aM, gather(y1, sYX), 0.0);
+    // Mz (My Lx~ u + Mx Ly~ u) in Z
+    const double o = mma(aM, gather(s1, sZY) + gather(s2, sZX), t3);
+    double* dst = v + (size_t)(c0 + q) * 64 + lane;
+    if (RES) *dst = b0[q] - h * o;
+    else *dst = h * o;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_apply_mfma4_batch(const ApplyJob* jobs, int count, const DevTab& t,
+                                    hipStream_t s) {
+  if (t.lay.N != 4 || count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
+  Batch<double> B;
+  const bool residual = jobs[0].b != nullptr;
+  // cells per wave: 4 when every mesh of the launch allows it, else 2 or 1
+  int cpw = 4;
+  for (int i = 0; i < count; ++i)
+    while (cpw > 1 && jobs[i].n % cpw) cpw >>= 1;
+  B.count = count;
+  B.start[0] = 0;
+  for (int i = 0; i < count; ++i) {
+    const ApplyJob& j = jobs[i];
+    if (j.n < 1 || j.n > 1024 || !j.u || !j.v || (j.b != nullptr) != residual)
+      return hipErrorInvalidValue;
+    Desc<double>& d = B.d[i];
+    d.in = (const double*)j.u;
+    d.out = (double*)j.v;
+    d.aux = (const double*)j.b;
+    d.h = j.h;
+    d.n = j.n;
+    d.a0 = cpw;
+    d.a1 = j.n / cpw;
+    d.a2 = (j.order > 0 && j.n % j.order == 0) ? j.order : ((j.n % 8 == 0) ? 8 : 1);
+    const int64_t items = (int64_t)j.n * j.n * (j.n / cpw);
+    if (B.start[i] + items > 0x7fffffff) return hipErrorInvalidValue;
+    B.start[i + 1] = B.start[i] + (int)items;
+  }
+  const int grid = (B.start[count] + kT / 64 - 1) / (kT / 64);
+  if (grid == 0) return hipSuccess;
+#define LAUNCH(RR, CC) \
+  hipLaunchKernelGGL((apply_mfma4_kernel<RR, CC>), dim3(grid), dim3(kT), 0, s, B, t.tab, t.lay)
+  if (cpw == 4) {
+    if (residual) LAUNCH(true, 4); else LAUNCH(false, 4);
+  } else if (cpw == 2) {
+    if (residual) LAUNCH(true, 2); else LAUNCH(false, 2);
+  } else {
+    if (residual) LAUNCH(true, 1); else LAUNCH(false, 1);
+  }
+#undef LAUNCH
+  return hipGetLastError();
+}
+
+}  // namespace sipg

@@ -326,6 +326,8 @@ std::vector<double> build_device_table(int k, int n0, TableLayout& lay) {
   lay.fdc_s = take(Gc * Gc);
   lay.fdc_l = take(Gc);
   lay.p1 = take(2 * N * N);
+  lay.lr = take(N * N);
+  lay.rl = take(N * N);
   lay.total = off;
   std::vector<double> tab(off, 0.0);
   for (int i = 0; i < N * N; ++i) tab[lay.mass + i] = t.mass[i];
@@ -334,6 +336,10 @@ std::vector<double> build_device_table(int k, int n0, TableLayout& lay) {
   for (int a = 0; a < N; ++a) {
     tab[lay.d0 + a] = t.d0[a];
     tab[lay.d1 + a] = t.d1[a];
+  }
+  for (int i = 0; i < N * N; ++i) {
+    tab[lay.lr + i] = t.lr[i];
+    tab[lay.rl + i] = t.rl[i];
   }
   tab[lay.gam] = t.gamma_hat;
   std::vector<double> Lm, Mm, S, lam;

@@ -28,6 +28,8 @@ struct TableLayout {
   int fdc_s = 0;  // coarse eigenvectors [Gc x Gc]
   int fdc_l = 0;  // coarse eigenvalues [Gc]
   int p1 = 0;     // 1D prolongation [2N x N]: row (child c, node a), column b
+  int lr = 0;     // Lh off-diagonal block L_{c,c+1} [N x N] (coupling to the upper cell)
+  int rl = 0;     // Lh off-diagonal block L_{c+1,c} [N x N] (coupling to the lower cell)
   int mass_f = 0; // float copies for the FP32 path start here (same order)
   int total = 0;
 };
