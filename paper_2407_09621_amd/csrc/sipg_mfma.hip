@@ -173,7 +173,7 @@ hipError_t launch_apply_mfma4_batch(const ApplyJob* jobs, int count, const DevTa
   Batch<double> B;
   const bool residual = jobs[0].b != nullptr;
   // cells per wave: 4 when every mesh of the launch allows it, else 2 or 1
-  int cpw = 4;
+  int cpw = 8;
   for (int i = 0; i < count; ++i)
     while (cpw > 1 && jobs[i].n % cpw) cpw >>= 1;
   B.count = count;
@@ -199,7 +199,9 @@ hipError_t launch_apply_mfma4_batch(const ApplyJob* jobs, int count, const DevTa
   if (grid == 0) return hipSuccess;
 #define LAUNCH(RR, CC) \
   hipLaunchKernelGGL((apply_mfma4_kernel<RR, CC>), dim3(grid), dim3(kT), 0, s, B, t.tab, t.lay)
-  if (cpw == 4) {
+  if (cpw == 8) {
+    if (residual) LAUNCH(true, 8); else LAUNCH(false, 8);
+  } else if (cpw == 4) {
     if (residual) LAUNCH(true, 4); else LAUNCH(false, 4);
   } else if (cpw == 2) {
     if (residual) LAUNCH(true, 2); else LAUNCH(false, 2);
