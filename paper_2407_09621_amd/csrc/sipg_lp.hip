@@ -479,7 +479,6 @@ __global__ __launch_bounds__(kThreads) void patch_fd_lp_kernel(
   // waves then synchronise only with themselves after the table load.
   constexpr bool WL = (G2 <= 64) && (64 % G2 == 0);
   const int lane = tid & 63, wv = tid >> 6;
-  __syncthreads();
   auto psync = [&]() {
     if constexpr (WL) wave_lds_sync();
     else __syncthreads();
@@ -495,14 +494,21 @@ __global__ __launch_bounds__(kThreads) void patch_fd_lp_kernel(
     vz = 2 * pz + (bz ? 1 : 2);
   };
   const int nn = n * n;
+  // first cell of each patch of the block, computed once per patch (the
+  // gather and scatter loops below then divide only by compile-time sizes)
+  __shared__ int s_cb[PPB];
+  for (int q = tid; q < np; q += kThreads) {
+    int vx, vy, vz;
+    vertex(q, vx, vy, vz);
+    s_cb[q] = (vx - 1) + n * (vy - 1) + nn * (vz - 1);
+  }
+  __syncthreads();
   for (int w = w_first; w < w_hi; w += w_step) {
     const int pl = w / G3, rr = w - pl * G3;
-    int vx, vy, vz;
-    vertex(pl, vx, vy, vz);
     const int cell8 = rr / N3, loc = rr - cell8 * N3;
     const int dx = cell8 & 1, dy = (cell8 >> 1) & 1, dz = cell8 >> 2;
     const int i = loc % N, j = (loc / N) % N, l = loc / N2;
-    const int c = (vx - 1 + dx) + n * (vy - 1 + dy) + nn * (vz - 1 + dz);
+    const int c = s_cb[pl] + dx + n * dy + nn * dz;
     s_X[pl * G3 + (dx * N + i) + G * (dy * N + j) + G2 * (dz * N + l)] = r[(size_t)c * N3 + loc];
   }
   psync();
@@ -581,12 +587,10 @@ __global__ __launch_bounds__(kThreads) void patch_fd_lp_kernel(
   psync();
   for (int w = w_first; w < w_hi; w += w_step) {
     const int q = w / G3, rr = w - q * G3;
-    int ux, uy, uz;
-    vertex(q, ux, uy, uz);
     const int cell8 = rr / N3, loc = rr - cell8 * N3;
     const int dx = cell8 & 1, dy = (cell8 >> 1) & 1, dz = cell8 >> 2;
     const int i = loc % N, j = (loc / N) % N, l = loc / N2;
-    const int c = (ux - 1 + dx) + n * (uy - 1 + dy) + nn * (uz - 1 + dz);
+    const int c = s_cb[q] + dx + n * dy + nn * dz;
     x[(size_t)c * N3 + loc] += s_X[q * G3 + (dx * N + i) + G * (dy * N + j) + G2 * (dz * N + l)];
   }
 }
