@@ -51,6 +51,9 @@ hipError_t launch_prolongate_add_f32(int N, const float* ec, float* xf, const De
 // contract as launch_apply_batch with prec 0 and N = 4.
 hipError_t launch_apply_mfma4_batch(const ApplyJob* jobs, int count, const DevTab& t,
                                     hipStream_t s);
+// FP64 apply of degree 7 on the matrix cores (one cell per wave)
+hipError_t launch_apply_mfma8_batch(const ApplyJob* jobs, int count, const DevTab& t,
+                                    hipStream_t s);
 
 // Batched forms: up to kMaxBatch problems of one degree per launch.
 // prec 0 = FP64 vectors, 1 = FP32 vectors (VALU arithmetic).

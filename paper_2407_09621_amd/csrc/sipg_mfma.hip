@@ -32,7 +32,7 @@ namespace sipg {
 
 namespace {
 
-constexpr int kT = 256;  // 4 waves, one cell each
+constexpr int kT = 256;  // 4 waves per workgroup
 
 __device__ __forceinline__ double mma(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
@@ -165,6 +165,201 @@ __global__ __launch_bounds__(kT) void apply_mfma4_kernel(Batch<double> B,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Degree 7 (N = 8): 512 coefficients per cell, 8 per lane.  Each direction's
+// index d = d_lo + 4 d_hi has d_lo in a lane-bit pair and d_hi in a register
+// bit; register r holds (x_hi, y_hi, z_hi) = (r & 1, r >> 1 & 1, r >> 2) in
+// every layout, and a layout (a, b, c) names the directions at lane bit pairs
+// 0-1, 2-3 and 4-5.  An 8x8 matrix along the direction c is four 4x4 blocks:
+// output half o of register r collects the blocks (o, 0) and (o, 1) applied
+// to the two registers that differ from r in that direction's hi bit.
+//
+// Two forms of the product:
+//   normal:  A = block, B = data (c at bits 4-5); the layout is unchanged.
+//   swapped: A = data, B = block transposed; the result holds the new c index
+//            at bits 0-1 and the old bits 0-1 direction at bits 4-5, so the
+//            layout (a, b, c) becomes (c, b, a) at no cost.
+// A block of a row-major matrix has the same lane pattern in both roles
+// (lane 16k + 4b + i holds Q[i][k] as A, Q[j][k] as B for j = i).
+//
+// Global loads are fastest with x in lane bits 0-1 (four lanes read 32
+// contiguous bytes), so every cell is read in (x, y, z) or (x, z, y) and the
+// layouts that put x at bits 4-5 are made in registers (ds_bpermute):
+//   t3 = My Mx Lz~ u:  (x,y,z) -Lz~ swapped-> (z,y,x) -Mx-> (z,y,x)
+//                       -permute-> (z,x,y) -My swapped-> (y,x,z)
+//   s1 = My Lx~ u:      (x,y,z) -permute-> (y,z,x) -Lx~ swapped-> (x,z,y)
+//                       -My swapped-> (y,z,x)
+//   s2 = Mx Ly~ u:      (x,z,y) -Ly~ swapped-> (y,z,x) -Mx-> (y,z,x)
+//   v  = h [Mz (s1 + s2) + t3]: (y,z,x) -permute-> (y,x,z) -Mz, plus t3->
+//        (y,x,z) -permute-> (x,y,z), stored
+// 224 products and seven layout changes per cell, one cell per wave.
+
+// lane offset of the coefficient (lo bits only) for a layout whose lane bit
+// pairs hold the directions with strides s0, s1, s2 (1, 8 or 64)
+__device__ __forceinline__ int lane_off8(int lane, int s0, int s1, int s2) {
+  return (lane & 3) * s0 + ((lane >> 2) & 3) * s1 + (lane >> 4) * s2;
+}
+
+// register offset of the hi bits: x_hi * 4 + y_hi * 32 + z_hi * 256
+__host__ __device__ constexpr int reg_off8(int r) {
+  return (r & 1) * 4 + ((r >> 1) & 1) * 32 + (r >> 2) * 256;
+}
+
+// block (o, i) of a row-major 8x8 matrix as an MFMA operand
+__device__ __forceinline__ double blk8(const double* __restrict__ q, int o, int i, int lane) {
+  return q[(4 * o + (lane & 3)) * 8 + 4 * i + (lane >> 4)];
+}
+
+// register r with the hi bit of direction bit `db` set to i
+__host__ __device__ constexpr int with_hi(int r, int db, int i) {
+  return (r & ~(1 << db)) | (i << db);
+}
+
+struct Op8 {
+  double b[2][2];  // blocks (o, i)
+};
+
+__device__ __forceinline__ Op8 load_op8(const double* __restrict__ q, int lane) {
+  Op8 m;
+  m.b[0][0] = blk8(q, 0, 0, lane);
+  m.b[0][1] = blk8(q, 0, 1, lane);
+  m.b[1][0] = blk8(q, 1, 0, lane);
+  m.b[1][1] = blk8(q, 1, 1, lane);
+  return m;
+}
+
+// y[r] (+)= Q along direction bit DB, normal form (matrix is A)
+template <int DB>
+__device__ __forceinline__ void mul_normal(const Op8& Q, const double* x, double* y, bool acc) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int o = (r >> DB) & 1;
+    double c = acc ? y[r] : 0.0;
+    c = mma(Q.b[o][0], x[with_hi(r, DB, 0)], c);
+    c = mma(Q.b[o][1], x[with_hi(r, DB, 1)], c);
+    y[r] = c;
+  }
+}
+
+// y[r] (+)= Q along direction bit DB, swapped form (data is A)
+template <int DB>
+__device__ __forceinline__ void mul_swapped(const Op8& Q, const double* x, double* y, bool acc) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int o = (r >> DB) & 1;
+    double c = acc ? y[r] : 0.0;
+    c = mma(x[with_hi(r, DB, 0)], Q.b[o][0], c);
+    c = mma(x[with_hi(r, DB, 1)], Q.b[o][1], c);
+    y[r] = c;
+  }
+}
+
+// the 8 registers of a cell at q (layout offset included)
+__device__ __forceinline__ void load8(const double* __restrict__ q, double* a) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) a[r] = q[reg_off8(r)];
+}
+
+__device__ __forceinline__ void zero_if(bool z, double* a) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) a[r] = z ? 0.0 : a[r];
+}
+
+__device__ __forceinline__ void permute8(const double* a, double* b, int src) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) b[r] = gather(a[r], src);
+}
+
+template <bool RES>
+__global__ __launch_bounds__(kT) void apply_mfma8_kernel(Batch<double> B,
+                                                       const double* __restrict__ tab,
+                                                       TableLayout lay) {
+  const int lane = threadIdx.x & 63;
+  const int gi = __builtin_amdgcn_readfirstlane(blockIdx.x * (kT / 64) + (threadIdx.x >> 6));
+  if (gi >= B.start[B.count]) return;  // wave-uniform; no barriers in this kernel
+  const int pb = batch_find(B, gi);
+  const double* __restrict__ u = B.d[pb].in;
+  double* __restrict__ v = B.d[pb].out;
+  const double* __restrict__ bv = B.d[pb].aux;
+  const double h = B.d[pb].h;
+  const int n = B.d[pb].n, nn = n * n;
+  const int c = cell_of(gi - B.start[pb], n, B.d[pb].a2);
+  const int cx = c % n, cy = (c / n) % n, cz = c / nn;
+  auto var = [&](int q) { return (q == 0 ? 1 : 0) | (q == n - 1 ? 2 : 0); };
+
+  const int oXYZ = lane_off8(lane, 1, 8, 64);
+  const int oXZY = lane_off8(lane, 1, 64, 8);
+  // sources of the layout changes: (x,y,z) -> (y,z,x); exchange of pairs 1
+  // and 2 (an involution); exchange of pairs 0 and 1
+  const int p0 = lane & 3, p1 = (lane >> 2) & 3, p2 = lane >> 4;
+  const int sToX = p2 | (p0 << 2) | (p1 << 4);
+  const int s12 = p0 | (p2 << 2) | (p1 << 4);
+  const int s01 = p1 | (p0 << 2) | (p2 << 4);
+  const double* pc = u + (size_t)c * 512;
+  const ptrdiff_t sx = 512, sy = (ptrdiff_t)n * 512, sz = (ptrdiff_t)nn * 512;
+
+  const Op8 M = load_op8(tab + lay.mass, lane);
+  const Op8 RL = load_op8(tab + lay.rl, lane);  // coupling to the lower neighbour
+  const Op8 LR = load_op8(tab + lay.lr, lane);  // coupling to the upper neighbour
+
+  // All loads are unconditional (a missing neighbour reads the cell itself
+  // and is zeroed after the load), so they form one basic block that the
+  // compiler may schedule ahead of the products.
+  double u0[8], zm[8], zp[8], xm[8], xp[8], ym[8], yp[8];
+  load8(pc + oXYZ, u0);
+  load8(pc + oXYZ + (cz > 0 ? -sz : 0), zm);
+  load8(pc + oXYZ + (cz < n - 1 ? sz : 0), zp);
+  load8(pc + oXYZ + (cx > 0 ? -sx : 0), xm);
+  load8(pc + oXYZ + (cx < n - 1 ? sx : 0), xp);
+  load8(pc + oXZY + (cy > 0 ? -sy : 0), ym);
+  load8(pc + oXZY + (cy < n - 1 ? sy : 0), yp);
+  zero_if(cz == 0, zm);
+  zero_if(cz == n - 1, zp);
+  zero_if(cx == 0, xm);
+  zero_if(cx == n - 1, xp);
+  zero_if(cy == 0, ym);
+  zero_if(cy == n - 1, yp);
+
+  double t3[8], w[8], s[8], a[8];
+  {  // t3 = My Mx Lz~ u
+    const Op8 Lz = load_op8(tab + lay.lcell + var(cz) * 64, lane);
+    mul_swapped<2>(Lz, u0, w, false);
+    mul_swapped<2>(RL, zm, w, true);
+    mul_swapped<2>(LR, zp, w, true);  // (z, y, x)
+    mul_normal<0>(M, w, a, false);    // Mx
+    permute8(a, w, s12);              // (z, x, y)
+    mul_swapped<1>(M, w, t3, false);  // My -> (y, x, z)
+  }
+  {  // s1 = My Lx~ u
+    const Op8 Lx = load_op8(tab + lay.lcell + var(cx) * 64, lane);
+    permute8(u0, a, sToX);            // (y, z, x)
+    mul_swapped<0>(Lx, a, w, false);
+    permute8(xm, a, sToX);
+    mul_swapped<0>(RL, a, w, true);
+    permute8(xp, a, sToX);
+    mul_swapped<0>(LR, a, w, true);   // (x, z, y)
+    mul_swapped<1>(M, w, s, false);   // My -> (y, z, x)
+  }
+  {  // s2 = Mx Ly~ u, added to s1
+    const Op8 Ly = load_op8(tab + lay.lcell + var(cy) * 64, lane);
+    permute8(u0, a, s12);             // (x, z, y)
+    mul_swapped<1>(Ly, a, w, false);
+    mul_swapped<1>(RL, ym, w, true);
+    mul_swapped<1>(LR, yp, w, true);  // (y, z, x)
+    mul_normal<0>(M, w, s, true);     // Mx
+  }
+  permute8(s, w, s12);                // (y, x, z)
+  mul_normal<2>(M, w, t3, true);      // Mz, (y, x, z)
+  double* dst = v + (size_t)c * 512 + oXYZ;
+  const double* bsrc = RES ? bv + (size_t)c * 512 + oXYZ : nullptr;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const double o = h * gather(t3[r], s01);  // (x, y, z)
+    if (RES) dst[reg_off8(r)] = bsrc[reg_off8(r)] - o;
+    else dst[reg_off8(r)] = o;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_apply_mfma4_batch(const ApplyJob* jobs, int count, const DevTab& t,
@@ -172,7 +367,7 @@ hipError_t launch_apply_mfma4_batch(const ApplyJob* jobs, int count, const DevTa
   if (t.lay.N != 4 || count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
   Batch<double> B;
   const bool residual = jobs[0].b != nullptr;
-  // cells per wave: 4 when every mesh of the launch allows it, else 2 or 1
+  // cells per wave: 8 when every mesh of the launch allows it, else 4, 2 or 1
   int cpw = 8;
   for (int i = 0; i < count; ++i)
     while (cpw > 1 && jobs[i].n % cpw) cpw >>= 1;
@@ -209,6 +404,43 @@ hipError_t launch_apply_mfma4_batch(const ApplyJob* jobs, int count, const DevTa
     if (residual) LAUNCH(true, 1); else LAUNCH(false, 1);
   }
 #undef LAUNCH
+  return hipGetLastError();
+}
+
+}  // namespace sipg
+
+namespace sipg {
+
+hipError_t launch_apply_mfma8_batch(const ApplyJob* jobs, int count, const DevTab& t,
+                                    hipStream_t s) {
+  if (t.lay.N != 8 || count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
+  Batch<double> B;
+  const bool residual = jobs[0].b != nullptr;
+  B.count = count;
+  B.start[0] = 0;
+  for (int i = 0; i < count; ++i) {
+    const ApplyJob& j = jobs[i];
+    if (j.n < 1 || j.n > 1024 || !j.u || !j.v || (j.b != nullptr) != residual)
+      return hipErrorInvalidValue;
+    Desc<double>& d = B.d[i];
+    d.in = (const double*)j.u;
+    d.out = (double*)j.v;
+    d.aux = (const double*)j.b;
+    d.h = j.h;
+    d.n = j.n;
+    d.a0 = 1;
+    d.a1 = j.n;
+    d.a2 = (j.order > 0 && j.n % j.order == 0) ? j.order : 1;
+    const int64_t items = (int64_t)j.n * j.n * j.n;
+    if (B.start[i] + items > 0x7fffffff) return hipErrorInvalidValue;
+    B.start[i + 1] = B.start[i] + (int)items;
+  }
+  const int grid = (B.start[count] + kT / 64 - 1) / (kT / 64);
+  if (grid == 0) return hipSuccess;
+  if (residual)
+    hipLaunchKernelGGL((apply_mfma8_kernel<true>), dim3(grid), dim3(kT), 0, s, B, t.tab, t.lay);
+  else
+    hipLaunchKernelGGL((apply_mfma8_kernel<false>), dim3(grid), dim3(kT), 0, s, B, t.tab, t.lay);
   return hipGetLastError();
 }
 
