@@ -30,9 +30,12 @@ FP64_PEAK_TFLOPS = 78.6
 FP16_PEAK_TFLOPS = 2500.0     # dense FP16 matrix-core peak
 BYTES_PER_DOF = 16.0          # read u, write v (FP64)
 # HBM bytes per launch of the apply kernel as profiled (FETCH_SIZE x 2 +
-# WRITE_SIZE x 1, profiles/apply_f64_wave_k3n64_k5n40_k7n32.md); set an entry
+# WRITE_SIZE x 1, profiles/apply_f64_k3n64_k5n40_k7n32.md); set an entry
 # to None when the kernel changes until it is profiled again.
-PROFILED_TRAFFIC = {"k3_n64": 313.2e6, "k5_n40": 273.4e6, "k7_n32": 400.4e6}
+PROFILED_TRAFFIC = {"k3_n64": 313.3e6, "k5_n40": 273.4e6, "k7_n32": 327.3e6}
+# the kernel each benchmark degree runs (FP64 apply)
+APPLY_KERNEL = {"k3_n64": "apply_mfma4_kernel", "k5_n40": "apply_wave_kernel",
+                "k7_n32": "apply_mfma8_kernel"}
 ROTATE = 4
 
 
@@ -364,8 +367,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": dk["hbm_gb_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dk["hbm_gb_s"] / HBM_PEAK_GBS, 4),
                 "traffic": PROFILED_TRAFFIC.get(dom[0]),
-                "kernel": ("apply_mfma4_kernel" if dom[0] == "k3_n64" else "apply_wave_kernel")
-                          + f" ({dom[0]})",
+                "kernel": APPLY_KERNEL[dom[0]] + f" ({dom[0]})",
                 "bytes_per_launch": int(dk["n_dofs"] * BYTES_PER_DOF)}
 
     lp_rates = lp_apply_rates(probs, stream, max(10, args.steps // 4))

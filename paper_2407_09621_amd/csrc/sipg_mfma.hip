@@ -1,17 +1,17 @@
-// FP64 SIPG operator apply on the matrix cores for degree 3 (N = 4).
+// FP64 SIPG operator apply on the matrix cores for degrees 3 (N = 4) and
+// 7 (N = 8).
 //
-// A cell of degree 3 holds 64 coefficients: one per lane of a wave, in the
-// natural order i + 4 j + 16 l.  v_mfma_f64_4x4x4f64 computes four 4x4x4
-// products at once; its operands put the contraction index k at lane bits
-// 4-5 (A[b][i][k] at lane 16k + 4b + i, B[b][k][j] at lane 16k + 4b + j) and
-// its result D[b][i][j] at lane 16i + 4b + j.  So a 1D matrix Q applied
-// along the direction stored in lane bits 4-5 is ONE instruction whose
-// output keeps the layout, with the contracted index replaced by the row
-// index.  Three layouts put each direction at bits 4-5:
-//   Z (natural): x at bits 0-1, y at 2-3, z at 4-5
-//   X          : z at bits 0-1, y at 2-3, x at 4-5
-//   Y          : x at bits 0-1, z at 2-3, y at 4-5
-// and one ds_bpermute per 32-bit half moves a value between them.
+// v_mfma_f64_4x4x4f64 computes four 4x4x4 products at once; its operands put
+// the contraction index k at lane bits 4-5 (A[b][i][k] at lane 16k + 4b + i,
+// B[b][k][j] at lane 16k + 4b + j) and its result D[b][i][j] at lane
+// 16i + 4b + j.  A cell's coefficients of one 4-index block per direction
+// fill the 64 lanes with one direction per lane-bit pair, so a 1D matrix Q
+// applied along the direction at bits 4-5 is one instruction:
+//   normal  (A = Q, B = data): the layout is unchanged;
+//   swapped (A = data, B = Q): the new index lands at bits 0-1 and the
+//            direction that was at bits 0-1 moves to bits 4-5.
+// The swapped form changes layouts for free; the remaining layout changes
+// are one ds_bpermute per 32-bit half.
 //
 // The operator (Sec. 2.1, eq. tensorproduct_3d) with the block-tridiagonal
 // 1D matrices written out per cell:
@@ -19,10 +19,9 @@
 //   Ld~ u = Lcc u_c + Lrl u_{c-e_d} + Llr u_{c+e_d}
 // where Lcc is the cell block (by boundary type) and Lrl, Llr are the
 // rank-2 couplings to the lower and upper face neighbour (Sec. 2.1's face
-// evaluators folded into 4x4 blocks).  Every term is a 4x4 contraction:
-// 9 products for the three Ld~ (own cell and two neighbours each), 5 for
-// the mass factors; about 14 permutations.  Loads and stores are coalesced
-// 512-byte lines, one per cell.
+// evaluators folded into blocks).  Every term is a contraction with a small
+// matrix: 9 for the three Ld~ (own cell and two neighbours each) and 5 for
+// the mass factors.
 #include <hip/hip_runtime.h>
 
 #include "batch.h"
@@ -78,6 +77,19 @@ __device__ __forceinline__ int cell_of(int t, int n, int blk) {
 // One wave owns CPW consecutive cells of an x-row: their dependency chains
 // (load, permute, product, permute, ...) are independent and interleave,
 // and the x-neighbours inside the row come from registers.
+//
+// With the data as the A operand (B = the matrix, same lane pattern), a
+// product contracts the direction at bits 4-5 and exchanges bit pairs 0-1
+// and 4-5 of the layout at no cost.  Writing (a, b, c) for the directions at
+// bit pairs 0-1, 2-3, 4-5 (loads and stores use (x, y, z)):
+//   t3 = My Mx Lz~ u:  (x,y,z) -Lz~ swapped-> (z,y,x) -Mx-> (z,y,x)
+//                       -permute-> (z,x,y) -My swapped-> (y,x,z)
+//   s1 = My Lx~ u:      row in (y,z,x) -Lx~ swapped-> (x,z,y) -My swapped-> (y,z,x)
+//   s2 = Mx Ly~ u:      (x,z,y) -Ly~ swapped-> (y,z,x) -Mx-> (y,z,x)
+//   v  = h [Mz (s1 + s2) + t3]: (y,z,x) -permute-> (y,x,z) -Mz, plus t3->
+//        (y,x,z) -permute-> (x,y,z)
+// The y neighbours are read directly in (x,z,y).  Per cell: 14 products and
+// about five permutations.
 template <bool RES, int CPW>
 __global__ __launch_bounds__(kT) void apply_mfma4_kernel(Batch<double> B,
                                                          const double* __restrict__ tab,
@@ -97,23 +109,30 @@ __global__ __launch_bounds__(kT) void apply_mfma4_kernel(Batch<double> B,
   const int c0 = cell_of(t / ntx * n + (t % ntx) * CPW, n, B.d[pb].a2);
   const int cx0 = c0 % n, cy = (c0 / n) % n, cz = c0 / nn;
 
-  // ---- loads (natural layout): the row's cells, the two row ends' outer
-  // x-neighbours, and each cell's y and z neighbours
-  const double* pc = u + (size_t)c0 * 64 + lane;
+  // lane sources of the layout changes (permutations of bit pairs)
+  const int p0 = lane & 3, p1 = (lane >> 2) & 3, p2 = lane >> 4;
+  const int sToX = p2 | (p0 << 2) | (p1 << 4);  // (x,y,z) -> (y,z,x)
+  const int s12 = p0 | (p2 << 2) | (p1 << 4);   // exchange pairs 1 and 2
+  const int s01 = p1 | (p0 << 2) | (p2 << 4);   // exchange pairs 0 and 1
+  const int oXZY = p0 + 16 * p1 + 4 * p2;       // element held in layout (x,z,y)
+
+  // ---- loads: the row's cells, the two row ends' outer x-neighbours, each
+  // cell's z neighbours (x,y,z) and y neighbours (x,z,y)
+  const double* pc = u + (size_t)c0 * 64;
   double u0[CPW], uym[CPW], uyp[CPW], uzm[CPW], uzp[CPW], b0[CPW];
 #pragma unroll
   for (int q = 0; q < CPW; ++q) {
-    u0[q] = pc[q * 64];
-    uym[q] = cy > 0 ? pc[q * 64 - (ptrdiff_t)n * 64] : 0.0;
-    uyp[q] = cy < n - 1 ? pc[q * 64 + (ptrdiff_t)n * 64] : 0.0;
-    uzm[q] = cz > 0 ? pc[q * 64 - (ptrdiff_t)nn * 64] : 0.0;
-    uzp[q] = cz < n - 1 ? pc[q * 64 + (ptrdiff_t)nn * 64] : 0.0;
+    u0[q] = pc[q * 64 + lane];
+    uym[q] = cy > 0 ? pc[q * 64 + oXZY - (ptrdiff_t)n * 64] : 0.0;
+    uyp[q] = cy < n - 1 ? pc[q * 64 + oXZY + (ptrdiff_t)n * 64] : 0.0;
+    uzm[q] = cz > 0 ? pc[q * 64 + lane - (ptrdiff_t)nn * 64] : 0.0;
+    uzp[q] = cz < n - 1 ? pc[q * 64 + lane + (ptrdiff_t)nn * 64] : 0.0;
     b0[q] = RES ? bv[(size_t)(c0 + q) * 64 + lane] : 0.0;
   }
-  const double uxm0 = cx0 > 0 ? pc[-64] : 0.0;
-  const double uxpE = cx0 + CPW < n ? pc[CPW * 64] : 0.0;
+  const double uxm0 = cx0 > 0 ? pc[lane - 64] : 0.0;
+  const double uxpE = cx0 + CPW < n ? pc[CPW * 64 + lane] : 0.0;
 
-  // ---- A operands (uniform tables)
+  // ---- matrix operands (uniform tables; the same registers serve as A and B)
   auto var = [&](int q) { return (q == 0 ? 1 : 0) | (q == n - 1 ? 2 : 0); };
   const double aM = a_operand(tab + lay.mass, lane);
   const double aLy = a_operand(tab + lay.lcell + var(cy) * 16, lane);
@@ -124,41 +143,32 @@ __global__ __launch_bounds__(kT) void apply_mfma4_kernel(Batch<double> B,
   const double aL0 = a_operand(tab + lay.lcell + var(cx0) * 16, lane);
   const double aL1 = a_operand(tab + lay.lcell + var(cx0 + CPW - 1) * 16, lane);
 
-  // lane sources of the layout changes (all are permutations of bit pairs)
-  const int p0 = lane & 3, p1 = (lane >> 2) & 3, p2 = lane >> 4;
-  const int sZX = p2 | (p1 << 2) | (p0 << 4);  // Z <-> X (swap pairs 0 and 2)
-  const int sZY = p0 | (p2 << 2) | (p1 << 4);  // Z <-> Y (swap pairs 1 and 2)
-  const int sXY = p1 | (p2 << 2) | (p0 << 4);  // X -> Y
-  const int sYX = p2 | (p0 << 2) | (p1 << 4);  // Y -> X
-
-  double ux[CPW + 2];  // the row in X layout with its outer neighbours
-  ux[0] = gather(uxm0, sZX);
+  double ux[CPW + 2];  // the row in (y,z,x) with its outer neighbours
+  ux[0] = gather(uxm0, sToX);
 #pragma unroll
-  for (int q = 0; q < CPW; ++q) ux[q + 1] = gather(u0[q], sZX);
-  ux[CPW + 1] = gather(uxpE, sZX);
+  for (int q = 0; q < CPW; ++q) ux[q + 1] = gather(u0[q], sToX);
+  ux[CPW + 1] = gather(uxpE, sToX);
 
 #pragma unroll
   for (int q = 0; q < CPW; ++q) {
-    // Lz~ u in Z, then Mx (in X), then My (in Y), back to Z
-    double z1 = mma(aLz, u0[q], 0.0);
-    z1 = mma(aRL, uzm[q], z1);
-    z1 = mma(aLR, uzp[q], z1);
-    double t3 = mma(aM, gather(z1, sZX), 0.0);
-    t3 = mma(aM, gather(t3, sXY), 0.0);
-    t3 = gather(t3, sZY);
-    // Lx~ u in X, then My in Y
+    // t3 = My Mx Lz~ u
+    double w = mma(u0[q], aLz, 0.0);
+    w = mma(uzm[q], aRL, w);
+    w = mma(uzp[q], aLR, w);                           // (z,y,x)
+    const double t3 = mma(gather(mma(aM, w, 0.0), s12), aM, 0.0);  // (y,x,z)
+    // s1 = My Lx~ u
     const double aLx = (q == 0) ? aL0 : ((q == CPW - 1) ? aL1 : aLi);
-    double x1 = mma(aLx, ux[q + 1], 0.0);
-    x1 = mma(aRL, ux[q], x1);
-    x1 = mma(aLR, ux[q + 2], x1);
-    const double s1 = mma(aM, gather(x1, sXY), 0.0);
-    // Ly~ u in Y, then Mx in X
-    double y1 = mma(aLy, gather(u0[q], sZY), 0.0);
-    y1 = mma(aRL, gather(uym[q], sZY), y1);
-    y1 = mma(aLR, gather(uyp[q], sZY), y1);
-    const double s2 = mma(aM, gather(y1, sYX), 0.0);
-    // Mz (My Lx~ u + Mx Ly~ u) in Z
-    const double o = mma(aM, gather(s1, sZY) + gather(s2, sZX), t3);
+    w = mma(ux[q + 1], aLx, 0.0);
+    w = mma(ux[q], aRL, w);
+    w = mma(ux[q + 2], aLR, w);                        // (x,z,y)
+    double s = mma(w, aM, 0.0);                        // (y,z,x)
+    // s2 = Mx Ly~ u
+    w = mma(gather(u0[q], s12), aLy, 0.0);
+    w = mma(uym[q], aRL, w);
+    w = mma(uyp[q], aLR, w);                           // (y,z,x)
+    s = mma(aM, w, s);
+    // Mz (s1 + s2) + t3, back to (x,y,z)
+    const double o = gather(mma(aM, gather(s, s12), t3), s01);
     double* dst = v + (size_t)(c0 + q) * 64 + lane;
     if (RES) *dst = b0[q] - h * o;
     else *dst = h * o;
