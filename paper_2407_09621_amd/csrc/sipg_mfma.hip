@@ -370,6 +370,89 @@ __global__ __launch_bounds__(kT) void apply_mfma8_kernel(Batch<double> B,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fast-diagonalization solve on the vertex patches of one colour for degree
+// 3 (Sec. 7's smoother; exact inverse of the patch matrix):
+//   x_P += (1/h) (Sz Sy Sx) diag(1 / (lx_i + ly_j + lz_l)) (Sz Sy Sx)^T r_P
+// A patch is 2x2x2 cells, 8 nodes per direction: the degree-7 layout applies
+// with the register index = the patch cell (dx, dy, dz) and the lane = the
+// node inside the cell, so every register is one coalesced 512-byte line of
+// a cell.  One patch per wave; 96 products and three layout changes:
+//   (x,y,z) -Sz^T swapped-> (z,y,x) -Sx^T-> -permute-> (z,x,y) -Sy^T->
+//   scale -Sy swapped-> (y,x,z) -Sz-> -permute-> (y,z,x) -Sx swapped->
+//   (x,z,y) -permute-> (x,y,z)
+// Patches of one colour share no cell, so the scatter-add needs no atomics.
+
+// blocks of the transpose of a row-major 8x8 matrix
+__device__ __forceinline__ Op8 load_op8t(const double* __restrict__ q, int lane) {
+  Op8 m;
+#pragma unroll
+  for (int o = 0; o < 2; ++o)
+#pragma unroll
+    for (int i = 0; i < 2; ++i) m.b[o][i] = q[(4 * i + (lane >> 4)) * 8 + 4 * o + (lane & 3)];
+  return m;
+}
+
+__global__ __launch_bounds__(kT) void patch_mfma4_kernel(Batch<double> B,
+                                                         const double* __restrict__ tab,
+                                                         TableLayout lay, int bx, int by, int bz) {
+  const int lane = threadIdx.x & 63;
+  const int gi = __builtin_amdgcn_readfirstlane(blockIdx.x * (kT / 64) + (threadIdx.x >> 6));
+  if (gi >= B.start[B.count]) return;  // wave-uniform; no barriers in this kernel
+  const int pb = batch_find(B, gi);
+  const double* __restrict__ r = B.d[pb].in;
+  double* __restrict__ x = B.d[pb].out;
+  const int n = B.d[pb].n, npx = B.d[pb].a0, npy = B.d[pb].a1, nn = n * n;
+  const double h = B.d[pb].h;
+  const int p = gi - B.start[pb];
+  // the patch's vertex (interior vertices 1 .. n-1 of the colour's parity)
+  const int vx = 2 * (p % npx) + (bx ? 1 : 2);
+  const int vy = 2 * ((p / npx) % npy) + (by ? 1 : 2);
+  const int vz = 2 * (p / (npx * npy)) + (bz ? 1 : 2);
+  auto type = [&](int v) { return (v == 1 ? 1 : 0) | (v == n - 1 ? 2 : 0); };
+  const int tx = type(vx), ty = type(vy), tz = type(vz);
+  const double* pc = r + (size_t)((vx - 1) + n * (vy - 1) + nn * (vz - 1)) * 64 + lane;
+  double* px = x + (size_t)((vx - 1) + n * (vy - 1) + nn * (vz - 1)) * 64 + lane;
+  auto cell_off = [&](int q) { return (ptrdiff_t)((q & 1) + n * ((q >> 1) & 1) + nn * (q >> 2)) * 64; };
+
+  double X[8], W[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) X[q] = pc[cell_off(q)];
+  const int p0 = lane & 3, p1 = (lane >> 2) & 3, p2 = lane >> 4;
+  const int s12 = p0 | (p2 << 2) | (p1 << 4);  // exchange pairs 1 and 2
+  const double* S = tab + lay.fd_s;
+  const double* lam = tab + lay.fd_l;
+
+  {  // forward: S^T along z, x, y
+    const Op8 Tz = load_op8t(S + tz * 64, lane);
+    const Op8 Tx = load_op8t(S + tx * 64, lane);
+    const Op8 Ty = load_op8t(S + ty * 64, lane);
+    mul_swapped<2>(Tz, X, W, false);  // (z, y, x)
+    mul_normal<0>(Tx, W, X, false);
+    permute8(X, W, s12);              // (z, x, y)
+    mul_normal<1>(Ty, W, X, false);
+  }
+  // eigenvalue scaling; in (z, x, y) lane bit pairs hold z, x, y
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const double l = lam[tx * 8 + p1 + 4 * (q & 1)] + lam[ty * 8 + p2 + 4 * ((q >> 1) & 1)] +
+                     lam[tz * 8 + p0 + 4 * (q >> 2)];
+    X[q] = X[q] / (h * l);
+  }
+  {  // backward: S along y, z, x
+    const Op8 Sy = load_op8(S + ty * 64, lane);
+    const Op8 Sz = load_op8(S + tz * 64, lane);
+    const Op8 Sx = load_op8(S + tx * 64, lane);
+    mul_swapped<1>(Sy, X, W, false);  // (y, x, z)
+    mul_normal<2>(Sz, W, X, false);
+    permute8(X, W, s12);              // (y, z, x)
+    mul_swapped<0>(Sx, W, X, false);  // (x, z, y)
+    permute8(X, W, s12);              // (x, y, z)
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) px[cell_off(q)] += W[q];
+}
+
 }  // namespace
 
 hipError_t launch_apply_mfma4_batch(const ApplyJob* jobs, int count, const DevTab& t,
@@ -451,6 +534,40 @@ hipError_t launch_apply_mfma8_batch(const ApplyJob* jobs, int count, const DevTa
     hipLaunchKernelGGL((apply_mfma8_kernel<true>), dim3(grid), dim3(kT), 0, s, B, t.tab, t.lay);
   else
     hipLaunchKernelGGL((apply_mfma8_kernel<false>), dim3(grid), dim3(kT), 0, s, B, t.tab, t.lay);
+  return hipGetLastError();
+}
+
+}  // namespace sipg
+
+namespace sipg {
+
+hipError_t launch_patch_mfma4_batch(int colour, const PatchJob* jobs, int count,
+                                    const DevTab& t, hipStream_t s) {
+  if (t.lay.N != 4 || count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
+  const int bx = colour & 1, by = (colour >> 1) & 1, bz = (colour >> 2) & 1;
+  Batch<double> B;
+  B.count = count;
+  B.start[0] = 0;
+  for (int i = 0; i < count; ++i) {
+    const PatchJob& j = jobs[i];
+    if (j.n < 2 || j.n > 1024 || !j.r || !j.x) return hipErrorInvalidValue;
+    // vertices in [1, n-1]: odd ones 1, 3, ..; even ones 2, 4, ..
+    auto cnt = [&](int bit) { return bit ? j.n / 2 : (j.n - 1) / 2; };
+    Desc<double>& d = B.d[i];
+    d.in = (const double*)j.r;
+    d.out = (double*)j.x;
+    d.aux = nullptr;
+    d.h = j.h;
+    d.n = j.n;
+    d.a0 = cnt(bx);
+    d.a1 = cnt(by);
+    d.a2 = d.a0 * d.a1 * cnt(bz);
+    if (B.start[i] + (int64_t)d.a2 > 0x7fffffff) return hipErrorInvalidValue;
+    B.start[i + 1] = B.start[i] + d.a2;
+  }
+  const int grid = (B.start[count] + kT / 64 - 1) / (kT / 64);
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(patch_mfma4_kernel, dim3(grid), dim3(kT), 0, s, B, t.tab, t.lay, bx, by, bz);
   return hipGetLastError();
 }
 
