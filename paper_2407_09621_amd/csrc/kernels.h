@@ -54,9 +54,10 @@ hipError_t launch_apply_mfma4_batch(const ApplyJob* jobs, int count, const DevTa
 // FP64 apply of degree 7 on the matrix cores (one cell per wave)
 hipError_t launch_apply_mfma8_batch(const ApplyJob* jobs, int count, const DevTab& t,
                                     hipStream_t s);
-// FP64 patch solve of degree 3 on the matrix cores (one patch per wave); same
-// contract as launch_patch_fd_batch with prec 0 and N = 4.
-hipError_t launch_patch_mfma4_batch(int colour, const PatchJob* jobs, int count,
+// Patch solve of degree 3 on the matrix cores (one patch per wave, FP64
+// products); same contract as launch_patch_fd_batch with N = 4 (prec 0: FP64
+// vectors, 1: FP32 vectors).
+hipError_t launch_patch_mfma4_batch(int prec, int colour, const PatchJob* jobs, int count,
                                     const DevTab& t, hipStream_t s);
 
 // Batched forms: up to kMaxBatch problems of one degree per launch.

@@ -382,6 +382,8 @@ __global__ __launch_bounds__(kT) void apply_mfma8_kernel(Batch<double> B,
 //   scale -Sy swapped-> (y,x,z) -Sz-> -permute-> (y,z,x) -Sx swapped->
 //   (x,z,y) -permute-> (x,y,z)
 // Patches of one colour share no cell, so the scatter-add needs no atomics.
+// T is the vector type: FP32 vectors (the FP32 V-cycle) are widened on load
+// and the update is rounded to FP32 on store; the products are FP64.
 
 // blocks of the transpose of a row-major 8x8 matrix
 __device__ __forceinline__ Op8 load_op8t(const double* __restrict__ q, int lane) {
@@ -393,15 +395,15 @@ __device__ __forceinline__ Op8 load_op8t(const double* __restrict__ q, int lane)
   return m;
 }
 
-__global__ __launch_bounds__(kT) void patch_mfma4_kernel(Batch<double> B,
-                                                         const double* __restrict__ tab,
+template <typename T>
+__global__ __launch_bounds__(kT) void patch_mfma4_kernel(Batch<T> B, const double* __restrict__ tab,
                                                          TableLayout lay, int bx, int by, int bz) {
   const int lane = threadIdx.x & 63;
   const int gi = __builtin_amdgcn_readfirstlane(blockIdx.x * (kT / 64) + (threadIdx.x >> 6));
   if (gi >= B.start[B.count]) return;  // wave-uniform; no barriers in this kernel
   const int pb = batch_find(B, gi);
-  const double* __restrict__ r = B.d[pb].in;
-  double* __restrict__ x = B.d[pb].out;
+  const T* __restrict__ r = B.d[pb].in;
+  T* __restrict__ x = B.d[pb].out;
   const int n = B.d[pb].n, npx = B.d[pb].a0, npy = B.d[pb].a1, nn = n * n;
   const double h = B.d[pb].h;
   const int p = gi - B.start[pb];
@@ -411,13 +413,13 @@ __global__ __launch_bounds__(kT) void patch_mfma4_kernel(Batch<double> B,
   const int vz = 2 * (p / (npx * npy)) + (bz ? 1 : 2);
   auto type = [&](int v) { return (v == 1 ? 1 : 0) | (v == n - 1 ? 2 : 0); };
   const int tx = type(vx), ty = type(vy), tz = type(vz);
-  const double* pc = r + (size_t)((vx - 1) + n * (vy - 1) + nn * (vz - 1)) * 64 + lane;
-  double* px = x + (size_t)((vx - 1) + n * (vy - 1) + nn * (vz - 1)) * 64 + lane;
+  const T* pc = r + (size_t)((vx - 1) + n * (vy - 1) + nn * (vz - 1)) * 64 + lane;
+  T* px = x + (size_t)((vx - 1) + n * (vy - 1) + nn * (vz - 1)) * 64 + lane;
   auto cell_off = [&](int q) { return (ptrdiff_t)((q & 1) + n * ((q >> 1) & 1) + nn * (q >> 2)) * 64; };
 
   double X[8], W[8];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) X[q] = pc[cell_off(q)];
+  for (int q = 0; q < 8; ++q) X[q] = (double)pc[cell_off(q)];
   const int p0 = lane & 3, p1 = (lane >> 2) & 3, p2 = lane >> 4;
   const int s12 = p0 | (p2 << 2) | (p1 << 4);  // exchange pairs 1 and 2
   const double* S = tab + lay.fd_s;
@@ -450,7 +452,7 @@ __global__ __launch_bounds__(kT) void patch_mfma4_kernel(Batch<double> B,
     permute8(X, W, s12);              // (x, y, z)
   }
 #pragma unroll
-  for (int q = 0; q < 8; ++q) px[cell_off(q)] += W[q];
+  for (int q = 0; q < 8; ++q) px[cell_off(q)] = (T)((double)px[cell_off(q)] + W[q]);
 }
 
 }  // namespace
@@ -541,11 +543,14 @@ hipError_t launch_apply_mfma8_batch(const ApplyJob* jobs, int count, const DevTa
 
 namespace sipg {
 
-hipError_t launch_patch_mfma4_batch(int colour, const PatchJob* jobs, int count,
-                                    const DevTab& t, hipStream_t s) {
+namespace {
+
+template <typename T>
+hipError_t patch_mfma4(int colour, const PatchJob* jobs, int count, const DevTab& t,
+                       hipStream_t s) {
   if (t.lay.N != 4 || count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
   const int bx = colour & 1, by = (colour >> 1) & 1, bz = (colour >> 2) & 1;
-  Batch<double> B;
+  Batch<T> B;
   B.count = count;
   B.start[0] = 0;
   for (int i = 0; i < count; ++i) {
@@ -553,11 +558,11 @@ hipError_t launch_patch_mfma4_batch(int colour, const PatchJob* jobs, int count,
     if (j.n < 2 || j.n > 1024 || !j.r || !j.x) return hipErrorInvalidValue;
     // vertices in [1, n-1]: odd ones 1, 3, ..; even ones 2, 4, ..
     auto cnt = [&](int bit) { return bit ? j.n / 2 : (j.n - 1) / 2; };
-    Desc<double>& d = B.d[i];
-    d.in = (const double*)j.r;
-    d.out = (double*)j.x;
+    Desc<T>& d = B.d[i];
+    d.in = (const T*)j.r;
+    d.out = (T*)j.x;
     d.aux = nullptr;
-    d.h = j.h;
+    d.h = (T)j.h;
     d.n = j.n;
     d.a0 = cnt(bx);
     d.a1 = cnt(by);
@@ -567,8 +572,17 @@ hipError_t launch_patch_mfma4_batch(int colour, const PatchJob* jobs, int count,
   }
   const int grid = (B.start[count] + kT / 64 - 1) / (kT / 64);
   if (grid == 0) return hipSuccess;
-  hipLaunchKernelGGL(patch_mfma4_kernel, dim3(grid), dim3(kT), 0, s, B, t.tab, t.lay, bx, by, bz);
+  hipLaunchKernelGGL(patch_mfma4_kernel<T>, dim3(grid), dim3(kT), 0, s, B, t.tab, t.lay, bx, by,
+                     bz);
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_patch_mfma4_batch(int prec, int colour, const PatchJob* jobs, int count,
+                                    const DevTab& t, hipStream_t s) {
+  return prec == 0 ? patch_mfma4<double>(colour, jobs, count, t, s)
+                   : patch_mfma4<float>(colour, jobs, count, t, s);
 }
 
 }  // namespace sipg

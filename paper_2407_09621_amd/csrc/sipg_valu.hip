@@ -970,7 +970,7 @@ hipError_t launch_apply_batch(int prec, int N, const ApplyJob* jobs, int count, 
 hipError_t launch_patch_fd_batch(int prec, int N, int colour, const PatchJob* jobs, int count,
                                  const DevTab& t, hipStream_t s) {
   if (t.lay.N != N || colour < 0 || colour > 7) return hipErrorInvalidValue;
-  if (prec == 0 && N == 4) return launch_patch_mfma4_batch(colour, jobs, count, t, s);
+  if (N == 4) return launch_patch_mfma4_batch(prec, colour, jobs, count, t, s);
   if (prec == 0) {
 #define CALL(NN) patch_impl<double, NN>(colour, jobs, count, t, s)
     SIPG_DISPATCH_N(N, CALL)
