@@ -95,7 +95,8 @@ __global__ __launch_bounds__(kT) void apply_mfma4_kernel(Batch<double> B,
                                                          const double* __restrict__ tab,
                                                          TableLayout lay) {
   const int lane = threadIdx.x & 63;
-  const int gi = xcd_remap4(blockIdx.x, gridDim.x) * (kT / 64) + (threadIdx.x >> 6);
+  const int gi = __builtin_amdgcn_readfirstlane(xcd_remap4(blockIdx.x, gridDim.x) * (kT / 64) +
+                                                (threadIdx.x >> 6));
   if (gi >= B.start[B.count]) return;  // wave-uniform; no barriers in this kernel
   const int pb = batch_find(B, gi);
   const double* __restrict__ u = B.d[pb].in;
@@ -117,20 +118,33 @@ __global__ __launch_bounds__(kT) void apply_mfma4_kernel(Batch<double> B,
   const int oXZY = p0 + 16 * p1 + 4 * p2;       // element held in layout (x,z,y)
 
   // ---- loads: the row's cells, the two row ends' outer x-neighbours, each
-  // cell's z neighbours (x,y,z) and y neighbours (x,z,y)
+  // cell's z neighbours (x,y,z) and y neighbours (x,z,y).  All loads are
+  // unconditional (a missing neighbour reads the cell itself and is zeroed
+  // after the load): one basic block the compiler can schedule freely.
   const double* pc = u + (size_t)c0 * 64;
+  const ptrdiff_t dym = cy > 0 ? -(ptrdiff_t)n * 64 : 0, dyp = cy < n - 1 ? (ptrdiff_t)n * 64 : 0;
+  const ptrdiff_t dzm = cz > 0 ? -(ptrdiff_t)nn * 64 : 0, dzp = cz < n - 1 ? (ptrdiff_t)nn * 64 : 0;
   double u0[CPW], uym[CPW], uyp[CPW], uzm[CPW], uzp[CPW], b0[CPW];
 #pragma unroll
   for (int q = 0; q < CPW; ++q) {
     u0[q] = pc[q * 64 + lane];
-    uym[q] = cy > 0 ? pc[q * 64 + oXZY - (ptrdiff_t)n * 64] : 0.0;
-    uyp[q] = cy < n - 1 ? pc[q * 64 + oXZY + (ptrdiff_t)n * 64] : 0.0;
-    uzm[q] = cz > 0 ? pc[q * 64 + lane - (ptrdiff_t)nn * 64] : 0.0;
-    uzp[q] = cz < n - 1 ? pc[q * 64 + lane + (ptrdiff_t)nn * 64] : 0.0;
+    uym[q] = pc[q * 64 + oXZY + dym];
+    uyp[q] = pc[q * 64 + oXZY + dyp];
+    uzm[q] = pc[q * 64 + lane + dzm];
+    uzp[q] = pc[q * 64 + lane + dzp];
     b0[q] = RES ? bv[(size_t)(c0 + q) * 64 + lane] : 0.0;
   }
-  const double uxm0 = cx0 > 0 ? pc[lane - 64] : 0.0;
-  const double uxpE = cx0 + CPW < n ? pc[CPW * 64 + lane] : 0.0;
+  double uxm0 = pc[lane + (cx0 > 0 ? -64 : 0)];
+  double uxpE = pc[lane + (cx0 + CPW < n ? CPW * 64 : (CPW - 1) * 64)];
+#pragma unroll
+  for (int q = 0; q < CPW; ++q) {
+    uym[q] = cy > 0 ? uym[q] : 0.0;
+    uyp[q] = cy < n - 1 ? uyp[q] : 0.0;
+    uzm[q] = cz > 0 ? uzm[q] : 0.0;
+    uzp[q] = cz < n - 1 ? uzp[q] : 0.0;
+  }
+  uxm0 = cx0 > 0 ? uxm0 : 0.0;
+  uxpE = cx0 + CPW < n ? uxpE : 0.0;
 
   // ---- matrix operands (uniform tables; the same registers serve as A and B)
   auto var = [&](int q) { return (q == 0 ? 1 : 0) | (q == n - 1 ? 2 : 0); };

@@ -179,7 +179,7 @@ __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
   __shared__ T s_r_all[WAVES * CPB * NR];
 
   const int tid = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int gi = xcd_remap(blockIdx.x, gridDim.x) * WAVES + wave;
+  const int gi = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * WAVES + wave);
   if (gi >= B.start[B.count]) return;  // wave-uniform; no workgroup barriers below
   const int pb = batch_find(B, gi);
   const int grp = gi - B.start[pb];
@@ -217,17 +217,31 @@ __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
   const bool hy0 = act && cy > 0, hy1 = act && cy < n - 1;
   const bool hz0 = act && cz > 0, hz1 = act && cz < n - 1;
   if constexpr (COAL) {
-    const T* pc = u + (size_t)c * N3 + ln;
+    // unconditional loads (idle lanes and missing neighbours read inside the
+    // own cell and are zeroed after the load): one basic block
+    const T* pc = u + (size_t)c * N3 + (act ? ln : 0);
     const ptrdiff_t sx = N3, sy = (ptrdiff_t)n * N3, sz = (ptrdiff_t)nn * N3;
+    const ptrdiff_t dxm = hx0 ? -sx : 0, dxp = hx1 ? sx : 0, dym = hy0 ? -sy : 0;
+    const ptrdiff_t dyp = hy1 ? sy : 0, dzm = hz0 ? -sz : 0, dzp = hz1 ? sz : 0;
 #pragma unroll
     for (int a = 0; a < N; ++a) {
-      own[a] = act ? pc[a * N2] : 0.0;
-      xlo[a] = hx0 ? pc[a * N2 - sx] : 0.0;
-      xhi[a] = hx1 ? pc[a * N2 + sx] : 0.0;
-      ylo[a] = hy0 ? pc[a * N2 - sy] : 0.0;
-      yhi[a] = hy1 ? pc[a * N2 + sy] : 0.0;
-      zlo[a] = hz0 ? pc[a * N2 - sz] : 0.0;
-      zhi[a] = hz1 ? pc[a * N2 + sz] : 0.0;
+      own[a] = pc[a * N2];
+      xlo[a] = pc[a * N2 + dxm];
+      xhi[a] = pc[a * N2 + dxp];
+      ylo[a] = pc[a * N2 + dym];
+      yhi[a] = pc[a * N2 + dyp];
+      zlo[a] = pc[a * N2 + dzm];
+      zhi[a] = pc[a * N2 + dzp];
+    }
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      own[a] = act ? own[a] : (T)0;
+      xlo[a] = hx0 ? xlo[a] : (T)0;
+      xhi[a] = hx1 ? xhi[a] : (T)0;
+      ylo[a] = hy0 ? ylo[a] : (T)0;
+      yhi[a] = hy1 ? yhi[a] : (T)0;
+      zlo[a] = hz0 ? zlo[a] : (T)0;
+      zhi[a] = hz1 ? zhi[a] : (T)0;
     }
     // own and x-neighbours: z-lines -> x-lines (j, l) = (lp, lq)
     const int w = cl * N3 + ln;
