@@ -96,11 +96,14 @@ def test_fgmres_with_lowprec_vcycle(prec, ec):
         assert info["iterations"] <= 40
 
 
-def test_lowprec_vcycle_close_to_fp64_vcycle():
+@pytest.mark.parametrize("k", [2, 3])
+def test_lowprec_vcycle_close_to_fp64_vcycle(k):
+    """k=3 also runs the FP32 V-cycle's patch solve on the matrix cores
+    (FP32 vectors, FP64 products)."""
     from paper_2407_09621_amd import Problem
-    announce("vcycle lp vs f64")
+    announce("vcycle lp vs f64", k)
     import torch
-    k, n = 2, 8
+    n = 8
     b = torch.from_numpy(inputs.uniform_vector(Problem(k, n).n_dofs(), 9)).to("cuda")
     x64 = torch.zeros_like(b)
     Problem(k, n).vcycle(x64, b)

@@ -16,7 +16,7 @@ from paper_2407_09621_amd import inputs
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("k,n", [(1, 4), (2, 5), (3, 4), (5, 3), (7, 2), (2, 2)])
+@pytest.mark.parametrize("k,n", [(1, 4), (2, 5), (3, 4), (3, 7), (3, 8), (5, 3), (7, 2), (2, 2)])
 def test_patch_correction_matches_dense_solves(k, n):
     from paper_2407_09621_amd import Problem
     announce("patch", k, n)
