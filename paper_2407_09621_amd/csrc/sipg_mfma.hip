@@ -206,17 +206,16 @@ __global__ __launch_bounds__(kT) void apply_mfma4_kernel(Batch<double> B,
 // A block of a row-major matrix has the same lane pattern in both roles
 // (lane 16k + 4b + i holds Q[i][k] as A, Q[j][k] as B for j = i).
 //
-// Global loads are fastest with x in lane bits 0-1 (four lanes read 32
-// contiguous bytes), so every cell is read in (x, y, z) or (x, z, y) and the
-// layouts that put x at bits 4-5 are made in registers (ds_bpermute):
+// Global loads are fastest in the natural order (x, y, z): every cell is
+// read that way and the other layouts are made in registers (ds_bpermute):
 //   t3 = My Mx Lz~ u:  (x,y,z) -Lz~ swapped-> (z,y,x) -Mx-> (z,y,x)
 //                       -permute-> (z,x,y) -My swapped-> (y,x,z)
 //   s1 = My Lx~ u:      (x,y,z) -permute-> (y,z,x) -Lx~ swapped-> (x,z,y)
 //                       -My swapped-> (y,z,x)
-//   s2 = Mx Ly~ u:      (x,z,y) -Ly~ swapped-> (y,z,x) -Mx-> (y,z,x)
+//   s2 = Mx Ly~ u:      (x,y,z) -permute-> (x,z,y) -Ly~ swapped-> (y,z,x) -Mx->
 //   v  = h [Mz (s1 + s2) + t3]: (y,z,x) -permute-> (y,x,z) -Mz, plus t3->
 //        (y,x,z) -permute-> (x,y,z), stored
-// 224 products and seven layout changes per cell, one cell per wave.
+// 224 products and nine layout changes per cell, one cell per wave.
 
 // lane offset of the coefficient (lo bits only) for a layout whose lane bit
 // pairs hold the directions with strides s0, s1, s2 (1, 8 or 64)
@@ -312,7 +311,6 @@ __global__ __launch_bounds__(kT) void apply_mfma8_kernel(Batch<double> B,
   auto var = [&](int q) { return (q == 0 ? 1 : 0) | (q == n - 1 ? 2 : 0); };
 
   const int oXYZ = lane_off8(lane, 1, 8, 64);
-  const int oXZY = lane_off8(lane, 1, 64, 8);
   // sources of the layout changes: (x,y,z) -> (y,z,x); exchange of pairs 1
   // and 2 (an involution); exchange of pairs 0 and 1
   const int p0 = lane & 3, p1 = (lane >> 2) & 3, p2 = lane >> 4;
@@ -335,8 +333,8 @@ __global__ __launch_bounds__(kT) void apply_mfma8_kernel(Batch<double> B,
   load8(pc + oXYZ + (cz < n - 1 ? sz : 0), zp);
   load8(pc + oXYZ + (cx > 0 ? -sx : 0), xm);
   load8(pc + oXYZ + (cx < n - 1 ? sx : 0), xp);
-  load8(pc + oXZY + (cy > 0 ? -sy : 0), ym);
-  load8(pc + oXZY + (cy < n - 1 ? sy : 0), yp);
+  load8(pc + oXYZ + (cy > 0 ? -sy : 0), ym);
+  load8(pc + oXYZ + (cy < n - 1 ? sy : 0), yp);
   zero_if(cz == 0, zm);
   zero_if(cz == n - 1, zp);
   zero_if(cx == 0, xm);
@@ -368,8 +366,10 @@ __global__ __launch_bounds__(kT) void apply_mfma8_kernel(Batch<double> B,
     const Op8 Ly = load_op8(tab + lay.lcell + var(cy) * 64, lane);
     permute8(u0, a, s12);             // (x, z, y)
     mul_swapped<1>(Ly, a, w, false);
-    mul_swapped<1>(RL, ym, w, true);
-    mul_swapped<1>(LR, yp, w, true);  // (y, z, x)
+    permute8(ym, a, s12);
+    mul_swapped<1>(RL, a, w, true);
+    permute8(yp, a, s12);
+    mul_swapped<1>(LR, a, w, true);   // (y, z, x)
     mul_normal<0>(M, w, s, true);     // Mx
   }
   permute8(s, w, s12);                // (y, x, z)
