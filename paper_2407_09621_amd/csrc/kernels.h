@@ -47,11 +47,12 @@ hipError_t launch_restrict_f32(int N, const float* rf, float* rc, const DevTab& 
 hipError_t launch_prolongate_add_f32(int N, const float* ec, float* xf, const DevTab& t, int nc,
                                      hipStream_t s);
 
-// FP64 apply of degree 3 on the matrix cores (one wave per cell); same
-// contract as launch_apply_batch with prec 0 and N = 4.
+// FP64 apply of degree 3 on the matrix cores (one wave per up to 8 cells of
+// an x-row); same contract as launch_apply_batch with prec 0 and N = 4.
 hipError_t launch_apply_mfma4_batch(const ApplyJob* jobs, int count, const DevTab& t,
                                     hipStream_t s);
-// FP64 apply of degree 7 on the matrix cores (one cell per wave)
+// FP64 apply of degree 7 on the matrix cores (one cell per wave); same
+// contract as launch_apply_batch with prec 0 and N = 8.
 hipError_t launch_apply_mfma8_batch(const ApplyJob* jobs, int count, const DevTab& t,
                                     hipStream_t s);
 // Patch solve of degree 3 on the matrix cores (one patch per wave, FP64

@@ -50,6 +50,8 @@ __device__ __forceinline__ double a_operand(const double* __restrict__ q, int la
   return q[(lane & 3) * 4 + (lane >> 4)];
 }
 
+// workgroup b of nb -> its position in an order that gives each of the 8 XCDs
+// (which receive workgroups round-robin) one contiguous range
 __device__ __forceinline__ int xcd_remap4(int b, int nb) {
   const int q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
   return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;

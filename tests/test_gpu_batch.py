@@ -48,6 +48,28 @@ def test_batch_apply_matches_single_and_oracle():
         assert rel_l2(to_cpu(v), sipg.kron_apply(to_cpu(u), n, k)) < 1e-13, (k, n)
 
 
+@pytest.mark.parametrize("probs", [
+    [(7, 1), (7, 2), (7, 3), (7, 4)],        # degree 7 on the matrix cores, one cell per wave
+    [(3, 8), (3, 16)],                        # degree 3, 8 cells per wave
+    [(3, 16), (3, 4), (3, 2), (3, 1), (3, 3)],  # degree 3, the batch falls back to 1 cell per wave
+])
+def test_batch_apply_matrix_core_degrees(probs):
+    """Several mesh sizes of one matrix-core degree in one launch, plain and
+    residual form."""
+    from paper_2407_09621_amd import Batch, Problem
+    announce("batch apply matrix cores", probs)
+    B = Batch(probs)
+    us = _vectors(B, 60)
+    vs = B.apply(us)
+    for (k, n), u, v in zip(probs, us, vs):
+        assert rel_l2(to_cpu(v), sipg.kron_apply(to_cpu(u), n, k)) < 1e-13, (k, n)
+    for (k, n), u in zip(probs, us):
+        b = to_gpu(inputs.uniform_vector(n ** 3 * (k + 1) ** 3, 70 + n))
+        r = to_cpu(Problem(k, n, n_levels=1).residual(b, u))
+        ref = to_cpu(b) - sipg.kron_apply(to_cpu(u), n, k)
+        assert rel_l2(r, ref) < 1e-12, (k, n)
+
+
 def test_batch_apply_more_than_one_launch_per_degree():
     """20 problems of one degree: two launches of at most 16 problems."""
     from paper_2407_09621_amd import Batch
