@@ -163,24 +163,41 @@ __device__ __forceinline__ void wave_lds_sync() {
 // paths feed identical values to identical arithmetic.  (Also measured:
 // persistent waves that prefetch the next tile during the y and z stages
 // lose more to the lower occupancy than they gain.)
-template <typename T, int N, bool RES>
+//
+// WG: the workgroup's waves share one tile of CPT = kThreads / N^2 cells
+// (consecutive in memory order) and synchronise with workgroup barriers;
+// used where whole cells per wave would leave many lanes idle (N = 6: 7
+// cells on 252 of 256 lanes instead of one cell on 36 of 64).
+template <typename T, int N, bool RES, bool WG = false>
 __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
     Batch<T> B, const T* __restrict__ tab, TableLayout lay) {
   constexpr int N2 = N * N, N3 = N2 * N, CPB = (64 / N2) > 0 ? 64 / N2 : 1;
   constexpr int WAVES = kThreads / 64;
+  constexpr int CPT = kThreads / N2;            // cells of a workgroup tile (WG)
+  constexpr int CS = WG ? CPT : CPB;            // cells of one LDS slice
+  constexpr int SLOTS = WG ? CPT : WAVES * CPB;  // cells of all slices
   constexpr bool COAL = N >= 5;
+  static_assert(!WG || COAL, "the workgroup tile is implemented for the staged loads");
   // per cell: t1, t2 and a region holding first (COAL) one staged neighbour
   // cell, then the y-face traces [face 0,1][value, derivative][i + N l] and
   // z-face traces [face 0,1][value, derivative][i + N j]; the z-traces after
   // Mx overwrite the y-traces once those are read
   constexpr int NR = (COAL && N3 > 8 * N2) ? N3 : 8 * N2;
-  __shared__ T s_t1_all[WAVES * CPB * N3];
-  __shared__ T s_t2_all[WAVES * CPB * N3];
-  __shared__ T s_r_all[WAVES * CPB * NR];
+  __shared__ T s_t1_all[SLOTS * N3];
+  __shared__ T s_t2_all[SLOTS * N3];
+  __shared__ T s_r_all[SLOTS * NR];
+  // LDS ordering between the lanes sharing a tile
+  auto lds_sync = [&]() {
+    if constexpr (WG) __syncthreads();
+    else wave_lds_sync();
+  };
 
-  const int tid = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int gi = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * WAVES + wave);
-  if (gi >= B.start[B.count]) return;  // wave-uniform; no workgroup barriers below
+  const int tid = WG ? threadIdx.x : (threadIdx.x & 63), wave = WG ? 0 : (threadIdx.x >> 6);
+  const int gi = __builtin_amdgcn_readfirstlane(WG ? xcd_remap(blockIdx.x, gridDim.x)
+                                                   : xcd_remap(blockIdx.x, gridDim.x) * WAVES + wave);
+  // wave-uniform (workgroup-uniform with WG): every barrier below is reached
+  // by all threads that pass this point
+  if (gi >= B.start[B.count]) return;
   const int pb = batch_find(B, gi);
   const int grp = gi - B.start[pb];
   const T* __restrict__ u = B.d[pb].in;
@@ -193,20 +210,25 @@ __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
   tm.ntx = B.d[pb].a1;
   tm.blk = B.d[pb].a2;
   tm.ngroups = B.start[pb + 1] - B.start[pb];
-  T* s_t1 = s_t1_all + wave * (CPB * N3);
-  T* s_t2 = s_t2_all + wave * (CPB * N3);
-  T* s_ty = s_r_all + wave * (CPB * NR);
-  T* s_tz = s_ty + CPB * 4 * N2;
+  T* s_t1 = s_t1_all + wave * (CS * N3);
+  T* s_t2 = s_t2_all + wave * (CS * N3);
+  T* s_ty = s_r_all + wave * (CS * NR);
+  T* s_tz = s_ty + CS * 4 * N2;
   T* s_tzm = s_ty;
   // staging (COAL): t1 and t2 are free until the x stage writes them
   T* s_n0 = s_t2;
   T* s_n1 = s_ty;
   const int n = tm.n, nn = n * n, nc = tm.tx;
-  const int c0 = tile_first_cell(tm, grp);
-  const int cy = (c0 / n) % n, cz = c0 / nn, cx0 = c0 % n;
-  const bool act = tid < nc * N2;
+  // WG: CPT consecutive cells from grp * CPT (the last tile may be short);
+  // else TX cells of an x-row
+  const int c0 = WG ? grp * CPT : tile_first_cell(tm, grp);
+  const bool act = WG ? (tid < CPT * N2 && c0 + tid / N2 < nn * n) : (tid < nc * N2);
   const int cl = act ? tid / N2 : 0, ln = tid - cl * N2;
-  const int c = c0 + cl, cx = cx0 + cl;
+  const int c = c0 + cl;
+  // cell coordinates: per lane with WG, else the tile's row plus cl
+  const int cx = WG ? c % n : c0 % n + cl;
+  const int cy = WG ? (c / n) % n : (c0 / n) % n;
+  const int cz = WG ? c / nn : c0 / nn;
   // this thread owns x-line (j, l) = (ln % N, ln / N) of cell c and the
   // y-/z-face trace lines at (i, l) = (ln % N, ln / N) and (i, j) = ln.
   const int lp = ln % N, lq = ln / N;
@@ -253,7 +275,7 @@ __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
         s_n1[w + a * N2] = xhi[a];
       }
     }
-    wave_lds_sync();
+    lds_sync();
     const int rx = cl * N3 + ln * N;
     if (act) {
 #pragma unroll
@@ -263,7 +285,7 @@ __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
         xhi[a] = s_n1[rx + a];
       }
     }
-    wave_lds_sync();
+    lds_sync();
     // y-neighbours: z-lines -> y-lines (i, l) = (lp, lq)
     if (act) {
 #pragma unroll
@@ -272,7 +294,7 @@ __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
         s_n1[w + a * N2] = yhi[a];
       }
     }
-    wave_lds_sync();
+    lds_sync();
     const int ry = cl * N3 + lp + lq * N2;
     if (act) {
 #pragma unroll
@@ -281,7 +303,7 @@ __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
         yhi[a] = s_n1[ry + a * N];
       }
     }
-    wave_lds_sync();  // the staging slice becomes the trace buffers below
+    lds_sync();  // the staging slice becomes the trace buffers below
   } else {
     const T* pc = u + (size_t)c * N3;
     const T* pxl = pc - N3 + ln * N;
@@ -350,50 +372,53 @@ __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
     tz[2 * N2 + ln] = zhi[0];
     tz[3 * N2 + ln] = g3;
   }
-  wave_lds_sync();
+  lds_sync();
 
   // ---- y stage: lines (i, l) = (lp, lq); also Mx on the z traces at (i, j)
+  T cc[N], e[N];
+  const int ybase = cl * N3 + lp + lq * N2;
+  const T* Mrow_y = s_M + lp * N;
   if (act) {
-    T a1[N], a2[N], cc[N], e[N];
-    const int base = cl * N3 + lp + lq * N2;
+    T a1[N], a2[N];
 #pragma unroll
     for (int b = 0; b < N; ++b) {
-      a1[b] = s_t1[base + b * N];
-      a2[b] = s_t2[base + b * N];
+      a1[b] = s_t1[ybase + b * N];
+      a2[b] = s_t2[ybase + b * N];
     }
     matvec<N>(s_M, a1, cc);
     matvec_acc<N>(s_L, a2, cc);
     add_boundary_correction<N>(cc, a2, cy == 0, cy == n - 1, s_d0, s_d1);
     matvec<N>(s_M, a2, e);
     const T* ty = s_ty + cl * 4 * N2 + lq * N;
-    const T* Mrow = s_M + lp * N;
     T f0 = 0.0, q0 = 0.0, f1 = 0.0, q1 = 0.0;
 #pragma unroll
     for (int b = 0; b < N; ++b) {  // (Mx trace)(i, l) = sum_i' M[i][i'] trace(i', l)
-      f0 = fma(Mrow[b], ty[0 * N2 + b], f0);
-      q0 = fma(Mrow[b], ty[1 * N2 + b], q0);
-      f1 = fma(Mrow[b], ty[2 * N2 + b], f1);
-      q1 = fma(Mrow[b], ty[3 * N2 + b], q1);
+      f0 = fma(Mrow_y[b], ty[0 * N2 + b], f0);
+      q0 = fma(Mrow_y[b], ty[1 * N2 + b], q0);
+      f1 = fma(Mrow_y[b], ty[2 * N2 + b], f1);
+      q1 = fma(Mrow_y[b], ty[3 * N2 + b], q1);
     }
     if (hy0) add_lower_face<N>(cc, f0, q0, gam, s_d0);
     if (hy1) add_upper_face<N>(cc, f1, q1, gam, s_d1);
+  }
+  lds_sync();  // every lane has read its y-traces before they are overwritten
+  if (act) {
     const T* tz = s_tz + cl * 4 * N2 + lq * N;
     T* tzm = s_tzm + cl * 4 * N2 + lq * N + lp;
-    wave_lds_sync();  // every lane has read its y-traces before they are overwritten
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       T acc = 0.0;
 #pragma unroll
-      for (int b = 0; b < N; ++b) acc = fma(Mrow[b], tz[r * N2 + b], acc);
+      for (int b = 0; b < N; ++b) acc = fma(Mrow_y[b], tz[r * N2 + b], acc);
       tzm[r * N2] = acc;
     }
 #pragma unroll
     for (int b = 0; b < N; ++b) {
-      s_t1[base + b * N] = cc[b];
-      s_t2[base + b * N] = e[b];
+      s_t1[ybase + b * N] = cc[b];
+      s_t2[ybase + b * N] = e[b];
     }
   }
-  wave_lds_sync();
+  lds_sync();
 
   // ---- z stage: lines (i, j) = ln, written straight to global memory
   if (act) {
@@ -831,6 +856,10 @@ hipError_t make_batch(Batch<T>& B, int count, F&& fill) {
 template <typename T, int N>
 hipError_t apply_impl(const ApplyJob* jobs, int count, const DevTab& t, hipStream_t s) {
   constexpr int CPW = (64 / (N * N)) > 0 ? 64 / (N * N) : 1;
+  // N = 6: whole cells per wave would leave 28 of 64 lanes idle; the
+  // workgroup shares a tile of kThreads / 36 = 7 cells instead
+  constexpr bool WG = (N == 6);
+  constexpr int CPT = kThreads / (N * N);
   Batch<T> B;
   bool residual = jobs[0].b != nullptr;
   hipError_t e = make_batch(B, count, [&](int i, Desc<T>& d, int64_t& items) {
@@ -848,18 +877,19 @@ hipError_t apply_impl(const ApplyJob* jobs, int count, const DevTab& t, hipStrea
     d.a0 = tx;
     d.a1 = j.n / tx;
     d.a2 = (j.order > 0 && j.n % j.order == 0) ? j.order : ((j.n % 8 == 0) ? 8 : 1);
-    items = (int64_t)d.a1 * j.n * j.n;
+    const int64_t cells = (int64_t)j.n * j.n * j.n;
+    items = WG ? (cells + CPT - 1) / CPT : (int64_t)d.a1 * j.n * j.n;
     return hipSuccess;
   });
   if (e != hipSuccess) return e;
-  const int waves = kThreads / 64;
-  const int grid = (B.start[count] + waves - 1) / waves;
+  const int per_block = WG ? 1 : kThreads / 64;  // work items (tiles) per workgroup
+  const int grid = (B.start[count] + per_block - 1) / per_block;
   if (grid == 0) return hipSuccess;
   if (residual)
-    hipLaunchKernelGGL((apply_wave_kernel<T, N, true>), dim3(grid), dim3(kThreads), 0, s, B,
+    hipLaunchKernelGGL((apply_wave_kernel<T, N, true, WG>), dim3(grid), dim3(kThreads), 0, s, B,
                        tab_of<T>(t), t.lay);
   else
-    hipLaunchKernelGGL((apply_wave_kernel<T, N, false>), dim3(grid), dim3(kThreads), 0, s, B,
+    hipLaunchKernelGGL((apply_wave_kernel<T, N, false, WG>), dim3(grid), dim3(kThreads), 0, s, B,
                        tab_of<T>(t), t.lay);
   return hipGetLastError();
 }
