@@ -856,9 +856,10 @@ hipError_t make_batch(Batch<T>& B, int count, F&& fill) {
 template <typename T, int N>
 hipError_t apply_impl(const ApplyJob* jobs, int count, const DevTab& t, hipStream_t s) {
   constexpr int CPW = (64 / (N * N)) > 0 ? 64 / (N * N) : 1;
-  // N = 6: whole cells per wave would leave 28 of 64 lanes idle; the
-  // workgroup shares a tile of kThreads / 36 = 7 cells instead
-  constexpr bool WG = (N == 6);
+  // N = 5, 6, 7: whole cells per wave would leave 14, 28 or 15 of 64 lanes
+  // idle; the workgroup shares a tile of kThreads / N^2 = 10, 7 or 5 cells
+  // instead (250, 252, 245 of 256 lanes)
+  constexpr bool WG = (N >= 5 && N <= 7);
   constexpr int CPT = kThreads / (N * N);
   Batch<T> B;
   bool residual = jobs[0].b != nullptr;
