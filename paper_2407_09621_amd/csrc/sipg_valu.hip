@@ -67,6 +67,42 @@ __device__ __forceinline__ void matvec_t(const T* __restrict__ A, const T (&x)[N
   }
 }
 
+// For large N: keep loop-invariant LDS matrix reads inside the loop (a
+// compiler-only memory clobber; without it the whole matrix is hoisted into
+// registers, 256 VGPRs and one wave per SIMD at N = 8).
+template <int N>
+__device__ __forceinline__ void keep_lds_reads_local() {
+  if constexpr (N >= 6) asm volatile("" ::: "memory");
+}
+
+// Patch-size products with the matrix in LDS: one output row at a time,
+// with a scheduling barrier between rows, so the compiler does not hoist all
+// G^2 matrix reads ahead of the arithmetic (that filled the register file:
+// 256 VGPRs and one wave per SIMD for N >= 6).
+template <int G, typename T>
+__device__ __forceinline__ void matvec_rows(const T* __restrict__ A, const T (&x)[G], T (&y)[G]) {
+#pragma unroll
+  for (int a = 0; a < G; ++a) {
+    T s = 0;
+#pragma unroll
+    for (int b = 0; b < G; ++b) s = fma(A[a * G + b], x[b], s);
+    y[a] = s;
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+template <int G, typename T>
+__device__ __forceinline__ void matvec_rows_t(const T* __restrict__ A, const T (&x)[G], T (&y)[G]) {
+#pragma unroll
+  for (int a = 0; a < G; ++a) {
+    T s = 0;
+#pragma unroll
+    for (int b = 0; b < G; ++b) s = fma(A[b * G + a], x[b], s);
+    y[a] = s;
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 // Face coupling to the lower neighbour (its high-end value f and derivative
 // g = d1 . u) and to the upper neighbour (low-end value f, g = d0 . u).
 template <int N, typename T>
@@ -542,7 +578,7 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
   if (act) {
 #pragma unroll
     for (int a = 0; a < G; ++a) in[a] = X[o0 + a];
-    matvec_t<G>(s_S + tx * G2, in, out);
+    matvec_rows_t<G>(s_S + tx * G2, in, out);
 #pragma unroll
     for (int a = 0; a < G; ++a) X[o0 + a] = out[a];
   }
@@ -550,7 +586,7 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
   if (act) {
 #pragma unroll
     for (int a = 0; a < G; ++a) in[a] = X[o1 + a * G];
-    matvec_t<G>(s_S + ty * G2, in, out);
+    matvec_rows_t<G>(s_S + ty * G2, in, out);
 #pragma unroll
     for (int a = 0; a < G; ++a) X[o1 + a * G] = out[a];
   }
@@ -558,12 +594,12 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
   if (act) {
 #pragma unroll
     for (int a = 0; a < G; ++a) in[a] = X[o2 + a * G2];
-    matvec_t<G>(s_S + tz * G2, in, out);
+    matvec_rows_t<G>(s_S + tz * G2, in, out);
     // eigenvalue scaling: line (la, lb) = (i', j'), running over l'
     const T lij = s_l[tx * G + la] + s_l[ty * G + lb];
 #pragma unroll
     for (int a = 0; a < G; ++a) in[a] = out[a] / (h * (lij + s_l[tz * G + a]));
-    matvec<G>(s_S + tz * G2, in, out);
+    matvec_rows<G>(s_S + tz * G2, in, out);
 #pragma unroll
     for (int a = 0; a < G; ++a) X[o2 + a * G2] = out[a];
   }
@@ -571,7 +607,7 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
   if (act) {
 #pragma unroll
     for (int a = 0; a < G; ++a) in[a] = X[o1 + a * G];
-    matvec<G>(s_S + ty * G2, in, out);
+    matvec_rows<G>(s_S + ty * G2, in, out);
 #pragma unroll
     for (int a = 0; a < G; ++a) X[o1 + a * G] = out[a];
   }
@@ -579,7 +615,7 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
   if (act) {
 #pragma unroll
     for (int a = 0; a < G; ++a) in[a] = X[o0 + a];
-    matvec<G>(s_S + tx * G2, in, out);
+    matvec_rows<G>(s_S + tx * G2, in, out);
 #pragma unroll
     for (int a = 0; a < G; ++a) X[o0 + a] = out[a];
   }
@@ -703,6 +739,7 @@ __global__ __launch_bounds__(kThreads) void restrict_kernel(
 #pragma unroll
       for (int a = 0; a < G; ++a) s = fma(s_P[a * N + b], in[a], s);
       X[b] = s;
+      keep_lds_reads_local<N>();
     }
   }
   __syncthreads();
@@ -720,6 +757,7 @@ __global__ __launch_bounds__(kThreads) void restrict_kernel(
 #pragma unroll
       for (int a = 0; a < G; ++a) s = fma(s_P[a * N + b], in[a], s);
       X[b * G] = s;
+      keep_lds_reads_local<N>();
     }
   }
   __syncthreads();
@@ -738,6 +776,7 @@ __global__ __launch_bounds__(kThreads) void restrict_kernel(
 #pragma unroll
       for (int a = 0; a < G; ++a) s = fma(s_P[a * N + b], in[a], s);
       dst[b * N2] = s;
+      keep_lds_reads_local<N>();
     }
   }
 }
@@ -781,6 +820,7 @@ __global__ __launch_bounds__(kThreads) void prolongate_add_kernel(
 #pragma unroll
       for (int b = 0; b < N; ++b) s = fma(s_P[a * N + b], in[b], s);
       X[a * G2] = s;
+      keep_lds_reads_local<N>();
     }
   }
   __syncthreads();
@@ -797,6 +837,7 @@ __global__ __launch_bounds__(kThreads) void prolongate_add_kernel(
 #pragma unroll
       for (int b = 0; b < N; ++b) s = fma(s_P[a * N + b], in[b], s);
       X[a * G] = s;
+      keep_lds_reads_local<N>();
     }
   }
   __syncthreads();
@@ -813,6 +854,7 @@ __global__ __launch_bounds__(kThreads) void prolongate_add_kernel(
 #pragma unroll
       for (int b = 0; b < N; ++b) s = fma(s_P[a * N + b], in[b], s);
       X[a] = s;
+      keep_lds_reads_local<N>();
     }
   }
   __syncthreads();
