@@ -32,7 +32,7 @@ BYTES_PER_DOF = 16.0          # read u, write v (FP64)
 # HBM bytes per launch of the apply kernel as profiled (FETCH_SIZE x 2 +
 # WRITE_SIZE x 1, profiles/apply_f64_k3n64_k5n40_k7n32.md); set an entry
 # to None when the kernel changes until it is profiled again.
-PROFILED_TRAFFIC = {"k3_n64": 310.8e6, "k5_n40": None, "k7_n32": 327.3e6}
+PROFILED_TRAFFIC = {"k3_n64": 314.1e6, "k5_n40": 274.1e6, "k7_n32": 327.3e6}
 # the kernel each benchmark degree runs (FP64 apply)
 APPLY_KERNEL = {"k3_n64": "apply_mfma4_kernel", "k5_n40": "apply_wave_kernel",
                 "k7_n32": "apply_mfma8_kernel"}

@@ -255,12 +255,17 @@ __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
   T* s_n0 = s_t2;
   T* s_n1 = s_ty;
   const int n = tm.n, nn = n * n, nc = tm.tx;
-  // WG: CPT consecutive cells from grp * CPT (the last tile may be short);
-  // else TX cells of an x-row
+  // WG: CPT consecutive cells of the blocked order (x fastest, then (z, y)
+  // in blk x blk blocks, so the tiles that share y/z neighbours run close
+  // in time) from index grp * CPT; the last tile may be short.  Else TX
+  // cells of an x-row.
+  TileMap t1 = tm;
+  t1.tx = 1;
+  t1.ntx = n;
   const int c0 = WG ? grp * CPT : tile_first_cell(tm, grp);
   const bool act = WG ? (tid < CPT * N2 && c0 + tid / N2 < nn * n) : (tid < nc * N2);
   const int cl = act ? tid / N2 : 0, ln = tid - cl * N2;
-  const int c = c0 + cl;
+  const int c = WG ? tile_first_cell(t1, c0 + cl) : c0 + cl;
   // cell coordinates: per lane with WG, else the tile's row plus cl
   const int cx = WG ? c % n : c0 % n + cl;
   const int cy = WG ? (c / n) % n : (c0 / n) % n;
