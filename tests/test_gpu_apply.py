@@ -31,7 +31,7 @@ def test_apply_matches_assembled_matrix(k, n):
     np.testing.assert_allclose(v, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
 
 
-@pytest.mark.parametrize("k,n", [(2, 3), (3, 5), (7, 3)])
+@pytest.mark.parametrize("k,n", [(2, 3), (3, 5), (4, 6), (5, 6), (6, 4), (7, 3)])
 def test_residual_matches(k, n):
     from paper_2407_09621_amd import Problem
     announce("residual", k, n)
