@@ -548,15 +548,22 @@ __global__ __launch_bounds__(kThreads) void patch_fd_lp_kernel(
   }
   psync();
   {
-    LineMV<GP, BF, EC> mt, mf;
-    mt.load(S + tz * G2, G, true);
-    mf.load(S + tz * G2, G, false);
+    // the transposed and the plain matrix one after the other: a scheduling
+    // barrier keeps the second one's fragments from being loaded (and held)
+    // while the first is in use
+    {
+      LineMV<GP, BF, EC> mt;
+      mt.load(S + tz * G2, G, true);
 #pragma unroll
-    for (int a = 0; a < G; ++a) in[a] = act ? X[o2 + a * G2] : 0.0f;
-    line_mv<G>(mt, in, out);
+      for (int a = 0; a < G; ++a) in[a] = act ? X[o2 + a * G2] : 0.0f;
+      line_mv<G>(mt, in, out);
+    }
     const float lij = act ? s_l[tx * G + la] + s_l[ty * G + lb] : 1.0f;
 #pragma unroll
     for (int a = 0; a < G; ++a) in[a] = act ? out[a] / (h * (lij + s_l[tz * G + a])) : 0.0f;
+    __builtin_amdgcn_sched_barrier(0);
+    LineMV<GP, BF, EC> mf;
+    mf.load(S + tz * G2, G, false);
     line_mv<G>(mf, in, out);
     if (act)
 #pragma unroll
