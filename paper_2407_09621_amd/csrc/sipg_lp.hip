@@ -249,21 +249,32 @@ __device__ __forceinline__ int tile_first_cell(const TileMapLp& m, int t) {
 // one lane per 1D line); the N x N products of the three stages run as
 // LineMV calls of all 64 lanes, face traces and rank-2 terms in FP32.
 // ---------------------------------------------------------------------------
-template <int N, bool BF, bool EC, bool RES>
+// WG: the workgroup's waves share one tile of kThreads / N^2 cells of the
+// blocked order, with workgroup barriers (as in the FP64 vector kernel).
+template <int N, bool BF, bool EC, bool RES, bool WG = false>
 __global__ __launch_bounds__(kThreads) void apply_lp_kernel(
     Batch<float> B, const float* __restrict__ tab, TableLayout lay) {
   constexpr int N2 = N * N, N3 = N2 * N, CPB = (64 / N2) > 0 ? 64 / N2 : 1;
   constexpr int NP = Pad<N>::value;
   constexpr int WAVES = kThreads / 64;
-  __shared__ float s_t1_all[WAVES * CPB * N3];
-  __shared__ float s_t2_all[WAVES * CPB * N3];
-  __shared__ float s_ty_all[WAVES * CPB * 4 * N2];
-  __shared__ float s_tz_all[WAVES * CPB * 4 * N2];
-  __shared__ float s_tzm_all[WAVES * CPB * 4 * N2];
+  constexpr int CPT = kThreads / N2;
+  constexpr int CS = WG ? CPT : CPB;
+  constexpr int SLOTS = WG ? CPT : WAVES * CPB;
+  __shared__ float s_t1_all[SLOTS * N3];
+  __shared__ float s_t2_all[SLOTS * N3];
+  __shared__ float s_ty_all[SLOTS * 4 * N2];
+  __shared__ float s_tz_all[SLOTS * 4 * N2];
+  __shared__ float s_tzm_all[SLOTS * 4 * N2];
+  auto lds_sync = [&]() {
+    if constexpr (WG) __syncthreads();
+    else wave_lds_sync();
+  };
 
-  const int tid = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int gi = xcd_remap(blockIdx.x, gridDim.x) * WAVES + wave;
-  if (gi >= B.start[B.count]) return;  // wave-uniform
+  const int tid = WG ? threadIdx.x : (threadIdx.x & 63), wave = WG ? 0 : (threadIdx.x >> 6);
+  const int gi = __builtin_amdgcn_readfirstlane(WG ? xcd_remap(blockIdx.x, gridDim.x)
+                                                   : xcd_remap(blockIdx.x, gridDim.x) * WAVES + wave);
+  // wave-uniform (workgroup-uniform with WG)
+  if (gi >= B.start[B.count]) return;
   const int pb = batch_find(B, gi);
   const int grp = gi - B.start[pb];
   const float* __restrict__ u = B.d[pb].in;
@@ -276,17 +287,22 @@ __global__ __launch_bounds__(kThreads) void apply_lp_kernel(
   tm.ntx = B.d[pb].a1;
   tm.blk = B.d[pb].a2;
   tm.ngroups = B.start[pb + 1] - B.start[pb];
-  float* s_t1 = s_t1_all + wave * (CPB * N3);
-  float* s_t2 = s_t2_all + wave * (CPB * N3);
-  float* s_ty = s_ty_all + wave * (CPB * 4 * N2);
-  float* s_tz = s_tz_all + wave * (CPB * 4 * N2);
-  float* s_tzm = s_tzm_all + wave * (CPB * 4 * N2);
+  float* s_t1 = s_t1_all + wave * (CS * N3);
+  float* s_t2 = s_t2_all + wave * (CS * N3);
+  float* s_ty = s_ty_all + wave * (CS * 4 * N2);
+  float* s_tz = s_tz_all + wave * (CS * 4 * N2);
+  float* s_tzm = s_tzm_all + wave * (CS * 4 * N2);
   const int n = tm.n, nn = n * n, nc = tm.tx;
-  const int c0 = tile_first_cell(tm, grp);
-  const int cy = (c0 / n) % n, cz = c0 / nn, cx0 = c0 % n;
-  const bool act = tid < nc * N2;
+  TileMapLp t1 = tm;
+  t1.tx = 1;
+  t1.ntx = n;
+  const int c0 = WG ? grp * CPT : tile_first_cell(tm, grp);
+  const bool act = WG ? (tid < CPT * N2 && c0 + tid / N2 < nn * n) : (tid < nc * N2);
   const int cl = act ? tid / N2 : 0, ln = tid - cl * N2;
-  const int c = c0 + cl, cx = cx0 + cl;
+  const int c = WG ? tile_first_cell(t1, c0 + cl) : c0 + cl;
+  const int cx = WG ? c % n : c0 % n + cl;
+  const int cy = WG ? (c / n) % n : (c0 / n) % n;
+  const int cz = WG ? c / nn : c0 / nn;
   const int lp = ln % N, lq = ln / N;
 
   const float* __restrict__ gM = tab + lay.mass;
@@ -366,7 +382,7 @@ __global__ __launch_bounds__(kThreads) void apply_lp_kernel(
       tz[3 * N2 + ln] = g3;
     }
   }
-  wave_lds_sync();
+  lds_sync();
 
   // ---- y stage: lines (i, l) = (lp, lq); Mx on the z traces at (i, j)
   {
@@ -410,7 +426,7 @@ __global__ __launch_bounds__(kThreads) void apply_lp_kernel(
       }
     }
   }
-  wave_lds_sync();
+  lds_sync();
 
   // ---- z stage: lines (i, j) = ln
   {
@@ -605,6 +621,8 @@ __global__ __launch_bounds__(kThreads) void patch_fd_lp_kernel(
 template <int N, bool BF, bool EC>
 hipError_t apply_lp_impl(const ApplyJob* jobs, int count, const DevTab& t, hipStream_t s) {
   constexpr int CPW = (64 / (N * N)) > 0 ? 64 / (N * N) : 1;
+  constexpr bool WG = (N >= 5 && N <= 7);  // workgroup tiles of 10, 7, 5 cells
+  constexpr int CPT = kThreads / (N * N);
   if (count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
   Batch<float> B;
   const bool residual = jobs[0].b != nullptr;
@@ -626,18 +644,20 @@ hipError_t apply_lp_impl(const ApplyJob* jobs, int count, const DevTab& t, hipSt
     d.a0 = tx;
     d.a1 = j.n / tx;
     d.a2 = (j.order > 0 && j.n % j.order == 0) ? j.order : ((j.n % 8 == 0) ? 8 : 1);
-    const int64_t items = (int64_t)d.a1 * j.n * j.n;
+    const int64_t cells = (int64_t)j.n * j.n * j.n;
+    const int64_t items = WG ? (cells + CPT - 1) / CPT : (int64_t)d.a1 * j.n * j.n;
     if (B.start[i] + items > ((int64_t)1 << 30)) return hipErrorInvalidValue;
     B.start[i + 1] = B.start[i] + (int)items;
   }
   for (int i = count; i < kMaxBatch; ++i) B.start[i + 1] = B.start[count];
-  const int waves = kThreads / 64;
-  const int grid = (B.start[count] + waves - 1) / waves;
+  const int per_block = WG ? 1 : kThreads / 64;
+  const int grid = (B.start[count] + per_block - 1) / per_block;
+  if (grid == 0) return hipSuccess;
   if (residual)
-    hipLaunchKernelGGL((apply_lp_kernel<N, BF, EC, true>), dim3(grid), dim3(kThreads), 0, s, B,
-                       t.tabf, t.lay);
+    hipLaunchKernelGGL((apply_lp_kernel<N, BF, EC, true, WG>), dim3(grid), dim3(kThreads), 0, s,
+                       B, t.tabf, t.lay);
   else
-    hipLaunchKernelGGL((apply_lp_kernel<N, BF, EC, false>), dim3(grid), dim3(kThreads), 0, s,
+    hipLaunchKernelGGL((apply_lp_kernel<N, BF, EC, false, WG>), dim3(grid), dim3(kThreads), 0, s,
                        B, t.tabf, t.lay);
   return hipGetLastError();
 }
