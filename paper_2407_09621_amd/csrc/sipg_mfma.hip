@@ -378,6 +378,9 @@ __global__ __launch_bounds__(kT) void apply_mfma8_kernel(Batch<double> B,
   mul_normal<2>(M, w, t3, true);      // Mz, (y, x, z)
   double* dst = v + (size_t)c * 512 + oXYZ;
   const double* bsrc = RES ? bv + (size_t)c * 512 + oXYZ : nullptr;
+  // the residual's b is read here, not with the other loads: holding it
+  // through the products would cost a wave per SIMD
+  if (RES) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const double o = h * gather(t3[r], s01);  // (x, y, z)
