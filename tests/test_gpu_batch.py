@@ -201,6 +201,20 @@ def test_batch_zero_rhs_and_restart_growth():
         assert infos[1]["rel_res_true"] < 1e-10
 
 
+@pytest.mark.parametrize("k,n", [(5, 16), (7, 8)])
+def test_autotune_keeps_apply(k, n):
+    """The cell order the tuner picks changes which wave or workgroup tile
+    handles a cell, never the cell's arithmetic: results stay bit-identical
+    (degree 5: workgroup tiles; degree 7: matrix cores)."""
+    from paper_2407_09621_amd import Problem
+    announce("autotune apply", k, n)
+    P = Problem(k, n, n_levels=1)
+    u = to_gpu(inputs.uniform_vector(P.n_dofs(), 6))
+    v0 = to_cpu(P.apply(u))
+    assert P.autotune() in (1, 2, 4, 8)
+    assert np.array_equal(to_cpu(P.apply(u)), v0)
+
+
 def test_autotune_keeps_results():
     from paper_2407_09621_amd import Batch, Problem
     announce("autotune")
