@@ -1,5 +1,7 @@
 """Flexible GMRES with right preconditioning (Saad 1993), as used in Sec. 7.1
-and 7.2 of the paper as the FP64 outer iteration.
+and 7.2 of the paper as the FP64 outer iteration, and the non-flexible
+right-preconditioned GMRES it is compared with (Sec. 7.2, the robustness
+argument for FGMRES).
 
 Readings: Arnoldi by modified Gram-Schmidt; x0 = 0; the iteration stops once
 the Arnoldi residual estimate |g_{j+1}| <= rtol * ||b||_2 (the paper stops on
@@ -10,8 +12,13 @@ import numpy as np
 
 
 def fgmres(apply_A, b, precond, rtol=1e-10, restart=30, max_iters=300, x0=None,
-           on_iteration=None, on_estimate=None):
+           on_iteration=None, on_estimate=None, flexible=True):
     """Solve A x = b.  ``precond(v)`` may change from step to step (flexible).
+
+    ``flexible=False`` is right-preconditioned GMRES: the same Arnoldi process
+    on A M, but only the basis V is kept and the update is x += M(V y), one
+    more preconditioner application, which equals the flexible update only
+    when M is the same linear map in every step.
 
     Returns (x, info) with info = dict(iterations, rel_res_est, rel_res_true,
     history, converged).  ``on_iteration(j, z)`` may inspect (and replace) the
@@ -78,7 +85,10 @@ def fgmres(apply_A, b, precond, rtol=1e-10, restart=30, max_iters=300, x0=None,
         y = np.zeros(j_done)
         for i in range(j_done - 1, -1, -1):
             y[i] = (g[i] - H[i, i + 1:j_done] @ y[i + 1:]) / H[i, i]
-        x = x + Z[:j_done].T @ y
+        if flexible:
+            x = x + Z[:j_done].T @ y
+        else:
+            x = x + precond(V[:j_done].T @ y)
         if abs(g[j_done]) <= tol:
             converged = True
     rel_true = float(np.linalg.norm(b - apply_A(x)) / nb)

@@ -17,6 +17,10 @@ Readings of points the paper leaves open (the smoother is only named
   Pre- and post-smoothing use the same order (so the preconditioner is not
   symmetric, as the paper notes for the parallel multiplicative smoother).
 * V(2, 2): two pre- and two post-sweeps.  Coarse solve: exact.
+* Additive variant (for the comparison the paper draws when it explains why
+  the multiplicative smoother makes the preconditioner non-symmetric): one
+  residual per sweep, every patch's exact local correction summed, the sum
+  damped by omega (1/8 by default: every cell lies in 8 vertex patches).
 """
 import numpy as np
 import scipy.linalg as sla
@@ -99,10 +103,10 @@ def patch_type(n, v):
 
 
 class Level:
-    def __init__(self, n, k):
+    def __init__(self, n, k, penalty_scale=1.0):
         self.n = n
         self.k = k
-        self.A = sipg.assemble(n, k)
+        self.A = sipg.assemble(n, k, penalty_scale=penalty_scale)
         self.patches = vertex_patches(n)
         self._chol = {}
 
@@ -132,10 +136,24 @@ def smooth(level, x, b, sweeps):
     return x
 
 
+def smooth_additive(level, x, b, sweeps, damping=0.125):
+    """Additive vertex-patch sweeps: x += omega sum_P R_P^T A_PP^{-1} R_P (b - A x)."""
+    x = np.array(x, dtype=np.float64, copy=True)
+    for _ in range(sweeps):
+        r = b - level.A @ x
+        c = np.zeros_like(x)
+        for v, _colour in level.patches:
+            idx = patch_dofs(level.n, level.k, v)
+            c[idx] += sla.cho_solve(level.patch_factor(v), r[idx])
+        x = x + damping * c
+    return x
+
+
 class Hierarchy:
     """Levels 0 (coarsest, n0 cells per direction) .. L-1 (finest, n)."""
 
-    def __init__(self, n, k, n_levels=None, coarsest=None):
+    def __init__(self, n, k, n_levels=None, coarsest=None, smoother="multiplicative",
+                 damping=0.125, penalty_scale=1.0):
         if coarsest is None:
             # halve while even and above 3: 2 for n = 2^L, 3 for n = 3 * 2^L
             m = n
@@ -151,7 +169,9 @@ class Hierarchy:
         if n_levels is not None:
             ns = ns[len(ns) - n_levels:]
         self.k = k
-        self.levels = [Level(m, k) for m in ns]
+        self.smoother = smoother
+        self.damping = damping
+        self.levels = [Level(m, k, penalty_scale) for m in ns]
         self.P = [None] + [prolongation(ns[i - 1], k) for i in range(1, len(ns))]
         self.coarse = spla.splu(self.levels[0].A.tocsc())
         self.nu_pre = 2
@@ -162,12 +182,17 @@ class Hierarchy:
         if l == 0:
             return self.coarse.solve(b)
         lev = self.levels[l]
-        x = smooth(lev, x, b, self.nu_pre)
+        x = self.smooth(lev, x, b, self.nu_pre)
         r = b - lev.A @ x
         rc = self.P[l].T @ r
         ec = self.vcycle(l - 1, np.zeros(rc.shape), rc)
         x = x + self.P[l] @ ec
-        return smooth(lev, x, b, self.nu_post)
+        return self.smooth(lev, x, b, self.nu_post)
+
+    def smooth(self, lev, x, b, sweeps):
+        if self.smoother == "additive":
+            return smooth_additive(lev, x, b, sweeps, self.damping)
+        return smooth(lev, x, b, sweeps)
 
     def precondition(self, v):
         """z = V-cycle on the finest level with zero initial guess."""

@@ -38,9 +38,11 @@ import scipy.sparse as sp
 from . import basis1d
 
 
-def penalty_hat(k):
-    """h-free interior penalty 2k(k+1): gamma_e = k(k+1)(1/h + 1/h) (Sec. 2)."""
-    return 2.0 * k * (k + 1)
+def penalty_hat(k, penalty_scale=1.0):
+    """h-free interior penalty 2k(k+1): gamma_e = k(k+1)(1/h + 1/h) (Sec. 2).
+    ``penalty_scale`` multiplies it (a user choice of the penalty; the scheme
+    stays symmetric for any value and coercive for values >= 1)."""
+    return 2.0 * k * (k + 1) * penalty_scale
 
 
 # ---------------------------------------------------------------------------
@@ -103,12 +105,12 @@ def _face_points(k, d, side):
     return np.array(pts), np.array(wts)
 
 
-def interior_face_blocks(k, d, h):
+def interior_face_blocks(k, d, h, penalty_scale=1.0):
     """The four blocks of the interior-face bilinear form on a face with
     normal e_d between the lower cell K- and the upper cell K+ (both of size
     h).  Returns dict with keys ('-','-'), ('-','+'), ('+','-'), ('+','+'):
     block[(t, s)][I, J] = a_e(phi_J on K_s, phi_I on K_t)."""
-    gamma = k * (k + 1) * (1.0 / h + 1.0 / h)
+    gamma = penalty_scale * k * (k + 1) * (1.0 / h + 1.0 / h)
     pm, wq = _face_points(k, d, 1.0)   # K- sees the face at xi_d = 1
     pp, _ = _face_points(k, d, 0.0)    # K+ sees it at xi_d = 0
     wq = wq * h * h
@@ -133,10 +135,10 @@ def interior_face_blocks(k, d, h):
     return blocks
 
 
-def boundary_face_block(k, d, side, h):
+def boundary_face_block(k, d, side, h, penalty_scale=1.0):
     """Boundary face xi_d = side of a cell: {v} = v, [[v]] = v n with the
     outward normal n, gamma = 2k(k+1)/h (reading: mirror cell, h- = h+)."""
-    gamma = k * (k + 1) * (1.0 / h + 1.0 / h)
+    gamma = penalty_scale * k * (k + 1) * (1.0 / h + 1.0 / h)
     p, wq = _face_points(k, d, float(side))
     wq = wq * h * h
     v, g = _tensor_basis_at(k, p, h)
@@ -166,7 +168,7 @@ def _coo_block(rows_base, cols_base, block):
     return r.ravel(), c.ravel(), d.ravel()
 
 
-def assemble(n, k, boundary_terms=True):
+def assemble(n, k, boundary_terms=True, penalty_scale=1.0):
     """Sparse CSR matrix of the SIPG form on n^3 cells of size h = 1/n:
     cell loop, interior-face loop and boundary-face loop of the matrix-free
     skeleton in Sec. 2.1 (items (ii)(a)-(d)), with each local integral
@@ -189,7 +191,7 @@ def assemble(n, k, boundary_terms=True):
 
     add(cells, cells, cell_matrix(k, h))
     for d in range(3):
-        blocks = interior_face_blocks(k, d, h)
+        blocks = interior_face_blocks(k, d, h, penalty_scale)
         lower = cells[coord[d] < n - 1]
         upper = lower + stride[d]
         add(lower, lower, blocks[('-', '-')])
@@ -198,9 +200,9 @@ def assemble(n, k, boundary_terms=True):
         add(upper, upper, blocks[('+', '+')])
         if boundary_terms:
             add(cells[coord[d] == 0], cells[coord[d] == 0],
-                boundary_face_block(k, d, 0, h))
+                boundary_face_block(k, d, 0, h, penalty_scale))
             add(cells[coord[d] == n - 1], cells[coord[d] == n - 1],
-                boundary_face_block(k, d, 1, h))
+                boundary_face_block(k, d, 1, h, penalty_scale))
     R = np.concatenate(R)
     C = np.concatenate(C)
     D = np.concatenate(D)
@@ -213,7 +215,7 @@ def assemble(n, k, boundary_terms=True):
 # Second derivation: Kronecker sum on the global tensor grid
 # ---------------------------------------------------------------------------
 
-def global_1d(n, k):
+def global_1d(n, k, penalty_scale=1.0):
     """Global 1D matrices on the line of n cells, size nN x nN:
     M = h * blockdiag(Mhat) and L = (1/h) * (Khat blocks + 1D face terms).
 
@@ -226,7 +228,7 @@ def global_1d(n, k):
     N = k + 1
     Mh, Kh = basis1d.mass_stiffness(k)
     s0, s1, d0, d1 = basis1d.end_vectors(k)
-    g = penalty_hat(k)
+    g = penalty_hat(k, penalty_scale)
     o = np.outer
     LL = g * o(s1, s1) - 0.5 * (o(s1, d1) + o(d1, s1))
     LR = -g * o(s1, s0) - 0.5 * o(s1, d0) + 0.5 * o(d1, s0)
@@ -271,10 +273,10 @@ def _along(U, A, axis):
     return np.moveaxis(V.reshape(shp), -1, axis)
 
 
-def kron_apply(u, n, k):
+def kron_apply(u, n, k, penalty_scale=1.0):
     """v = A u with A = Mz(x)My(x)Lx + Mz(x)Ly(x)Mx + Lz(x)My(x)Mx applied
     factor by factor on the global tensor grid (eq. tensorproduct_3d)."""
-    M, L = global_1d(n, k)
+    M, L = global_1d(n, k, penalty_scale)
     M = sp.csr_matrix(M)
     L = sp.csr_matrix(L)
     U = to_tensor(u, n, k)

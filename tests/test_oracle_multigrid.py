@@ -131,3 +131,93 @@ def test_fgmres_multigrid_small_problem():
     assert info["iterations"] <= 5 and info["rel_res_true"] < 1e-10
     xs = spla.spsolve(A.tocsc(), b)
     assert np.linalg.norm(x - xs) < 1e-9 * np.linalg.norm(xs)
+
+
+def _map_matrix(fun, n_dofs):
+    """Matrix of a linear map given as a function (column by column)."""
+    return np.stack([fun(e) for e in np.eye(n_dofs)], axis=1)
+
+
+def test_additive_sweep_is_damped_sum_of_explicit_patch_inverses():
+    """Brute force on a tiny mesh: one additive sweep from x = 0 is
+    omega * sum_P E_P inv(A_PP) E_P^T b with the patch inverses formed by
+    explicit dense inversion, which makes the sweep a symmetric map; a
+    multiplicative sweep is not symmetric (the reason Sec. 7.2 gives for
+    FGMRES instead of CG)."""
+    n, k, om = 3, 1, 0.3
+    lev = multigrid.Level(n, k)
+    A = lev.A.toarray()
+    nd = A.shape[0]
+    B = np.zeros((nd, nd))
+    for v, _ in lev.patches:
+        idx = multigrid.patch_dofs(n, k, v)
+        B[np.ix_(idx, idx)] += np.linalg.inv(A[np.ix_(idx, idx)])
+    S = _map_matrix(lambda b: multigrid.smooth_additive(lev, np.zeros(nd), b, 1, om), nd)
+    np.testing.assert_allclose(S, om * B, atol=1e-12 * np.abs(om * B).max())
+    assert np.abs(S - S.T).max() < 1e-12 * np.abs(S).max()
+    Sm = _map_matrix(lambda b: multigrid.smooth(lev, np.zeros(nd), b, 1), nd)
+    assert np.abs(Sm - Sm.T).max() > 1e-3 * np.abs(Sm).max()
+
+
+def test_additive_single_patch_undamped_is_exact_solve():
+    n, k = 2, 2
+    lev = multigrid.Level(n, k)
+    b = inputs.uniform_vector(lev.A.shape[0], 3)
+    x = multigrid.smooth_additive(lev, np.zeros_like(b), b, 1, damping=1.0)
+    np.testing.assert_allclose(lev.A @ x, b, atol=1e-12 * np.abs(b).max())
+
+
+def test_additive_vcycle_preconditions_but_weaker_than_multiplicative():
+    """The damped additive smoother (omega = 1/8, every cell in 8 patches)
+    still gives a convergent FGMRES, with several times the iterations of the
+    multiplicative one."""
+    n, k = 4, 2
+    b = rhs.rhs(rhs.single_sine(), n, k)
+    Hm = multigrid.Hierarchy(n, k)
+    Ha = multigrid.Hierarchy(n, k, smoother="additive")
+    A = Hm.levels[-1].A
+    _, im = fgmres.fgmres(lambda q: A @ q, b, Hm.precondition, rtol=1e-10)
+    xa, ia = fgmres.fgmres(lambda q: A @ q, b, Ha.precondition, rtol=1e-10, max_iters=100)
+    assert im["converged"] and ia["converged"]
+    assert ia["rel_res_true"] < 1e-9
+    assert ia["iterations"] >= 2 * im["iterations"]
+
+
+def test_gmres_equals_fgmres_for_a_fixed_linear_preconditioner():
+    """With the same linear M in every step (here a fixed SPD matrix), right-
+    preconditioned GMRES (x += M V y) and FGMRES (x += Z y) produce the same
+    iterates; an update that forgot M (x += V y) would not solve A x = b."""
+    n, k = 2, 1
+    A = sipg.assemble(n, k).toarray()
+    nd = A.shape[0]
+    rng = np.random.default_rng(4)
+    Q = rng.standard_normal((nd, nd))
+    M = np.diag(1.0 / np.diag(A)) + 1e-3 * (Q @ Q.T) / nd
+    b = inputs.uniform_vector(nd, 8)
+    for m in (5, 40):
+        xf, inf = fgmres.fgmres(lambda q: A @ q, b, lambda v: M @ v, rtol=1e-12, restart=m)
+        xg, ing = fgmres.fgmres(lambda q: A @ q, b, lambda v: M @ v, rtol=1e-12, restart=m,
+                                flexible=False)
+        assert inf["converged"] and ing["converged"]
+        assert abs(inf["iterations"] - ing["iterations"]) <= 1
+        np.testing.assert_allclose(xg, xf, atol=1e-9 * np.abs(xf).max())
+        assert np.linalg.norm(b - A @ xg) <= 1e-11 * np.linalg.norm(b)
+
+
+def test_gmres_loses_accuracy_with_a_varying_preconditioner():
+    """A preconditioner that differs from step to step (a fixed M plus a
+    step-dependent perturbation): FGMRES still reaches the tolerance in the
+    true residual, GMRES's final update M(V y) does not match the Arnoldi
+    relation and its true residual stays above the estimate (Sec. 7.2)."""
+    n, k = 2, 1
+    A = sipg.assemble(n, k).toarray()
+    nd = A.shape[0]
+    Minv = np.diag(1.0 / np.diag(A))
+    rng = np.random.default_rng(6)
+    def prec(v):
+        return Minv @ v * (1.0 + 0.2 * rng.uniform(-1, 1, nd))
+    b = inputs.uniform_vector(nd, 9)
+    xf, inf = fgmres.fgmres(lambda q: A @ q, b, prec, rtol=1e-10, restart=60)
+    xg, ing = fgmres.fgmres(lambda q: A @ q, b, prec, rtol=1e-10, restart=60, flexible=False)
+    assert inf["converged"] and inf["rel_res_true"] < 1e-9
+    assert ing["rel_res_true"] > 100 * ing["rel_res_est"]

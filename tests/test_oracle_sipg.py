@@ -29,13 +29,17 @@ def test_constants_annihilated_without_boundary_faces(k, n):
     assert np.abs(A @ one).max() <= 1e-13 * abs(A).max()
 
 
-@pytest.mark.parametrize("k,n", [(1, 1), (1, 4), (2, 3), (3, 2), (4, 2)])
-def test_energy_closed_forms(k, n):
+@pytest.mark.parametrize("k,n,s", [(1, 1, 1.0), (1, 4, 1.0), (2, 3, 1.0), (3, 2, 1.0),
+                                   (4, 2, 1.0), (2, 3, 2.5), (3, 2, 7.0)])
+def test_energy_closed_forms(k, n, s):
     """Exact values of the form for globally smooth functions (no interior
-    jumps), gamma = 2k(k+1) n:  a(1,1) = 6 gamma, a(x,x) = 7 gamma/3 - 1,
-    a(x,y) = 3 gamma/2."""
-    A = sipg.assemble(n, k)
-    g = 2 * k * (k + 1) * n
+    jumps), gamma = s 2k(k+1) n (s the penalty scale):  a(1,1) = 6 gamma,
+    a(x,x) = 7 gamma/3 - 1, a(x,y) = 3 gamma/2 (only boundary faces carry
+    jumps: int_dOmega 1 = 6, int_dOmega x^2 = 7/3, int x dn x = 1,
+    int_dOmega x y = 3/2, int y dn x + x dn y = 3/2 - 3/2 = 0 ... computed
+    from the six faces of the unit cube)."""
+    A = sipg.assemble(n, k, penalty_scale=s)
+    g = s * 2 * k * (k + 1) * n
     one = np.ones(A.shape[0])
     X = _interp(lambda x, y, z: x, n, k)
     Y = _interp(lambda x, y, z: y, n, k)
@@ -44,16 +48,18 @@ def test_energy_closed_forms(k, n):
     assert abs(Y @ (A @ X) - 1.5 * g) < 1e-10 * g
 
 
-@pytest.mark.parametrize("k,n", [(1, 2), (2, 3), (3, 3), (4, 2), (5, 2), (7, 2)])
-def test_quadrature_assembly_equals_kronecker_sum(k, n):
-    A = sipg.assemble(n, k)
+@pytest.mark.parametrize("k,n,s", [(1, 2, 1.0), (2, 3, 1.0), (3, 3, 1.0), (4, 2, 1.0),
+                                   (5, 2, 1.0), (7, 2, 1.0), (3, 3, 3.0)])
+def test_quadrature_assembly_equals_kronecker_sum(k, n, s):
+    A = sipg.assemble(n, k, penalty_scale=s)
     u = inputs.uniform_vector(A.shape[0], seed=100 + k)
     v = A @ u
-    w = sipg.kron_apply(u, n, k)
+    w = sipg.kron_apply(u, n, k, penalty_scale=s)
     assert np.linalg.norm(v - w) <= 1e-13 * np.linalg.norm(v)
-    rows = np.random.default_rng(k).choice(A.shape[0], 40, replace=False)
-    np.testing.assert_allclose(sipg.apply_rows(u, n, k, rows), v[rows],
-                               rtol=0, atol=1e-12 * np.abs(v).max())
+    if s == 1.0:
+        rows = np.random.default_rng(k).choice(A.shape[0], 40, replace=False)
+        np.testing.assert_allclose(sipg.apply_rows(u, n, k, rows), v[rows],
+                                   rtol=0, atol=1e-12 * np.abs(v).max())
 
 
 @pytest.mark.parametrize("k", [2, 3])
@@ -78,6 +84,19 @@ def test_l2_convergence_order(k, ns):
         errs.append(rhs.l2_error(rhs.single_sine(), x, n, k))
     rate = np.log(errs[-2] / errs[-1]) / np.log(ns[-1] / ns[-2])
     assert abs(rate - (k + 1)) < 0.35, (errs, rate)
+
+
+@pytest.mark.parametrize("k,n,tol", [(1, 2, 5e-4), (3, 2, 1e-6), (5, 2, 1e-9)])
+def test_l2_error_absolute_scale(k, n, tol):
+    """||u - 0||_L2 of u = sin(pi x) sin(pi y) sin(pi z) is sqrt(1/8) (each
+    factor has mean square 1/2), and of two orthogonal modes
+    a1 s(1,1,1) + a2 s(2,1,3) it is sqrt((a1^2 + a2^2) / 8).  The (k+3)-point
+    rule is not exact for sines; the bound is its quadrature error, which
+    falls with k (the symmetric single mode is integrated to rounding)."""
+    zero = np.zeros(sipg.n_dofs(n, k))
+    assert abs(rhs.l2_error(rhs.single_sine(), zero, n, k) - np.sqrt(1 / 8)) < 1e-12
+    two = rhs.SineModes([0.7, -1.3], [(1, 1, 1), (2, 1, 3)])
+    assert abs(rhs.l2_error(two, zero, n, k) - np.sqrt((0.49 + 1.69) / 8)) < tol
 
 
 def test_rhs_and_l2_of_polynomials():
