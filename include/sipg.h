@@ -17,7 +17,10 @@
  * Vectors are cell-blocked: cell c = cx + n*cy + n*n*cz owns the N^3
  * contiguous entries c*N^3 + i + N*j + N*N*l (x fastest).  Every vector
  * argument is a DEVICE pointer owned by the caller, holding sipg_n_dofs()
- * entries, 8-byte aligned (FP64) or 4-byte aligned (FP32).  Input and output
+ * entries, aligned to its element size (8 bytes FP64, 4 bytes FP32): the
+ * kernels issue element-sized loads, so sub-views of larger tensors are
+ * valid arguments; 256-byte alignment (what hipMalloc and torch return)
+ * gives the coalescing the throughput figures assume.  Input and output
  * vectors of one call must not overlap unless the entry point says so.
  * Calls are asynchronous on the given HIP stream (NULL = default stream)
  * unless stated otherwise; the host arguments are read before return.
@@ -29,6 +32,7 @@
 #ifndef SIPG_H
 #define SIPG_H
 
+#include <stddef.h>
 #include <stdint.h>
 #include <hip/hip_runtime_api.h>
 
@@ -53,23 +57,54 @@ typedef enum {
   SIPG_BF16 = 3   /* FP32 storage, BF16 products with FP32 accumulation */
 } sipg_precision;
 
+/* Device allocator callbacks: alloc returns `bytes` of device memory
+ * aligned to 256 bytes (NULL on failure) usable on `stream`; dealloc
+ * releases a block alloc returned.  `ctx` is passed through. */
+typedef void* (*sipg_alloc_fn)(size_t bytes, hipStream_t stream, void* ctx);
+typedef void (*sipg_dealloc_fn)(void* ptr, hipStream_t stream, void* ctx);
+
 typedef struct {
   int k;                 /* polynomial degree, 1..7 */
   int n_cells;           /* cells per direction on the finest level */
   int n_levels;          /* 0: coarsen down to 1, 2 or 3 cells per direction */
   int mg_precision;      /* sipg_precision of the V-cycle (preconditioner) */
-  int error_correction;  /* 1: split-operand error correction in FP16/BF16 */
+  int error_correction;  /* FP16/BF16 products: 0 none; 1 both operands split
+                            into hi + 2^-s lo (Alg. matmul, s = 11 FP16, 8
+                            BF16); 2 only the constant matrix operand split
+                            (two products instead of three) */
   int nu_pre;            /* pre-smoothing sweeps (2 for V(2,2)) */
   int nu_post;           /* post-smoothing sweeps */
+  int smoother;          /* 0: multiplicative vertex-patch smoother (colour by
+                            colour, a fresh residual per colour; the paper's
+                            choice, Sec. 7.1); 1: additive (one residual per
+                            sweep, all patch corrections summed and damped;
+                            FP64 V-cycles only) */
+  double damping;        /* additive smoother: x += damping * sum_P corrections
+                            (0 means 1/8: every cell lies in 8 patches) */
+  double penalty_scale;  /* penalty gamma = penalty_scale * k(k+1)(1/h+ + 1/h-)
+                            (Sec. 2); 0 means 1.  Must lie in [1, 100]: below
+                            1 the form need not stay coercive */
+  sipg_alloc_fn alloc;   /* NULL: hipMalloc / hipFree.  Otherwise every block
+                            of the handle's workspace comes from alloc (on the
+                            stream given to sipg_create) and goes back through
+                            dealloc, e.g. torch's caching allocator */
+  sipg_dealloc_fn dealloc;
+  void* alloc_ctx;
 } sipg_config;
 
 typedef struct sipg_problem sipg_problem;
 
 /* Build the level hierarchy, 1D tables and workspace (Sec. 2.1, Sec. 7.1).
  * The penalty is gamma = k(k+1)(1/h+ + 1/h-) = 2k(k+1)/h on every face
- * (Sec. 2).  Requires n_cells = n0 * 2^(L-1) with n0 in {1, 2, 3}.  The
- * handle owns its workspace (freed by sipg_destroy).  Synchronous. */
-sipg_status sipg_create(const sipg_config* cfg, sipg_problem** out);
+ * (Sec. 2), times cfg->penalty_scale.  Requires n_cells = n0 * 2^(L-1); the
+ * exact coarse solve needs n0 in {1, 2, 3}.  mg_precision SIPG_BF16 with
+ * error_correction 0 is refused (SIPG_ERR_UNSUPPORTED) for k >= 5: with the
+ * 1D operator rounded to 8 significand bits the preconditioned iteration
+ * stalls there (use error_correction 1 or 2).  The additive smoother is
+ * refused for mg_precision other than SIPG_F64.  The handle owns its workspace,
+ * allocated on `stream` through cfg->alloc when given (freed by
+ * sipg_destroy).  Synchronizes `stream`. */
+sipg_status sipg_create(const sipg_config* cfg, hipStream_t stream, sipg_problem** out);
 
 /* Free the handle and its workspace.  NULL-safe.  Synchronizes the device. */
 void sipg_destroy(sipg_problem* p);
@@ -88,13 +123,16 @@ sipg_status sipg_apply(sipg_problem* p, int level, const double* u, double* v,
 /* v = A_l u with FP32 vectors in a reduced-precision arithmetic (Sec. 5,
  * Sec. 7.1): precision SIPG_F32 (FP32 throughout), SIPG_F16 or SIPG_BF16
  * (1D contractions on the matrix cores with FP16/BF16 operands and FP32
- * accumulation; FP16 lines are scaled by powers of two into range).  ec = 1
- * adds the split-operand error correction of Alg. matmul (ignored for F32).
+ * accumulation; FP16 lines are scaled by powers of two into range).  ec as
+ * sipg_config.error_correction: 1 the split-operand error correction of
+ * Alg. matmul, 2 only the matrix operand split (ignored for F32).
  * u, v: n_dofs(level) floats, must not overlap. */
 sipg_status sipg_apply_lp(sipg_problem* p, int level, const float* u, float* v,
                           int precision, int ec, hipStream_t stream);
 
-/* r = b - A_l x in FP64.  r must not overlap x or b. */
+/* r = b - A_l x in FP64: the defect that Alg. v_cycle restricts to the
+ * coarser level and the smoother (Sec. 7.1) corrects, with A_l the operator
+ * of sipg_apply.  r must not overlap x or b. */
 sipg_status sipg_residual(sipg_problem* p, int level, const double* b,
                           const double* x, double* r, hipStream_t stream);
 
@@ -112,6 +150,18 @@ sipg_status sipg_smooth(sipg_problem* p, int level, double* x, const double* b,
  * overlap. */
 sipg_status sipg_patch_correct(sipg_problem* p, int level, int colour,
                                const double* r, double* x, hipStream_t stream);
+
+/* The smoother and one colour step of it on FP32 vectors, in the handle's
+ * reduced precision (mg_precision SIPG_F32, SIPG_F16 or SIPG_BF16 with its
+ * error_correction; SIPG_ERR_ARG for an FP64 handle): the residual through
+ * the kernels of sipg_apply_lp, the patch solves with the six 2N x 2N
+ * eigenvector contractions of the fast diagonalization on the matrix cores
+ * (FP32 vector arithmetic for SIPG_F32), FP32 accumulation (Sec. 5, 7.1).
+ * Same contracts as sipg_smooth and sipg_patch_correct. */
+sipg_status sipg_smooth_lp(sipg_problem* p, int level, float* x, const float* b, int sweeps,
+                           hipStream_t stream);
+sipg_status sipg_patch_correct_lp(sipg_problem* p, int level, int colour, const float* r,
+                                  float* x, hipStream_t stream);
 
 /* Level transfers (canonical embedding of nested spaces and its transpose;
  * Alg. v_cycle coarsen / coarse-grid correction).  `level` is the FINE
@@ -135,6 +185,15 @@ sipg_status sipg_coarse_solve(sipg_problem* p, const double* b, double* x,
 sipg_status sipg_vcycle(sipg_problem* p, int level, double* x, const double* b,
                         hipStream_t stream);
 
+typedef enum {
+  SIPG_FGMRES = 0,  /* flexible GMRES: keeps every preconditioned vector z_j and
+                       forms x += Z y (Saad 1993; the paper's solver, Sec. 7) */
+  SIPG_GMRES = 1    /* right-preconditioned GMRES: keeps only the Arnoldi basis
+                       and forms x += M(V y) with one more V-cycle, which
+                       assumes the same linear M in every step (the
+                       comparison of Sec. 7.2, Fig. fgmres_vs_gmres) */
+} sipg_krylov_variant;
+
 typedef struct {
   double rtol;        /* stop when |Arnoldi residual| <= rtol * ||b||_2 */
   int restart;        /* Krylov dimension before restart (<= 64) */
@@ -143,6 +202,7 @@ typedef struct {
   int log_history;    /* 1: record the residual estimate of every iteration */
   double stagnation;  /* learned stage: switch it off after an iteration whose
                          estimate falls by less than this factor (0: 0.9) */
+  int variant;        /* sipg_krylov_variant (0: FGMRES) */
 } sipg_solve_opts;
 
 typedef struct {
@@ -158,9 +218,14 @@ typedef struct {
 
 /* Solve A x = b on the finest level with right-preconditioned flexible GMRES
  * (Saad 1993; Sec. 7.1-7.2), FP64 outer iteration and Gram-Schmidt
- * (classical, twice), preconditioner = one V-cycle from zero.  x is the
- * initial guess on entry (pass zeros for x0 = 0) and the solution on return.
- * Blocks until done.  Returns SIPG_ERR_NOT_CONVERGED if max_iters is hit. */
+ * (classical, twice), preconditioner = one V-cycle from zero (opts->variant
+ * SIPG_GMRES: the non-flexible form).  x is the initial guess on entry (pass
+ * zeros for x0 = 0) and the solution on return.  A NaN or Inf in a
+ * preconditioned vector switches that step to the plain V-cycle (learned
+ * stage on) or to the identity (info->fell_back = 1).  Device scalars reach
+ * the host through a pinned buffer by copies ordered on `stream`, which is
+ * synchronized once per Krylov step.  Blocks until done.  Returns
+ * SIPG_ERR_NOT_CONVERGED if max_iters is hit. */
 sipg_status sipg_fgmres(sipg_problem* p, double* x, const double* b,
                         const sipg_solve_opts* opts, sipg_solve_info* info,
                         hipStream_t stream);
@@ -197,7 +262,9 @@ sipg_status sipg_autotune(sipg_problem* p, int level, const double* u, double* v
  * launches that each cover up to 16 problems of one degree. */
 typedef struct sipg_batch sipg_batch;
 
-sipg_status sipg_batch_create(const sipg_config* cfgs, int count, sipg_batch** out);
+/* Each problem is created as by sipg_create(&cfgs[i], stream, ...). */
+sipg_status sipg_batch_create(const sipg_config* cfgs, int count, hipStream_t stream,
+                              sipg_batch** out);
 void sipg_batch_destroy(sipg_batch* b);
 int sipg_batch_count(const sipg_batch* b);
 /* Borrowed handle of problem i (owned by the batch; do not destroy). */
@@ -307,6 +374,13 @@ typedef struct {
  * inside the grid).  Runs on an internal stream; blocks until done. */
 sipg_status sipg_cnn_train(sipg_problem* p, sipg_cnn* c, const sipg_cnn_train_opts* o,
                            sipg_cnn_train_info* info);
+/* Parameters and output scale to / from a file: the 8 bytes "SIPGCNN1",
+ * an int32 parameter count (SIPG_CNN_PARAMS), a float32 sigma, then the
+ * parameters as float32, all little-endian.  load checks the magic and the
+ * count (SIPG_ERR_ARG on a mismatch or a short file, SIPG_ERR_UNSUPPORTED on
+ * an I/O error) and resets the Adam state.  Synchronous. */
+sipg_status sipg_cnn_save(const sipg_cnn* c, const char* path);
+sipg_status sipg_cnn_load(sipg_cnn* c, const char* path);
 /* Use `c` as the problem's learned stage (NULL detaches).  The problem
  * borrows the handle: keep it alive while attached. */
 sipg_status sipg_cnn_attach(sipg_problem* p, sipg_cnn* c);

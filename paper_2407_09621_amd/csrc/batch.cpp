@@ -23,11 +23,12 @@ struct sipg_batch {
   std::vector<sipg_problem*> P;
   std::vector<int> nodes;          // distinct N values present
   int prec = SIPG_F64;
-  bool ec = false;
+  int ec = 0;
   int nu_pre = 2, nu_post = 2;
   hipStream_t stream = nullptr;    // internal capture stream (default priority)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   std::map<int, hipGraphExec_t> graphs;  // Krylov index j -> captured V-cycle
+  std::vector<int> graph_gen;            // krylov_gen of every problem at capture
   double* h_pinned = nullptr;            // host scalars of all problems
 };
 
@@ -263,7 +264,8 @@ sipg_status b_apply64(sipg_batch* B, const std::vector<int>& probs,
 
 extern "C" {
 
-sipg_status sipg_batch_create(const sipg_config* cfgs, int count, sipg_batch** out) {
+sipg_status sipg_batch_create(const sipg_config* cfgs, int count, hipStream_t stream,
+                              sipg_batch** out) {
   if (!cfgs || !out || count < 1 || count > 4096) return fail(SIPG_ERR_ARG, "bad batch");
   *out = nullptr;
   for (int i = 1; i < count; ++i)
@@ -271,14 +273,17 @@ sipg_status sipg_batch_create(const sipg_config* cfgs, int count, sipg_batch** o
         cfgs[i].error_correction != cfgs[0].error_correction ||
         cfgs[i].nu_pre != cfgs[0].nu_pre || cfgs[i].nu_post != cfgs[0].nu_post)
       return fail(SIPG_ERR_ARG, "all problems of a batch share precision and smoothing steps");
+  for (int i = 0; i < count; ++i)
+    if (cfgs[i].smoother != 0)
+      return fail(SIPG_ERR_UNSUPPORTED, "batches use the multiplicative smoother");
   auto* B = new sipg_batch();
   B->prec = cfgs[0].mg_precision;
-  B->ec = cfgs[0].error_correction != 0;
+  B->ec = cfgs[0].error_correction;
   B->nu_pre = cfgs[0].nu_pre;
   B->nu_post = cfgs[0].nu_post;
   for (int i = 0; i < count; ++i) {
     sipg_problem* q = nullptr;
-    sipg_status st = sipg_create(&cfgs[i], &q);
+    sipg_status st = sipg_create(&cfgs[i], stream, &q);
     if (st != SIPG_OK) {
       std::string msg = g_err;
       sipg_batch_destroy(B);
@@ -337,7 +342,7 @@ sipg_status sipg_batch_autotune(sipg_batch* B, hipStream_t s) {
       continue;
     }
     double* tmp = nullptr;
-    SIPG_TRY(dev_alloc(&tmp, q->ndofs[q->L - 1]));
+    SIPG_TRY(prob_alloc(q, &tmp, q->ndofs[q->L - 1]));
     q->order.assign(q->L, 0);
     sipg_status st = SIPG_OK;
     for (int l = 0; l < q->L && st == SIPG_OK; ++l) {
@@ -346,7 +351,8 @@ sipg_status sipg_batch_autotune(sipg_batch* B, hipStream_t s) {
       int best = 0;
       if (st == SIPG_OK) st = sipg_autotune(q, l, q->wr[l], tmp, &best, s);
     }
-    hipFree(tmp);
+    hipStreamSynchronize(s);
+    prob_free(q, tmp);
     if (st != SIPG_OK) return st;
     done[key] = q->order;
   }
@@ -407,20 +413,38 @@ sipg_status sipg_batch_solve(sipg_batch* B, double* const* x, const double* cons
   if (o->restart < 1 || o->restart > 64) return fail(SIPG_ERR_ARG, "restart must be in 1..64");
   if (o->max_iters < 1 || !(o->rtol > 0.0)) return fail(SIPG_ERR_ARG, "bad options");
   if (o->use_learned) return fail(SIPG_ERR_UNSUPPORTED, "learned stage not available in batches");
+  if (o->variant != SIPG_FGMRES) return fail(SIPG_ERR_UNSUPPORTED, "batches run FGMRES");
   const int P = (int)B->P.size();
   const int m = o->restart;
   for (int p = 0; p < P; ++p) {
     if (!x[p] || !b[p] || (const void*)x[p] == (const void*)b[p])
       return fail(SIPG_ERR_ARG, "bad vector pointer");
-    const double *oldV = B->P[p]->V, *oldZ = B->P[p]->Z;
     SIPG_TRY(ensure_krylov(B->P[p], m));
-    if (B->P[p]->V != oldV || B->P[p]->Z != oldZ) drop_graphs(B);  // Krylov space moved
     std::memset(&infos[p], 0, sizeof(sipg_solve_info));
   }
-  // work on the internal stream, ordered after the caller's stream
+  // Captured V-cycles hold Krylov addresses: they are stale once any problem
+  // reallocated its Krylov space (here or in sipg_fgmres through a borrowed
+  // handle), whether or not the new block landed at the old address.
+  {
+    std::vector<int> gen(P);
+    for (int p = 0; p < P; ++p) gen[p] = B->P[p]->krylov_gen;
+    if (gen != B->graph_gen) {
+      drop_graphs(B);
+      B->graph_gen = gen;
+    }
+  }
+  // work on the internal stream, ordered after the caller's stream; on every
+  // exit from here on the caller's stream waits for that work
   hipStream_t s = B->stream;
   SIPG_HIP(hipEventRecord(B->ev_in, s_user));
   SIPG_HIP(hipStreamWaitEvent(s, B->ev_in, 0));
+  struct Join {
+    sipg_batch* B;
+    hipStream_t s, user;
+    ~Join() {
+      if (hipEventRecord(B->ev_out, s) == hipSuccess) hipStreamWaitEvent(user, B->ev_out, 0);
+    }
+  } join{B, s, s_user};
   SIPG_HIP(hipStreamSynchronize(s));
   const auto t0 = std::chrono::steady_clock::now();
   double* hp = B->h_pinned;
@@ -626,8 +650,6 @@ sipg_status sipg_batch_solve(sipg_batch* B, double* const* x, const double* cons
     infos[p].seconds = secs;
     all_conv = all_conv && conv[p];
   }
-  SIPG_HIP(hipEventRecord(B->ev_out, s));
-  SIPG_HIP(hipStreamWaitEvent(s_user, B->ev_out, 0));
   if (!all_conv) return fail(SIPG_ERR_NOT_CONVERGED, "iteration limit reached");
   return SIPG_OK;
 }

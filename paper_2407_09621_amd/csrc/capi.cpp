@@ -3,6 +3,7 @@
 // host-side sequences of kernel launches on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -39,6 +40,17 @@ sipg_status residual(sipg_problem* p, int l, const double* b, const double* x, d
 sipg_status smooth(sipg_problem* p, int l, double* x, const double* b, int sweeps,
                    hipStream_t s) {
   if (p->n[l] < 2) return SIPG_OK;
+  if (p->cfg.smoother == 1) {  // additive: one residual, all patches, damped sum
+    for (int sw = 0; sw < sweeps; ++sw) {
+      SIPG_TRY(residual(p, l, b, x, p->wr[l], s));
+      SIPG_HIP(launch_fill(p->wc[l], 0.0, p->ndofs[l], s));
+      for (int colour = 0; colour < 8; ++colour)
+        SIPG_HIP(launch_patch_fd_f64(p->N, colour, p->wr[l], p->wc[l], p->tab, p->n[l],
+                                     level_h(p, l), s));
+      SIPG_HIP(launch_axpy(p->cfg.damping, p->wc[l], x, p->ndofs[l], s));
+    }
+    return SIPG_OK;
+  }
   for (int sw = 0; sw < sweeps; ++sw)
     for (int colour = 0; colour < 8; ++colour) {
       SIPG_TRY(residual(p, l, b, x, p->wr[l], s));
@@ -58,17 +70,24 @@ sipg_status residual_lp(sipg_problem* p, int l, const float* b, const float* x, 
   return SIPG_OK;
 }
 
+sipg_status patch_lp(sipg_problem* p, int l, int colour, const float* r, float* x,
+                     hipStream_t s) {
+  if (p->n[l] < 2) return SIPG_OK;
+  if (p->prec == SIPG_F32)
+    SIPG_HIP(launch_patch_fd_f32(p->N, colour, r, x, p->tab, p->n[l], level_h(p, l), s));
+  else
+    SIPG_HIP(launch_patch_fd_lp(p->N, p->prec == SIPG_BF16, p->ec, colour, r, x, p->tab,
+                                p->n[l], level_h(p, l), s));
+  return SIPG_OK;
+}
+
 sipg_status smooth_lp(sipg_problem* p, int l, float* x, const float* b, int sweeps,
                       hipStream_t s) {
   if (p->n[l] < 2) return SIPG_OK;
   for (int sw = 0; sw < sweeps; ++sw)
     for (int colour = 0; colour < 8; ++colour) {
       SIPG_TRY(residual_lp(p, l, b, x, p->fr[l], s));
-      if (p->prec == SIPG_F32)
-        SIPG_HIP(launch_patch_fd_f32(p->N, colour, p->fr[l], x, p->tab, p->n[l], level_h(p, l), s));
-      else
-        SIPG_HIP(launch_patch_fd_lp(p->N, p->prec == SIPG_BF16, p->ec, colour, p->fr[l], x,
-                                    p->tab, p->n[l], level_h(p, l), s));
+      SIPG_TRY(patch_lp(p, l, colour, p->fr[l], x, s));
     }
   return SIPG_OK;
 }
@@ -119,23 +138,16 @@ sipg_status vcycle(sipg_problem* p, int l, double* x, const double* b, hipStream
   return SIPG_OK;
 }
 
-// dot products of V[0..nv) with w; result copied to the host
+// dot products of V[0..nv) with w; the result reaches the host through the
+// handle's pinned buffer (stream-ordered copy, then a stream sync)
 sipg_status mdot_host(sipg_problem* p, const double* V, int64_t ld, int nv, const double* w,
                       int64_t n, double* dev_out, double* host_out, hipStream_t s) {
   SIPG_HIP(launch_mdot(V, ld, nv, w, n, p->d_partial, dev_out, s));
   if (host_out) {
-    SIPG_HIP(hipMemcpyAsync(host_out, dev_out, sizeof(double) * nv, hipMemcpyDeviceToHost, s));
+    SIPG_HIP(hipMemcpyAsync(p->h_pinned, dev_out, sizeof(double) * nv, hipMemcpyDeviceToHost, s));
     SIPG_HIP(hipStreamSynchronize(s));
+    std::memcpy(host_out, p->h_pinned, sizeof(double) * nv);
   }
-  return SIPG_OK;
-}
-
-// flag = 1 if x holds a NaN or Inf (synchronizes the stream)
-sipg_status nonfinite(sipg_problem* p, const double* x, int64_t n, int* flag, hipStream_t s) {
-  SIPG_HIP(hipMemsetAsync(p->d_flag, 0, sizeof(int), s));
-  SIPG_HIP(launch_finite_check(x, n, p->d_flag, s));
-  SIPG_HIP(hipMemcpyAsync(flag, p->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
-  SIPG_HIP(hipStreamSynchronize(s));
   return SIPG_OK;
 }
 
@@ -145,10 +157,10 @@ constexpr double kStagnation = 0.9;
 
 sipg_status ensure_aux(sipg_problem* p, size_t count) {
   if (count <= p->aux_size) return SIPG_OK;
-  if (p->d_aux) hipFree(p->d_aux);
+  prob_free(p, p->d_aux);
   p->d_aux = nullptr;
   p->aux_size = 0;
-  SIPG_TRY(dev_alloc(&p->d_aux, count));
+  SIPG_TRY(prob_alloc(p, &p->d_aux, count));
   p->aux_size = count;
   return SIPG_OK;
 }
@@ -159,12 +171,15 @@ namespace sipg {
 sipg_status ensure_krylov(sipg_problem* p, int m) {
   if (m <= p->restart_alloc) return SIPG_OK;
   const int64_t n = p->ndofs[p->L - 1];
-  if (p->V) hipFree(p->V);
-  if (p->Z) hipFree(p->Z);
+  // the old blocks may still be read by queued work
+  SIPG_HIP(hipDeviceSynchronize());
+  prob_free(p, p->V);
+  prob_free(p, p->Z);
   p->V = p->Z = nullptr;
   p->restart_alloc = 0;
-  SIPG_TRY(dev_alloc(&p->V, (size_t)(m + 1) * n));
-  SIPG_TRY(dev_alloc(&p->Z, (size_t)m * n));
+  ++p->krylov_gen;  // anything that captured the old addresses is stale now
+  SIPG_TRY(prob_alloc(p, &p->V, (size_t)(m + 1) * n));
+  SIPG_TRY(prob_alloc(p, &p->Z, (size_t)m * n));
   p->restart_alloc = m;
   return SIPG_OK;
 }
@@ -174,7 +189,7 @@ extern "C" {
 
 const char* sipg_last_error(void) { return g_err.c_str(); }
 
-sipg_status sipg_create(const sipg_config* cfg, sipg_problem** out) {
+sipg_status sipg_create(const sipg_config* cfg, hipStream_t stream, sipg_problem** out) {
   if (!cfg || !out) return fail(SIPG_ERR_ARG, "NULL argument");
   *out = nullptr;
   if (cfg->k < 1 || cfg->k > 7) return fail(SIPG_ERR_ARG, "k must be in 1..7");
@@ -183,14 +198,26 @@ sipg_status sipg_create(const sipg_config* cfg, sipg_problem** out) {
     return fail(SIPG_ERR_ARG, "smoothing steps must be in 0..16");
   if (cfg->mg_precision < SIPG_F64 || cfg->mg_precision > SIPG_BF16)
     return fail(SIPG_ERR_ARG, "mg_precision must be a sipg_precision");
-  if (cfg->error_correction != 0 && cfg->error_correction != 1)
-    return fail(SIPG_ERR_ARG, "error_correction must be 0 or 1");
-  // level sizes: halve while even and above 3
-  // (a coarsest level above 3 cells per direction is allowed for operator
-  // work; its exact coarse solve then reports SIPG_ERR_UNSUPPORTED)
+  if (cfg->error_correction < 0 || cfg->error_correction > 2)
+    return fail(SIPG_ERR_ARG, "error_correction must be 0, 1 or 2");
+  const double pen = cfg->penalty_scale == 0.0 ? 1.0 : cfg->penalty_scale;
+  if (!(pen >= 1.0 && pen <= 100.0)) return fail(SIPG_ERR_ARG, "penalty_scale must be 0 or in [1, 100]");
+  if ((cfg->alloc == nullptr) != (cfg->dealloc == nullptr))
+    return fail(SIPG_ERR_ARG, "alloc and dealloc must be given together");
+  if (cfg->mg_precision == SIPG_BF16 && cfg->error_correction == 0 && cfg->k >= 5)
+    return fail(SIPG_ERR_UNSUPPORTED,
+                "BF16 V-cycle without error correction stalls for k >= 5 (the 1D operator "
+                "rounded to 8 significand bits moves the lowest eigenvalues by many times their "
+                "size); use error_correction 1 or 2");
+  if (cfg->smoother != 0 && cfg->smoother != 1) return fail(SIPG_ERR_ARG, "smoother must be 0 or 1");
+  if (cfg->smoother == 1 && cfg->mg_precision != SIPG_F64)
+    return fail(SIPG_ERR_UNSUPPORTED, "the additive smoother runs in FP64 only");
+  if (cfg->damping < 0.0 || cfg->damping > 1.0) return fail(SIPG_ERR_ARG, "damping must be in [0, 1]");
   // Default hierarchy: halve while even and above 3 (coarsest 2 for powers of
   // two, 3 for three times a power of two); n_levels > 0 takes that many of
-  // the finest levels of the full halving sequence (down to 1 cell).
+  // the finest levels of the full halving sequence (down to 1 cell).  A
+  // coarsest level above 3 cells per direction is allowed for operator work;
+  // its exact coarse solve then reports SIPG_ERR_UNSUPPORTED.
   std::vector<int> ns{cfg->n_cells};
   while (ns.back() % 2 == 0) ns.push_back(ns.back() / 2);
   std::vector<int> lv(ns.rbegin(), ns.rend());
@@ -203,6 +230,9 @@ sipg_status sipg_create(const sipg_config* cfg, sipg_problem** out) {
   }
   auto* p = new sipg_problem();
   p->cfg = *cfg;
+  p->cfg.penalty_scale = pen;
+  if (p->cfg.damping == 0.0) p->cfg.damping = 0.125;
+  p->alloc_stream = stream;
   p->k = cfg->k;
   p->N = cfg->k + 1;
   p->n = lv;
@@ -212,46 +242,50 @@ sipg_status sipg_create(const sipg_config* cfg, sipg_problem** out) {
   for (int m : lv) p->ndofs.push_back((int64_t)m * m * m * N3);
   std::vector<double> tab;
   try {
-    tab = build_device_table(p->k, p->n0, p->tab.lay);
+    tab = build_device_table(p->k, p->n0, p->tab.lay, pen);
   } catch (const std::exception& e) {
     delete p;
     return fail(SIPG_ERR_ARG, e.what());
   }
-  sipg_status st = dev_alloc(&p->d_tab, tab.size());
-  if (st == SIPG_OK && hipMemcpy(p->d_tab, tab.data(), tab.size() * sizeof(double),
-                                 hipMemcpyHostToDevice) != hipSuccess)
+  std::vector<float> tf(tab.begin(), tab.end());  // FP32 copy (FP32 / FP16 / BF16 kernels)
+  sipg_status st = prob_alloc(p, &p->d_tab, tab.size());
+  if (st == SIPG_OK) st = prob_alloc(p, &p->d_tabf, tf.size());
+  if (st == SIPG_OK && (hipMemcpyAsync(p->d_tab, tab.data(), tab.size() * sizeof(double),
+                                       hipMemcpyHostToDevice, stream) != hipSuccess ||
+                        hipMemcpyAsync(p->d_tabf, tf.data(), tf.size() * sizeof(float),
+                                       hipMemcpyHostToDevice, stream) != hipSuccess ||
+                        hipStreamSynchronize(stream) != hipSuccess))
     st = fail(SIPG_ERR_HIP, "table upload failed");
   p->tab.tab = p->d_tab;
+  p->tab.tabf = p->d_tabf;
   p->wx.assign(p->L, nullptr);
   p->wb.assign(p->L, nullptr);
   p->wr.assign(p->L, nullptr);
+  p->wc.assign(p->L, nullptr);
   for (int l = 0; l < p->L && st == SIPG_OK; ++l) {
-    st = dev_alloc(&p->wr[l], p->ndofs[l]);
-    if (st == SIPG_OK && l < p->L - 1) st = dev_alloc(&p->wx[l], p->ndofs[l]);
-    if (st == SIPG_OK && l < p->L - 1) st = dev_alloc(&p->wb[l], p->ndofs[l]);
+    st = prob_alloc(p, &p->wr[l], p->ndofs[l]);
+    if (st == SIPG_OK && cfg->smoother == 1) st = prob_alloc(p, &p->wc[l], p->ndofs[l]);
+    if (st == SIPG_OK && l < p->L - 1) st = prob_alloc(p, &p->wx[l], p->ndofs[l]);
+    if (st == SIPG_OK && l < p->L - 1) st = prob_alloc(p, &p->wb[l], p->ndofs[l]);
   }
   p->prec = cfg->mg_precision;
-  p->ec = cfg->error_correction != 0;
-  {  // FP32 copy of the tables (FP32 / FP16 / BF16 kernels read it)
-    std::vector<float> tf(tab.begin(), tab.end());
-    if (st == SIPG_OK) st = dev_alloc(&p->d_tabf, tf.size());
-    if (st == SIPG_OK && hipMemcpy(p->d_tabf, tf.data(), tf.size() * sizeof(float),
-                                   hipMemcpyHostToDevice) != hipSuccess)
-      st = fail(SIPG_ERR_HIP, "table upload failed");
-    p->tab.tabf = p->d_tabf;
-  }
+  p->ec = cfg->error_correction;
   p->fx.assign(p->L, nullptr);
   p->fb.assign(p->L, nullptr);
   p->fr.assign(p->L, nullptr);
   if (p->prec != SIPG_F64)
     for (int l = 0; l < p->L && st == SIPG_OK; ++l) {
-      st = dev_alloc(&p->fx[l], p->ndofs[l]);
-      if (st == SIPG_OK) st = dev_alloc(&p->fb[l], p->ndofs[l]);
-      if (st == SIPG_OK) st = dev_alloc(&p->fr[l], p->ndofs[l]);
+      st = prob_alloc(p, &p->fx[l], p->ndofs[l]);
+      if (st == SIPG_OK) st = prob_alloc(p, &p->fb[l], p->ndofs[l]);
+      if (st == SIPG_OK) st = prob_alloc(p, &p->fr[l], p->ndofs[l]);
     }
-  if (st == SIPG_OK) st = dev_alloc(&p->d_partial, (size_t)kDotBlocks * 65);
-  if (st == SIPG_OK) st = dev_alloc(&p->d_small, 512);
-  if (st == SIPG_OK) st = dev_alloc(&p->d_flag, 1);
+  if (st == SIPG_OK) st = prob_alloc(p, &p->d_partial, (size_t)kDotBlocks * 65);
+  if (st == SIPG_OK) st = prob_alloc(p, &p->d_small, 512);
+  if (st == SIPG_OK) st = prob_alloc(p, &p->d_flag, 64);
+  if (st == SIPG_OK && hipHostMalloc((void**)&p->h_pinned, 256 * sizeof(double)) != hipSuccess) {
+    p->h_pinned = nullptr;
+    st = fail(SIPG_ERR_HIP, "pinned host buffer allocation failed");
+  }
   if (st != SIPG_OK) {
     std::string msg = g_err;
     sipg_destroy(p);
@@ -264,23 +298,24 @@ sipg_status sipg_create(const sipg_config* cfg, sipg_problem** out) {
 void sipg_destroy(sipg_problem* p) {
   if (!p) return;
   hipDeviceSynchronize();
-  auto fr = [](void* q) { if (q) hipFree(q); };
-  fr(p->d_tab);
-  for (auto q : p->wx) fr(q);
-  for (auto q : p->wb) fr(q);
-  for (auto q : p->wr) fr(q);
-  fr(p->V);
-  fr(p->Z);
-  fr(p->d_partial);
-  fr(p->d_small);
-  fr(p->d_flag);
-  fr(p->d_aux);
-  fr(p->d_tabf);
-  for (auto q : p->fx) fr(q);
-  for (auto q : p->fb) fr(q);
-  for (auto q : p->fr) fr(q);
-  fr(p->stage_c);
-  fr(p->stage_q);
+  prob_free(p, p->d_tab);
+  for (auto q : p->wx) prob_free(p, q);
+  for (auto q : p->wb) prob_free(p, q);
+  for (auto q : p->wr) prob_free(p, q);
+  for (auto q : p->wc) prob_free(p, q);
+  prob_free(p, p->V);
+  prob_free(p, p->Z);
+  prob_free(p, p->d_partial);
+  prob_free(p, p->d_small);
+  prob_free(p, p->d_flag);
+  prob_free(p, p->d_aux);
+  prob_free(p, p->d_tabf);
+  for (auto q : p->fx) prob_free(p, q);
+  for (auto q : p->fb) prob_free(p, q);
+  for (auto q : p->fr) prob_free(p, q);
+  prob_free(p, p->stage_c);
+  prob_free(p, p->stage_q);
+  if (p->h_pinned) hipHostFree(p->h_pinned);
   delete p;
 }
 
@@ -331,6 +366,26 @@ sipg_status sipg_patch_correct(sipg_problem* p, int level, int colour, const dou
   if (p->n[level] < 2) return SIPG_OK;
   SIPG_HIP(launch_patch_fd_f64(p->N, colour, r, x, p->tab, p->n[level], level_h(p, level), s));
   return SIPG_OK;
+}
+
+sipg_status sipg_smooth_lp(sipg_problem* p, int level, float* x, const float* b, int sweeps,
+                           hipStream_t s) {
+  SIPG_TRY(check_level(p, level));
+  if (p->prec == SIPG_F64) return fail(SIPG_ERR_ARG, "the handle's mg_precision is FP64");
+  if (!x || !b) return fail(SIPG_ERR_ARG, "NULL vector");
+  if ((const void*)x == (const void*)b) return fail(SIPG_ERR_ARG, "x and b must not alias");
+  if (sweeps < 0) return fail(SIPG_ERR_ARG, "sweeps must be >= 0");
+  return smooth_lp(p, level, x, b, sweeps, s);
+}
+
+sipg_status sipg_patch_correct_lp(sipg_problem* p, int level, int colour, const float* r, float* x,
+                                  hipStream_t s) {
+  SIPG_TRY(check_level(p, level));
+  if (p->prec == SIPG_F64) return fail(SIPG_ERR_ARG, "the handle's mg_precision is FP64");
+  if (!x || !r) return fail(SIPG_ERR_ARG, "NULL vector");
+  if ((const void*)x == (const void*)r) return fail(SIPG_ERR_ARG, "x and r must not alias");
+  if (colour < 0 || colour > 7) return fail(SIPG_ERR_ARG, "colour must be in 0..7");
+  return patch_lp(p, level, colour, r, x, s);
 }
 
 sipg_status sipg_restrict(sipg_problem* p, int level, const double* rf, double* rc,
@@ -409,7 +464,8 @@ sipg_status sipg_apply_lp(sipg_problem* p, int level, const float* u, float* v, 
   if (precision == SIPG_F32) {
     SIPG_HIP(launch_apply_f32(p->N, u, v, nullptr, p->tab, p->n[level], level_h(p, level), s));
   } else if (precision == SIPG_F16 || precision == SIPG_BF16) {
-    SIPG_HIP(launch_apply_lp(p->N, precision == SIPG_BF16, ec != 0, u, v, nullptr, p->tab,
+    if (ec < 0 || ec > 2) return fail(SIPG_ERR_ARG, "ec must be 0, 1 or 2");
+    SIPG_HIP(launch_apply_lp(p->N, precision == SIPG_BF16, ec, u, v, nullptr, p->tab,
                              p->n[level], level_h(p, level), s));
   } else {
     return fail(SIPG_ERR_ARG, "precision must be SIPG_F32, SIPG_F16 or SIPG_BF16");
@@ -425,13 +481,17 @@ sipg_status sipg_fgmres(sipg_problem* p, double* x, const double* b, const sipg_
   if (o->max_iters < 1) return fail(SIPG_ERR_ARG, "max_iters must be >= 1");
   if (!(o->rtol > 0.0)) return fail(SIPG_ERR_ARG, "rtol must be > 0");
   if (o->use_learned && !p->cnn) return fail(SIPG_ERR_ARG, "use_learned set but no network attached");
+  if (o->variant != SIPG_FGMRES && o->variant != SIPG_GMRES)
+    return fail(SIPG_ERR_ARG, "variant must be SIPG_FGMRES or SIPG_GMRES");
+  if (o->variant == SIPG_GMRES && o->use_learned)
+    return fail(SIPG_ERR_ARG, "the learned stage needs the flexible variant");
   std::memset(info, 0, sizeof(*info));
   bool learned = o->use_learned != 0;
   const double stagnation = o->stagnation > 0.0 ? o->stagnation : kStagnation;
   const int m = o->restart;
   const int L = p->L - 1;
   const int64_t n = p->ndofs[L];
-  SIPG_TRY(ensure_krylov(p, m));
+  SIPG_TRY(ensure_krylov(p, std::max(m, 2)));  // GMRES uses two Z slots as scratch
   SIPG_HIP(hipStreamSynchronize(s));
   const auto t0 = std::chrono::steady_clock::now();
   double* d_h = p->d_small;        // [0, 65)
@@ -447,7 +507,7 @@ sipg_status sipg_fgmres(sipg_problem* p, double* x, const double* b, const sipg_
     return SIPG_OK;
   }
   const double tol = o->rtol * nb;
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hcol(m + 1);
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
   auto Hm = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
   int it = 0, hist = 0;
   bool converged = false;
@@ -458,6 +518,7 @@ sipg_status sipg_fgmres(sipg_problem* p, double* x, const double* b, const sipg_
     if (o->log_history && hist < 128) info->history[hist] = v;
     ++hist;
   };
+  const bool flexible = o->variant == SIPG_FGMRES;
   while (it < o->max_iters && !converged) {
     SIPG_TRY(residual(p, L, b, x, p->V, s));
     double beta2 = 0.0;
@@ -475,39 +536,45 @@ sipg_status sipg_fgmres(sipg_problem* p, double* x, const double* b, const sipg_
     int jd = 0;
     for (int j = 0; j < m; ++j) {
       double* Vj = p->V + (size_t)j * n;
-      double* Zj = p->Z + (size_t)j * n;
+      // FGMRES keeps every preconditioned vector; GMRES one scratch slot
+      double* Zj = p->Z + (size_t)(flexible ? j : 0) * n;
       double* w = p->V + (size_t)(j + 1) * n;
-      SIPG_HIP(launch_fill(Zj, 0.0, n, s));
-      SIPG_TRY(vcycle_any(p, L, Zj, Vj, s));
-      if (learned) SIPG_TRY(cnn_stage(p, Vj, Zj, s));
-      int flag = 0;
-      SIPG_TRY(nonfinite(p, Zj, n, &flag, s));
-      if (flag && learned) {  // the learned stage failed: plain V-cycle from here on
-        learned = false;
-        info->fell_back = 1;
+      // 0: the configured preconditioner; 1: plain V-cycle after a non-finite
+      // learned correction; 2: identity after a non-finite V-cycle
+      int mode = 0;
+      double hn = 0.0;
+      while (true) {
         SIPG_HIP(launch_fill(Zj, 0.0, n, s));
-        SIPG_TRY(vcycle_any(p, L, Zj, Vj, s));
-        SIPG_TRY(nonfinite(p, Zj, n, &flag, s));
-      }
-      if (flag) {  // preconditioner broke down: fall back to the identity
-        SIPG_HIP(launch_scale_copy(Vj, 1.0, Zj, n, s));
-        info->fell_back = 1;
-      }
-      {
+        if (mode < 2) SIPG_TRY(vcycle_any(p, L, Zj, Vj, s));
+        else SIPG_HIP(launch_scale_copy(Vj, 1.0, Zj, n, s));
+        if (mode == 0 && learned) SIPG_TRY(cnn_stage(p, Vj, Zj, s));
         ApplyJob aj{Zj, w, nullptr, p->n[L], level_h(p, L), tile_order(p, L)};
         SIPG_HIP(launch_apply_batch(0, p->N, &aj, 1, p->tab, s));
+        // classical Gram-Schmidt, twice; the Hessenberg column and ||w||^2
+        // come back in one stream-ordered copy (a NaN or Inf in z shows up
+        // there, so no separate check is needed)
+        SIPG_HIP(launch_mdot(p->V, n, j + 1, w, n, p->d_partial, d_h, s));
+        SIPG_HIP(launch_maxpy(p->V, n, j + 1, d_h, w, n, nullptr, 1.0, s));
+        SIPG_HIP(launch_mdot(p->V, n, j + 1, w, n, p->d_partial, d_h2, s));
+        SIPG_HIP(launch_maxpy(p->V, n, j + 1, d_h2, w, n, d_h, 1.0, s));
+        SIPG_HIP(launch_mdot(w, n, 1, w, n, p->d_partial, d_h + 70, s));
+        SIPG_HIP(hipMemcpyAsync(p->h_pinned, d_h, sizeof(double) * 71, hipMemcpyDeviceToHost, s));
+        SIPG_HIP(hipStreamSynchronize(s));
+        hn = std::sqrt(p->h_pinned[70]);
+        bool finite = std::isfinite(hn);
+        for (int i = 0; i <= j; ++i) finite = finite && std::isfinite(p->h_pinned[i]);
+        if (finite) break;
+        if (mode == 0 && learned) {  // the learned stage failed: plain V-cycle from here on
+          learned = false;
+          mode = 1;
+        } else if (mode < 2) {       // the preconditioner broke down: identity for this step
+          mode = 2;
+        } else {
+          return fail(SIPG_ERR_NONFINITE, "Arnoldi vector is not finite");
+        }
+        info->fell_back = 1;
       }
-      // classical Gram-Schmidt, twice
-      SIPG_HIP(launch_mdot(p->V, n, j + 1, w, n, p->d_partial, d_h, s));
-      SIPG_HIP(launch_maxpy(p->V, n, j + 1, d_h, w, n, nullptr, 1.0, s));
-      SIPG_HIP(launch_mdot(p->V, n, j + 1, w, n, p->d_partial, d_h2, s));
-      SIPG_HIP(launch_maxpy(p->V, n, j + 1, d_h2, w, n, d_h, 1.0, s));
-      double w2 = 0.0;
-      SIPG_TRY(mdot_host(p, w, n, 1, w, n, d_nrm, &w2, s));
-      SIPG_HIP(hipMemcpy(hcol.data(), d_h, sizeof(double) * (j + 1), hipMemcpyDeviceToHost));
-      const double hn = std::sqrt(w2);
-      if (!std::isfinite(hn)) return fail(SIPG_ERR_NONFINITE, "Arnoldi vector is not finite");
-      for (int i = 0; i <= j; ++i) Hm(i, j) = hcol[i];
+      for (int i = 0; i <= j; ++i) Hm(i, j) = p->h_pinned[i];
       Hm(j + 1, j) = hn;
       if (hn > 0.0) SIPG_HIP(launch_scale_copy(w, 1.0 / hn, w, n, s));
       for (int i = 0; i < j; ++i) {
@@ -536,8 +603,21 @@ sipg_status sipg_fgmres(sipg_problem* p, double* x, const double* b, const sipg_
       for (int c = i + 1; c < jd; ++c) sacc -= Hm(i, c) * y[c];
       y[i] = sacc / Hm(i, i);
     }
-    SIPG_HIP(hipMemcpy(p->d_small + 192, y.data(), sizeof(double) * jd, hipMemcpyHostToDevice));
-    SIPG_HIP(launch_maxpy(p->Z, n, jd, p->d_small + 192, x, n, nullptr, -1.0, s));
+    std::memcpy(p->h_pinned + 128, y.data(), sizeof(double) * jd);
+    SIPG_HIP(hipMemcpyAsync(p->d_small + 192, p->h_pinned + 128, sizeof(double) * jd,
+                            hipMemcpyHostToDevice, s));
+    if (flexible) {  // x += Z y
+      SIPG_HIP(launch_maxpy(p->Z, n, jd, p->d_small + 192, x, n, nullptr, -1.0, s));
+    } else {  // x += M (V y): one more preconditioner application
+      double* t = p->Z + (size_t)n;
+      SIPG_HIP(launch_fill(t, 0.0, n, s));
+      SIPG_HIP(launch_maxpy(p->V, n, jd, p->d_small + 192, t, n, nullptr, -1.0, s));
+      SIPG_HIP(launch_fill(p->Z, 0.0, n, s));
+      SIPG_TRY(vcycle_any(p, L, p->Z, t, s));
+      SIPG_HIP(launch_axpy(1.0, p->Z, x, n, s));
+    }
+    // the copy above reads the pinned buffer: let it finish before reuse
+    SIPG_HIP(hipStreamSynchronize(s));
     if (std::fabs(g[jd]) <= tol) converged = true;
   }
   SIPG_TRY(residual(p, L, b, x, p->V, s));

@@ -7,6 +7,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -200,8 +201,8 @@ sipg_status cnn_stage(sipg_problem* p, const double* v, double* z, hipStream_t s
   const int n = p->n[L], N = p->N, G = n * N;
   const int64_t nd = p->ndofs[L];
   SIPG_TRY(ensure_ws(c, (int64_t)G * G * G, false));
-  if (!p->stage_c) SIPG_TRY(dev_alloc(&p->stage_c, nd));
-  if (!p->stage_q) SIPG_TRY(dev_alloc(&p->stage_q, nd));
+  if (!p->stage_c) SIPG_TRY(prob_alloc(p, &p->stage_c, nd));
+  if (!p->stage_q) SIPG_TRY(prob_alloc(p, &p->stage_q, nd));
   double* rho = p->wr[L];
   double* scale = p->d_small + 400;
   double* dots = p->d_small + 408;  // [rho . q, q . q]
@@ -289,6 +290,48 @@ sipg_status sipg_cnn_get_params(const sipg_cnn* c, float* params, float* sigma) 
     SIPG_HIP(hipMemcpy(params, c->prm, sizeof(float) * C::kParams, hipMemcpyDeviceToHost));
   if (sigma) *sigma = c->sigma;
   return SIPG_OK;
+}
+
+// File format: "SIPGCNN1", int32 parameter count, float32 sigma, float32
+// parameters, little-endian (the byte order of the host; gfx950 hosts are
+// x86-64 or AArch64 little-endian).
+static const char kCnnMagic[8] = {'S', 'I', 'P', 'G', 'C', 'N', 'N', '1'};
+
+sipg_status sipg_cnn_save(const sipg_cnn* c, const char* path) {
+  if (!c || !path) return fail(SIPG_ERR_ARG, "NULL argument");
+  std::vector<float> prm(C::kParams);
+  float sigma = 0.0f;
+  SIPG_TRY(sipg_cnn_get_params(c, prm.data(), &sigma));
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(SIPG_ERR_UNSUPPORTED, std::string("cannot open for writing: ") + path);
+  const int32_t count = C::kParams;
+  bool ok = std::fwrite(kCnnMagic, 1, 8, f) == 8 && std::fwrite(&count, 4, 1, f) == 1 &&
+            std::fwrite(&sigma, 4, 1, f) == 1 &&
+            std::fwrite(prm.data(), 4, prm.size(), f) == prm.size();
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok) return fail(SIPG_ERR_UNSUPPORTED, std::string("write failed: ") + path);
+  return SIPG_OK;
+}
+
+sipg_status sipg_cnn_load(sipg_cnn* c, const char* path) {
+  if (!c || !path) return fail(SIPG_ERR_ARG, "NULL argument");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(SIPG_ERR_UNSUPPORTED, std::string("cannot open: ") + path);
+  char magic[8] = {0};
+  int32_t count = 0;
+  float sigma = 0.0f;
+  std::vector<float> prm(C::kParams);
+  const bool head = std::fread(magic, 1, 8, f) == 8 && std::fread(&count, 4, 1, f) == 1 &&
+                    std::fread(&sigma, 4, 1, f) == 1;
+  const bool body = head && std::memcmp(magic, kCnnMagic, 8) == 0 && count == C::kParams &&
+                    std::fread(prm.data(), 4, prm.size(), f) == prm.size();
+  std::fclose(f);
+  if (!head || std::memcmp(magic, kCnnMagic, 8) != 0)
+    return fail(SIPG_ERR_ARG, std::string("not a network file: ") + path);
+  if (count != C::kParams)
+    return fail(SIPG_ERR_ARG, "parameter count " + std::to_string(count) + " does not match");
+  if (!body) return fail(SIPG_ERR_ARG, std::string("short file: ") + path);
+  return sipg_cnn_set_params(c, prm.data(), sigma);
 }
 
 sipg_status sipg_cnn_init(sipg_cnn* c, uint64_t seed) {

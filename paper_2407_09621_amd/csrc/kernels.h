@@ -90,14 +90,15 @@ hipError_t launch_to_f64(const float* src, double* dst, int64_t n, hipStream_t s
 hipError_t launch_zero_f32(float* x, int64_t n, hipStream_t s);
 
 // Low-precision kernels: FP32 storage, FP16 (bf16 = false) or BF16 products
-// on the matrix cores with FP32 accumulation, optional error correction.
-hipError_t launch_apply_lp(int N, bool bf16, bool ec, const float* u, float* v, const float* b,
+// on the matrix cores with FP32 accumulation; ec = 0 none, 1 both operands
+// split (Alg. matmul), 2 only the matrix operand split.
+hipError_t launch_apply_lp(int N, bool bf16, int ec, const float* u, float* v, const float* b,
                            const DevTab& t, int n, double h, hipStream_t s);
-hipError_t launch_patch_fd_lp(int N, bool bf16, bool ec, int colour, const float* r, float* x,
+hipError_t launch_patch_fd_lp(int N, bool bf16, int ec, int colour, const float* r, float* x,
                               const DevTab& t, int n, double h, hipStream_t s);
-hipError_t launch_apply_lp_batch(int N, bool bf16, bool ec, const ApplyJob* jobs, int count,
+hipError_t launch_apply_lp_batch(int N, bool bf16, int ec, const ApplyJob* jobs, int count,
                                  const DevTab& t, hipStream_t s);
-hipError_t launch_patch_fd_lp_batch(int N, bool bf16, bool ec, int colour, const PatchJob* jobs,
+hipError_t launch_patch_fd_lp_batch(int N, bool bf16, int ec, int colour, const PatchJob* jobs,
                                     int count, const DevTab& t, hipStream_t s);
 
 // Manufactured right-hand side and L2 error (tables prepared on the host).

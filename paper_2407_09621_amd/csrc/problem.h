@@ -54,6 +54,10 @@ struct sipg_problem {
   sipg::DevTab tab;
   double* d_tab = nullptr;
   std::vector<double*> wx, wb, wr;  // per-level V-cycle vectors
+  std::vector<double*> wc;          // additive smoother: summed patch corrections
+  hipStream_t alloc_stream = nullptr;  // stream handed to the allocator callbacks
+  int krylov_gen = 0;               // bumped whenever V / Z are reallocated
+  double* h_pinned = nullptr;       // pinned host scalars (Hessenberg column, y)
   double* V = nullptr;              // Krylov basis, (restart + 1) vectors
   double* Z = nullptr;              // preconditioned vectors, restart vectors
   int restart_alloc = 0;
@@ -64,7 +68,7 @@ struct sipg_problem {
   size_t aux_size = 0;
   // low-precision V-cycle (mg_precision != F64): FP32 level vectors
   int prec = SIPG_F64;
-  bool ec = false;
+  int ec = 0;  // 0 none, 1 both operands split, 2 matrix operand split
   float* d_tabf = nullptr;
   std::vector<float*> fx, fb, fr;
   std::vector<int> order;  // tile order of the apply per level (autotuned; 0 = default)
@@ -75,6 +79,32 @@ struct sipg_problem {
 
 namespace sipg {
 inline double level_h(const sipg_problem* p, int l) { return 1.0 / p->n[l]; }
+
+// Workspace of a problem handle: through the caller's allocator callbacks
+// when the configuration names them, else hipMalloc / hipFree.
+template <typename T>
+sipg_status prob_alloc(sipg_problem* p, T** ptr, size_t count) {
+  *ptr = nullptr;
+  if (count == 0) return SIPG_OK;
+  const size_t bytes = count * sizeof(T);
+  if (p->cfg.alloc) {
+    *ptr = (T*)p->cfg.alloc(bytes, p->alloc_stream, p->cfg.alloc_ctx);
+    if (!*ptr) return fail(SIPG_ERR_OOM, "allocator callback returned NULL");
+    if (((uintptr_t)*ptr) & 255) {
+      p->cfg.dealloc(*ptr, p->alloc_stream, p->cfg.alloc_ctx);
+      *ptr = nullptr;
+      return fail(SIPG_ERR_ARG, "allocator callback returned a block not aligned to 256 bytes");
+    }
+    return SIPG_OK;
+  }
+  return dev_alloc(ptr, count);
+}
+inline void prob_free(sipg_problem* p, void* ptr) {
+  if (!ptr) return;
+  if (p->cfg.dealloc) p->cfg.dealloc(ptr, p->alloc_stream, p->cfg.alloc_ctx);
+  else hipFree(ptr);
+}
+
 sipg_status ensure_krylov(sipg_problem* p, int m);
 // z += learned correction of the residual v - A z on the finest level
 sipg_status cnn_stage(sipg_problem* p, const double* v, double* z, hipStream_t s);

@@ -18,7 +18,13 @@
 // Error correction (both operands refined, as the paper's Alg. matmul):
 // x = x_hi + 2^-s x_lo with x_lo = round((x - x_hi) 2^s), s = 11 for FP16
 // and 8 for BF16; S x ~ S_hi x_hi + 2^-s (S_lo x_hi + S_hi x_lo), the
-// correction accumulated in its own FP32 accumulator.
+// correction accumulated in its own FP32 accumulator.  EC = 1 is that
+// scheme; EC = 2 refines only the constant matrix operand
+// (S x ~ S_hi x_hi + 2^-s S_lo x_hi, two products): the rounded 1D
+// operator of BF16 (8 significand bits) moves the lowest eigenvalues of
+// the discrete Laplacian by more than their size at degrees >= 4, which
+// stalls the smoother, while rounding the vector operand only perturbs
+// each entry relatively.
 #include <hip/hip_runtime.h>
 
 #include "batch.h"
@@ -82,7 +88,7 @@ struct Lp<true> {  // BF16
 // y = S x for the line held by every lane (all 64 lanes must call).  NP is
 // the padded line length (multiple of 4); S is n x n (n <= NP), row-major,
 // possibly different per group of 4 lanes.
-template <int NP, bool BF, bool EC>
+template <int NP, bool BF, int EC>
 struct LineMV {
   typedef Lp<BF> L;
   static constexpr int C = NP / 4;
@@ -107,7 +113,7 @@ struct LineMV {
           w[q] = (s - v[q]) * L::kSplit;
         }
         hi[rc][kc] = L::pack(v[0], v[1], v[2], v[3]);
-        if (EC) lo[rc][kc] = L::pack(w[0], w[1], w[2], w[3]);
+        if (EC != 0) lo[rc][kc] = L::pack(w[0], w[1], w[2], w[3]);
       }
   }
 
@@ -135,19 +141,19 @@ struct LineMV {
         w[q] = (t - v[q]) * L::kSplit;
       }
       xh[kc] = L::pack(v[0], v[1], v[2], v[3]);
-      if (EC) xl[kc] = L::pack(w[0], w[1], w[2], w[3]);
+      if (EC == 1) xl[kc] = L::pack(w[0], w[1], w[2], w[3]);
     }
 #pragma unroll
     for (int rc = 0; rc < C; ++rc) {
       f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
       for (int kc = 0; kc < C; ++kc) acc = L::mfma(hi[rc][kc], xh[kc], acc);
-      if (EC) {
+      if (EC != 0) {
         f4 cor = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int kc = 0; kc < C; ++kc) {
           cor = L::mfma(lo[rc][kc], xh[kc], cor);
-          cor = L::mfma(hi[rc][kc], xl[kc], cor);
+          if (EC == 1) cor = L::mfma(hi[rc][kc], xl[kc], cor);
         }
         acc += cor * (1.0f / L::kSplit);
       }
@@ -200,7 +206,7 @@ __device__ __forceinline__ void add_boundary_correction(float (&t)[N], const flo
 }
 
 // line of length N inside a padded register array
-template <int N, int NP, bool BF, bool EC>
+template <int N, int NP, bool BF, int EC>
 __device__ __forceinline__ void line_mv(const LineMV<NP, BF, EC>& m, const float (&x)[N],
                                         float (&y)[N]) {
   float xp[NP], yp[NP];
@@ -210,7 +216,7 @@ __device__ __forceinline__ void line_mv(const LineMV<NP, BF, EC>& m, const float
 #pragma unroll
   for (int a = 0; a < N; ++a) y[a] = yp[a];
 }
-template <int N, int NP, bool BF, bool EC>
+template <int N, int NP, bool BF, int EC>
 __device__ __forceinline__ void line_mv_acc(const LineMV<NP, BF, EC>& m, const float (&x)[N],
                                             float (&y)[N]) {
   float t[N];
@@ -251,7 +257,7 @@ __device__ __forceinline__ int tile_first_cell(const TileMapLp& m, int t) {
 // ---------------------------------------------------------------------------
 // WG: the workgroup's waves share one tile of kThreads / N^2 cells of the
 // blocked order, with workgroup barriers (as in the FP64 vector kernel).
-template <int N, bool BF, bool EC, bool RES, bool WG = false>
+template <int N, bool BF, int EC, bool RES, bool WG = false>
 __global__ __launch_bounds__(kThreads) void apply_lp_kernel(
     Batch<float> B, const float* __restrict__ tab, TableLayout lay) {
   constexpr int N2 = N * N, N3 = N2 * N, CPB = (64 / N2) > 0 ? 64 / N2 : 1;
@@ -471,7 +477,7 @@ __global__ __launch_bounds__(kThreads) void apply_lp_kernel(
 // contractions on the matrix cores.  Lines of one patch are consecutive
 // lanes, so every group of 4 lanes shares the patch (and its 1D type).
 // ---------------------------------------------------------------------------
-template <int N, bool BF, bool EC>
+template <int N, bool BF, int EC>
 __global__ __launch_bounds__(kThreads) void patch_fd_lp_kernel(
     Batch<float> B, const float* __restrict__ tab, TableLayout lay, int bx, int by, int bz) {
   constexpr int G = 2 * N, G2 = G * G, G3 = G2 * G, N2 = N * N, N3 = N2 * N;
@@ -618,7 +624,7 @@ __global__ __launch_bounds__(kThreads) void patch_fd_lp_kernel(
   }
 }
 
-template <int N, bool BF, bool EC>
+template <int N, bool BF, int EC>
 hipError_t apply_lp_impl(const ApplyJob* jobs, int count, const DevTab& t, hipStream_t s) {
   constexpr int CPW = (64 / (N * N)) > 0 ? 64 / (N * N) : 1;
   constexpr bool WG = (N >= 5 && N <= 7);  // workgroup tiles of 10, 7, 5 cells
@@ -662,7 +668,7 @@ hipError_t apply_lp_impl(const ApplyJob* jobs, int count, const DevTab& t, hipSt
   return hipGetLastError();
 }
 
-template <int N, bool BF, bool EC>
+template <int N, bool BF, int EC>
 hipError_t patch_lp_impl(int colour, const PatchJob* jobs, int count, const DevTab& t,
                          hipStream_t s) {
   constexpr int G2 = 4 * N * N;
@@ -696,26 +702,26 @@ hipError_t patch_lp_impl(int colour, const PatchJob* jobs, int count, const DevT
 
 }  // namespace
 
-#define SIPG_LP_DISPATCH(N, BF, EC, CALL)                         \
-  switch (N) {                                                    \
-    case 2: return EC ? (BF ? CALL(2, true, true) : CALL(2, false, true)) \
-                      : (BF ? CALL(2, true, false) : CALL(2, false, false)); \
-    case 3: return EC ? (BF ? CALL(3, true, true) : CALL(3, false, true)) \
-                      : (BF ? CALL(3, true, false) : CALL(3, false, false)); \
-    case 4: return EC ? (BF ? CALL(4, true, true) : CALL(4, false, true)) \
-                      : (BF ? CALL(4, true, false) : CALL(4, false, false)); \
-    case 5: return EC ? (BF ? CALL(5, true, true) : CALL(5, false, true)) \
-                      : (BF ? CALL(5, true, false) : CALL(5, false, false)); \
-    case 6: return EC ? (BF ? CALL(6, true, true) : CALL(6, false, true)) \
-                      : (BF ? CALL(6, true, false) : CALL(6, false, false)); \
-    case 7: return EC ? (BF ? CALL(7, true, true) : CALL(7, false, true)) \
-                      : (BF ? CALL(7, true, false) : CALL(7, false, false)); \
-    case 8: return EC ? (BF ? CALL(8, true, true) : CALL(8, false, true)) \
-                      : (BF ? CALL(8, true, false) : CALL(8, false, false)); \
-    default: return hipErrorInvalidValue;                         \
+#define SIPG_LP_EC(NN, BF, EC, CALL)                                      \
+  switch (EC) {                                                           \
+    case 0: return BF ? CALL(NN, true, 0) : CALL(NN, false, 0);           \
+    case 1: return BF ? CALL(NN, true, 1) : CALL(NN, false, 1);           \
+    case 2: return BF ? CALL(NN, true, 2) : CALL(NN, false, 2);           \
+    default: return hipErrorInvalidValue;                                 \
+  }
+#define SIPG_LP_DISPATCH(N, BF, EC, CALL) \
+  switch (N) {                            \
+    case 2: SIPG_LP_EC(2, BF, EC, CALL)   \
+    case 3: SIPG_LP_EC(3, BF, EC, CALL)   \
+    case 4: SIPG_LP_EC(4, BF, EC, CALL)   \
+    case 5: SIPG_LP_EC(5, BF, EC, CALL)   \
+    case 6: SIPG_LP_EC(6, BF, EC, CALL)   \
+    case 7: SIPG_LP_EC(7, BF, EC, CALL)   \
+    case 8: SIPG_LP_EC(8, BF, EC, CALL)   \
+    default: return hipErrorInvalidValue; \
   }
 
-hipError_t launch_apply_lp_batch(int N, bool bf16, bool ec, const ApplyJob* jobs, int count,
+hipError_t launch_apply_lp_batch(int N, bool bf16, int ec, const ApplyJob* jobs, int count,
                                  const DevTab& t, hipStream_t s) {
   if (t.lay.N != N) return hipErrorInvalidValue;
 #define CALL(NN, BB, EE) apply_lp_impl<NN, BB, EE>(jobs, count, t, s)
@@ -723,7 +729,7 @@ hipError_t launch_apply_lp_batch(int N, bool bf16, bool ec, const ApplyJob* jobs
 #undef CALL
 }
 
-hipError_t launch_patch_fd_lp_batch(int N, bool bf16, bool ec, int colour, const PatchJob* jobs,
+hipError_t launch_patch_fd_lp_batch(int N, bool bf16, int ec, int colour, const PatchJob* jobs,
                                     int count, const DevTab& t, hipStream_t s) {
   if (t.lay.N != N || colour < 0 || colour > 7) return hipErrorInvalidValue;
 #define CALL(NN, BB, EE) patch_lp_impl<NN, BB, EE>(colour, jobs, count, t, s)
@@ -731,13 +737,13 @@ hipError_t launch_patch_fd_lp_batch(int N, bool bf16, bool ec, int colour, const
 #undef CALL
 }
 
-hipError_t launch_apply_lp(int N, bool bf16, bool ec, const float* u, float* v, const float* b,
+hipError_t launch_apply_lp(int N, bool bf16, int ec, const float* u, float* v, const float* b,
                            const DevTab& t, int n, double h, hipStream_t s) {
   ApplyJob j{u, v, b, n, h};
   return launch_apply_lp_batch(N, bf16, ec, &j, 1, t, s);
 }
 
-hipError_t launch_patch_fd_lp(int N, bool bf16, bool ec, int colour, const float* r, float* x,
+hipError_t launch_patch_fd_lp(int N, bool bf16, int ec, int colour, const float* r, float* x,
                               const DevTab& t, int n, double h, hipStream_t s) {
   PatchJob j{r, x, n, h};
   return launch_patch_fd_lp_batch(N, bf16, ec, colour, &j, 1, t, s);

@@ -125,7 +125,7 @@ void lagrange_eval(const std::vector<double>& nodes, const std::vector<double>& 
   }
 }
 
-Tables1D make_tables_1d(int k) {
+Tables1D make_tables_1d(int k, double penalty_scale) {
   if (k < 1 || k > kMaxN - 1) throw std::invalid_argument("degree out of range");
   Tables1D t;
   t.k = k;
@@ -157,7 +157,7 @@ Tables1D make_tables_1d(int k) {
   lagrange_eval(t.nodes, ends, Ve, &De);
   t.d0.assign(De.begin(), De.begin() + N);
   t.d1.assign(De.begin() + N, De.end());
-  const double g = 2.0 * k * (k + 1);
+  const double g = 2.0 * k * (k + 1) * penalty_scale;
   t.gamma_hat = g;
 
   // 1D face terms (from the SIPG face integral on a point face with jump
@@ -307,8 +307,8 @@ void line_matrices(const Tables1D& t, int cells, bool low_bdry, bool high_bdry,
 
 }  // namespace
 
-std::vector<double> build_device_table(int k, int n0, TableLayout& lay) {
-  Tables1D t = make_tables_1d(k);
+std::vector<double> build_device_table(int k, int n0, TableLayout& lay, double penalty_scale) {
+  Tables1D t = make_tables_1d(k, penalty_scale);
   const int N = t.N, G = 2 * N, Gc = (n0 >= 1 && n0 <= 3) ? n0 * N : 0;
   lay = TableLayout();
   lay.N = N;

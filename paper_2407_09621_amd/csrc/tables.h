@@ -44,7 +44,8 @@ struct Tables1D {
   double gamma_hat = 0;
 };
 
-Tables1D make_tables_1d(int k);
+// penalty_scale multiplies the h-free penalty 2k(k+1) (1 = the paper's gamma).
+Tables1D make_tables_1d(int k, double penalty_scale = 1.0);
 
 // Generalized eigenpairs L S = M S diag(lam), S^T M S = I for symmetric L and
 // SPD M of size n (row-major).  Returns false if M is not SPD.
@@ -58,6 +59,7 @@ void lagrange_eval(const std::vector<double>& nodes, const std::vector<double>& 
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
 
 // Full device table for degree k and coarse size n0; fills `layout`.
-std::vector<double> build_device_table(int k, int n0, TableLayout& layout);
+std::vector<double> build_device_table(int k, int n0, TableLayout& layout,
+                                       double penalty_scale = 1.0);
 
 }  // namespace sipg

@@ -27,16 +27,62 @@ class SipgError(RuntimeError):
         self.status = status
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+DEALLOC_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+SMOOTHER = {"multiplicative": 0, "additive": 1}
+VARIANT = {"fgmres": 0, "gmres": 1}
+
+
 class Config(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int), ("n_cells", ctypes.c_int), ("n_levels", ctypes.c_int),
                 ("mg_precision", ctypes.c_int), ("error_correction", ctypes.c_int),
-                ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int)]
+                ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int),
+                ("smoother", ctypes.c_int), ("damping", ctypes.c_double),
+                ("penalty_scale", ctypes.c_double),
+                ("alloc", ALLOC_FN), ("dealloc", DEALLOC_FN), ("alloc_ctx", ctypes.c_void_p)]
 
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("restart", ctypes.c_int), ("max_iters", ctypes.c_int),
                 ("use_learned", ctypes.c_int), ("log_history", ctypes.c_int),
-                ("stagnation", ctypes.c_double)]
+                ("stagnation", ctypes.c_double), ("variant", ctypes.c_int)]
+
+
+def _torch_alloc(nbytes, stream, ctx):
+    import torch
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+    except Exception:
+        return None
+
+
+def _torch_dealloc(ptr, stream, ctx):
+    try:
+        import torch
+        torch.cuda.caching_allocator_delete(int(ptr))
+    except Exception:
+        pass
+
+
+# kept alive for the life of the process: the library calls them from C
+TORCH_ALLOC = ALLOC_FN(_torch_alloc)
+TORCH_DEALLOC = DEALLOC_FN(_torch_dealloc)
+
+
+def make_config(k, n_cells, n_levels=0, mg_precision="f64", error_correction=0, nu_pre=2,
+                nu_post=2, smoother="multiplicative", damping=0.0, penalty_scale=1.0,
+                allocator=None):
+    """sipg_config for one problem.  error_correction: 0, 1 (both operands
+    split) or 2 (matrix operand split); True means 1.  allocator "torch" routes
+    the handle's workspace through torch's caching allocator."""
+    cfg = Config(k, n_cells, n_levels, PRECISION[mg_precision], int(error_correction),
+                 nu_pre, nu_post, SMOOTHER[smoother], float(damping), float(penalty_scale))
+    if allocator == "torch":
+        cfg.alloc = TORCH_ALLOC
+        cfg.dealloc = TORCH_DEALLOC
+    elif allocator is not None:
+        raise ValueError("allocator must be None or 'torch'")
+    return cfg
 
 
 class SolveInfo(ctypes.Structure):
@@ -73,7 +119,11 @@ def load_library(path=None):
     lib = ctypes.CDLL(p)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
     sig = {
-        "sipg_create": (i32, [ctypes.POINTER(Config), ctypes.POINTER(vp)]),
+        "sipg_create": (i32, [ctypes.POINTER(Config), vp, ctypes.POINTER(vp)]),
+        "sipg_smooth_lp": (i32, [vp, i32, vp, vp, i32, vp]),
+        "sipg_patch_correct_lp": (i32, [vp, i32, i32, vp, vp, vp]),
+        "sipg_cnn_save": (i32, [vp, ctypes.c_char_p]),
+        "sipg_cnn_load": (i32, [vp, ctypes.c_char_p]),
         "sipg_destroy": (None, [vp]),
         "sipg_num_levels": (i32, [vp]),
         "sipg_level_cells": (i32, [vp, i32]),
@@ -104,7 +154,7 @@ def load_library(path=None):
         "sipg_cnn_make_pairs": (i32, [vp, vp, i32, vp, vp, vp, vp]),
         "sipg_cnn_train": (i32, [vp, vp, ctypes.POINTER(CnnTrainOpts), ctypes.POINTER(CnnTrainInfo)]),
         "sipg_cnn_attach": (i32, [vp, vp]),
-        "sipg_batch_create": (i32, [ctypes.POINTER(Config), i32, ctypes.POINTER(vp)]),
+        "sipg_batch_create": (i32, [ctypes.POINTER(Config), i32, vp, ctypes.POINTER(vp)]),
         "sipg_batch_destroy": (None, [vp]),
         "sipg_batch_count": (i32, [vp]),
         "sipg_batch_problem": (vp, [vp, i32]),
@@ -149,13 +199,15 @@ class Problem:
     """A SIPG Poisson problem on n_cells^3 cells of degree k, with its level
     hierarchy (level 0 coarsest, level -1 finest)."""
 
-    def __init__(self, k, n_cells, n_levels=0, mg_precision="f64", error_correction=False,
-                 nu_pre=2, nu_post=2):
+    def __init__(self, k, n_cells, n_levels=0, mg_precision="f64", error_correction=0,
+                 nu_pre=2, nu_post=2, smoother="multiplicative", damping=0.0, penalty_scale=1.0,
+                 allocator=None, stream=None):
         lib = load_library()
-        cfg = Config(k, n_cells, n_levels, PRECISION[mg_precision], int(bool(error_correction)),
-                     nu_pre, nu_post)
+        cfg = make_config(k, n_cells, n_levels, mg_precision, int(error_correction), nu_pre,
+                          nu_post, smoother, damping, penalty_scale, allocator)
         h = ctypes.c_void_p()
-        _check(lib.sipg_create(ctypes.byref(cfg), ctypes.byref(h)))
+        _check(lib.sipg_create(ctypes.byref(cfg), _stream(stream), ctypes.byref(h)))
+        self.mg_precision = mg_precision
         self._h = h
         self.k = k
         self.N = k + 1
@@ -196,7 +248,7 @@ class Problem:
         import torch
         v = torch.empty_like(u) if v is None else v
         _check(_lib.sipg_apply_lp(self._h, self._lvl(level), _ptr(u, torch.float32),
-                                  _ptr(v, torch.float32), PRECISION[precision], int(bool(ec)),
+                                  _ptr(v, torch.float32), PRECISION[precision], int(ec),
                                   _stream(stream)))
         return v
 
@@ -220,6 +272,20 @@ class Problem:
         import torch
         _check(_lib.sipg_smooth(self._h, self._lvl(level), _ptr(x, torch.float64),
                                 _ptr(b, torch.float64), int(sweeps), _stream(stream)))
+        return x
+
+    def smooth_lp(self, x, b, sweeps=1, level=-1, stream=None):
+        """Smoother sweeps on FP32 vectors in the handle's mg_precision."""
+        import torch
+        _check(_lib.sipg_smooth_lp(self._h, self._lvl(level), _ptr(x, torch.float32),
+                                   _ptr(b, torch.float32), int(sweeps), _stream(stream)))
+        return x
+
+    def patch_correct_lp(self, colour, r, x, level=-1, stream=None):
+        import torch
+        _check(_lib.sipg_patch_correct_lp(self._h, self._lvl(level), int(colour),
+                                          _ptr(r, torch.float32), _ptr(x, torch.float32),
+                                          _stream(stream)))
         return x
 
     def patch_correct(self, colour, r, x, level=-1, stream=None):
@@ -262,11 +328,12 @@ class Problem:
         self._network = network
 
     def fgmres(self, b, x=None, rtol=1e-10, restart=30, max_iters=200, log_history=True,
-               stream=None, raise_on_nonconvergence=True, use_learned=False, stagnation=0.0):
+               stream=None, raise_on_nonconvergence=True, use_learned=False, stagnation=0.0,
+               variant="fgmres"):
         import torch
         x = torch.zeros_like(b) if x is None else x
         opts = SolveOpts(rtol, restart, max_iters, int(bool(use_learned)), int(log_history),
-                         stagnation)
+                         stagnation, VARIANT[variant])
         info = SolveInfo()
         st = _lib.sipg_fgmres(self._h, _ptr(x, torch.float64), _ptr(b, torch.float64),
                               ctypes.byref(opts), ctypes.byref(info), _stream(stream))
@@ -325,14 +392,15 @@ class Batch:
     """Independent problems of uneven degree and size solved together
     (vectors are lists of CUDA tensors, one per problem)."""
 
-    def __init__(self, problems, mg_precision="f64", error_correction=False, nu_pre=2, nu_post=2):
+    def __init__(self, problems, mg_precision="f64", error_correction=0, nu_pre=2, nu_post=2,
+                 allocator=None, stream=None):
         lib = load_library()
         cfgs = (Config * len(problems))()
         for i, (k, n) in enumerate(problems):
-            cfgs[i] = Config(k, n, 0, PRECISION[mg_precision], int(bool(error_correction)),
-                             nu_pre, nu_post)
+            cfgs[i] = make_config(k, n, 0, mg_precision, int(error_correction), nu_pre, nu_post,
+                                  allocator=allocator)
         h = ctypes.c_void_p()
-        _check(lib.sipg_batch_create(cfgs, len(problems), ctypes.byref(h)))
+        _check(lib.sipg_batch_create(cfgs, len(problems), _stream(stream), ctypes.byref(h)))
         self._h = h
         self.problems = list(problems)
         self.sizes = []
@@ -376,7 +444,7 @@ class Batch:
               sequential=False, stream=None):
         import torch
         xs = [torch.zeros_like(b) for b in bs] if xs is None else xs
-        opts = SolveOpts(rtol, restart, max_iters, 0, 1, 0.0)
+        opts = SolveOpts(rtol, restart, max_iters, 0, 1, 0.0, 0)
         infos = (SolveInfo * len(bs))()
         if sequential:
             st = _lib.sipg_batch_solve_sequential(self._h, _ptr_array(xs, torch.float64, self.sizes),
@@ -511,22 +579,11 @@ class Network:
                     sigma=info.sigma, seconds=info.seconds, seconds_pairs=info.seconds_pairs)
 
     def save(self, path):
-        """Weights as raw little-endian float32 (`path`.bin) plus JSON meta."""
-        import json
-        p, sig = self.get_params()
-        p.astype("<f4").tofile(path + ".bin")
-        with open(path + ".json", "w") as f:
-            json.dump({"architecture": "conv3d 1-32-32-32-1, 3x3x3, zero padding, ReLU",
-                       "n_params": int(p.size), "sigma": sig, "dtype": "float32"}, f)
+        """Parameters and output scale to `path` (format of sipg_cnn_save)."""
+        _check(_lib.sipg_cnn_save(self._h, os.fsencode(path)))
 
     @classmethod
     def load(cls, path):
-        import json
-        with open(path + ".json") as f:
-            meta = json.load(f)
-        p = np.fromfile(path + ".bin", dtype="<f4")
         net = cls()
-        if p.size != meta["n_params"] or p.size != net.n_params:
-            raise ValueError("weight file does not match the network")
-        net.set_params(p, meta["sigma"])
+        _check(_lib.sipg_cnn_load(net._h, os.fsencode(path)))
         return net

@@ -159,5 +159,50 @@ def test_batch_rejects_mixed_precision_before_allocating():
     cfgs[1] = binding.Config(2, 4, 0, binding.PRECISION["f16"], 1, 2, 2)
     h = ctypes.c_void_p()
     with pytest.raises(SipgError, match="share precision"):
-        binding._check(binding.load_library().sipg_batch_create(cfgs, 2, ctypes.byref(h)))
+        binding._check(binding.load_library().sipg_batch_create(cfgs, 2, None, ctypes.byref(h)))
     assert not h.value
+
+
+@pytest.mark.parametrize("kw,status,msg", [
+    (dict(k=5, mg_precision="bf16", error_correction=0), 2, "stalls"),
+    (dict(k=7, mg_precision="bf16", error_correction=0), 2, "stalls"),
+    (dict(k=3, error_correction=3), 1, "error_correction"),
+    (dict(k=3, penalty_scale=0.5), 1, "penalty_scale"),
+    (dict(k=3, mg_precision="f16", smoother="additive"), 2, "additive"),
+    (dict(k=0), 1, "k must be"),
+])
+def test_create_rejects_before_any_device_call(kw, status, msg):
+    """Argument checks of sipg_create that run before any device call (so
+    they hold without a GPU): the refused BF16 V-cycle without correction at
+    k >= 5, EC modes, the penalty scale and the additive smoother's
+    precision."""
+    from paper_2407_09621_amd import sipg as binding
+    args = dict(k=3, n_cells=4)
+    args.update(kw)
+    cfg = binding.make_config(**args)
+    h = ctypes.c_void_p()
+    st = binding.load_library().sipg_create(ctypes.byref(cfg), None, ctypes.byref(h))
+    assert st == status and not h.value
+    assert msg in binding.load_library().sipg_last_error().decode()
+
+
+def test_create_rejects_half_an_allocator():
+    from paper_2407_09621_amd import sipg as binding
+    cfg = binding.make_config(3, 4)
+    cfg.alloc = binding.TORCH_ALLOC
+    h = ctypes.c_void_p()
+    st = binding.load_library().sipg_create(ctypes.byref(cfg), None, ctypes.byref(h))
+    assert st == 1 and not h.value
+    assert "together" in binding.load_library().sipg_last_error().decode()
+
+
+def test_header_and_binding_agree_on_struct_layouts():
+    """The ctypes mirrors of the header's structs: field count and order of
+    sipg_config and sipg_solve_opts (sizes follow from the types)."""
+    from paper_2407_09621_amd import sipg as binding
+    text = open(HEADER).read()
+    for cname, pyname in (("sipg_config", "Config"), ("sipg_solve_opts", "SolveOpts")):
+        body = re.search(r"typedef struct \{([^{}]*)\} " + cname + ";", text).group(1)
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        fields = re.findall(r"(\w+);", body)
+        assert fields == [f[0] for f in getattr(binding, pyname)._fields_], cname

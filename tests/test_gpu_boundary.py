@@ -1,0 +1,152 @@
+"""GPU checks of the C-ABI options beyond the default path: workspace from
+the caller's allocator (torch's caching allocator), the penalty scale
+(Sec. 2, gamma), the reduced-precision smoother entry point, the network
+file format through the C ABI, the non-flexible GMRES variant and the
+additive smoother (Sec. 7.2's comparisons).  Each result is compared with
+the oracle or with the default entry point."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from gpu_util import announce, rel_l2, to_cpu, to_gpu
+from oracle import fgmres as ofg
+from oracle import multigrid, rhs, sipg
+from paper_2407_09621_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def test_torch_allocator_owns_the_workspace():
+    """With allocator='torch' every workspace block comes from torch's
+    caching allocator (its counter rises by the handle's workspace and falls
+    back on destroy) and the results equal the default handle's bit for bit."""
+    import torch
+    from paper_2407_09621_amd import Problem
+    announce("torch allocator")
+    k, n = 3, 8
+    amps, pqr = inputs.single_sine_modes()
+    P0 = Problem(k, n)
+    b = P0.rhs_sines(amps, pqr)
+    x0, i0 = P0.fgmres(b, rtol=1e-10)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    P1 = Problem(k, n, allocator="torch")
+    during = torch.cuda.memory_allocated()
+    # level vectors (3 per level below the finest, 1 on it) at least
+    assert during - before >= 8 * P1.n_dofs()
+    x1, i1 = P1.fgmres(b, rtol=1e-10)
+    assert i1["iterations"] == i0["iterations"]
+    assert torch.equal(x0, x1)
+    u = torch.from_numpy(inputs.uniform_vector(P1.n_dofs(), 3)).cuda()
+    assert torch.equal(P0.apply(u), P1.apply(u))
+    P1.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == before
+
+
+@pytest.mark.parametrize("k,n,s", [(2, 3, 2.5), (3, 4, 7.0), (7, 2, 1.5)])
+def test_penalty_scale_apply_and_solve(k, n, s):
+    from paper_2407_09621_amd import Problem
+    announce("penalty scale", k, n, s)
+    P = Problem(k, n, penalty_scale=s)
+    A = sipg.assemble(n, k, penalty_scale=s)
+    u = inputs.uniform_vector(P.n_dofs(), 12 + k)
+    v = to_cpu(P.apply(to_gpu(u)))
+    assert rel_l2(v, A @ u) < 1e-12
+    b = inputs.uniform_vector(P.n_dofs(), 13 + k)
+    x, info = P.fgmres(to_gpu(b), rtol=1e-11)
+    assert rel_l2(to_cpu(x), spla.spsolve(A.tocsc(), b)) < 1e-8
+
+
+@pytest.mark.parametrize("prec,ec,tol", [("f32", 0, 1e-5), ("f16", 1, 1e-5), ("bf16", 2, 2e-2)])
+def test_lowprec_smoother_matches_oracle(prec, ec, tol):
+    """sipg_smooth_lp (two sweeps on FP32 vectors) against the oracle's FP64
+    sweeps; the bound is that of one V-cycle's smoothing (a few units of the
+    data format times the steps, with the eps of the rounded operator)."""
+    import torch
+    from paper_2407_09621_amd import Problem
+    announce("smooth lp", prec, ec)
+    k, n = 2, 4
+    P = Problem(k, n, n_levels=1, mg_precision=prec, error_correction=ec)
+    lev = multigrid.Level(n, k)
+    b = inputs.uniform_vector(P.n_dofs(), 41).astype(np.float32)
+    x0 = inputs.uniform_vector(P.n_dofs(), 42).astype(np.float32)
+    x = to_gpu(x0)
+    P.smooth_lp(x, to_gpu(b), 2)
+    ref = multigrid.smooth(lev, x0.astype(np.float64), b.astype(np.float64), 2)
+    assert rel_l2(to_cpu(x).astype(np.float64), ref) < tol
+
+
+def test_network_file_roundtrip_and_rejection(tmp_path):
+    from paper_2407_09621_amd import Network
+    from paper_2407_09621_amd.sipg import SipgError
+    announce("cnn file")
+    net = Network(seed=3)
+    p, _ = net.get_params()
+    net.set_params(p, 0.25)
+    path = str(tmp_path / "net.bin")
+    net.save(path)
+    raw = open(path, "rb").read()
+    assert raw[:8] == b"SIPGCNN1" and len(raw) == 16 + 4 * net.n_params
+    assert np.frombuffer(raw[8:12], "<i4")[0] == net.n_params
+    assert np.frombuffer(raw[12:16], "<f4")[0] == 0.25
+    assert np.array_equal(np.frombuffer(raw[16:], "<f4"), p)
+    back = Network.load(path)
+    p1, s1 = back.get_params()
+    assert np.array_equal(p1, p) and s1 == 0.25
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(raw[:100])
+    with pytest.raises(SipgError, match="short"):
+        Network.load(str(bad))
+    bad.write_bytes(b"XXXXXXXX" + raw[8:])
+    with pytest.raises(SipgError, match="not a network"):
+        Network.load(str(bad))
+
+
+def test_gmres_variant_with_linear_and_nonlinear_preconditioners():
+    """Right-preconditioned GMRES against FGMRES (Sec. 7.2): with the FP64
+    V-cycle (a fixed linear map) both give the same iterations and solution;
+    with the FP16 V-cycle (rounding makes it vary from call to call) FGMRES
+    still reaches rtol in the true residual and GMRES is no better."""
+    from paper_2407_09621_amd import Problem
+    announce("gmres variant")
+    k, n = 3, 8
+    amps, pqr = inputs.single_sine_modes()
+    P = Problem(k, n)
+    b = P.rhs_sines(amps, pqr)
+    xf, inf = P.fgmres(b, rtol=1e-10)
+    xg, ing = P.fgmres(b, rtol=1e-10, variant="gmres")
+    assert abs(inf["iterations"] - ing["iterations"]) <= 1
+    assert ing["rel_res_true"] < 1e-9
+    assert rel_l2(to_cpu(xg), to_cpu(xf)) < 1e-8
+    P16 = Problem(k, n, mg_precision="f16", error_correction=0)
+    x16f, i16f = P16.fgmres(b, rtol=1e-10, max_iters=60)
+    x16g, i16g = P16.fgmres(b, rtol=1e-10, max_iters=60, variant="gmres",
+                            raise_on_nonconvergence=False)
+    print(f"  f16 FGMRES {i16f['iterations']} its true {i16f['rel_res_true']:.2e}; "
+          f"GMRES {i16g['iterations']} its est {i16g['rel_res_est']:.2e} "
+          f"true {i16g['rel_res_true']:.2e}")
+    assert i16f["rel_res_true"] < 1e-10
+    assert i16g["rel_res_true"] >= 0.5 * i16f["rel_res_true"]
+
+
+@pytest.mark.parametrize("k,n", [(2, 4), (3, 4)])
+def test_additive_smoother_vcycle_and_solve_match_oracle(k, n):
+    from paper_2407_09621_amd import Problem
+    announce("additive", k, n)
+    P = Problem(k, n, smoother="additive")
+    H = multigrid.Hierarchy(n, k, smoother="additive")
+    b = inputs.uniform_vector(P.n_dofs(), 90 + k)
+    x0 = inputs.uniform_vector(P.n_dofs(), 91 + k)
+    x = to_gpu(x0)
+    P.vcycle(x, to_gpu(b))
+    assert rel_l2(to_cpu(x), H.vcycle(len(H.levels) - 1, x0, b)) < 1e-10
+    amps, pqr = inputs.single_sine_modes()
+    bb = P.rhs_sines(amps, pqr)
+    xs, info = P.fgmres(bb, rtol=1e-10, max_iters=100)
+    A = H.levels[-1].A
+    _, io = ofg.fgmres(lambda v: A @ v, to_cpu(bb), H.precondition, rtol=1e-10, max_iters=100)
+    assert abs(info["iterations"] - io["iterations"]) <= 1
+    Pm = Problem(k, n)
+    _, im = Pm.fgmres(bb, rtol=1e-10)
+    assert info["iterations"] > im["iterations"]
