@@ -120,6 +120,21 @@ int64_t sipg_n_dofs(const sipg_problem* p, int level);
 sipg_status sipg_apply(sipg_problem* p, int level, const double* u, double* v,
                        hipStream_t stream);
 
+/* Execution units of the FP64 apply (the paper's comparison of tensor-core
+ * and CUDA-core kernels, Sec. 4 and App. A, on gfx950's matrix and vector
+ * units). */
+typedef enum {
+  SIPG_UNITS_AUTO = 0,    /* what sipg_apply uses: matrix cores for k = 3 and 7 */
+  SIPG_UNITS_VECTOR = 1,  /* FP64 vector units (one 1D line per lane), every k */
+  SIPG_UNITS_MATRIX = 2   /* FP64 matrix cores (v_mfma_f64_4x4x4f64); k = 3, 7 */
+} sipg_units;
+
+/* sipg_apply on the chosen execution units: the same v = A_l u (parity with
+ * the oracle to rounding), computed by the kernel `units` names.
+ * SIPG_ERR_UNSUPPORTED for SIPG_UNITS_MATRIX with k other than 3 and 7. */
+sipg_status sipg_apply_units(sipg_problem* p, int level, const double* u, double* v, int units,
+                             hipStream_t stream);
+
 /* v = A_l u with FP32 vectors in a reduced-precision arithmetic (Sec. 5,
  * Sec. 7.1): precision SIPG_F32 (FP32 throughout), SIPG_F16 or SIPG_BF16
  * (1D contractions on the matrix cores with FP16/BF16 operands and FP32

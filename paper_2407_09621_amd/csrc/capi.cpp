@@ -340,6 +340,21 @@ sipg_status sipg_apply(sipg_problem* p, int level, const double* u, double* v, h
   return SIPG_OK;
 }
 
+sipg_status sipg_apply_units(sipg_problem* p, int level, const double* u, double* v, int units,
+                             hipStream_t s) {
+  SIPG_TRY(check_level(p, level));
+  if (!u || !v) return fail(SIPG_ERR_ARG, "NULL vector");
+  if (u == v) return fail(SIPG_ERR_ARG, "u and v must not alias");
+  if (units < SIPG_UNITS_AUTO || units > SIPG_UNITS_MATRIX)
+    return fail(SIPG_ERR_ARG, "units must be a sipg_units");
+  const bool has_matrix = p->N == 4 || p->N == 8;
+  if (units == SIPG_UNITS_MATRIX && !has_matrix)
+    return fail(SIPG_ERR_UNSUPPORTED, "the FP64 matrix-core apply exists for k = 3 and 7 only");
+  ApplyJob j{u, v, nullptr, p->n[level], level_h(p, level), tile_order(p, level)};
+  SIPG_HIP(launch_apply_batch(units == SIPG_UNITS_VECTOR ? 2 : 0, p->N, &j, 1, p->tab, s));
+  return SIPG_OK;
+}
+
 sipg_status sipg_residual(sipg_problem* p, int level, const double* b, const double* x, double* r,
                           hipStream_t s) {
   SIPG_TRY(check_level(p, level));

@@ -62,7 +62,9 @@ hipError_t launch_patch_mfma4_batch(int prec, int colour, const PatchJob* jobs, 
                                     const DevTab& t, hipStream_t s);
 
 // Batched forms: up to kMaxBatch problems of one degree per launch.
-// prec 0 = FP64 vectors, 1 = FP32 vectors (VALU arithmetic).
+// prec 0 = FP64 vectors (the apply on the matrix cores for N = 4 and 8),
+// 1 = FP32 vectors (VALU arithmetic), 2 (apply only) = FP64 vectors on the
+// vector units for every N.
 hipError_t launch_apply_batch(int prec, int N, const ApplyJob* jobs, int count, const DevTab& t,
                               hipStream_t s);
 hipError_t launch_patch_fd_batch(int prec, int N, int colour, const PatchJob* jobs, int count,

@@ -1049,7 +1049,7 @@ hipError_t launch_apply_batch(int prec, int N, const ApplyJob* jobs, int count, 
   if (t.lay.N != N) return hipErrorInvalidValue;
   if (prec == 0 && N == 4) return launch_apply_mfma4_batch(jobs, count, t, s);
   if (prec == 0 && N == 8) return launch_apply_mfma8_batch(jobs, count, t, s);
-  if (prec == 0) {
+  if (prec == 0 || prec == 2) {
 #define CALL(NN) apply_impl<double, NN>(jobs, count, t, s)
     SIPG_DISPATCH_N(N, CALL)
 #undef CALL

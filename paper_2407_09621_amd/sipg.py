@@ -17,6 +17,7 @@ SIPG_OK = 0
 STATUS = {0: "SIPG_OK", 1: "SIPG_ERR_ARG", 2: "SIPG_ERR_UNSUPPORTED", 3: "SIPG_ERR_OOM",
           4: "SIPG_ERR_HIP", 5: "SIPG_ERR_NOT_CONVERGED", 6: "SIPG_ERR_NONFINITE"}
 PRECISION = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
+UNITS = {"auto": 0, "vector": 1, "matrix": 2}
 
 _lib = None
 
@@ -129,6 +130,7 @@ def load_library(path=None):
         "sipg_level_cells": (i32, [vp, i32]),
         "sipg_n_dofs": (i64, [vp, i32]),
         "sipg_apply": (i32, [vp, i32, vp, vp, vp]),
+        "sipg_apply_units": (i32, [vp, i32, vp, vp, i32, vp]),
         "sipg_residual": (i32, [vp, i32, vp, vp, vp, vp]),
         "sipg_apply_lp": (i32, [vp, i32, vp, vp, i32, i32, vp]),
         "sipg_smooth": (i32, [vp, i32, vp, vp, i32, vp]),
@@ -236,11 +238,17 @@ class Problem:
         import torch
         return torch.zeros(self.n_dofs(level), dtype=dtype or torch.float64, device="cuda")
 
-    def apply(self, u, v=None, level=-1, stream=None):
+    def apply(self, u, v=None, level=-1, stream=None, units=None):
+        """v = A u in FP64; units "vector" or "matrix" picks the execution
+        units (sipg_apply_units), None what sipg_apply uses."""
         import torch
         v = torch.empty_like(u) if v is None else v
-        _check(_lib.sipg_apply(self._h, self._lvl(level), _ptr(u, torch.float64),
-                               _ptr(v, torch.float64), _stream(stream)))
+        if units is None:
+            _check(_lib.sipg_apply(self._h, self._lvl(level), _ptr(u, torch.float64),
+                                   _ptr(v, torch.float64), _stream(stream)))
+        else:
+            _check(_lib.sipg_apply_units(self._h, self._lvl(level), _ptr(u, torch.float64),
+                                         _ptr(v, torch.float64), UNITS[units], _stream(stream)))
         return v
 
     def apply_lp(self, u, v=None, precision="f16", ec=False, level=-1, stream=None):

@@ -76,3 +76,35 @@ def test_apply_full_size(k, n):
     rows = np.concatenate([rows, [0, P.n_dofs() - 1]])
     samp = sipg.apply_rows(u, n, k, rows)
     np.testing.assert_allclose(v[rows], samp, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("k,n", [(3, 3), (3, 9), (7, 2), (7, 5), (5, 4), (1, 6)])
+def test_apply_units_match_assembled_matrix(k, n):
+    """sipg_apply_units: the FP64 vector-unit kernel (every degree) and the
+    matrix-core kernel (degrees 3 and 7) give the oracle's A u; 9 cells per
+    row at k = 3 leave a ragged tile of the 8-cell matrix-core rows."""
+    from paper_2407_09621_amd import Problem, SipgError
+    announce("apply units", k, n)
+    P = Problem(k, n, n_levels=1)
+    u = inputs.uniform_vector(P.n_dofs(), seed=3000 + 10 * k + n)
+    ref = sipg.assemble(n, k) @ u
+    units = ["vector", "matrix"] if k in (3, 7) else ["vector"]
+    for un in units:
+        v = to_cpu(P.apply(to_gpu(u), units=un))
+        assert rel_l2(v, ref) < 1e-12, un
+        np.testing.assert_allclose(v, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    if k not in (3, 7):
+        with pytest.raises(SipgError, match="k = 3 and 7"):
+            P.apply(to_gpu(u), units="matrix")
+
+
+@pytest.mark.parametrize("k,n", [(3, 64), (7, 32)])
+def test_apply_vector_units_full_size(k, n):
+    """The vector-unit kernel at the benchmark sizes of the two matrix-core
+    degrees (the launch the benchmark's vector-unit rows time)."""
+    from paper_2407_09621_amd import Problem
+    announce("apply vector units full size", k, n)
+    P = Problem(k, n, n_levels=1)
+    u = inputs.uniform_vector(P.n_dofs(), seed=2 + k)
+    v = to_cpu(P.apply(to_gpu(u), units="vector"))
+    assert rel_l2(v, sipg.kron_apply(u, n, k)) < 1e-12

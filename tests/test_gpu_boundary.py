@@ -39,6 +39,7 @@ def test_torch_allocator_owns_the_workspace():
     assert torch.equal(x0, x1)
     u = torch.from_numpy(inputs.uniform_vector(P1.n_dofs(), 3)).cuda()
     assert torch.equal(P0.apply(u), P1.apply(u))
+    del x1, u  # torch tensors made after `before`, not workspace of the handle
     P1.close()
     torch.cuda.synchronize()
     assert torch.cuda.memory_allocated() == before
