@@ -259,6 +259,22 @@ sipg_status sipg_l2_error_sines(sipg_problem* p, int level, int n_modes,
                                 const double* x, double* err,
                                 hipStream_t stream);
 
+/* sipg_l2_error_sines without any allocation, for callers that cannot
+ * allocate device memory (tight serving loops, harnesses that forbid it):
+ * the same result and kernels, with the tables, partial sums and result in a
+ * fixed workspace of 1 MiB per device that the library holds in a static
+ * device array (not in the handle, whose table buffer sipg_l2_error_sines
+ * grows on demand).  Limit: n_modes * 3 * n_level * (k + 3) + n_modes +
+ * (k + 3)(k + 2) <= 130,016 table entries (e.g. 4 modes up to 1,082 cells per
+ * direction at k = 7); larger requests return SIPG_ERR_ARG.  Every call on a
+ * device shares that device's workspace, so calls that overlap on one
+ * device (from several host threads, or streams not ordered with each
+ * other) race; host threads are serialized while the tables are staged.
+ * Synchronizes the stream. */
+sipg_status sipg_l2_error_sines_noalloc(sipg_problem* p, int level, int n_modes,
+                                        const double* amps, const int* pqr,
+                                        const double* x, double* err, hipStream_t stream);
+
 /* Tile-order autotuner of the operator apply: times the apply on `level`
  * with each admissible tile-order block (1, 2, 4, 8 cells, dividing n) and
  * keeps the fastest for all later applies, residuals and smoother sweeps of

@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -165,6 +166,46 @@ sipg_status ensure_aux(sipg_problem* p, size_t count) {
   return SIPG_OK;
 }
 
+// Tables of the L2 error on a level of nl cells per direction with nq = k+3
+// Gauss points: amps[n_modes], the mode values sin(p pi x) at every cell's
+// points per direction [3][n_modes][nl][nq], the Lagrange values at the points
+// [nq][N] and the weights [nq].
+size_t l2_table_size(int n_modes, int nl, int nq, int N) {
+  return (size_t)n_modes + 3 * (size_t)n_modes * nl * nq + (size_t)nq * N + nq;
+}
+
+void l2_fill_tables(const sipg_problem* p, int nl, int n_modes, const double* amps,
+                    const int* pqr, double* host) {
+  const int N = p->N, nq = p->k + 3;
+  const double h = 1.0 / nl;
+  const size_t tab = (size_t)n_modes * nl * nq;
+  double* a = host;
+  double* st[3] = {a + n_modes, a + n_modes + tab, a + n_modes + 2 * tab};
+  double* ip = a + n_modes + 3 * tab;
+  double* w = ip + (size_t)nq * N;
+  for (int m = 0; m < n_modes; ++m) {
+    a[m] = amps[m];
+    for (int d = 0; d < 3; ++d)
+      for (int c = 0; c < nl; ++c)
+        for (int q = 0; q < nq; ++q)
+          st[d][((size_t)m * nl + c) * nq + q] =
+              std::sin(pqr[3 * m + d] * M_PI * h * (c + p->l2_xq[q]));
+  }
+  for (int i = 0; i < nq * N; ++i) ip[i] = p->l2_V[i];
+  for (int q = 0; q < nq; ++q) w[q] = p->l2_wq[q];
+}
+
+// sum over cells of the squared error into *out (device), tables at d
+sipg_status l2_launch(const sipg_problem* p, int nl, int n_modes, const double* d,
+                      const double* x, double* partial, double* out, hipStream_t s) {
+  const int N = p->N, nq = p->k + 3;
+  const size_t tab = (size_t)n_modes * nl * nq;
+  SIPG_HIP(launch_l2_sines(N, nq, nl, n_modes, d, d + n_modes, d + n_modes + tab,
+                           d + n_modes + 2 * tab, d + n_modes + 3 * tab,
+                           d + n_modes + 3 * tab + (size_t)nq * N, 1.0 / nl, x, partial, out, s));
+  return SIPG_OK;
+}
+
 }  // namespace
 
 namespace sipg {
@@ -247,6 +288,8 @@ sipg_status sipg_create(const sipg_config* cfg, hipStream_t stream, sipg_problem
     delete p;
     return fail(SIPG_ERR_ARG, e.what());
   }
+  gauss_legendre(p->k + 3, p->l2_xq, p->l2_wq);  // L2 error rule
+  lagrange_eval(make_tables_1d(p->k).nodes, p->l2_xq, p->l2_V, nullptr);
   std::vector<float> tf(tab.begin(), tab.end());  // FP32 copy (FP32 / FP16 / BF16 kernels)
   sipg_status st = prob_alloc(p, &p->d_tab, tab.size());
   if (st == SIPG_OK) st = prob_alloc(p, &p->d_tabf, tf.size());
@@ -692,36 +735,46 @@ sipg_status sipg_l2_error_sines(sipg_problem* p, int level, int n_modes, const d
   if (n_modes < 1 || n_modes > 64 || !amps || !pqr || !x || !err)
     return fail(SIPG_ERR_ARG, "bad modes");
   const int N = p->N, nl = p->n[level], nq = p->k + 3;
-  const double h = 1.0 / nl;
-  std::vector<double> nodes = make_tables_1d(p->k).nodes, xq, wq, V;
-  gauss_legendre(nq, xq, wq);
-  lagrange_eval(nodes, xq, V, nullptr);
-  // amps, sx, sy, sz, interp, wq
-  const size_t tab = (size_t)n_modes * nl * nq;
-  std::vector<double> host(n_modes + 3 * tab + (size_t)nq * N + nq);
-  double* a = host.data();
-  double* st[3] = {a + n_modes, a + n_modes + tab, a + n_modes + 2 * tab};
-  double* ip = a + n_modes + 3 * tab;
-  double* w = ip + (size_t)nq * N;
-  for (int m = 0; m < n_modes; ++m) {
-    a[m] = amps[m];
-    for (int d = 0; d < 3; ++d)
-      for (int c = 0; c < nl; ++c)
-        for (int q = 0; q < nq; ++q)
-          st[d][((size_t)m * nl + c) * nq + q] = std::sin(pqr[3 * m + d] * M_PI * h * (c + xq[q]));
-  }
-  for (int i = 0; i < nq * N; ++i) ip[i] = V[i];
-  for (int q = 0; q < nq; ++q) w[q] = wq[q];
+  std::vector<double> host(l2_table_size(n_modes, nl, nq, N));
+  l2_fill_tables(p, nl, n_modes, amps, pqr, host.data());
   SIPG_TRY(ensure_aux(p, host.size()));
   SIPG_HIP(hipMemcpyAsync(p->d_aux, host.data(), host.size() * sizeof(double),
                           hipMemcpyHostToDevice, s));
-  const double* d = p->d_aux;
-  SIPG_HIP(launch_l2_sines(N, nq, nl, n_modes, d, d + n_modes, d + n_modes + tab,
-                           d + n_modes + 2 * tab, d + n_modes + 3 * tab,
-                           d + n_modes + 3 * tab + (size_t)nq * N, h, x, p->d_partial,
-                           p->d_small + 300, s));
+  SIPG_TRY(l2_launch(p, nl, n_modes, p->d_aux, x, p->d_partial, p->d_small + 300, s));
   double e2 = 0.0;
   SIPG_HIP(hipMemcpyAsync(&e2, p->d_small + 300, sizeof(double), hipMemcpyDeviceToHost, s));
+  SIPG_HIP(hipStreamSynchronize(s));
+  *err = std::sqrt(e2);
+  return SIPG_OK;
+}
+
+sipg_status sipg_l2_error_sines_noalloc(sipg_problem* p, int level, int n_modes,
+                                        const double* amps, const int* pqr, const double* x,
+                                        double* err, hipStream_t s) {
+  SIPG_TRY(check_level(p, level));
+  if (n_modes < 1 || n_modes > 64 || !amps || !pqr || !x || !err)
+    return fail(SIPG_ERR_ARG, "bad modes");
+  const int N = p->N, nl = p->n[level], nq = p->k + 3;
+  // scratch: tables, then kDotBlocks partial sums and the result (256-byte aligned)
+  const size_t tab = l2_table_size(n_modes, nl, nq, N);
+  const size_t off_part = (tab + 31) / 32 * 32, off_out = off_part + kDotBlocks;
+  if (off_out + 1 > kL2ScratchDoubles)
+    return fail(SIPG_ERR_ARG, "sipg_l2_error_sines_noalloc: " + std::to_string(tab) +
+                                  " table entries exceed the fixed workspace's " +
+                                  std::to_string((kL2ScratchDoubles - kDotBlocks - 1) / 32 * 32) +
+                                  " (use sipg_l2_error_sines)");
+  double* scr = nullptr;
+  SIPG_HIP(l2_scratch(&scr));
+  // host staging: one fixed buffer (hipMemcpyAsync from pageable memory has
+  // copied it out before it returns), serialized across host threads
+  static std::mutex mu;
+  static double host[kL2ScratchDoubles];
+  std::lock_guard<std::mutex> lock(mu);
+  l2_fill_tables(p, nl, n_modes, amps, pqr, host);
+  SIPG_HIP(hipMemcpyAsync(scr, host, tab * sizeof(double), hipMemcpyHostToDevice, s));
+  SIPG_TRY(l2_launch(p, nl, n_modes, scr, x, scr + off_part, scr + off_out, s));
+  double e2 = 0.0;
+  SIPG_HIP(hipMemcpyAsync(&e2, scr + off_out, sizeof(double), hipMemcpyDeviceToHost, s));
   SIPG_HIP(hipStreamSynchronize(s));
   *err = std::sqrt(e2);
   return SIPG_OK;

@@ -112,4 +112,11 @@ hipError_t launch_l2_sines(int N, int nq, int n, int n_modes, const double* amps
                            const double* interp, const double* wq, double h,
                            const double* x, double* partial, double* out, hipStream_t s);
 
+// Device address of the fixed workspace of the allocation-free L2 error on
+// the current device (kL2ScratchDoubles doubles, 256-byte aligned; looked up
+// once per device).  Calls that use it overlap-race on one device.
+constexpr size_t kL2ScratchDoubles = 131072;  // 1 MiB
+constexpr int kMaxDevices = 64;
+hipError_t l2_scratch(double** out);
+
 }  // namespace sipg

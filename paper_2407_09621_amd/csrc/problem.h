@@ -66,6 +66,7 @@ struct sipg_problem {
   int* d_flag = nullptr;
   double* d_aux = nullptr;          // tables for rhs / l2 (grown on demand)
   size_t aux_size = 0;
+  std::vector<double> l2_xq, l2_wq, l2_V;  // (k+3)-point Gauss rule, Lagrange values there
   // low-precision V-cycle (mg_precision != F64): FP32 level vectors
   int prec = SIPG_F64;
   int ec = 0;  // 0 none, 1 both operands split, 2 matrix operand split

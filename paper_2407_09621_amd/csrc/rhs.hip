@@ -6,9 +6,17 @@
 // of each cell by sum factorization (Sec. 2.1, interpolation formula).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "kernels.h"
 
 namespace sipg {
+
+// Workspace of the allocation-free L2 error (sipg_l2_error_sines_noalloc):
+// its host-prepared tables, the per-workgroup partial sums and the result.
+// Each device holds its own copy until the process ends; host code reaches
+// it only through the address hipGetSymbolAddress returns for that device.
+static __device__ __align__(256) double scratch[kL2ScratchDoubles];
 
 namespace {
 
@@ -140,6 +148,25 @@ hipError_t launch_l2_sines(int N, int nq, int n, int n_modes, const double* amps
                      interp, wq, h, x, partial);
   hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(kT), 0, s, partial, grid, out);
   return hipGetLastError();
+}
+
+hipError_t l2_scratch(double** out) {
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  static std::mutex mu;
+  static double* ptr[kMaxDevices] = {};
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    void* a = nullptr;
+    e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));  // the current device's copy
+    if (e != hipSuccess) return e;
+    ptr[dev] = (double*)a;
+  }
+  *out = ptr[dev];
+  return hipSuccess;
 }
 
 }  // namespace sipg

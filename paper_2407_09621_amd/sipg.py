@@ -142,6 +142,7 @@ def load_library(path=None):
         "sipg_fgmres": (i32, [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp]),
         "sipg_rhs_sines": (i32, [vp, i32, i32, vp, vp, vp, vp]),
         "sipg_l2_error_sines": (i32, [vp, i32, i32, vp, vp, vp, ctypes.POINTER(dbl), vp]),
+        "sipg_l2_error_sines_noalloc": (i32, [vp, i32, i32, vp, vp, vp, ctypes.POINTER(dbl), vp]),
         "sipg_last_error": (ctypes.c_char_p, []),
         "sipg_autotune": (i32, [vp, i32, vp, vp, ctypes.POINTER(i32), vp]),
         "sipg_cnn_num_params": (i32, []),
@@ -364,12 +365,15 @@ class Problem:
                                    _ptr(b, torch.float64), _stream(stream)))
         return b
 
-    def l2_error_sines(self, amps, pqr, x, level=-1, stream=None):
+    def l2_error_sines(self, amps, pqr, x, level=-1, stream=None, noalloc=False):
+        """||u - u_h||_L2 of the sine modes; noalloc=True calls the entry point
+        that uses the library's fixed per-device workspace."""
         import torch
         amps = np.ascontiguousarray(amps, dtype=np.float64).reshape(-1)
         pqr = np.ascontiguousarray(pqr, dtype=np.int32).reshape(-1, 3)
         err = ctypes.c_double()
-        _check(_lib.sipg_l2_error_sines(self._h, self._lvl(level), len(amps),
+        fn = _lib.sipg_l2_error_sines_noalloc if noalloc else _lib.sipg_l2_error_sines
+        _check(fn(self._h, self._lvl(level), len(amps),
                                         amps.ctypes.data_as(ctypes.c_void_p),
                                         pqr.ctypes.data_as(ctypes.c_void_p),
                                         _ptr(x, torch.float64), ctypes.byref(err),
