@@ -75,10 +75,16 @@ typedef struct {
   int nu_pre;            /* pre-smoothing sweeps (2 for V(2,2)) */
   int nu_post;           /* post-smoothing sweeps */
   int smoother;          /* 0: multiplicative vertex-patch smoother (colour by
-                            colour, a fresh residual per colour; the paper's
-                            choice, Sec. 7.1); 1: additive (one residual per
-                            sweep, all patch corrections summed and damped;
-                            FP64 V-cycles only) */
+                            colour, the paper's choice, Sec. 7.1), each colour
+                            step one fused launch: the new patch values are the
+                            local solve with the right-hand side minus the face
+                            couplings of the outside neighbours, which equals
+                            x_P + inv(A_PP) (b - A x)_P (FP64 / FP32 V-cycles;
+                            FP16 / BF16 take form 2); 1: additive (one residual
+                            per sweep, all patch corrections summed and damped;
+                            FP64 V-cycles only); 2: multiplicative with a
+                            separate residual launch per colour (same result to
+                            rounding) */
   double damping;        /* additive smoother: x += damping * sum_P corrections
                             (0 means 1/8: every cell lies in 8 patches) */
   double penalty_scale;  /* penalty gamma = penalty_scale * k(k+1)(1/h+ + 1/h-)
@@ -134,6 +140,19 @@ typedef enum {
  * SIPG_ERR_UNSUPPORTED for SIPG_UNITS_MATRIX with k other than 3 and 7. */
 sipg_status sipg_apply_units(sipg_problem* p, int level, const double* u, double* v, int units,
                              hipStream_t stream);
+
+/* v = A_l u in FP64 evaluated patch by patch, the paper's form (Sec. 2.1,
+ * Fig. patch_int): every interior vertex's patch of 2 x 2 x 2 cells applies
+ * the Kronecker sum of its own 2N x 2N window matrices (mass and
+ * stiffness-plus-face; each interior face integral in one window, the cell
+ * integrals shared by the windows that contain the cell) to its (2N)^3
+ * coefficients, and the patches' results are summed into v, colour by
+ * colour (patches of one colour share no cell).  The same A u as sipg_apply
+ * up to rounding, with about 8 times the products per DoF; for comparing
+ * the two evaluations.  Needs n_level >= 2.  u, v must not overlap; v is
+ * overwritten. */
+sipg_status sipg_apply_patchwise(sipg_problem* p, int level, const double* u, double* v,
+                                 hipStream_t stream);
 
 /* v = A_l u with FP32 vectors in a reduced-precision arithmetic (Sec. 5,
  * Sec. 7.1): precision SIPG_F32 (FP32 throughout), SIPG_F16 or SIPG_BF16
@@ -369,6 +388,16 @@ sipg_status sipg_cnn_forward(sipg_cnn* c, int G, int batch, const float* in, flo
 sipg_status sipg_cnn_gradient(sipg_cnn* c, int G, int batch, const float* in,
                               const float* target, const float* mask, float* grad,
                               float* loss, hipStream_t stream);
+/* Residual-aware loss on the problem's finest level (the learned stage
+ * should cancel the residual the V-cycle leaves, and A amplifies the
+ * high-frequency part of any pointwise error in e): for the scaled residual
+ * rho (device FP64 cell vector of the finest level, e.g. rho / s of a
+ * training pair), c = sigma net(grid(rho)) mapped to cells,
+ * L = ||rho - A c||^2 / ||rho||^2; grad (device, SIPG_CNN_PARAMS floats) =
+ * dL/dparameters through dL/dy = -2 sigma grid(A (rho - A c)) / ||rho||^2;
+ * *loss (device float, may be NULL) = L.  sigma must be set (> 0). */
+sipg_status sipg_cnn_gradient_residual(sipg_cnn* c, sipg_problem* p, const double* rho,
+                                       float* grad, float* loss, hipStream_t stream);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with the
  * device gradient `grad`. */
 sipg_status sipg_cnn_adam_step(sipg_cnn* c, const float* grad, float lr, hipStream_t stream);
@@ -390,6 +419,10 @@ typedef struct {
   float lr;            /* Adam learning rate */
   int log_every;       /* read the loss back every this many steps (0: first/last) */
   uint64_t seed;       /* seed of the draws (modes, crop offsets) */
+  int loss;            /* 0: masked MSE on the error, on random crops (crop,
+                          crops_per_pair); 1: the residual the correction leaves,
+                          ||rho/s - A c||^2 / ||rho/s||^2 with c = sigma net(rho/s),
+                          on the whole grid (sipg_cnn_gradient_residual) */
 } sipg_cnn_train_opts;
 typedef struct {
   int steps;

@@ -144,20 +144,49 @@ def loss_and_grads(params, sigma, xs, ts, masks):
     loss = 0.0
     grads = {k: np.zeros_like(v) for k, v in params.items()}
     for x, t, m in zip(xs, ts, masks):
-        y, (a0, a1, a2, a3) = forward(params, x)
+        y, acts = forward(params, x)
         d = sigma * y - t
         loss += float(np.sum(m * d * d)) / total
         gy = (2.0 * sigma / total) * m * d
-        g3, gw4, gb4 = conv3d_backward(a3, params["w4"], gy[None])
-        g3 = g3 * (a3 > 0)
-        g2, gw3, gb3 = conv3d_backward(a2, params["w3"], g3)
-        g2 = g2 * (a2 > 0)
-        g1, gw2, gb2 = conv3d_backward(a1, params["w2"], g2)
-        g1 = g1 * (a1 > 0)
-        _, gw1, gb1 = conv3d_backward(a0, params["w1"], g1)
-        for name, g in (("w1", gw1), ("b1", gb1), ("w2", gw2), ("b2", gb2),
-                        ("w3", gw3), ("b3", gb3), ("w4", gw4), ("b4", gb4)):
+        for name, g in _backprop(params, acts, gy).items():
             grads[name] += g
+    return loss, grads
+
+
+def _backprop(params, acts, gy):
+    """Parameter gradients of one grid from the output gradient gy (chain
+    rule through the four convolutions and the ReLUs)."""
+    a0, a1, a2, a3 = acts
+    g3, gw4, gb4 = conv3d_backward(a3, params["w4"], gy[None])
+    g3 = g3 * (a3 > 0)
+    g2, gw3, gb3 = conv3d_backward(a2, params["w3"], g3)
+    g2 = g2 * (a2 > 0)
+    g1, gw2, gb2 = conv3d_backward(a1, params["w2"], g2)
+    g1 = g1 * (a1 > 0)
+    _, gw1, gb1 = conv3d_backward(a0, params["w1"], g1)
+    return {"w1": gw1, "b1": gb1, "w2": gw2, "b2": gb2, "w3": gw3, "b3": gb3, "w4": gw4,
+            "b4": gb4}
+
+
+def residual_loss_and_grads(params, sigma, A, rho_grids, n, k):
+    """Residual-aware loss of the stage (a project reading: the stage should
+    cancel the post-V-cycle residual, not match the error pointwise, since A
+    amplifies the high-frequency part of any error in e): for scaled
+    residual grids rho_p (input), the correction c_p = sigma net(rho_p)
+    mapped to cells and L = sum_p ||rho_p - A c_p||^2 / sum_p ||rho_p||^2
+    (cell vectors), with its exact gradient: dL/dy_p = -2 sigma
+    grid(A r_p) / sum_p ||rho_p||^2, r_p = rho_p - A c_p (A symmetric),
+    propagated through the network as in loss_and_grads."""
+    total = float(sum(np.sum(np.asarray(g) ** 2) for g in rho_grids))
+    loss = 0.0
+    grads = {key: np.zeros_like(v) for key, v in params.items()}
+    for g in rho_grids:
+        y, acts = forward(params, g)
+        r = grid_to_cells(g, n, k) - A @ (sigma * grid_to_cells(y, n, k))
+        loss += float(r @ r) / total
+        gy = (-2.0 * sigma / total) * cells_to_grid(A @ r, n, k)
+        for name, gg in _backprop(params, acts, gy).items():
+            grads[name] += gg
     return loss, grads
 
 

@@ -287,6 +287,68 @@ def kron_apply(u, n, k, penalty_scale=1.0):
     return from_tensor(V, n, k)
 
 
+def patch_1d(n, k, w, penalty_scale=1.0):
+    """Mass and stiffness-plus-face matrices (2N x 2N) of the 1D window w
+    (cells w-1 and w, 1 <= w <= n-1) of a line of n cells, for the patch-wise
+    evaluation of Sec. 2.1 (Fig. patch_int): the window carries the whole
+    face integral of its interior face and, at the ends of the line, of the
+    boundary face of its end cell; each cell integral (mass and stiffness)
+    is shared by the windows that contain the cell (weight 1/2, or 1 for the
+    first and last cell, which lie in one window only).  Summed over all
+    windows they give the global M and L of global_1d."""
+    if not (n >= 2 and 1 <= w <= n - 1):
+        raise ValueError("windows exist for 1 <= w <= n - 1, n >= 2")
+    h = 1.0 / n
+    N = k + 1
+    Mh, Kh = basis1d.mass_stiffness(k)
+    s0, s1, d0, d1 = basis1d.end_vectors(k)
+    g = penalty_hat(k, penalty_scale)
+    o = np.outer
+    a, b = w - 1, w
+    wa = 1.0 if a == 0 else 0.5
+    wb = 1.0 if b == n - 1 else 0.5
+    L = np.zeros((2 * N, 2 * N))
+    L[:N, :N] = wa * Kh + g * o(s1, s1) - 0.5 * (o(s1, d1) + o(d1, s1))
+    L[:N, N:] = -g * o(s1, s0) - 0.5 * o(s1, d0) + 0.5 * o(d1, s0)
+    L[N:, :N] = -g * o(s0, s1) + 0.5 * o(s0, d1) - 0.5 * o(d0, s1)
+    L[N:, N:] = wb * Kh + g * o(s0, s0) + 0.5 * (o(s0, d0) + o(d0, s0))
+    if a == 0:
+        L[:N, :N] += g * o(s0, s0) + (o(s0, d0) + o(d0, s0))
+    if b == n - 1:
+        L[N:, N:] += g * o(s1, s1) - (o(s1, d1) + o(d1, s1))
+    M = np.zeros((2 * N, 2 * N))
+    M[:N, :N] = wa * Mh
+    M[N:, N:] = wb * Mh
+    return h * M, L / h
+
+
+def patchwise_apply(u, n, k, penalty_scale=1.0):
+    """v = A u evaluated patch by patch (Sec. 2.1, Fig. patch_int): for every
+    interior vertex (wx, wy, wz) the 2x2x2-cell patch applies its own
+    Kronecker sum Mz (x) My (x) Lx + Mz (x) Ly (x) Mx + Lz (x) My (x) Mx of
+    the window matrices (patch_1d) to the patch's (2N)^3 coefficients, and
+    the results are summed into v.  Because every window matrix sum gives
+    the global 1D matrices, the sum over patches is A u exactly."""
+    N = k + 1
+    U = to_tensor(u, n, k)
+    V = np.zeros_like(U)
+    mats = [patch_1d(n, k, w, penalty_scale) for w in range(1, n)]
+    for wz in range(1, n):
+        Mz, Lz = mats[wz - 1]
+        for wy in range(1, n):
+            My, Ly = mats[wy - 1]
+            for wx in range(1, n):
+                Mx, Lx = mats[wx - 1]
+                sl = (slice((wz - 1) * N, (wz + 1) * N), slice((wy - 1) * N, (wy + 1) * N),
+                      slice((wx - 1) * N, (wx + 1) * N))
+                P = U[sl]
+                Q = _along(_along(_along(P, Lx, 2), My, 1), Mz, 0)
+                Q += _along(_along(_along(P, Mx, 2), Ly, 1), Mz, 0)
+                Q += _along(_along(_along(P, Mx, 2), My, 1), Lz, 0)
+                V[sl] += Q
+    return from_tensor(V, n, k)
+
+
 def apply_rows(u, n, k, rows):
     """(A u)_r for selected global rows r, from the local quadrature
     matrices: cell block plus the face blocks of the row's cell.  Used to

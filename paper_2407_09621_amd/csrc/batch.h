@@ -47,6 +47,7 @@ struct PatchJob {
   void* x;
   int n;
   double h;
+  const void* b = nullptr;  // set: fused colour step, r = x_in, x = x_out, b = right-hand side
 };
 struct TransferJob {
   const void* in;

@@ -52,6 +52,18 @@ sipg_status smooth(sipg_problem* p, int l, double* x, const double* b, int sweep
     }
     return SIPG_OK;
   }
+  if (p->cfg.smoother == 0) {  // fused colour steps, x and wr[l] in turn (8 per sweep)
+    double* cur = x;
+    double* other = p->wr[l];
+    for (int sw = 0; sw < sweeps; ++sw)
+      for (int colour = 0; colour < 8; ++colour) {
+        PatchJob j{cur, other, p->n[l], level_h(p, l), b};
+        SIPG_HIP(launch_patch_fd_batch(0, p->N, colour, &j, 1, p->tab, s));
+        SIPG_HIP(launch_copy_uncovered(0, p->N, colour, cur, other, p->n[l], s));
+        std::swap(cur, other);
+      }
+    return SIPG_OK;
+  }
   for (int sw = 0; sw < sweeps; ++sw)
     for (int colour = 0; colour < 8; ++colour) {
       SIPG_TRY(residual(p, l, b, x, p->wr[l], s));
@@ -85,6 +97,18 @@ sipg_status patch_lp(sipg_problem* p, int l, int colour, const float* r, float* 
 sipg_status smooth_lp(sipg_problem* p, int l, float* x, const float* b, int sweeps,
                       hipStream_t s) {
   if (p->n[l] < 2) return SIPG_OK;
+  if (p->prec == SIPG_F32 && p->cfg.smoother == 0) {  // fused colour steps (see smooth)
+    float* cur = x;
+    float* other = p->fr[l];
+    for (int sw = 0; sw < sweeps; ++sw)
+      for (int colour = 0; colour < 8; ++colour) {
+        PatchJob j{cur, other, p->n[l], level_h(p, l), b};
+        SIPG_HIP(launch_patch_fd_batch(1, p->N, colour, &j, 1, p->tab, s));
+        SIPG_HIP(launch_copy_uncovered(1, p->N, colour, cur, other, p->n[l], s));
+        std::swap(cur, other);
+      }
+    return SIPG_OK;
+  }
   for (int sw = 0; sw < sweeps; ++sw)
     for (int colour = 0; colour < 8; ++colour) {
       SIPG_TRY(residual_lp(p, l, b, x, p->fr[l], s));
@@ -250,7 +274,7 @@ sipg_status sipg_create(const sipg_config* cfg, hipStream_t stream, sipg_problem
                 "BF16 V-cycle without error correction stalls for k >= 5 (the 1D operator "
                 "rounded to 8 significand bits moves the lowest eigenvalues by many times their "
                 "size); use error_correction 1 or 2");
-  if (cfg->smoother != 0 && cfg->smoother != 1) return fail(SIPG_ERR_ARG, "smoother must be 0 or 1");
+  if (cfg->smoother < 0 || cfg->smoother > 2) return fail(SIPG_ERR_ARG, "smoother must be 0, 1 or 2");
   if (cfg->smoother == 1 && cfg->mg_precision != SIPG_F64)
     return fail(SIPG_ERR_UNSUPPORTED, "the additive smoother runs in FP64 only");
   if (cfg->damping < 0.0 || cfg->damping > 1.0) return fail(SIPG_ERR_ARG, "damping must be in [0, 1]");
@@ -395,6 +419,18 @@ sipg_status sipg_apply_units(sipg_problem* p, int level, const double* u, double
     return fail(SIPG_ERR_UNSUPPORTED, "the FP64 matrix-core apply exists for k = 3 and 7 only");
   ApplyJob j{u, v, nullptr, p->n[level], level_h(p, level), tile_order(p, level)};
   SIPG_HIP(launch_apply_batch(units == SIPG_UNITS_VECTOR ? 2 : 0, p->N, &j, 1, p->tab, s));
+  return SIPG_OK;
+}
+
+sipg_status sipg_apply_patchwise(sipg_problem* p, int level, const double* u, double* v,
+                                 hipStream_t s) {
+  SIPG_TRY(check_level(p, level));
+  if (!u || !v) return fail(SIPG_ERR_ARG, "NULL vector");
+  if (u == v) return fail(SIPG_ERR_ARG, "u and v must not alias");
+  if (p->n[level] < 2) return fail(SIPG_ERR_ARG, "patch-wise evaluation needs n >= 2 cells");
+  SIPG_HIP(launch_fill(v, 0.0, p->ndofs[level], s));
+  for (int colour = 0; colour < 8; ++colour)
+    SIPG_HIP(launch_patch_apply_f64(p->N, colour, u, v, p->tab, p->n[level], level_h(p, level), s));
   return SIPG_OK;
 }
 

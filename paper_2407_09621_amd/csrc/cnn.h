@@ -62,7 +62,15 @@ hipError_t launch_f32_to_f16(const float* a, _Float16* b, int64_t n, hipStream_t
 hipError_t launch_axpy_ratio(const double* num, const double* den, const double* x, double* y,
                              int64_t n, hipStream_t s);
 
+// out = v / scale[0] (0 if scale[0] = 0), scale on the device
+hipError_t launch_div_scale(const double* v, const double* scale, double* out, int64_t n,
+                            hipStream_t s);
+
 // ---- training -----------------------------------------------------------------
+// Residual loss: sums[0] = rr / pp, sums[1] = sigma pp / (2 S) for the output
+// gradient g4 = -grid(A r) / S (device scalars rr = ||r||^2, pp = ||rho||^2)
+hipError_t launch_residual_sums(const double* rr, const double* pp, const double* S, float sigma,
+                                float* sums, hipStream_t s);
 // Loss L = sum m (sigma y - t)^2 / sum m.  g4 = 2 m (y - t / sigma), which is
 // dL/dy times sum(m) / sigma^2 (kept O(1) for the FP16 backward pass);
 // sums[0] = L, sums[1] = sum m (two-pass, partial holds >= 2 * 1024 floats)

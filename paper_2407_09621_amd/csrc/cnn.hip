@@ -318,6 +318,29 @@ __global__ __launch_bounds__(kT) void axpy_ratio_kernel(const double* __restrict
     y[e] = fma(a, x[e], y[e]);
 }
 
+// out = v / scale[0] (0 where scale[0] = 0)
+__global__ __launch_bounds__(kT) void div_scale_kernel(const double* __restrict__ v,
+                                                       const double* __restrict__ scale,
+                                                       double* __restrict__ out, int64_t n) {
+  const double d = scale[0];
+  const double a = d > 0.0 ? 1.0 / d : 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x; e < n; e += (int64_t)gridDim.x * kT)
+    out[e] = a * v[e];
+}
+
+// sums[0] = rr / pp (the relative residual loss), sums[1] = sigma pp / (2 S)
+// (the normalisation that turns the scaled output gradient -grid(A r) / S
+// into dL/dy, see launch_reduce_rows)
+__global__ void residual_sums_kernel(const double* __restrict__ rr, const double* __restrict__ pp,
+                                     const double* __restrict__ S, float sigma,
+                                     float* __restrict__ sums) {
+  if (threadIdx.x == 0) {
+    const double p = pp[0], sc = S[0];
+    sums[0] = p > 0.0 ? (float)(rr[0] / p) : 0.0f;
+    sums[1] = (p > 0.0 && sc > 0.0) ? (float)(sigma * p / (2.0 * sc)) : 1.0f;
+  }
+}
+
 __global__ __launch_bounds__(kT) void f32_to_f16_kernel(const float* __restrict__ a,
                                                         _Float16* __restrict__ b, int64_t n) {
   for (int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x; e < n; e += (int64_t)gridDim.x * kT)
@@ -620,6 +643,20 @@ hipError_t launch_axpy_ratio(const double* num, const double* den, const double*
   int64_t g = (n + kT - 1) / kT;
   hipLaunchKernelGGL(axpy_ratio_kernel, dim3((unsigned)(g < 8192 ? (g < 1 ? 1 : g) : 8192)),
                      dim3(kT), 0, s, num, den, x, y, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_div_scale(const double* v, const double* scale, double* out, int64_t n,
+                            hipStream_t s) {
+  int64_t g = (n + kT - 1) / kT;
+  hipLaunchKernelGGL(div_scale_kernel, dim3((unsigned)(g < 8192 ? (g < 1 ? 1 : g) : 8192)),
+                     dim3(kT), 0, s, v, scale, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_sums(const double* rr, const double* pp, const double* S, float sigma,
+                                float* sums, hipStream_t s) {
+  hipLaunchKernelGGL(residual_sums_kernel, dim3(1), dim3(64), 0, s, rr, pp, S, sigma, sums);
   return hipGetLastError();
 }
 

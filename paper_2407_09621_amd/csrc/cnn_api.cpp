@@ -92,12 +92,10 @@ sipg_status forward(sipg_cnn* c, int G, int ns, float* y, float scale, hipStream
   return SIPG_OK;
 }
 
-// gradient of the masked loss on x16 / tgt / msk into `grad`; loss in c->sums[0]
-sipg_status backward(sipg_cnn* c, int G, int ns, float* grad, hipStream_t s) {
-  const int64_t np = (int64_t)ns * G * G * G;
+// parameter gradient from the output gradient in c->g4 (scaled as
+// launch_loss leaves it, with the matching normalisation in c->sums[1])
+sipg_status backward_from_output(sipg_cnn* c, int G, int ns, float* grad, hipStream_t s) {
   const float sig = c->sigma > 0.0f ? c->sigma : 1.0f;
-  SIPG_TRY(forward(c, G, ns, c->y, 1.0f, s));
-  SIPG_HIP(C::launch_loss(c->y, c->tgt, c->msk, np, sig, c->g4, c->lpart, c->sums, s));
   SIPG_HIP(C::launch_out_bwd(c->g4, c->a3, G, ns, c->prm, c->g3, s));
   SIPG_HIP(C::launch_out_wgrad(c->a3, c->g4, G, ns, c->part, s));
   SIPG_HIP(C::launch_reduce_rows(c->part, C::kSegOut, c->sums, sig, grad + C::kW4, s));
@@ -110,6 +108,46 @@ sipg_status backward(sipg_cnn* c, int G, int ns, float* grad, hipStream_t s) {
   SIPG_HIP(C::launch_in_wgrad(c->x16, c->g1, G, ns, c->part, s));
   SIPG_HIP(C::launch_reduce_rows(c->part, C::kSegIn, c->sums, sig, grad + C::kW1, s));
   return SIPG_OK;
+}
+
+// gradient of the masked loss on x16 / tgt / msk into `grad`; loss in c->sums[0]
+sipg_status backward(sipg_cnn* c, int G, int ns, float* grad, hipStream_t s) {
+  const int64_t np = (int64_t)ns * G * G * G;
+  const float sig = c->sigma > 0.0f ? c->sigma : 1.0f;
+  SIPG_TRY(forward(c, G, ns, c->y, 1.0f, s));
+  SIPG_HIP(C::launch_loss(c->y, c->tgt, c->msk, np, sig, c->g4, c->lpart, c->sums, s));
+  return backward_from_output(c, G, ns, grad, s);
+}
+
+// Residual-aware loss on the problem's finest level for the scaled residual
+// rho_s (FP64 cell vector): c = sigma net(grid(rho_s)), r = rho_s - A c,
+// L = ||r||^2 / ||rho_s||^2 into c->sums[0] and dL/dparameters into grad,
+// through dL/dy = -2 sigma grid(A r) / ||rho_s||^2 (A symmetric).  wc, wq:
+// two cell vectors of workspace; p->d_small[440..444] hold device scalars.
+sipg_status residual_backward(sipg_cnn* c, sipg_problem* p, const double* rho_s, double* wc,
+                              double* wq, float* grad, hipStream_t s) {
+  const int L = p->L - 1;
+  const int n = p->n[L], N = p->N, G = n * N;
+  const int64_t nd = p->ndofs[L];
+  const float sig = c->sigma > 0.0f ? c->sigma : 1.0f;
+  double* one = p->d_small + 440;
+  double* rr = p->d_small + 441;
+  double* pp = p->d_small + 442;
+  double* S = p->d_small + 443;
+  SIPG_HIP(launch_fill(one, 1.0, 1, s));
+  SIPG_HIP(C::launch_gather_f16(rho_s, n, N, one, c->x16, s));
+  SIPG_TRY(forward(c, G, 1, nullptr, 0.0f, s));
+  SIPG_HIP(launch_fill(wc, 0.0, nd, s));
+  SIPG_HIP(C::launch_out_scatter(c->a3, n, N, c->prm, sig, one, wc, s));  // c
+  SIPG_TRY(sipg_apply(p, L, wc, wq, s));                                   // A c
+  SIPG_HIP(launch_axpy(-1.0, rho_s, wq, nd, s));                           // -r
+  SIPG_HIP(launch_mdot(wq, nd, 1, wq, nd, p->d_partial, rr, s));
+  SIPG_HIP(launch_mdot(rho_s, nd, 1, rho_s, nd, p->d_partial, pp, s));
+  SIPG_TRY(sipg_apply(p, L, wq, wc, s));                                   // -A r
+  SIPG_HIP(C::launch_pow2_absmax(wc, nd, p->d_partial, S, s));
+  SIPG_HIP(C::launch_gather_f32(wc, n, N, S, c->g4, s));                  // -grid(A r) / S
+  SIPG_HIP(C::launch_residual_sums(rr, pp, S, sig, c->sums, s));
+  return backward_from_output(c, G, 1, grad, s);
 }
 
 sipg_status adam(sipg_cnn* c, const float* grad, float lr, hipStream_t s) {
@@ -155,13 +193,15 @@ sipg_status make_pair(sipg_problem* p, double* x, PairBufs& w, float* rho_g, flo
   SIPG_HIP(C::launch_gather_f32(w.rho, p->n[L], p->N, w.scale, rho_g, s));
   SIPG_HIP(C::launch_gather_f32(w.e, p->n[L], p->N, w.scale, e_g, s));
   SIPG_HIP(C::launch_pow2_absmax(w.e, n, p->d_partial, w.scale + 1, s));
-  double hs[2];
-  SIPG_HIP(hipMemcpyAsync(hs, w.scale, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-  SIPG_HIP(hipStreamSynchronize(s));
-  if (!(hs[0] > 0.0) || !(hs[1] > 0.0) || !std::isfinite(hs[0]) || !std::isfinite(hs[1]))
-    return fail(SIPG_ERR_NONFINITE, "degenerate training pair (zero or non-finite error)");
-  SIPG_HIP(launch_scale_copy(w.e, 1.0 / hs[1], x, n, s));    // next x of the chain
-  if (s_rho) *s_rho = hs[0];
+  SIPG_HIP(C::launch_div_scale(w.e, w.scale + 1, x, n, s));  // next x of the chain
+  if (s_rho) {  // the scales are checked on the host only when asked for
+    double hs[2];
+    SIPG_HIP(hipMemcpyAsync(hs, w.scale, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    SIPG_HIP(hipStreamSynchronize(s));
+    if (!(hs[0] > 0.0) || !(hs[1] > 0.0) || !std::isfinite(hs[0]) || !std::isfinite(hs[1]))
+      return fail(SIPG_ERR_NONFINITE, "degenerate training pair (zero or non-finite error)");
+    *s_rho = hs[0];
+  }
   return SIPG_OK;
 }
 
@@ -376,6 +416,21 @@ sipg_status sipg_cnn_gradient(sipg_cnn* c, int G, int batch, const float* in,
   return SIPG_OK;
 }
 
+sipg_status sipg_cnn_gradient_residual(sipg_cnn* c, sipg_problem* p, const double* rho,
+                                       float* grad, float* loss, hipStream_t s) {
+  if (!c || !p || !rho || !grad) return fail(SIPG_ERR_ARG, "NULL argument");
+  SIPG_TRY(check_problem_grid(p));
+  const int L = p->L - 1;
+  const int G = p->n[L] * p->N;
+  const int64_t nd = p->ndofs[L];
+  SIPG_TRY(ensure_ws(c, (int64_t)G * G * G, true));
+  if (!p->stage_c) SIPG_TRY(prob_alloc(p, &p->stage_c, nd));
+  if (!p->stage_q) SIPG_TRY(prob_alloc(p, &p->stage_q, nd));
+  SIPG_TRY(residual_backward(c, p, rho, p->stage_c, p->stage_q, grad, s));
+  if (loss) SIPG_HIP(hipMemcpyAsync(loss, c->sums, sizeof(float), hipMemcpyDeviceToDevice, s));
+  return SIPG_OK;
+}
+
 sipg_status sipg_cnn_adam_step(sipg_cnn* c, const float* grad, float lr, hipStream_t s) {
   if (!c || !grad) return fail(SIPG_ERR_ARG, "NULL argument");
   if (!(lr > 0.0f)) return fail(SIPG_ERR_ARG, "lr must be > 0");
@@ -413,9 +468,11 @@ sipg_status sipg_cnn_train(sipg_problem* p, sipg_cnn* c, const sipg_cnn_train_op
   const int G = p->n[L] * p->N;
   const int64_t n = p->ndofs[L];
   if (o->n_chains < 1 || o->chain_length < 1) return fail(SIPG_ERR_ARG, "empty training run");
-  if (o->crops_per_pair < 1 || o->crops_per_pair > 16)
+  if (o->loss != 0 && o->loss != 1) return fail(SIPG_ERR_ARG, "loss must be 0 or 1");
+  const bool resid = o->loss == 1;
+  if (!resid && (o->crops_per_pair < 1 || o->crops_per_pair > 16))
     return fail(SIPG_ERR_ARG, "crops_per_pair must be in 1..16");
-  if (o->crop < C::kTile || o->crop % C::kTile || o->crop > G)
+  if (!resid && (o->crop < C::kTile || o->crop % C::kTile || o->crop > G))
     return fail(SIPG_ERR_ARG, "crop must be a multiple of 16 and <= n (k+1)");
   if (!(o->lr > 0.0f)) return fail(SIPG_ERR_ARG, "lr must be > 0");
   std::memset(info, 0, sizeof(*info));
@@ -431,7 +488,8 @@ sipg_status sipg_cnn_train(sipg_problem* p, sipg_cnn* c, const sipg_cnn_train_op
   if (st == SIPG_OK) st = dev_alloc(&x, n);
   if (st == SIPG_OK) st = dev_alloc(&rho_g, n);
   if (st == SIPG_OK) st = dev_alloc(&e_g, n);
-  if (st == SIPG_OK) st = ensure_ws(c, (int64_t)nc * cr * cr * cr, true);
+  if (st == SIPG_OK)
+    st = ensure_ws(c, resid ? (int64_t)G * G * G : (int64_t)nc * cr * cr * cr, true);
   Rng rng{o->seed};
   double gen = 0.0;
   for (int ch = 0; ch < o->n_chains && st == SIPG_OK; ++ch) {
@@ -452,7 +510,10 @@ sipg_status sipg_cnn_train(sipg_problem* p, sipg_cnn* c, const sipg_cnn_train_op
       if (st != SIPG_OK) break;
       if (!(c->sigma > 0.0f)) {  // output scale from the first pair: mean |e| / mean |rho|
         std::vector<float> hr(n), he(n);
-        if (hipMemcpy(hr.data(), rho_g, sizeof(float) * n, hipMemcpyDeviceToHost) != hipSuccess ||
+        // the pair was made on the non-blocking stream s: finish it before the
+        // (null-stream) copies read the grids
+        if (hipStreamSynchronize(s) != hipSuccess ||
+            hipMemcpy(hr.data(), rho_g, sizeof(float) * n, hipMemcpyDeviceToHost) != hipSuccess ||
             hipMemcpy(he.data(), e_g, sizeof(float) * n, hipMemcpyDeviceToHost) != hipSuccess) {
           st = fail(SIPG_ERR_HIP, "copy failed");
           break;
@@ -464,15 +525,23 @@ sipg_status sipg_cnn_train(sipg_problem* p, sipg_cnn* c, const sipg_cnn_train_op
         }
         c->sigma = (float)std::ldexp(1.0, (int)std::lround(std::log2(se / sr)));
       }
-      C::CropJob job{};
-      job.count = nc;
-      for (int k = 0; k < nc; ++k)
-        for (int a = 0; a < 3; ++a) job.off[k][a] = rng.below(G - cr + 1);
-      if (C::launch_crops(rho_g, e_g, G, cr, job, c->x16, c->tgt, c->msk, s) != hipSuccess) {
-        st = fail(SIPG_ERR_HIP, "crop launch failed");
-        break;
+      if (resid) {  // the whole grid: rho / s into w.e (free after make_pair)
+        if (C::launch_div_scale(w.rho, w.scale, w.e, n, s) != hipSuccess) {
+          st = fail(SIPG_ERR_HIP, "scale launch failed");
+          break;
+        }
+        st = residual_backward(c, p, w.e, w.r, w.z, c->grad, s);
+      } else {
+        C::CropJob job{};
+        job.count = nc;
+        for (int k = 0; k < nc; ++k)
+          for (int a = 0; a < 3; ++a) job.off[k][a] = rng.below(G - cr + 1);
+        if (C::launch_crops(rho_g, e_g, G, cr, job, c->x16, c->tgt, c->msk, s) != hipSuccess) {
+          st = fail(SIPG_ERR_HIP, "crop launch failed");
+          break;
+        }
+        st = backward(c, cr, nc, c->grad, s);
       }
-      st = backward(c, cr, nc, c->grad, s);
       if (st == SIPG_OK) st = adam(c, c->grad, o->lr, s);
       if (st != SIPG_OK) break;
       const bool first = info->steps == 0;

@@ -30,6 +30,18 @@ hipError_t launch_patch_fd_f64(int N, int colour, const double* r, double* x,
 hipError_t launch_patch_fd_f32(int N, int colour, const float* r, float* x, const DevTab& t,
                                int n, double h, hipStream_t s);
 
+// out = in on the cells that no vertex patch of `colour` covers (the layers
+// next to the domain boundary that the colour's vertices leave out); with
+// the fused colour step (PatchJob.b set) this completes the new vector.
+// prec 0 = FP64, 1 = FP32.
+hipError_t launch_copy_uncovered(int prec, int N, int colour, const void* in, void* out, int n,
+                                 hipStream_t s);
+
+// Patch-wise evaluation: v_P += (patch operator) u_P for the vertex patches
+// of `colour` (FP64, vector units); summed over the 8 colours v = A u.
+hipError_t launch_patch_apply_f64(int N, int colour, const double* u, double* v, const DevTab& t,
+                                  int n, double h, hipStream_t s);
+
 // x = A_0^{-1} b on the n0^3-cell coarse level (overwrites x).
 hipError_t launch_coarse_fd_f64(int N, int n0, const double* b, double* x,
                                 const DevTab& t, double h, hipStream_t s);

@@ -364,6 +364,8 @@ __global__ __launch_bounds__(kT) void apply_mfma8_kernel(Batch<double> B,
     mul_swapped<0>(LR, a, w, true);   // (x, z, y)
     mul_swapped<1>(M, w, s, false);   // My -> (y, z, x)
   }
+  zero_if(cy == 0, ym);
+  zero_if(cy == n - 1, yp);
   {  // s2 = Mx Ly~ u, added to s1
     const Op8 Ly = load_op8(tab + lay.lcell + var(cy) * 64, lane);
     permute8(u0, a, s12);             // (x, z, y)
@@ -386,6 +388,233 @@ __global__ __launch_bounds__(kT) void apply_mfma8_kernel(Batch<double> B,
     const double o = h * gather(t3[r], s01);  // (x, y, z)
     if (RES) dst[reg_off8(r)] = bsrc[reg_off8(r)] - o;
     else dst[reg_off8(r)] = o;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Degree 7 with the mirror-pair (even-odd) split.  The GLL nodes are
+// symmetric about the cell centre, so the reversal J of a direction maps the
+// mass matrix and the interior cell block onto themselves and the coupling
+// to the upper neighbour onto the one to the lower neighbour.  The register
+// bit of a direction now selects a mirror half: node idx(h, lo) = h ? 7 - lo
+// : lo (lo in the lane-bit pair), so J is an exchange of the two registers
+// and the split E = v_0 + v_1, O = v_0 - v_1 is two vector additions per
+// register pair.  In the split form a J-symmetric matrix acts on E and O with
+// one 4 x 4 block each (one product per register instead of two); the two
+// face couplings of a direction act through S = v_m + J v_p (its E part) and
+// D = v_m - J v_p (its O part) with two blocks each, for both neighbours at
+// once.  Per cell: 112 products (224 with the plain 8 x 8 blocks), about 140
+// FP64 additions for the splits, the same nine layout changes; boundary
+// cells add the boundary correction in the coupling form.  The chain is the
+// one of apply_mfma8_kernel (layouts in the same order); every term reaches
+// the split form in all three directions once, and three more splits at the
+// end give 8 times the result (scaled by h / 8).
+
+// (v_0, v_1) -> (v_0 + v_1, v_0 - v_1) along direction bit DB; applied to a
+// split pair it gives twice the halves back
+template <int DB>
+__device__ __forceinline__ void split8(double* x) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+    if (!((r >> DB) & 1)) {
+      const int r1 = r | (1 << DB);
+      const double a = x[r], b = x[r1];
+      x[r] = a + b;
+      x[r1] = a - b;
+    }
+}
+
+// y[r] (+)= Q_p x[r] along direction bit DB for x split along DB (p = the
+// register's bit: E block qe, O block qo); normal form or swapped (SW)
+template <int DB, bool SW>
+__device__ __forceinline__ void mul_sym(double qe, double qo, const double* x, double* y,
+                                        bool acc) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const double q = ((r >> DB) & 1) ? qo : qe;
+    const double c = acc ? y[r] : 0.0;
+    y[r] = SW ? mma(x[r], q, c) : mma(q, x[r], c);
+  }
+}
+
+// y[r] += c0 x[r, half 0] + c1 x[r, half 1] along DB for the registers of
+// split part PAR (x in halves along DB)
+template <int DB, bool SW, int PAR>
+__device__ __forceinline__ void mul_cpl(double c0, double c1, const double* x, double* y) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    if (((r >> DB) & 1) != PAR) continue;
+    double c = y[r];
+    c = SW ? mma(x[with_hi(r, DB, 0)], c0, c) : mma(c0, x[with_hi(r, DB, 0)], c);
+    c = SW ? mma(x[with_hi(r, DB, 1)], c1, c) : mma(c1, x[with_hi(r, DB, 1)], c);
+    y[r] = c;
+  }
+}
+
+// m <- m + J p, p <- m - J p along direction bit DB
+template <int DB>
+__device__ __forceinline__ void sum_diff8(double* m, double* p) {
+  double sd[8], df[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    sd[r] = m[r] + p[r ^ (1 << DB)];
+    df[r] = m[r] - p[r ^ (1 << DB)];
+  }
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    m[r] = sd[r];
+    p[r] = df[r];
+  }
+}
+
+// w += the boundary correction along direction bit DB in the coupling form
+// (blocks 8-11 of the even-odd table), from the cell u0 itself (natural
+// along DB, layout (x,y,z)); PERM: bring it to the layout of w first
+template <int DB, bool PERM>
+__device__ __forceinline__ void boundary8(const double* __restrict__ eo, int lane,
+                                          const double* u0, bool lo_end, bool hi_end, int src,
+                                          double* w) {
+  const double Q0 = a_operand(eo + 128, lane), Q1 = a_operand(eo + 144, lane);
+  const double Q2 = a_operand(eo + 160, lane), Q3 = a_operand(eo + 176, lane);
+  double m[8], p[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    m[r] = lo_end ? u0[r] : 0.0;
+    p[r] = hi_end ? u0[r] : 0.0;
+  }
+  sum_diff8<DB>(m, p);
+  if (PERM) {
+    double a[8];
+    permute8(m, a, src);
+    mul_cpl<DB, true, 0>(Q0, Q1, a, w);
+    permute8(p, a, src);
+    mul_cpl<DB, true, 1>(Q2, Q3, a, w);
+  } else {
+    mul_cpl<DB, true, 0>(Q0, Q1, m, w);
+    mul_cpl<DB, true, 1>(Q2, Q3, p, w);
+  }
+}
+
+// Three waves per SIMD: the kernel fits the 168-register budget without
+// spills (left alone the compiler took 176-190 registers, two waves).
+template <bool RES>
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(3, 3)))
+void apply_mfma8eo_kernel(Batch<double> B, const double* __restrict__ tab, TableLayout lay) {
+  const int lane = threadIdx.x & 63;
+  const int gi = __builtin_amdgcn_readfirstlane(blockIdx.x * (kT / 64) + (threadIdx.x >> 6));
+  if (gi >= B.start[B.count]) return;  // wave-uniform; no barriers in this kernel
+  const int pb = batch_find(B, gi);
+  const double* __restrict__ u = B.d[pb].in;
+  double* __restrict__ v = B.d[pb].out;
+  const double* __restrict__ bv = B.d[pb].aux;
+  const double h = B.d[pb].h;
+  const int n = B.d[pb].n, nn = n * n;
+  const int c = cell_of(gi - B.start[pb], n, B.d[pb].a2);
+  const int cx = c % n, cy = (c / n) % n, cz = c / nn;
+
+  // mirror-pair offsets of the layout (x, y, z): register r = (x_h, y_h, z_h)
+  const int p0 = lane & 3, p1 = (lane >> 2) & 3, p2 = lane >> 4;
+  int off[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+    off[r] = ((r & 1) ? 7 - p0 : p0) + 8 * (((r >> 1) & 1) ? 7 - p1 : p1) +
+             64 * ((r >> 2) ? 7 - p2 : p2);
+  const int sToX = p2 | (p0 << 2) | (p1 << 4);  // (x,y,z) -> (y,z,x)
+  const int s12 = p0 | (p2 << 2) | (p1 << 4);   // exchange pairs 1 and 2
+  const int s01 = p1 | (p0 << 2) | (p2 << 4);   // exchange pairs 0 and 1
+  const double* pc = u + (size_t)c * 512;
+  const ptrdiff_t sx = 512, sy = (ptrdiff_t)n * 512, sz = (ptrdiff_t)nn * 512;
+
+  const double* eo = tab + lay.eo;
+  const double Me = a_operand(eo + 0, lane), Mo = a_operand(eo + 16, lane);
+  const double Le = a_operand(eo + 32, lane), Lo = a_operand(eo + 48, lane);
+  const double R0 = a_operand(eo + 64, lane), R1 = a_operand(eo + 80, lane);
+  const double R2 = a_operand(eo + 96, lane), R3 = a_operand(eo + 112, lane);
+
+  // unconditional loads (a missing neighbour reads the cell and is zeroed)
+  double u0[8], zm[8], zp[8], xm[8], xp[8], ym[8], yp[8];
+  auto load = [&](const double* q, double* a) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) a[r] = q[off[r]];
+  };
+  load(pc, u0);
+  load(pc + (cz > 0 ? -sz : 0), zm);
+  load(pc + (cz < n - 1 ? sz : 0), zp);
+  load(pc + (cx > 0 ? -sx : 0), xm);
+  load(pc + (cx < n - 1 ? sx : 0), xp);
+  zero_if(cz == 0, zm);
+  zero_if(cz == n - 1, zp);
+
+  double t3[8], w[8], s[8], a[8], b[8];
+  {  // t3 = My Mx Lz~ u
+#pragma unroll
+    for (int r = 0; r < 8; ++r) b[r] = u0[r];
+    split8<2>(b);
+    mul_sym<2, true>(Le, Lo, b, w, false);  // (x,y,z) -> (z,y,x)
+    sum_diff8<2>(zm, zp);
+    mul_cpl<2, true, 0>(R0, R1, zm, w);
+    mul_cpl<2, true, 1>(R2, R3, zp, w);
+    if (cz == 0 || cz == n - 1) boundary8<2, false>(eo, lane, u0, cz == 0, cz == n - 1, 0, w);
+    split8<0>(w);
+    mul_sym<0, false>(Me, Mo, w, a, false);  // Mx
+    permute8(a, w, s12);                     // (z,x,y)
+    split8<1>(w);
+    mul_sym<1, true>(Me, Mo, w, t3, false);  // My -> (y,x,z)
+  }
+  // the y neighbours are read after the z term: holding them through it
+  // would not fit three waves per SIMD
+  __builtin_amdgcn_sched_barrier(0);
+  load(pc + (cy > 0 ? -sy : 0), ym);
+  load(pc + (cy < n - 1 ? sy : 0), yp);
+  zero_if(cx == 0, xm);
+  zero_if(cx == n - 1, xp);
+  {  // s1 = My Lx~ u
+#pragma unroll
+    for (int r = 0; r < 8; ++r) b[r] = u0[r];
+    split8<0>(b);
+    permute8(b, a, sToX);                   // (y,z,x)
+    mul_sym<0, true>(Le, Lo, a, w, false);  // -> (x,z,y)
+    sum_diff8<0>(xm, xp);
+    permute8(xm, a, sToX);
+    mul_cpl<0, true, 0>(R0, R1, a, w);
+    permute8(xp, a, sToX);
+    mul_cpl<0, true, 1>(R2, R3, a, w);
+    if (cx == 0 || cx == n - 1) boundary8<0, true>(eo, lane, u0, cx == 0, cx == n - 1, sToX, w);
+    split8<1>(w);
+    mul_sym<1, true>(Me, Mo, w, s, false);  // My -> (y,z,x)
+  }
+  zero_if(cy == 0, ym);
+  zero_if(cy == n - 1, yp);
+  {  // s2 = Mx Ly~ u, added to s1
+#pragma unroll
+    for (int r = 0; r < 8; ++r) b[r] = u0[r];
+    split8<1>(b);
+    permute8(b, a, s12);                    // (x,z,y)
+    mul_sym<1, true>(Le, Lo, a, w, false);  // -> (y,z,x)
+    sum_diff8<1>(ym, yp);
+    permute8(ym, a, s12);
+    mul_cpl<1, true, 0>(R0, R1, a, w);
+    permute8(yp, a, s12);
+    mul_cpl<1, true, 1>(R2, R3, a, w);
+    if (cy == 0 || cy == n - 1) boundary8<1, true>(eo, lane, u0, cy == 0, cy == n - 1, s12, w);
+    split8<0>(w);
+    mul_sym<0, false>(Me, Mo, w, s, true);  // Mx, (y,z,x)
+  }
+  permute8(s, w, s12);                      // (y,x,z)
+  split8<2>(w);
+  mul_sym<2, false>(Me, Mo, w, t3, true);   // Mz, (y,x,z), split in all directions
+  split8<0>(t3);
+  split8<1>(t3);
+  split8<2>(t3);                            // 8 x the halves
+  const double hs = 0.125 * h;
+  double* dst = v + (size_t)c * 512;
+  const double* bsrc = RES ? bv + (size_t)c * 512 : nullptr;
+  if (RES) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const double o = hs * gather(t3[r], s01);  // (x, y, z)
+    if (RES) dst[off[r]] = bsrc[off[r]] - o;
+    else dst[off[r]] = o;
   }
 }
 
@@ -551,10 +780,17 @@ hipError_t launch_apply_mfma8_batch(const ApplyJob* jobs, int count, const DevTa
   }
   const int grid = (B.start[count] + kT / 64 - 1) / (kT / 64);
   if (grid == 0) return hipSuccess;
-  if (residual)
+  if (t.lay.eo_ok) {  // the symmetries of the even-odd split hold (always, up to rounding)
+    if (residual)
+      hipLaunchKernelGGL((apply_mfma8eo_kernel<true>), dim3(grid), dim3(kT), 0, s, B, t.tab, t.lay);
+    else
+      hipLaunchKernelGGL((apply_mfma8eo_kernel<false>), dim3(grid), dim3(kT), 0, s, B, t.tab,
+                         t.lay);
+  } else if (residual) {
     hipLaunchKernelGGL((apply_mfma8_kernel<true>), dim3(grid), dim3(kT), 0, s, B, t.tab, t.lay);
-  else
+  } else {
     hipLaunchKernelGGL((apply_mfma8_kernel<false>), dim3(grid), dim3(kT), 0, s, B, t.tab, t.lay);
+  }
   return hipGetLastError();
 }
 

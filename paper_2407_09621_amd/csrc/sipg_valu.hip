@@ -55,6 +55,50 @@ __device__ __forceinline__ void matvec_acc(const T* __restrict__ A, const T (&x)
   }
 }
 
+// Even-odd form of a J-symmetric N x N matrix (Q[N-1-a][N-1-b] = Q[a][b],
+// as the mass matrix and the interior cell block on the symmetric GLL
+// nodes): with e_b = x_b + x_{N-1-b}, o_b = x_b - x_{N-1-b} (b < N/2; for
+// odd N the middle e = 2 x_mid) and the half-blocks QE[a][b] = (Q[a][b] +
+// Q[a][N-1-b]) / 2 (Q[a][mid] / 2 in the middle column) and QO[a][b] =
+// (Q[a][b] - Q[a][N-1-b]) / 2, y_a = (QE e)_a + (QO o)_a and y_{N-1-a} =
+// (QE e)_a - (QO o)_a: 2 (N/2)^2 products instead of N^2.
+template <int N, typename T>
+struct Split {
+  static constexpr int P = N / 2, PE = (N + 1) / 2;
+  T e[PE], o[P > 0 ? P : 1];
+  __device__ __forceinline__ explicit Split(const T (&x)[N]) {
+#pragma unroll
+    for (int b = 0; b < P; ++b) {
+      e[b] = x[b] + x[N - 1 - b];
+      o[b] = x[b] - x[N - 1 - b];
+    }
+    if constexpr (N % 2) e[P] = x[P] + x[P];
+  }
+};
+
+// y (+)= Q x for J-symmetric Q given by its half-blocks QE [PE x PE] and
+// QO [P x P] (row-major), on split input
+template <int N, bool ACC, typename T>
+__device__ __forceinline__ void matvec_sym(const T* __restrict__ QE, const T* __restrict__ QO,
+                                           const Split<N, T>& x, T (&y)[N]) {
+  constexpr int P = N / 2, PE = (N + 1) / 2;
+#pragma unroll
+  for (int a = 0; a < PE; ++a) {
+    T se = 0;
+#pragma unroll
+    for (int b = 0; b < PE; ++b) se = fma(QE[a * PE + b], x.e[b], se);
+    if (a < P) {
+      T so = 0;
+#pragma unroll
+      for (int b = 0; b < P; ++b) so = fma(QO[a * P + b], x.o[b], so);
+      y[a] = ACC ? y[a] + (se + so) : se + so;
+      y[N - 1 - a] = ACC ? y[N - 1 - a] + (se - so) : se - so;
+    } else {
+      y[a] = ACC ? y[a] + se : se;
+    }
+  }
+}
+
 // y = A^T x
 template <int N, typename T>
 __device__ __forceinline__ void matvec_t(const T* __restrict__ A, const T (&x)[N], T (&y)[N]) {
@@ -367,6 +411,12 @@ __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
   // 1D tables are uniform over the workgroup: read through the scalar path
   const T* __restrict__ s_M = tab + lay.mass;
   const T* __restrict__ s_L = tab + lay.lcell;  // interior block (variant 0)
+  // even-odd half-blocks of the mass and the interior block
+  constexpr int PE2 = ((N + 1) / 2) * ((N + 1) / 2);
+  const T* __restrict__ s_ME = tab + lay.sym;
+  const T* __restrict__ s_MO = s_ME + PE2;
+  const T* __restrict__ s_LE = s_MO + (N / 2) * (N / 2);
+  const T* __restrict__ s_LO = s_LE + PE2;
   const T* __restrict__ s_d0 = tab + lay.d0;
   const T* __restrict__ s_d1 = tab + lay.d1;
   const T gam = tab[lay.gam];
@@ -374,9 +424,10 @@ __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
   // ---- x stage in registers, traces of the y/z neighbours to LDS
   if (act) {
     T t1[N], t2[N];
-    matvec<N>(s_L, own, t1);
+    const Split<N, T> so(own);
+    matvec_sym<N, false>(s_LE, s_LO, so, t1);
     add_boundary_correction<N>(t1, own, cx == 0, cx == n - 1, s_d0, s_d1);
-    matvec<N>(s_M, own, t2);
+    matvec_sym<N, false>(s_ME, s_MO, so, t2);
     if (hx0) {
       T g = 0.0;
 #pragma unroll
@@ -426,10 +477,11 @@ __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
       a1[b] = s_t1[ybase + b * N];
       a2[b] = s_t2[ybase + b * N];
     }
-    matvec<N>(s_M, a1, cc);
-    matvec_acc<N>(s_L, a2, cc);
+    const Split<N, T> s1(a1), s2(a2);
+    matvec_sym<N, false>(s_ME, s_MO, s1, cc);
+    matvec_sym<N, true>(s_LE, s_LO, s2, cc);
     add_boundary_correction<N>(cc, a2, cy == 0, cy == n - 1, s_d0, s_d1);
-    matvec<N>(s_M, a2, e);
+    matvec_sym<N, false>(s_ME, s_MO, s2, e);
     const T* ty = s_ty + cl * 4 * N2 + lq * N;
     T f0 = 0.0, q0 = 0.0, f1 = 0.0, q1 = 0.0;
 #pragma unroll
@@ -470,8 +522,9 @@ __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
       a1[b] = s_t1[base + b * N2];
       a2[b] = s_t2[base + b * N2];
     }
-    matvec<N>(s_M, a1, o);
-    matvec_acc<N>(s_L, a2, o);
+    const Split<N, T> s1(a1), s2(a2);
+    matvec_sym<N, false>(s_ME, s_MO, s1, o);
+    matvec_sym<N, true>(s_LE, s_LO, s2, o);
     add_boundary_correction<N>(o, a2, cz == 0, cz == n - 1, s_d0, s_d1);
     // (My Mx trace)(i, j) = sum_j' M[j][j'] (Mx trace)(i, j')
     const T* tzm = s_tzm + cl * 4 * N2 + lp;
@@ -504,8 +557,21 @@ __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
 // with (S, l) the generalized eigenpairs of the 2N x 2N patch matrices
 // (Lh_P S = Mh_P S diag(l), S^T Mh_P S = I).  Patch layout in LDS:
 // i' + G j' + G^2 l' with i' = dx N + i over the two cells of each direction.
+//
+// FUSED: one colour step of the multiplicative smoother without a separate
+// residual.  With r = b - A x, the exact local solve gives
+//   x_P + A_PP^{-1} (b - A x)_P = A_PP^{-1} (b_P - A_{P,ext} x_ext),
+// where A_{P,ext} couples the patch to the cells across its six faces (the
+// principal submatrix A_PP holds everything inside the patch).  So the new
+// patch values are the fast-diagonalization solve of f_P = b_P minus the
+// face couplings of the outside neighbours, which need only their face
+// value and normal derivative (rank 2, as in the operator apply) times the
+// tangential masses.  The new values are written to a second vector (x_in is
+// read across the faces of neighbouring patches of the same colour, which
+// update their own cells in the same launch); cells outside every patch of
+// the colour are copied by launch_copy_uncovered.
 // ---------------------------------------------------------------------------
-template <typename T, int N>
+template <typename T, int N, bool FUSED = false>
 __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
     Batch<T> B, const T* __restrict__ tab, TableLayout lay, int bx, int by, int bz) {
   constexpr int G = 2 * N, G2 = G * G, G3 = G2 * G, N2 = N * N, N3 = N2 * N;
@@ -513,6 +579,10 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
   __shared__ T s_S[4 * G2];
   __shared__ T s_l[4 * G];
   __shared__ T s_X[PPB * G3];
+  // face traces [patch][face 2 d + side][value, derivative][G2] and the
+  // face tables d0, d1, mass
+  __shared__ T s_F[FUSED ? PPB * 12 * G2 : 1];
+  __shared__ T s_fd[FUSED ? 2 * N + N2 : 1];
   const int tid = threadIdx.x;
   const int bi = xcd_remap(blockIdx.x, gridDim.x);
   if (bi >= B.start[B.count]) return;
@@ -526,9 +596,17 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
   if (np <= 0) return;
   for (int i = tid; i < 4 * G2; i += kThreads) s_S[i] = tab[lay.fd_s + i];
   for (int i = tid; i < 4 * G; i += kThreads) s_l[i] = tab[lay.fd_l + i];
+  if constexpr (FUSED) {
+    for (int i = tid; i < N; i += kThreads) {
+      s_fd[i] = tab[lay.d0 + i];
+      s_fd[N + i] = tab[lay.d1 + i];
+    }
+    for (int i = tid; i < N2; i += kThreads) s_fd[2 * N + i] = tab[lay.mass + i];
+  }
   // A patch of G^2 <= 64 lines that divides 64 lives inside one wave: its
-  // waves then synchronise only with themselves after the table load.
-  constexpr bool WL = (G2 <= 64) && (64 % G2 == 0);
+  // waves then synchronise only with themselves after the table load (the
+  // fused form shares work items across the workgroup: barriers).
+  constexpr bool WL = !FUSED && (G2 <= 64) && (64 % G2 == 0);
   const int lane = tid & 63, wv = tid >> 6;
   auto psync = [&]() {
     if constexpr (WL) wave_lds_sync();
@@ -556,16 +634,114 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
     s_cb[q] = (vx - 1) + n * (vy - 1) + nn * (vz - 1);
   }
   __syncthreads();
-  // gather r_P
+  // gather r_P (fused: b_P)
+  const T* __restrict__ src = FUSED ? B.d[pb].aux : r;
   for (int w = w_first; w < w_hi; w += w_step) {
     const int pl = w / G3, rr = w - pl * G3;
     const int cell8 = rr / N3, loc = rr - cell8 * N3;
     const int dx = cell8 & 1, dy = (cell8 >> 1) & 1, dz = cell8 >> 2;
     const int i = loc % N, j = (loc / N) % N, l = loc / N2;
     const int c = s_cb[pl] + dx + n * dy + nn * dz;
-    s_X[pl * G3 + (dx * N + i) + G * (dy * N + j) + G2 * (dz * N + l)] = r[(size_t)c * N3 + loc];
+    s_X[pl * G3 + (dx * N + i) + G * (dy * N + j) + G2 * (dz * N + l)] = src[(size_t)c * N3 + loc];
   }
   psync();
+  if constexpr (FUSED) {
+    // f_P = b_P - h (tangential masses x face coupling) of the outside
+    // neighbours (x_in = r here).  Face f = 2 d + side; its G x G points
+    // (ta, tb) run over the tangential directions in increasing order.
+    const T gam = tab[lay.gam];
+    const T* __restrict__ fd0 = s_fd;
+    const T* __restrict__ fd1 = s_fd + N;
+    const T* __restrict__ fM = s_fd + 2 * N;
+    // cell and node offsets of (d-node a, tangential (ta, tb)) of face d
+    auto face_cell = [&](int d, int cd, int pl, int ta, int tb, int& c, int& loc, int& stride) {
+      int vx, vy, vz;
+      vertex(pl, vx, vy, vz);
+      const int ca = ta / N, ia = ta - ca * N, cb = tb / N, ib = tb - cb * N;
+      int cx, cy, cz, i, j, l;
+      if (d == 0) { cx = cd; cy = vy - 1 + ca; cz = vz - 1 + cb; i = 0; j = ia; l = ib; stride = 1; }
+      else if (d == 1) { cx = vx - 1 + ca; cy = cd; cz = vz - 1 + cb; i = ia; j = 0; l = ib; stride = N; }
+      else { cx = vx - 1 + ca; cy = vy - 1 + cb; cz = cd; i = ia; j = ib; l = 0; stride = N2; }
+      c = (cz * n + cy) * n + cx;
+      loc = i + N * j + N2 * l;
+    };
+    // traces of the outside neighbour lines
+    for (int w = tid; w < np * 6 * G2; w += kThreads) {
+      const int pl = w / (6 * G2), rem = w - pl * 6 * G2, f = rem / G2, pt = rem - f * G2;
+      const int d = f >> 1, side = f & 1;
+      int vx, vy, vz;
+      vertex(pl, vx, vy, vz);
+      const int vd = d == 0 ? vx : (d == 1 ? vy : vz);
+      const int cd = side ? vd + 1 : vd - 2;
+      T t1 = 0, t2 = 0;
+      if (cd >= 0 && cd < n) {
+        int c, loc, st;
+        face_cell(d, cd, pl, pt % G, pt / G, c, loc, st);
+        const T* line = r + (size_t)c * N3 + loc;
+        T a[N];
+#pragma unroll
+        for (int q = 0; q < N; ++q) a[q] = line[q * st];
+        t1 = side ? a[0] : a[N - 1];
+#pragma unroll
+        for (int q = 0; q < N; ++q) t2 = fma(side ? fd0[q] : fd1[q], a[q], t2);
+      }
+      T* F = s_F + (pl * 6 + f) * 2 * G2;
+      F[pt] = t1;
+      F[G2 + pt] = t2;
+    }
+    __syncthreads();
+    // tangential masses (each within its cell of the face), through registers
+    constexpr int NI = (PPB * 12 * G2 + kThreads - 1) / kThreads;
+    T tm[NI];
+#pragma unroll
+    for (int q = 0; q < NI; ++q) {
+      const int w = tid + q * kThreads;
+      tm[q] = 0;
+      if (w < np * 12 * G2) {
+        const int pt = w % G2, blk = w / G2;
+        const int ta = pt % G, tb = pt / G;
+        const int ca = ta / N, ia = ta - ca * N, cb = tb / N, ib = tb - cb * N;
+        const T* F = s_F + blk * G2 + ca * N + G * (cb * N);
+        T acc = 0;
+        for (int b2 = 0; b2 < N; ++b2) {
+          T row = 0;
+#pragma unroll
+          for (int a2 = 0; a2 < N; ++a2) row = fma(fM[ia * N + a2], F[a2 + G * b2], row);
+          acc = fma(fM[ib * N + b2], row, acc);
+        }
+        tm[q] = acc;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NI; ++q) {
+      const int w = tid + q * kThreads;
+      if (w < np * 12 * G2) s_F[w] = tm[q];
+    }
+    __syncthreads();
+    // subtract h times the couplings from f, one direction at a time (the
+    // two faces of a direction touch different nodes)
+    for (int d = 0; d < 3; ++d) {
+      for (int w = tid; w < np * 2 * G2 * N; w += kThreads) {
+        const int pl = w / (2 * G2 * N), rem = w - pl * 2 * G2 * N;
+        const int side = rem / (G2 * N), rr = rem - side * G2 * N;
+        const int pt = rr / N, a = rr - pt * N;
+        const int ta = pt % G, tb = pt / G;
+        const T* F = s_F + (pl * 6 + 2 * d + side) * 2 * G2;
+        const T f1 = F[pt], f2 = F[G2 + pt];
+        T val;
+        if (side == 0)  // the lower neighbour's coupling into node a of the low cell
+          val = (a == 0 ? -gam * f1 + T(0.5) * f2 : T(0)) - T(0.5) * fd0[a] * f1;
+        else            // the upper neighbour's coupling into node a of the high cell
+          val = (a == N - 1 ? -gam * f1 - T(0.5) * f2 : T(0)) + T(0.5) * fd1[a] * f1;
+        const int pos = side ? N + a : a;
+        const int idx = d == 0 ? pos + G * ta + G2 * tb
+                               : (d == 1 ? ta + G * pos + G2 * tb : ta + G * tb + G2 * pos);
+        s_X[pl * G3 + idx] -= h * val;
+      }
+      __syncthreads();
+    }
+  }
 
   const bool act = tid < np * G2;
   const int pl = act ? tid / G2 : 0, ln = tid - pl * G2;
@@ -625,14 +801,157 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
     for (int a = 0; a < G; ++a) X[o0 + a] = out[a];
   }
   psync();
-  // scatter-add into x
+  // scatter-add into x (fused: the new values, stored)
   for (int w = w_first; w < w_hi; w += w_step) {
     const int q = w / G3, rr = w - q * G3;
     const int cell8 = rr / N3, loc = rr - cell8 * N3;
     const int dx = cell8 & 1, dy = (cell8 >> 1) & 1, dz = cell8 >> 2;
     const int i = loc % N, j = (loc / N) % N, l = loc / N2;
     const int c = s_cb[q] + dx + n * dy + nn * dz;
-    x[(size_t)c * N3 + loc] += s_X[q * G3 + (dx * N + i) + G * (dy * N + j) + G2 * (dz * N + l)];
+    const T val = s_X[q * G3 + (dx * N + i) + G * (dy * N + j) + G2 * (dz * N + l)];
+    if constexpr (FUSED) x[(size_t)c * N3 + loc] = val;
+    else x[(size_t)c * N3 + loc] += val;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Patch-wise operator evaluation (Sec. 2.1, Fig. patch_int): the vertex
+// patches of one colour each add
+//   v_P += h (Mz (x) My (x) Lx + Mz (x) Ly (x) Mx + Lz (x) My (x) Mx) u_P
+// with the 2N x 2N window matrices of the patch's type per direction: every
+// window carries the whole integral of its interior face (and of a boundary
+// face of its end cell), the mass and stiffness of a cell are shared by the
+// windows that contain it (weight 1/2, or 1 for the first and last cell of
+// a line).  Summed over all (n-1)^3 patches this is A u; each DoF lies in up
+// to 8 patches, so the work per DoF is about 8 times the cell-wise one (the
+// paper's trade of redundant products for tensor-core-sized matrices).
+// Patch layout in LDS as in the patch solve: i' + G j' + G^2 l'.
+// ---------------------------------------------------------------------------
+template <typename T, int N>
+__global__ __launch_bounds__(kThreads) void patch_apply_kernel(
+    Batch<T> B, const T* __restrict__ tab, TableLayout lay, int bx, int by, int bz) {
+  constexpr int G = 2 * N, G2 = G * G, G3 = G2 * G, N2 = N * N, N3 = N2 * N;
+  constexpr int PPB = (kThreads / G2) > 0 ? kThreads / G2 : 1;
+  __shared__ T s_L[4 * G2];
+  __shared__ T s_M[N2];
+  __shared__ T s_X[PPB * G3];
+  __shared__ T s_Y[PPB * G3];
+  const int tid = threadIdx.x;
+  const int bi = xcd_remap(blockIdx.x, gridDim.x);
+  if (bi >= B.start[B.count]) return;
+  const int pb = batch_find(B, bi);
+  const T* __restrict__ u = B.d[pb].in;
+  T* __restrict__ v = B.d[pb].out;
+  const int n = B.d[pb].n, npx = B.d[pb].a0, npy = B.d[pb].a1, npatch = B.d[pb].a2;
+  const T h = B.d[pb].h;
+  const int p0 = (bi - B.start[pb]) * PPB;
+  const int np = min(PPB, npatch - p0);
+  if (np <= 0) return;
+  for (int i = tid; i < 4 * G2; i += kThreads) s_L[i] = tab[lay.pw_l + i];
+  for (int i = tid; i < N2; i += kThreads) s_M[i] = tab[lay.mass + i];
+  auto vertex = [&](int pl, int& vx, int& vy, int& vz) {
+    const int p = p0 + pl;
+    const int px = p % npx, py = (p / npx) % npy, pz = p / (npx * npy);
+    vx = 2 * px + (bx ? 1 : 2);
+    vy = 2 * py + (by ? 1 : 2);
+    vz = 2 * pz + (bz ? 1 : 2);
+  };
+  const int nn = n * n;
+  __shared__ int s_cb[PPB];
+  for (int q = tid; q < np; q += kThreads) {
+    int vx, vy, vz;
+    vertex(q, vx, vy, vz);
+    s_cb[q] = (vx - 1) + n * (vy - 1) + nn * (vz - 1);
+  }
+  __syncthreads();
+  for (int w = tid; w < np * G3; w += kThreads) {  // gather u_P
+    const int pl = w / G3, rr = w - pl * G3;
+    const int cell8 = rr / N3, loc = rr - cell8 * N3;
+    const int dx = cell8 & 1, dy = (cell8 >> 1) & 1, dz = cell8 >> 2;
+    const int i = loc % N, j = (loc / N) % N, l = loc / N2;
+    const int c = s_cb[pl] + dx + n * dy + nn * dz;
+    s_X[pl * G3 + (dx * N + i) + G * (dy * N + j) + G2 * (dz * N + l)] = u[(size_t)c * N3 + loc];
+  }
+  __syncthreads();
+
+  const bool act = tid < np * G2;
+  const int pl = act ? tid / G2 : 0, ln = tid - pl * G2;
+  int vx = 1, vy = 1, vz = 1;
+  if (act) vertex(pl, vx, vy, vz);
+  const int tx = (vx == 1 ? 1 : 0) | (vx == n - 1 ? 2 : 0);
+  const int ty = (vy == 1 ? 1 : 0) | (vy == n - 1 ? 2 : 0);
+  const int tz = (vz == 1 ? 1 : 0) | (vz == n - 1 ? 2 : 0);
+  T* X = s_X + pl * G3;
+  T* Y = s_Y + pl * G3;
+  const int la = ln % G, lb = ln / G;
+  const int o0 = la * G + lb * G2, o1 = la + lb * G2, o2 = la + lb * G;
+  // the window mass is block-diagonal: the shared cell mass times the
+  // weight of each half (1 for an end cell of the line, else 1/2)
+  auto mass = [&](int type, const T (&x)[G], T (&y)[G]) {
+    const T w0 = (type & 1) ? T(1) : T(0.5), w1 = (type & 2) ? T(1) : T(0.5);
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      T s0 = 0, s1 = 0;
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        s0 = fma(s_M[a * N + b], x[b], s0);
+        s1 = fma(s_M[a * N + b], x[N + b], s1);
+      }
+      y[a] = w0 * s0;
+      y[N + a] = w1 * s1;
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+  T in1[G], in2[G], out1[G], out2[G];
+  if (act) {  // x: t1 = Lx u, t2 = Mx u
+#pragma unroll
+    for (int a = 0; a < G; ++a) in1[a] = X[o0 + a];
+    matvec_rows<G>(s_L + tx * G2, in1, out1);
+    mass(tx, in1, out2);
+#pragma unroll
+    for (int a = 0; a < G; ++a) {
+      X[o0 + a] = out1[a];
+      Y[o0 + a] = out2[a];
+    }
+  }
+  __syncthreads();
+  if (act) {  // y: c = My t1 + Ly t2, e = My t2
+#pragma unroll
+    for (int a = 0; a < G; ++a) {
+      in1[a] = X[o1 + a * G];
+      in2[a] = Y[o1 + a * G];
+    }
+    mass(ty, in1, out1);
+    matvec_rows<G>(s_L + ty * G2, in2, out2);
+#pragma unroll
+    for (int a = 0; a < G; ++a) out1[a] += out2[a];
+    mass(ty, in2, out2);
+#pragma unroll
+    for (int a = 0; a < G; ++a) {
+      X[o1 + a * G] = out1[a];
+      Y[o1 + a * G] = out2[a];
+    }
+  }
+  __syncthreads();
+  if (act) {  // z: v = h (Mz c + Lz e)
+#pragma unroll
+    for (int a = 0; a < G; ++a) {
+      in1[a] = X[o2 + a * G2];
+      in2[a] = Y[o2 + a * G2];
+    }
+    mass(tz, in1, out1);
+    matvec_rows<G>(s_L + tz * G2, in2, out2);
+#pragma unroll
+    for (int a = 0; a < G; ++a) X[o2 + a * G2] = h * (out1[a] + out2[a]);
+  }
+  __syncthreads();
+  for (int w = tid; w < np * G3; w += kThreads) {  // scatter-add into v
+    const int q = w / G3, rr = w - q * G3;
+    const int cell8 = rr / N3, loc = rr - cell8 * N3;
+    const int dx = cell8 & 1, dy = (cell8 >> 1) & 1, dz = cell8 >> 2;
+    const int i = loc % N, j = (loc / N) % N, l = loc / N2;
+    const int c = s_cb[q] + dx + n * dy + nn * dz;
+    v[(size_t)c * N3 + loc] += s_X[q * G3 + (dx * N + i) + G * (dy * N + j) + G2 * (dz * N + l)];
   }
 }
 
@@ -944,7 +1263,8 @@ hipError_t apply_impl(const ApplyJob* jobs, int count, const DevTab& t, hipStrea
 
 template <typename T, int N>
 hipError_t patch_impl(int colour, const PatchJob* jobs, int count, const DevTab& t,
-                      hipStream_t s) {
+                      hipStream_t s, bool apply = false) {
+  const bool fused = count > 0 && jobs[0].b != nullptr;
   constexpr int G2 = 4 * N * N;
   constexpr int PPB = (kThreads / G2) > 0 ? kThreads / G2 : 1;
   const int bx = colour & 1, by = (colour >> 1) & 1, bz = (colour >> 2) & 1;
@@ -952,11 +1272,13 @@ hipError_t patch_impl(int colour, const PatchJob* jobs, int count, const DevTab&
   hipError_t e = make_batch(B, count, [&](int i, Desc<T>& d, int64_t& items) {
     const PatchJob& j = jobs[i];
     if (j.n < 2 || j.n > 1024 || !j.r || !j.x) return hipErrorInvalidValue;
+    if ((j.b != nullptr) != fused || (fused && (j.b == j.x || j.r == j.x)))
+      return hipErrorInvalidValue;
     // vertices v in [1, n-1]: odd ones 1,3,..; even ones 2,4,..
     auto cnt = [&](int bit) { return bit ? j.n / 2 : (j.n - 1) / 2; };
     d.in = (const T*)j.r;
     d.out = (T*)j.x;
-    d.aux = nullptr;
+    d.aux = (const T*)j.b;
     d.h = (T)j.h;
     d.n = j.n;
     d.a0 = cnt(bx);
@@ -967,8 +1289,72 @@ hipError_t patch_impl(int colour, const PatchJob* jobs, int count, const DevTab&
   });
   if (e != hipSuccess) return e;
   if (B.start[count] == 0) return hipSuccess;
-  hipLaunchKernelGGL((patch_fd_kernel<T, N>), dim3(B.start[count]), dim3(kThreads), 0, s, B,
-                     tab_of<T>(t), t.lay, bx, by, bz);
+  if (apply)
+    hipLaunchKernelGGL((patch_apply_kernel<T, N>), dim3(B.start[count]), dim3(kThreads), 0, s, B,
+                       tab_of<T>(t), t.lay, bx, by, bz);
+  else if (fused)
+    hipLaunchKernelGGL((patch_fd_kernel<T, N, true>), dim3(B.start[count]), dim3(kThreads), 0, s,
+                       B, tab_of<T>(t), t.lay, bx, by, bz);
+  else
+    hipLaunchKernelGGL((patch_fd_kernel<T, N>), dim3(B.start[count]), dim3(kThreads), 0, s, B,
+                       tab_of<T>(t), t.lay, bx, by, bz);
+  return hipGetLastError();
+}
+
+// out = in on the cells of the given layers: slab q is the layer
+// c_dir[q] = lay[q] (all n^2 cells of it), N^3 values per cell
+template <typename T>
+__global__ __launch_bounds__(kThreads) void copy_layers_kernel(const T* __restrict__ in,
+                                                               T* __restrict__ out, int n, int N3,
+                                                               int nslab, int4 dirs, int4 lays,
+                                                               int2 dirs2, int2 lays2) {
+  const int64_t per = (int64_t)n * n * N3;
+  const int64_t total = per * nslab;
+  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * kThreads) {
+    const int q = (int)(e / per);
+    const int64_t rem = e - q * per;
+    const int64_t cl = rem / N3;
+    const int loc = (int)(rem - cl * N3);
+    const int a = (int)(cl % n), b = (int)(cl / n);
+    const int dir = q < 4 ? (&dirs.x)[q] : (&dirs2.x)[q - 4];
+    const int layer = q < 4 ? (&lays.x)[q] : (&lays2.x)[q - 4];
+    int cx, cy, cz;
+    if (dir == 0) { cx = layer; cy = a; cz = b; }
+    else if (dir == 1) { cx = a; cy = layer; cz = b; }
+    else { cx = a; cy = b; cz = layer; }
+    const int64_t idx = (((int64_t)cz * n + cy) * n + cx) * N3 + loc;
+    out[idx] = in[idx];
+  }
+}
+
+template <typename T>
+hipError_t copy_uncovered_impl(int N, int colour, const T* in, T* out, int n, hipStream_t s) {
+  if (n < 1 || !in || !out || in == out) return hipErrorInvalidValue;
+  const int N3 = N * N * N;
+  int dirs[6], lays[6], ns = 0;
+  for (int d = 0; d < 3; ++d) {
+    const int bit = (colour >> d) & 1;
+    // vertices 1 <= v <= n - 1 of parity `bit`; a patch covers cells v - 1, v
+    const int vmin = bit ? 1 : 2;
+    const int vmax = ((n - 1) % 2 == bit) ? n - 1 : n - 2;
+    if (vmax < vmin) {  // no patch of this colour: every cell is outside
+      const int64_t total = (int64_t)n * n * n * N3;
+      return hipMemcpyAsync(out, in, total * sizeof(T), hipMemcpyDeviceToDevice, s);
+    }
+    for (int c = 0; c < vmin - 1; ++c) { dirs[ns] = d; lays[ns++] = c; }
+    for (int c = vmax + 1; c < n; ++c) { dirs[ns] = d; lays[ns++] = c; }
+  }
+  if (ns == 0) return hipSuccess;
+  const int64_t total = (int64_t)ns * n * n * N3;
+  int64_t g = (total + kThreads - 1) / kThreads;
+  if (g > 16384) g = 16384;
+  int4 d4 = {dirs[0], ns > 1 ? dirs[1] : 0, ns > 2 ? dirs[2] : 0, ns > 3 ? dirs[3] : 0};
+  int4 l4 = {lays[0], ns > 1 ? lays[1] : 0, ns > 2 ? lays[2] : 0, ns > 3 ? lays[3] : 0};
+  int2 d2 = {ns > 4 ? dirs[4] : 0, ns > 5 ? dirs[5] : 0};
+  int2 l2 = {ns > 4 ? lays[4] : 0, ns > 5 ? lays[5] : 0};
+  hipLaunchKernelGGL(copy_layers_kernel<T>, dim3((unsigned)g), dim3(kThreads), 0, s, in, out, n,
+                     N3, ns, d4, l4, d2, l2);
   return hipGetLastError();
 }
 
@@ -1062,13 +1448,30 @@ hipError_t launch_apply_batch(int prec, int N, const ApplyJob* jobs, int count, 
 hipError_t launch_patch_fd_batch(int prec, int N, int colour, const PatchJob* jobs, int count,
                                  const DevTab& t, hipStream_t s) {
   if (t.lay.N != N || colour < 0 || colour > 7) return hipErrorInvalidValue;
-  if (N == 4) return launch_patch_mfma4_batch(prec, colour, jobs, count, t, s);
+  const bool fused = count > 0 && jobs[0].b != nullptr;
+  if (N == 4 && !fused) return launch_patch_mfma4_batch(prec, colour, jobs, count, t, s);
   if (prec == 0) {
 #define CALL(NN) patch_impl<double, NN>(colour, jobs, count, t, s)
     SIPG_DISPATCH_N(N, CALL)
 #undef CALL
   }
 #define CALL(NN) patch_impl<float, NN>(colour, jobs, count, t, s)
+  SIPG_DISPATCH_N(N, CALL)
+#undef CALL
+}
+
+hipError_t launch_copy_uncovered(int prec, int N, int colour, const void* in, void* out, int n,
+                                 hipStream_t s) {
+  if (N < 2 || N > 8 || colour < 0 || colour > 7) return hipErrorInvalidValue;
+  return prec == 0 ? copy_uncovered_impl<double>(N, colour, (const double*)in, (double*)out, n, s)
+                   : copy_uncovered_impl<float>(N, colour, (const float*)in, (float*)out, n, s);
+}
+
+hipError_t launch_patch_apply_f64(int N, int colour, const double* u, double* v, const DevTab& t,
+                                  int n, double h, hipStream_t s) {
+  if (t.lay.N != N || colour < 0 || colour > 7) return hipErrorInvalidValue;
+  PatchJob j{u, v, n, h};
+#define CALL(NN) patch_impl<double, NN>(colour, &j, 1, t, s, true)
   SIPG_DISPATCH_N(N, CALL)
 #undef CALL
 }

@@ -4,6 +4,7 @@
 // 1D matrices.
 #include "tables.h"
 
+#include <algorithm>
 #include <cmath>
 #include <stdexcept>
 
@@ -307,6 +308,131 @@ void line_matrices(const Tables1D& t, int cells, bool low_bdry, bool high_bdry,
 
 }  // namespace
 
+// Even-odd (mirror-pair) blocks of the degree-7 1D operators.  The GLL
+// nodes are symmetric about the cell centre, so the reversal J (node a ->
+// N-1-a) maps the mass matrix and the interior cell block of Lh onto
+// themselves, the coupling to the upper neighbour onto the coupling to the
+// lower one (L_{c,c+1} = J L_{c+1,c} J), and the boundary correction at x = 1
+// onto the one at x = 0.  With node index idx(h, a) = h ? N-1-a : a
+// (a = 0..3) a vector splits into halves v_0, v_1 (h = 0, 1) and into
+// E = v_0 + v_1, O = v_0 - v_1.  A J-symmetric Q maps E to (Q00 + Q01) E and
+// O to (Q00 - Q01) O (blocks Qhh'[a][c] = Q[idx(h,a)][idx(h',c)]): one 4 x 4
+// block per half instead of two.  For a coupling B and its mirror J B J
+// acting on neighbours m and p, with S = v_m + J v_p and D = v_m - J v_p:
+// E(B v_m + J B J v_p) = (B00 + B10) S_0 + (B01 + B11) S_1 and
+// O(...) = (B00 - B10) D_0 + (B01 - B11) D_1.
+// Blocks (row-major 4 x 4): 0-1 mass even/odd, 2-3 interior cell block
+// even/odd, 4-7 lower coupling L_{c+1,c} as (e0, e1, o0, o1), 8-11 the
+// boundary correction at x = 0, Lcell[1] - Lcell[0], in the same form.
+// Returns false (blocks unusable) if a symmetry fails beyond rounding.
+bool even_odd_blocks(const Tables1D& t, double* out) {
+  const int N = t.N;
+  if (N != 8) return false;
+  auto at = [&](const std::vector<double>& q, int i, int j) { return q[i * N + j]; };
+  std::vector<double> dlt(N * N), dhi(N * N), dboth(N * N);
+  for (int i = 0; i < N * N; ++i) {
+    dlt[i] = t.lcell[1][i] - t.lcell[0][i];
+    dhi[i] = t.lcell[2][i] - t.lcell[0][i];
+    dboth[i] = t.lcell[3][i] - t.lcell[0][i];
+  }
+  double scale = 0.0, dev = 0.0;
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      const int mi = N - 1 - i, mj = N - 1 - j;
+      scale = std::max(scale, std::fabs(at(t.lcell[0], i, j)) + std::fabs(at(t.rl, i, j)));
+      dev = std::max(dev, std::fabs(at(t.mass, i, j) - at(t.mass, mi, mj)));
+      dev = std::max(dev, std::fabs(at(t.lcell[0], i, j) - at(t.lcell[0], mi, mj)));
+      dev = std::max(dev, std::fabs(at(t.lr, i, j) - at(t.rl, mi, mj)));
+      dev = std::max(dev, std::fabs(at(dhi, i, j) - at(dlt, mi, mj)));
+      dev = std::max(dev, std::fabs(at(dboth, i, j) - at(dlt, i, j) - at(dlt, mi, mj)));
+    }
+  if (!(dev <= 1e-12 * scale)) return false;
+  auto idx = [&](int h, int a) { return h ? N - 1 - a : a; };
+  auto sym = [&](const std::vector<double>& q, double* e, double* o) {
+    for (int a = 0; a < 4; ++a)
+      for (int c = 0; c < 4; ++c) {
+        e[a * 4 + c] = at(q, idx(0, a), idx(0, c)) + at(q, idx(0, a), idx(1, c));
+        o[a * 4 + c] = at(q, idx(0, a), idx(0, c)) - at(q, idx(0, a), idx(1, c));
+      }
+  };
+  auto cpl = [&](const std::vector<double>& q, double* b) {
+    for (int a = 0; a < 4; ++a)
+      for (int c = 0; c < 4; ++c) {
+        const double b00 = at(q, idx(0, a), idx(0, c)), b01 = at(q, idx(0, a), idx(1, c));
+        const double b10 = at(q, idx(1, a), idx(0, c)), b11 = at(q, idx(1, a), idx(1, c));
+        b[0 * 16 + a * 4 + c] = b00 + b10;
+        b[1 * 16 + a * 4 + c] = b01 + b11;
+        b[2 * 16 + a * 4 + c] = b00 - b10;
+        b[3 * 16 + a * 4 + c] = b01 - b11;
+      }
+  };
+  sym(t.mass, out + 0 * 16, out + 1 * 16);
+  sym(t.lcell[0], out + 2 * 16, out + 3 * 16);
+  cpl(t.rl, out + 4 * 16);
+  cpl(dlt, out + 8 * 16);
+  return true;
+}
+
+// Even-odd half-blocks of an N x N matrix Q with Q[N-1-a][N-1-b] = Q[a][b]
+// (true of the mass matrix and the interior cell block: the GLL nodes are
+// symmetric about the cell centre and the two faces of an interior cell
+// enter alike): QE[a][b] = (Q[a][b] + Q[a][N-1-b]) / 2 for b < N/2 and
+// Q[a][mid] / 2 in the middle column of odd N, QO[a][b] = (Q[a][b] -
+// Q[a][N-1-b]) / 2, rows a < (N+1)/2 and a < N/2.  Written to out as QE then
+// QO.  Returns false if the symmetry fails beyond rounding.
+bool half_blocks(const std::vector<double>& Q, int N, double* out) {
+  const int P = N / 2, PE = (N + 1) / 2;
+  double scale = 0.0, dev = 0.0;
+  for (int a = 0; a < N; ++a)
+    for (int b = 0; b < N; ++b) {
+      scale = std::max(scale, std::fabs(Q[a * N + b]));
+      dev = std::max(dev, std::fabs(Q[a * N + b] - Q[(N - 1 - a) * N + N - 1 - b]));
+    }
+  if (!(dev <= 1e-12 * scale)) return false;
+  double* QE = out;
+  double* QO = out + PE * PE;
+  for (int a = 0; a < PE; ++a)
+    for (int b = 0; b < PE; ++b)
+      QE[a * PE + b] = (b == N - 1 - b) ? 0.5 * Q[a * N + b] : 0.5 * (Q[a * N + b] + Q[a * N + N - 1 - b]);
+  for (int a = 0; a < P; ++a)
+    for (int b = 0; b < P; ++b) QO[a * P + b] = 0.5 * (Q[a * N + b] - Q[a * N + N - 1 - b]);
+  return true;
+}
+
+// Window matrices of the patch-wise evaluation (Sec. 2.1, Fig. patch_int):
+// the 2N x 2N stiffness-plus-face matrix of a window of two cells a, b
+// (h-free) holds the whole interior face between them, the boundary face of
+// a cell that ends the line, and the cell stiffness times the cell's share
+// (1 for the first and last cell of the line, which lie in one window, 1/2
+// otherwise):
+//   [[w_a K + F_aa (+ B_0), F_ab], [F_ba, w_b K + F_bb (+ B_1)]]
+// with the face blocks of the interior face (as in the global 1D matrix).
+// Summed over the windows of a line this is the global 1D matrix.
+void window_matrices(const Tables1D& t, double* out) {
+  const int N = t.N, G = 2 * N;
+  const double g = t.gamma_hat;
+  auto e0 = [&](int i) { return i == 0 ? 1.0 : 0.0; };
+  auto e1 = [&](int i) { return i == N - 1 ? 1.0 : 0.0; };
+  for (int type = 0; type < 4; ++type) {
+    const bool lo = type & 1, hi = type & 2;
+    const double wa = lo ? 1.0 : 0.5, wb = hi ? 1.0 : 0.5;
+    double* W = out + type * G * G;
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j) {
+        const double K = t.stiff[i * N + j];
+        // right face of the lower cell a, left face of the upper cell b
+        const double faa = g * e1(i) * e1(j) - 0.5 * (e1(i) * t.d1[j] + t.d1[i] * e1(j));
+        const double fbb = g * e0(i) * e0(j) + 0.5 * (e0(i) * t.d0[j] + t.d0[i] * e0(j));
+        const double b0 = g * e0(i) * e0(j) + (e0(i) * t.d0[j] + t.d0[i] * e0(j));
+        const double b1 = g * e1(i) * e1(j) - (e1(i) * t.d1[j] + t.d1[i] * e1(j));
+        W[i * G + j] = wa * K + faa + (lo ? b0 : 0.0);
+        W[(N + i) * G + N + j] = wb * K + fbb + (hi ? b1 : 0.0);
+        W[i * G + N + j] = t.lr[i * N + j];
+        W[(N + i) * G + j] = t.rl[i * N + j];
+      }
+  }
+}
+
 std::vector<double> build_device_table(int k, int n0, TableLayout& lay, double penalty_scale) {
   Tables1D t = make_tables_1d(k, penalty_scale);
   const int N = t.N, G = 2 * N, Gc = (n0 >= 1 && n0 <= 3) ? n0 * N : 0;
@@ -328,6 +454,9 @@ std::vector<double> build_device_table(int k, int n0, TableLayout& lay, double p
   lay.p1 = take(2 * N * N);
   lay.lr = take(N * N);
   lay.rl = take(N * N);
+  lay.eo = take(N == 8 ? 12 * 16 : 0);
+  lay.pw_l = take(4 * G * G);
+  lay.sym = take(2 * (((N + 1) / 2) * ((N + 1) / 2) + (N / 2) * (N / 2)));
   lay.total = off;
   std::vector<double> tab(off, 0.0);
   for (int i = 0; i < N * N; ++i) tab[lay.mass + i] = t.mass[i];
@@ -361,6 +490,11 @@ std::vector<double> build_device_table(int k, int n0, TableLayout& lay, double p
     for (int a = 0; a < N; ++a) pts[c * N + a] = 0.5 * (t.nodes[a] + c);
   lagrange_eval(t.nodes, pts, val, nullptr);
   for (int i = 0; i < 2 * N * N; ++i) tab[lay.p1 + i] = val[i];
+  if (N == 8) lay.eo_ok = even_odd_blocks(t, &tab[lay.eo]) ? 1 : 0;
+  window_matrices(t, &tab[lay.pw_l]);
+  if (!half_blocks(t.mass, N, &tab[lay.sym]) ||
+      !half_blocks(t.lcell[0], N, &tab[lay.sym] + ((N + 1) / 2) * ((N + 1) / 2) + (N / 2) * (N / 2)))
+    throw std::runtime_error("1D mass or interior block not symmetric under reversal");
   return tab;
 }
 

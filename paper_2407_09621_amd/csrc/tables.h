@@ -30,6 +30,14 @@ struct TableLayout {
   int p1 = 0;     // 1D prolongation [2N x N]: row (child c, node a), column b
   int lr = 0;     // Lh off-diagonal block L_{c,c+1} [N x N] (coupling to the upper cell)
   int rl = 0;     // Lh off-diagonal block L_{c+1,c} [N x N] (coupling to the lower cell)
+  int eo = 0;     // N = 8 only: even-odd blocks [12][4 x 4] of the mirror-pair form (see
+                  // build_device_table); eo_ok = 1 when the symmetries they rest on hold
+  int eo_ok = 0;
+  int sym = 0;    // even-odd half-blocks of Mh and of the interior Lh block:
+                  // ME [PE x PE], MO [P x P], LE, LO (P = N/2, PE = (N+1)/2)
+  int pw_l = 0;   // patch-wise evaluation: window stiffness-plus-face matrices [4][G x G]
+                  // by window type (bit0: lower cell first of the line, bit1: upper
+                  // cell last); the window mass is the cell mass times 1/2 or 1
   int mass_f = 0; // float copies for the FP32 path start here (same order)
   int total = 0;
 };

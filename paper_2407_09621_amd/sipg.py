@@ -30,7 +30,7 @@ class SipgError(RuntimeError):
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 DEALLOC_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
-SMOOTHER = {"multiplicative": 0, "additive": 1}
+SMOOTHER = {"multiplicative": 0, "additive": 1, "multiplicative_separate": 2}
 VARIANT = {"fgmres": 0, "gmres": 1}
 
 
@@ -95,7 +95,7 @@ class SolveInfo(ctypes.Structure):
 class CnnTrainOpts(ctypes.Structure):
     _fields_ = [("n_chains", ctypes.c_int), ("chain_length", ctypes.c_int),
                 ("crops_per_pair", ctypes.c_int), ("crop", ctypes.c_int), ("lr", ctypes.c_float),
-                ("log_every", ctypes.c_int), ("seed", ctypes.c_uint64)]
+                ("log_every", ctypes.c_int), ("seed", ctypes.c_uint64), ("loss", ctypes.c_int)]
 
 
 class CnnTrainInfo(ctypes.Structure):
@@ -131,6 +131,7 @@ def load_library(path=None):
         "sipg_n_dofs": (i64, [vp, i32]),
         "sipg_apply": (i32, [vp, i32, vp, vp, vp]),
         "sipg_apply_units": (i32, [vp, i32, vp, vp, i32, vp]),
+        "sipg_apply_patchwise": (i32, [vp, i32, vp, vp, vp]),
         "sipg_residual": (i32, [vp, i32, vp, vp, vp, vp]),
         "sipg_apply_lp": (i32, [vp, i32, vp, vp, i32, i32, vp]),
         "sipg_smooth": (i32, [vp, i32, vp, vp, i32, vp]),
@@ -154,6 +155,7 @@ def load_library(path=None):
         "sipg_cnn_forward": (i32, [vp, i32, i32, vp, vp, vp]),
         "sipg_cnn_gradient": (i32, [vp, i32, i32, vp, vp, vp, vp, vp, vp]),
         "sipg_cnn_adam_step": (i32, [vp, vp, ctypes.c_float, vp]),
+        "sipg_cnn_gradient_residual": (i32, [vp, vp, vp, vp, vp, vp]),
         "sipg_cnn_make_pairs": (i32, [vp, vp, i32, vp, vp, vp, vp]),
         "sipg_cnn_train": (i32, [vp, vp, ctypes.POINTER(CnnTrainOpts), ctypes.POINTER(CnnTrainInfo)]),
         "sipg_cnn_attach": (i32, [vp, vp]),
@@ -250,6 +252,14 @@ class Problem:
         else:
             _check(_lib.sipg_apply_units(self._h, self._lvl(level), _ptr(u, torch.float64),
                                          _ptr(v, torch.float64), UNITS[units], _stream(stream)))
+        return v
+
+    def apply_patchwise(self, u, v=None, level=-1, stream=None):
+        """v = A u in FP64 evaluated patch by patch (sipg_apply_patchwise)."""
+        import torch
+        v = torch.empty_like(u) if v is None else v
+        _check(_lib.sipg_apply_patchwise(self._h, self._lvl(level), _ptr(u, torch.float64),
+                                         _ptr(v, torch.float64), _stream(stream)))
         return v
 
     def apply_lp(self, u, v=None, precision="f16", ec=False, level=-1, stream=None):
@@ -562,6 +572,18 @@ class Network:
                                       _stream(stream)))
         return grad, loss
 
+    def gradient_residual(self, problem, rho, stream=None):
+        """(gradient tensor [n_params], loss) of the residual-aware loss
+        ||rho - A c||^2 / ||rho||^2, c = sigma net(rho), on the problem's
+        finest level (rho: FP64 cell vector)."""
+        import torch
+        grad = torch.empty(self.n_params, dtype=torch.float32, device=rho.device)
+        loss = torch.empty(1, dtype=torch.float32, device=rho.device)
+        _check(_lib.sipg_cnn_gradient_residual(self._h, problem._h, _ptr(rho, torch.float64),
+                                               _ptr(grad, torch.float32),
+                                               _ptr(loss, torch.float32), _stream(stream)))
+        return grad, loss
+
     def adam_step(self, grad, lr, stream=None):
         import torch
         if grad.numel() != self.n_params:
@@ -583,8 +605,12 @@ class Network:
         return rho, err, sc
 
     def train(self, problem, n_chains, chain_length=4, crops_per_pair=8, crop=32, lr=1e-3,
-              seed=0, log_every=0):
-        o = CnnTrainOpts(n_chains, chain_length, crops_per_pair, crop, lr, log_every, seed)
+              seed=0, log_every=0, loss="mse"):
+        """Train on solver-made pairs (sipg_cnn_train); loss "mse" (error
+        target, random crops) or "residual" (the residual the correction
+        leaves, whole grid)."""
+        o = CnnTrainOpts(n_chains, chain_length, crops_per_pair, crop, lr, log_every, seed,
+                         {"mse": 0, "residual": 1}[loss])
         info = CnnTrainInfo()
         _check(_lib.sipg_cnn_train(problem._h, self._h, ctypes.byref(o), ctypes.byref(info)))
         return dict(steps=info.steps, loss_first=info.loss_first, loss_last=info.loss_last,

@@ -52,6 +52,13 @@ extern "C" int shim_layout(int k, int n0, int* lay) {
 extern "C" void shim_table(int k, int n0, double* out) {
   TableLayout L; auto t = build_device_table(k, n0, L);
   std::memcpy(out, t.data(), t.size() * sizeof(double)); }
+extern "C" int shim_even_odd(int k, double pen, double* out) {
+  TableLayout L; auto t = build_device_table(k, 2, L, pen);
+  if (L.N != 8) return -1;
+  std::memcpy(out, t.data() + L.eo, 12 * 16 * sizeof(double)); return L.eo_ok; }
+extern "C" void shim_extra(int k, int n0, int* out) {
+  TableLayout L; build_device_table(k, n0, L);
+  out[0] = L.eo; out[1] = L.eo_ok; out[2] = L.pw_l; out[3] = L.sym; }
 extern "C" void shim_offdiag(int k, double* lr, double* rl) {
   Tables1D t = make_tables_1d(k);
   std::memcpy(lr, t.lr.data(), t.lr.size() * 8); std::memcpy(rl, t.rl.data(), t.rl.size() * 8); }
@@ -82,6 +89,12 @@ def host_tables(tmp_path_factory):
         rl = np.zeros(N * N)
         lib.shim_offdiag(k, lr.ctypes.data_as(ctypes.c_void_p), rl.ctypes.data_as(ctypes.c_void_p))
         return L, buf, lr.reshape(N, N), rl.reshape(N, N)
+    def extra(k, n0=2):
+        out = (ctypes.c_int * 4)()
+        lib.shim_extra(k, n0, out)
+        return dict(zip(["eo", "eo_ok", "pw_l", "sym"], list(out)))
+    get.lib = lib
+    get.layout_extra = extra
     return get
 
 
@@ -198,11 +211,146 @@ def test_create_rejects_half_an_allocator():
 
 def test_header_and_binding_agree_on_struct_layouts():
     """The ctypes mirrors of the header's structs: field count and order of
-    sipg_config and sipg_solve_opts (sizes follow from the types)."""
+    sipg_config, sipg_solve_opts and sipg_cnn_train_opts (sizes follow from
+    the types)."""
     from paper_2407_09621_amd import sipg as binding
-    text = open(HEADER).read()
-    for cname, pyname in (("sipg_config", "Config"), ("sipg_solve_opts", "SolveOpts")):
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    for cname, pyname in (("sipg_config", "Config"), ("sipg_solve_opts", "SolveOpts"),
+                          ("sipg_cnn_train_opts", "CnnTrainOpts")):
         body = re.search(r"typedef struct \{([^{}]*)\} " + cname + ";", text).group(1)
-        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
         fields = re.findall(r"(\w+);", body)
         assert fields == [f[0] for f in getattr(binding, pyname)._fields_], cname
+
+
+def _even_odd_model(blocks, u, n, h):
+    """Degree-7 operator applied by the mirror-pair (even-odd) scheme of the
+    matrix-core kernel, written with numpy on whole cells: E/O splits,
+    one 4 x 4 block per half for the J-symmetric mass and cell blocks, the
+    two couplings through S = v_m + J v_p and D = v_m - J v_p, the boundary
+    corrections in the coupling form, three inverse splits and the h scale."""
+    B = blocks.reshape(12, 4, 4)
+    Me, Mo, Le, Lo, Crl, Cb = B[0], B[1], B[2], B[3], B[4:8], B[8:12]
+    lo, hi = np.arange(4), 7 - np.arange(4)
+    U = u.reshape(n, n, n, 8, 8, 8)  # cz, cy, cx, l (z), j (y), i (x)
+
+    def eo(T, ax):
+        a, b = np.take(T, lo, axis=ax), np.take(T, hi, axis=ax)
+        return np.concatenate([a + b, a - b], axis=ax)
+
+    def uneo(T, ax):
+        e, o = np.take(T, range(4), axis=ax), np.take(T, range(4, 8), axis=ax)
+        out = np.empty_like(T)
+        idx = [slice(None)] * T.ndim
+        idx[ax] = lo
+        out[tuple(idx)] = (e + o) / 2
+        idx[ax] = hi
+        out[tuple(idx)] = (e - o) / 2
+        return out
+
+    def mul(Q, T, ax):
+        return np.moveaxis(np.tensordot(Q, T, axes=([1], [ax])), 0, ax)
+
+    def sym(Qe, Qo, T, ax):
+        e, o = np.take(T, range(4), axis=ax), np.take(T, range(4, 8), axis=ax)
+        return np.concatenate([mul(Qe, e, ax), mul(Qo, o, ax)], axis=ax)
+
+    def cpl(C, Um, Up, ax):
+        S, D = Um + np.flip(Up, ax), Um - np.flip(Up, ax)
+        E = mul(C[0], np.take(S, lo, axis=ax), ax) + mul(C[1], np.take(S, hi, axis=ax), ax)
+        O = mul(C[2], np.take(D, lo, axis=ax), ax) + mul(C[3], np.take(D, hi, axis=ax), ax)
+        return np.concatenate([E, O], axis=ax)
+
+    V = np.zeros_like(U)
+    z = np.zeros((8, 8, 8))
+    for cz in range(n):
+        for cy in range(n):
+            for cx in range(n):
+                c = (cz, cy, cx)
+                u0 = U[c]
+
+                def nb(d, s):
+                    q = list(c)
+                    q[d] += s
+                    return U[tuple(q)] if 0 <= q[d] < n else z
+
+                def dirterm(d, ax):
+                    w = sym(Le, Lo, eo(u0, ax), ax) + cpl(Crl, nb(d, -1), nb(d, 1), ax)
+                    if c[d] in (0, n - 1):
+                        w = w + cpl(Cb, u0 * (c[d] == 0), u0 * (c[d] == n - 1), ax)
+                    return w
+                # axes of a cell block: 0 = z, 1 = y, 2 = x
+                w = eo(dirterm(0, 0), 2)
+                w = eo(sym(Me, Mo, w, 2), 1)
+                t3 = sym(Me, Mo, w, 1)
+                s1 = sym(Me, Mo, eo(dirterm(2, 2), 1), 1)
+                s2 = sym(Me, Mo, eo(dirterm(1, 1), 2), 2)
+                t3 = t3 + sym(Me, Mo, eo(s1 + s2, 0), 0)
+                V[c] = h * uneo(uneo(uneo(t3, 0), 1), 2)
+    return V.reshape(-1)
+
+
+@pytest.mark.parametrize("n,pen", [(1, 1.0), (2, 1.0), (3, 1.0), (3, 2.5)])
+def test_even_odd_blocks_reproduce_the_operator(host_tables, n, pen):
+    """The degree-7 even-odd blocks of the device table (built by the
+    library's own host code) with the scheme the matrix-core kernel follows
+    reproduce the oracle's A u, interior and boundary cells (n = 1 puts
+    both boundaries on one cell), also at a scaled penalty; lower degrees
+    have no such blocks."""
+    import ctypes as ct
+    from oracle import sipg as osipg
+    lib = host_tables.lib
+    lib.shim_even_odd.argtypes = [ct.c_int, ct.c_double, ct.c_void_p]
+    out = np.zeros(12 * 16)
+    assert lib.shim_even_odd(7, ct.c_double(pen), out.ctypes.data_as(ct.c_void_p)) == 1
+    assert lib.shim_even_odd(5, ct.c_double(pen), out.ctypes.data_as(ct.c_void_p)) == -1
+    lib.shim_even_odd(7, ct.c_double(pen), out.ctypes.data_as(ct.c_void_p))
+    u = np.random.default_rng(n).uniform(-1, 1, n ** 3 * 512)
+    v = _even_odd_model(out, u, n, 1.0 / n)
+    ref = osipg.kron_apply(u, n, 7, penalty_scale=pen)
+    assert np.linalg.norm(v - ref) / np.linalg.norm(ref) < 1e-13
+
+
+@pytest.mark.parametrize("k", [1, 3, 7])
+def test_host_window_matrices_match_oracle(host_tables, k):
+    """The patch-wise evaluation's window matrices of the device table (four
+    window types) against the oracle's windows of lines of 2 and 4 cells
+    (h-free: L_w scaled by h)."""
+    from oracle import sipg as osipg
+    L, t, _, _ = host_tables(k, 2)
+    lay = host_tables.layout_extra(k, 2)
+    G = 2 * (k + 1)
+    W = t[lay["pw_l"]:lay["pw_l"] + 4 * G * G].reshape(4, G, G)
+    for n, w, typ in [(2, 1, 3), (4, 1, 1), (4, 2, 0), (4, 3, 2)]:
+        _, Lw = osipg.patch_1d(n, k, w)
+        np.testing.assert_allclose(W[typ], Lw / n, atol=1e-11 * np.abs(Lw / n).max())
+
+
+@pytest.mark.parametrize("k", range(1, 8))
+def test_host_even_odd_half_blocks(host_tables, k):
+    """The vector kernels apply the mass matrix and the interior cell block
+    through their even-odd half-blocks; rebuilt as y_a = (QE e)_a + (QO o)_a,
+    y_{N-1-a} = (QE e)_a - (QO o)_a (middle row of odd N: (QE e)_mid) they
+    reproduce Q x for the oracle's matrices (odd and even N)."""
+    from oracle import basis1d, sipg as osipg
+    L, t, _, _ = host_tables(k, 2)
+    off = host_tables.layout_extra(k, 2)["sym"]
+    N, P, PE = k + 1, (k + 1) // 2, (k + 2) // 2
+    Mh, _ = basis1d.mass_stiffness(k)
+    _, Lg = osipg.global_1d(3, k)
+    Lint = Lg[N:2 * N, N:2 * N] / 3
+    rng = np.random.default_rng(k)
+    base = off
+    for Q in (Mh, Lint):
+        QE = t[base:base + PE * PE].reshape(PE, PE)
+        QO = t[base + PE * PE:base + PE * PE + P * P].reshape(P, P)
+        base += PE * PE + P * P
+        x = rng.uniform(-1, 1, N)
+        e = np.array([x[b] + x[N - 1 - b] for b in range(PE)])
+        o = np.array([x[b] - x[N - 1 - b] for b in range(P)])
+        ye, yo = QE @ e, QO @ o
+        y = np.zeros(N)
+        for a in range(P):
+            y[a], y[N - 1 - a] = ye[a] + yo[a], ye[a] - yo[a]
+        if N % 2:
+            y[P] = ye[P]
+        np.testing.assert_allclose(y, Q @ x, atol=1e-12 * np.abs(Q).max() * np.abs(x).sum())

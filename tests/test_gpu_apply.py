@@ -108,3 +108,33 @@ def test_apply_vector_units_full_size(k, n):
     u = inputs.uniform_vector(P.n_dofs(), seed=2 + k)
     v = to_cpu(P.apply(to_gpu(u), units="vector"))
     assert rel_l2(v, sipg.kron_apply(u, n, k)) < 1e-12
+
+
+@pytest.mark.parametrize("k,n", [(1, 2), (2, 3), (3, 5), (4, 4), (5, 3), (6, 2), (7, 3)])
+def test_apply_patchwise_matches_assembled_matrix(k, n):
+    """sipg_apply_patchwise (the paper's patch-wise evaluation, every colour
+    of vertex patches, boundary and corner window types) gives the oracle's
+    A u; odd n leaves colours with fewer patches per direction."""
+    from paper_2407_09621_amd import Problem, SipgError
+    announce("apply patchwise", k, n)
+    P = Problem(k, n, n_levels=1)
+    u = inputs.uniform_vector(P.n_dofs(), seed=5000 + 10 * k + n)
+    v = to_cpu(P.apply_patchwise(to_gpu(u)))
+    ref = sipg.assemble(n, k) @ u
+    assert rel_l2(v, ref) < 1e-12
+    np.testing.assert_allclose(v, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    P1 = Problem(k, 1, n_levels=1)
+    with pytest.raises(SipgError, match="n >= 2"):
+        P1.apply_patchwise(to_gpu(inputs.uniform_vector(P1.n_dofs(), 1)))
+
+
+@pytest.mark.parametrize("k,n", [(3, 64), (7, 32)])
+def test_apply_patchwise_full_size(k, n):
+    """The patch-wise evaluation at the benchmark sizes against the oracle's
+    Kronecker apply (the launch the benchmark's patch-wise rows time)."""
+    from paper_2407_09621_amd import Problem
+    announce("apply patchwise full size", k, n)
+    P = Problem(k, n, n_levels=1)
+    u = inputs.uniform_vector(P.n_dofs(), seed=2 + k)
+    v = to_cpu(P.apply_patchwise(to_gpu(u)))
+    assert rel_l2(v, sipg.kron_apply(u, n, k)) < 1e-12

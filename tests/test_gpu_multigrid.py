@@ -92,3 +92,42 @@ def test_vcycle_matches(k, n):
     P.vcycle(x, to_gpu(b))
     ref = H.vcycle(len(H.levels) - 1, x0, b)
     assert rel_l2(to_cpu(x), ref) < 1e-10
+
+
+@pytest.mark.parametrize("k,n", [(2, 5), (3, 4), (3, 5), (5, 3), (7, 2), (1, 3), (6, 4)])
+def test_fused_and_separate_smoothers_match_oracle(k, n):
+    """Both forms of the multiplicative smoother: the fused colour step
+    (new patch values = local solve of b_P minus the outside neighbours'
+    face couplings, written to a second vector, uncovered layers copied) and
+    the separate residual per colour, against the oracle's sweeps; odd and
+    even n (different uncovered layers per colour), n = 2 (colours without
+    patches), two sweeps."""
+    from paper_2407_09621_amd import Problem
+    announce("smooth fused/separate", k, n)
+    lev = multigrid.Level(n, k)
+    b = inputs.uniform_vector(sipg.n_dofs(n, k), 80 + k)
+    x0 = inputs.uniform_vector(sipg.n_dofs(n, k), 90 + k)
+    ref = multigrid.smooth(lev, x0, b, 2)
+    for form in ("multiplicative", "multiplicative_separate"):
+        P = Problem(k, n, n_levels=1, smoother=form)
+        x = to_gpu(x0)
+        P.smooth(x, to_gpu(b), 2)
+        assert rel_l2(to_cpu(x), ref) < 1e-11, form
+
+
+@pytest.mark.parametrize("k,n", [(2, 8), (3, 8), (5, 4)])
+def test_fused_smoother_in_fp32_vcycle(k, n):
+    """The FP32 V-cycle with the fused colour steps against the FP32 V-cycle
+    with a separate residual per colour: both are FP32 roundings of the same
+    exact cycle (bound 8 u32 relative to the FP64 V-cycle), so they differ by
+    a few u32."""
+    import torch
+    from paper_2407_09621_amd import Problem
+    announce("fp32 vcycle fused/separate", k, n)
+    b = torch.from_numpy(inputs.uniform_vector(sipg.n_dofs(n, k), 11)).cuda()
+    x64 = torch.zeros_like(b)
+    Problem(k, n).vcycle(x64, b)
+    for form in ("multiplicative", "multiplicative_separate"):
+        x = torch.zeros_like(b)
+        Problem(k, n, mg_precision="f32", smoother=form).vcycle(x, b)
+        assert rel_l2(to_cpu(x), to_cpu(x64)) < 64 * 2.0 ** -24, form

@@ -122,3 +122,39 @@ def test_cell_blocked_tensor_permutation_roundtrip():
     P = sipg.node_coordinates(n, k)
     X = sipg.to_tensor(P[:, 0], n, k)
     assert np.all(np.diff(X, axis=2) >= 0) and np.all(np.diff(X, axis=1) == 0)
+
+
+@pytest.mark.parametrize("n,k,pen", [(2, 1, 1.0), (3, 2, 1.0), (3, 3, 2.5), (4, 1, 1.0), (2, 4, 1.0)])
+def test_patchwise_apply_equals_assembled(n, k, pen):
+    """The paper's patch-wise evaluation (Sec. 2.1, Fig. patch_int): the
+    sum over all interior-vertex patches of each patch's own Kronecker sum
+    of window matrices is the quadrature-assembled SIPG operator (interior,
+    boundary and corner patches; a scaled penalty)."""
+    u = np.random.default_rng(10 * n + k).uniform(-1, 1, sipg.n_dofs(n, k))
+    ref = sipg.assemble(n, k, penalty_scale=pen) @ u
+    v = sipg.patchwise_apply(u, n, k, penalty_scale=pen)
+    assert np.linalg.norm(v - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("n,k", [(2, 2), (5, 3)])
+def test_windows_sum_to_the_line_matrices(n, k):
+    """Every window carries its interior face once and each cell's mass and
+    stiffness with weights that add up to 1 over the windows containing the
+    cell: the windows summed along a line give the 1D matrices.  A window
+    alone is not the principal 2N x 2N block of the line (the cell integrals
+    are split), except for n = 2."""
+    N = k + 1
+    M, L = sipg.global_1d(n, k)
+    Ms, Ls = np.zeros_like(M), np.zeros_like(L)
+    for w in range(1, n):
+        Mw, Lw = sipg.patch_1d(n, k, w)
+        sl = slice((w - 1) * N, (w + 1) * N)
+        Ms[sl, sl] += Mw
+        Ls[sl, sl] += Lw
+    np.testing.assert_allclose(Ms, M, atol=1e-14 * np.abs(M).max())
+    np.testing.assert_allclose(Ls, L, atol=1e-12 * np.abs(L).max())
+    Mw, Lw = sipg.patch_1d(n, k, 1)
+    principal = np.allclose(Lw, L[:2 * N, :2 * N])
+    assert principal == (n == 2)
+    with pytest.raises(ValueError):
+        sipg.patch_1d(n, k, 0)
