@@ -418,6 +418,7 @@ def run_batch(count=BATCH_COUNT, seed=BATCH_SEED, restart=BATCH_RESTART,
 
 
 CNN_CHAINS = 5000   # x 4 pairs = the configured 20,000 solver-made pairs
+CNN_CHUNK = 250     # right-hand sides per training call
 
 
 def run_learned(chains=CNN_CHAINS, loss="residual"):
@@ -452,9 +453,19 @@ def run_learned(chains=CNN_CHAINS, loss="residual"):
         vals = [float(nw.gradient_residual(P, to_cells(rho[j]))[1].item()) for j in range(3)]
         return float(np.sqrt(np.mean(vals)))
 
-    tr = net.train(P, n_chains=chains, chain_length=4, crops_per_pair=8, crop=32, lr=1e-3,
-                   seed=2, loss=loss)
-    progress(f"learned stage trained on {tr['steps']} pairs ({loss} loss)")
+    # in chunks of CNN_CHUNK right-hand sides (the network keeps its Adam
+    # state and output scale between calls), one progress line per chunk
+    tr = None
+    for c0 in range(0, chains, CNN_CHUNK):
+        part = net.train(P, n_chains=min(CNN_CHUNK, chains - c0), chain_length=4,
+                         crops_per_pair=8, crop=32, lr=1e-3, seed=2 + c0, loss=loss)
+        if tr is None:
+            tr = part
+        else:
+            tr.update(steps=tr["steps"] + part["steps"], loss_last=part["loss_last"],
+                      sigma=part["sigma"], seconds=tr["seconds"] + part["seconds"],
+                      seconds_pairs=tr["seconds_pairs"] + part["seconds_pairs"])
+        progress(f"learned stage: {tr['steps']} pairs ({loss} loss), {tr['seconds']:.0f} s")
     untrained = Network(seed=1)
     untrained.set_params(untrained.get_params()[0], tr["sigma"])
     factor_before, factor_after = held_out(untrained), held_out(net)
@@ -582,6 +593,15 @@ def main():
                 P.apply(us[i % ROTATE], vs[i % ROTATE], stream=stream)
             torch.cuda.synchronize()
             print(f"profiled apply k={k} n={n}: 5 launches, {nd} DoFs", flush=True)
+            if k in (3, 7):
+                for i in range(5):
+                    P.apply(us[i % ROTATE], vs[i % ROTATE], stream=stream, units="vector")
+                torch.cuda.synchronize()
+                print(f"profiled vector-unit apply k={k} n={n}: 5 launches", flush=True)
+            for i in range(3):
+                P.apply_patchwise(us[i % ROTATE], vs[i % ROTATE], stream=stream)
+            torch.cuda.synchronize()
+            print(f"profiled patch-wise apply k={k} n={n}: 3 launches", flush=True)
             u32 = us[0].float()
             v32 = torch.empty_like(u32)
             for prec, ec in [("f16", 1), ("bf16", 1)]:
@@ -590,11 +610,12 @@ def main():
             torch.cuda.synchronize()
             del u32, v32
             print(f"profiled low-precision apply k={k} n={n}: 3 launches each", flush=True)
-        for prec, ec in (("f64", 0), ("f16", 1)):
-            Ps = Problem(3, 32, mg_precision=prec, error_correction=bool(ec))
+        for prec, ec, sm in (("f64", 0, "multiplicative"), ("f64", 0, "multiplicative_separate"),
+                             ("f16", 1, "multiplicative")):
+            Ps = Problem(3, 32, mg_precision=prec, error_correction=bool(ec), smoother=sm)
             amps, pqr = inputs.single_sine_modes()
             x, info = Ps.fgmres(Ps.rhs_sines(amps, pqr), rtol=1e-10)
-            print(f"profiled solve k=3 n=32 {prec}{'_ec' if ec else ''}: "
+            print(f"profiled solve k=3 n=32 {prec}{'_ec' if ec else ''} {sm}: "
                   f"{info['iterations']} iterations", flush=True)
             Ps.close()
         from paper_2407_09621_amd import Network

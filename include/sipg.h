@@ -80,7 +80,9 @@ typedef struct {
                             local solve with the right-hand side minus the face
                             couplings of the outside neighbours, which equals
                             x_P + inv(A_PP) (b - A x)_P (FP64 / FP32 V-cycles;
-                            FP16 / BF16 take form 2); 1: additive (one residual
+                            FP16 / BF16, and k = 3 in FP64, whose residual and
+                            patch kernels run on the matrix cores, take
+                            form 2); 1: additive (one residual
                             per sweep, all patch corrections summed and damped;
                             FP64 V-cycles only); 2: multiplicative with a
                             separate residual launch per colour (same result to

@@ -149,15 +149,22 @@ sipg_status b_fused_step(sipg_batch* B, const Vecs& v, const std::vector<Item>& 
 
 sipg_status b_smooth(sipg_batch* B, const Vecs& v, const std::vector<Item>& items, int sweeps,
                      hipStream_t s) {
-  if (B->prec == SIPG_F64 || B->prec == SIPG_F32) {  // fused colour steps, X and R in turn
-    for (int sw = 0; sw < sweeps; ++sw)
-      for (int c = 0; c < 8; ++c) SIPG_TRY(b_fused_step(B, v, items, c, c % 2 == 0, s));
-    return SIPG_OK;
+  // degrees whose colour step runs fused (X and R in turn, back in X after
+  // the 8 colours) and degrees that take a residual launch per colour
+  std::vector<Item> fused, split;
+  const int prec = B->prec == SIPG_F64 ? 0 : 1;
+  for (const Item& it : items) {
+    const bool f = (B->prec == SIPG_F64 || B->prec == SIPG_F32) &&
+                   fused_colour_step(prec, B->P[it.p]->N);
+    (f ? fused : split).push_back(it);
   }
   for (int sw = 0; sw < sweeps; ++sw)
     for (int c = 0; c < 8; ++c) {
-      SIPG_TRY(b_residual(B, v, items, s));
-      SIPG_TRY(b_patch(B, v, items, c, s));
+      if (!fused.empty()) SIPG_TRY(b_fused_step(B, v, fused, c, c % 2 == 0, s));
+      if (!split.empty()) {
+        SIPG_TRY(b_residual(B, v, split, s));
+        SIPG_TRY(b_patch(B, v, split, c, s));
+      }
     }
   return SIPG_OK;
 }

@@ -33,6 +33,34 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
+// A cell of zeros (up to N = 8): loads of a missing face neighbour point
+// here, so the loaded values need no select.  Never written.
+__device__ __align__(16) double g_zero_cell_f64[512];
+__device__ __align__(16) float g_zero_cell_f32[512];
+template <typename T>
+__device__ __forceinline__ const T* zero_cell();
+template <>
+__device__ __forceinline__ const double* zero_cell<double>() { return g_zero_cell_f64; }
+template <>
+__device__ __forceinline__ const float* zero_cell<float>() { return g_zero_cell_f32; }
+
+// 16 contiguous bytes of a vector (two doubles or four floats): one load or
+// LDS store instruction; both addresses must be 16-byte aligned.
+template <typename T>
+struct Piece16 {
+  static constexpr int kPer = 16 / sizeof(T);
+  typedef T V __attribute__((ext_vector_type(16 / sizeof(T))));
+  V v;
+  static __device__ __forceinline__ Piece16 load(const T* p) {
+    Piece16 q;
+    q.v = *reinterpret_cast<const V*>(p);
+    return q;
+  }
+  static __device__ __forceinline__ void store(T* p, const Piece16& q) {
+    *reinterpret_cast<V*>(p) = q.v;
+  }
+};
+
 template <int N, typename T>
 __device__ __forceinline__ void matvec(const T* __restrict__ A, const T (&x)[N], T (&y)[N]) {
 #pragma unroll
@@ -257,15 +285,18 @@ __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
   constexpr int CS = WG ? CPT : CPB;            // cells of one LDS slice
   constexpr int SLOTS = WG ? CPT : WAVES * CPB;  // cells of all slices
   constexpr bool COAL = N >= 5;
+  // cells split evenly into 16-byte pieces, NP per lane
+  constexpr bool V16 = (N * sizeof(T)) % 16 == 0;
+  constexpr int NP = V16 ? (int)(N * sizeof(T) / 16) : 1;
   static_assert(!WG || COAL, "the workgroup tile is implemented for the staged loads");
   // per cell: t1, t2 and a region holding first (COAL) one staged neighbour
   // cell, then the y-face traces [face 0,1][value, derivative][i + N l] and
   // z-face traces [face 0,1][value, derivative][i + N j]; the z-traces after
   // Mx overwrite the y-traces once those are read
   constexpr int NR = (COAL && N3 > 8 * N2) ? N3 : 8 * N2;
-  __shared__ T s_t1_all[SLOTS * N3];
-  __shared__ T s_t2_all[SLOTS * N3];
-  __shared__ T s_r_all[SLOTS * NR];
+  __shared__ __align__(16) T s_t1_all[SLOTS * N3];
+  __shared__ __align__(16) T s_t2_all[SLOTS * N3];
+  __shared__ __align__(16) T s_r_all[SLOTS * NR];
   // LDS ordering between the lanes sharing a tile
   auto lds_sync = [&]() {
     if constexpr (WG) __syncthreads();
@@ -324,59 +355,106 @@ __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
   const bool hy0 = act && cy > 0, hy1 = act && cy < n - 1;
   const bool hz0 = act && cz > 0, hz1 = act && cz < n - 1;
   if constexpr (COAL) {
-    // unconditional loads (idle lanes and missing neighbours read inside the
-    // own cell and are zeroed after the load): one basic block
-    const T* pc = u + (size_t)c * N3 + (act ? ln : 0);
+    // unconditional loads, one basic block: a missing neighbour is read from
+    // a cell of zeros, so no value needs a select after its load; idle lanes
+    // read the tile's first cell and use nothing.  The cells staged through
+    // LDS (own, x and y neighbours) are copied in 16-byte pieces where a
+    // cell splits evenly into them (lane ln moves pieces ln + N^2 r, in
+    // memory order); the z neighbours are read as z-lines, which is the
+    // layout their face traces need.
+    const T* zc = zero_cell<T>();
+    const T* cp = u + (size_t)c * N3;
     const ptrdiff_t sx = N3, sy = (ptrdiff_t)n * N3, sz = (ptrdiff_t)nn * N3;
-    const ptrdiff_t dxm = hx0 ? -sx : 0, dxp = hx1 ? sx : 0, dym = hy0 ? -sy : 0;
-    const ptrdiff_t dyp = hy1 ? sy : 0, dzm = hz0 ? -sz : 0, dzp = hz1 ? sz : 0;
+    const T* pxl = hx0 ? cp - sx : zc;
+    const T* pxh = hx1 ? cp + sx : zc;
+    const T* pyl = hy0 ? cp - sy : zc;
+    const T* pyh = hy1 ? cp + sy : zc;
+    const T* pzl = (hz0 ? cp - sz : zc) + ln;
+    const T* pzh = (hz1 ? cp + sz : zc) + ln;
 #pragma unroll
     for (int a = 0; a < N; ++a) {
-      own[a] = pc[a * N2];
-      xlo[a] = pc[a * N2 + dxm];
-      xhi[a] = pc[a * N2 + dxp];
-      ylo[a] = pc[a * N2 + dym];
-      yhi[a] = pc[a * N2 + dyp];
-      zlo[a] = pc[a * N2 + dzm];
-      zhi[a] = pc[a * N2 + dzp];
+      zlo[a] = pzl[a * N2];
+      zhi[a] = pzh[a * N2];
     }
-#pragma unroll
-    for (int a = 0; a < N; ++a) {
-      own[a] = act ? own[a] : (T)0;
-      xlo[a] = hx0 ? xlo[a] : (T)0;
-      xhi[a] = hx1 ? xhi[a] : (T)0;
-      ylo[a] = hy0 ? ylo[a] : (T)0;
-      yhi[a] = hy1 ? yhi[a] : (T)0;
-      zlo[a] = hz0 ? zlo[a] : (T)0;
-      zhi[a] = hz1 ? zhi[a] : (T)0;
-    }
-    // own and x-neighbours: z-lines -> x-lines (j, l) = (lp, lq)
     const int w = cl * N3 + ln;
-    if (act) {
+    if constexpr (V16) {
+      using P16 = Piece16<T>;
+      P16 qo[NP], ql[NP], qh[NP], yl[NP], yh[NP];
 #pragma unroll
-      for (int a = 0; a < N; ++a) {
-        s_t1[w + a * N2] = own[a];
-        s_n0[w + a * N2] = xlo[a];
-        s_n1[w + a * N2] = xhi[a];
+      for (int r = 0; r < NP; ++r) {
+        const int o = (ln + N2 * r) * P16::kPer;
+        qo[r] = P16::load(cp + o);
+        ql[r] = P16::load(pxl + o);
+        qh[r] = P16::load(pxh + o);
+        yl[r] = P16::load(pyl + o);
+        yh[r] = P16::load(pyh + o);
       }
-    }
-    lds_sync();
-    const int rx = cl * N3 + ln * N;
-    if (act) {
+      // own and x-neighbours: cell layout -> x-lines (j, l) = (lp, lq)
+      if (act) {
 #pragma unroll
-      for (int a = 0; a < N; ++a) {
-        own[a] = s_t1[rx + a];
-        xlo[a] = s_n0[rx + a];
-        xhi[a] = s_n1[rx + a];
+        for (int r = 0; r < NP; ++r) {
+          const int o = cl * N3 + (ln + N2 * r) * P16::kPer;
+          P16::store(s_t1 + o, qo[r]);
+          P16::store(s_n0 + o, ql[r]);
+          P16::store(s_n1 + o, qh[r]);
+        }
       }
-    }
-    lds_sync();
-    // y-neighbours: z-lines -> y-lines (i, l) = (lp, lq)
-    if (act) {
+      lds_sync();
+      const int rx = cl * N3 + ln * N;
+      if (act) {
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+          own[a] = s_t1[rx + a];
+          xlo[a] = s_n0[rx + a];
+          xhi[a] = s_n1[rx + a];
+        }
+      }
+      lds_sync();
+      // y-neighbours: cell layout -> y-lines (i, l) = (lp, lq)
+      if (act) {
+#pragma unroll
+        for (int r = 0; r < NP; ++r) {
+          const int o = cl * N3 + (ln + N2 * r) * P16::kPer;
+          P16::store(s_n0 + o, yl[r]);
+          P16::store(s_n1 + o, yh[r]);
+        }
+      }
+    } else {
 #pragma unroll
       for (int a = 0; a < N; ++a) {
-        s_n0[w + a * N2] = ylo[a];
-        s_n1[w + a * N2] = yhi[a];
+        own[a] = cp[ln + a * N2];
+        xlo[a] = pxl[ln + a * N2];
+        xhi[a] = pxh[ln + a * N2];
+        ylo[a] = pyl[ln + a * N2];
+        yhi[a] = pyh[ln + a * N2];
+      }
+      // own and x-neighbours: z-lines -> x-lines (j, l) = (lp, lq)
+      if (act) {
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+          s_t1[w + a * N2] = own[a];
+          s_n0[w + a * N2] = xlo[a];
+          s_n1[w + a * N2] = xhi[a];
+        }
+      }
+      lds_sync();
+      const int rx = cl * N3 + ln * N;
+      if (act) {
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+          own[a] = s_t1[rx + a];
+          xlo[a] = s_n0[rx + a];
+          xhi[a] = s_n1[rx + a];
+        }
+      }
+      lds_sync();
+      // y-neighbours: z-lines -> y-lines (i, l) = (lp, lq)
+      if (act) {
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+          s_n0[w + a * N2] = ylo[a];
+          s_n1[w + a * N2] = yhi[a];
+        }
       }
     }
     lds_sync();
