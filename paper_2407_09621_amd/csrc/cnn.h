@@ -25,7 +25,15 @@ constexpr int kTile = 16;                 // grids must be multiples of this siz
 // Partial-sum rows of the weight-gradient kernels: one row per block, each
 // row the contiguous parameter segment [w_l, b_l] of its layer.
 constexpr int kSegIn = kC * 27 + kC, kSegMid = kC * kC * 27 + kC, kSegOut = kC * 27 + 1;
-constexpr int kWgradBlocks = 256;
+constexpr int kWgradRows = 1024;
+
+// Workspace of the weight gradients for np grid points: ot holds np * 32
+// FP16 values (a channel-octet copy), os 3 * np * 32 (three x-shifted
+// copies; the one-channel layers use 3 * np of it).
+struct WgradBufs {
+  _Float16* ot;
+  _Float16* os;
+};
 
 // ---- inference / forward ----------------------------------------------------
 // a1 = ReLU(conv1(x)): x FP16 [ns][G^3], a1 FP16 [ns][G^3][32]
@@ -79,13 +87,14 @@ hipError_t launch_loss(const float* y, const float* t, const float* m, int64_t n
 // g3 = [a3 > 0] * conv4^T(g4) (FP16)
 hipError_t launch_out_bwd(const float* g4, const _Float16* a3, int G, int ns, const float* prm,
                           _Float16* g3, hipStream_t s);
-// block partials of the weight gradients (rows as above)
-hipError_t launch_out_wgrad(const _Float16* a3, const float* g4, int G, int ns, float* part,
-                            hipStream_t s);
-hipError_t launch_mid_wgrad(const _Float16* a, const _Float16* g, int G, int ns, float* part,
-                            hipStream_t s);
-hipError_t launch_in_wgrad(const _Float16* x, const _Float16* g1, int G, int ns, float* part,
-                           hipStream_t s);
+// Block partials (kWgradRows rows as above) of the weight gradients on the
+// matrix cores, through the octet copies in `w` (see cnn.hip)
+hipError_t launch_out_wgrad(const _Float16* a3, const float* g4, int G, int ns,
+                            const WgradBufs& w, float* part, hipStream_t s);
+hipError_t launch_mid_wgrad(const _Float16* a, const _Float16* g, int G, int ns,
+                            const WgradBufs& w, float* part, hipStream_t s);
+hipError_t launch_in_wgrad(const _Float16* x, const _Float16* g1, int G, int ns,
+                           const WgradBufs& w, float* part, hipStream_t s);
 // grad[i] = sigma^2 sum_b part[b][i] / sums[1] for i < seg
 hipError_t launch_reduce_rows(const float* part, int seg, const float* sums, float sigma,
                               float* grad, hipStream_t s);

@@ -436,85 +436,220 @@ __global__ __launch_bounds__(kT) void out_bwd_kernel(const float* __restrict__ g
   }
 }
 
-// Weight-gradient partials: block b sums over points [b chunk, (b+1) chunk)
-// of the whole batch.
-__global__ __launch_bounds__(896) void out_wgrad_kernel(const _Float16* __restrict__ a3,
-                                                        const float* __restrict__ g4, int G,
-                                                        int64_t total, int64_t chunk,
-                                                        float* __restrict__ part) {
-  const int t = threadIdx.x;
-  if (t > kSegOut - 1) return;
-  const int64_t G3 = (int64_t)G * G * G;
-  const int ci = t / 27, d = t % 27;
-  const int64_t p0 = (int64_t)blockIdx.x * chunk, p1 = p0 + chunk < total ? p0 + chunk : total;
-  float acc = 0.0f;
-  for (int64_t gp = p0; gp < p1; ++gp) {
-    const float g = g4[gp];
-    if (t == kSegOut - 1) {
-      acc += g;
-      continue;
-    }
-    const int64_t base = gp - gp % G3;
-    const int p = (int)(gp - base);
-    const int q = neighbour(p % G, (p / G) % G, p / (G * G), d, G, 1);
-    if (q >= 0) acc = fmaf(g, (float)a3[(base + q) * kC + ci], acc);
+// ---- weight gradients on the matrix cores ---------------------------------------
+// Every weight gradient is a sum over grid points of a product of two
+// point-indexed operands, dW[m][n] = sum_p A[p][m] B[p][n]: a GEMM whose
+// contraction runs over the points.  The matrix-core operand of one lane is
+// 8 consecutive contraction indices, so both operands are read as "octets",
+// 8 consecutive x-points of one channel (16 bytes), from copies laid out
+// [p / 8][channel][p % 8] (octets_kernel, or scalar_octets_kernel for the
+// one-channel fields).  A tap's x-shift is built into the copy (one copy per
+// shift s, holding src[p + s] and zero where x + s leaves the grid); its y
+// and z shifts move whole octets, because G is a multiple of 16.
+//   layers 2, 3: A = g^T (output channel), B = a shifted by the tap (input
+//                channel); 27 taps, each a 32 x 32 block; bias: B = ones.
+//   layer 1:     A = g1^T, B = x shifted by tap (tap d = column), column 27 =
+//                ones for the bias.
+//   layer 4:     A = a3^T, B = g4 shifted back by the tap (sum_p g4[p]
+//                a3[p + d] = sum_q a3[q] g4[q - d]); bias: A = ones, tap 13.
+// Operands as in the forward kernel (16x16x32: lane L holds A[L%16][8(L/16)
+// ..+7], B[8(L/16)..+7][L%16], D[4(L/16)+r][L%16]).
+
+__device__ __align__(16) _Float16 g_zero_octet[8];
+
+// dst[(o 32 + c) 8 + e] = src[(8 o + e + sh) 32 + c], zero where x + sh
+// leaves the grid line; one thread per (octet, 8 channels)
+__global__ __launch_bounds__(kT) void octets_kernel(const _Float16* __restrict__ src, int G,
+                                                    int64_t noct, int sh,
+                                                    _Float16* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (t >= noct * 4) return;
+  const int64_t o = t >> 2;
+  const int cg = (int)(t & 3);
+  const int x0 = (int)((8 * o) % G);
+  h8 v[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int xs = x0 + e + sh;
+    v[e] = (xs >= 0 && xs < G)
+               ? *reinterpret_cast<const h8*>(src + (8 * o + e + sh) * kC + cg * 8)
+               : h8{0, 0, 0, 0, 0, 0, 0, 0};
   }
-  part[(int64_t)blockIdx.x * kSegOut + t] = acc;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    h8 w;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) w[e] = v[e][c];
+    *reinterpret_cast<h8*>(dst + (o * kC + cg * 8 + c) * 8) = w;
+  }
 }
 
-__global__ __launch_bounds__(1024) void mid_wgrad_kernel(const _Float16* __restrict__ a,
-                                                         const _Float16* __restrict__ g, int G,
-                                                         int64_t total, int64_t chunk,
-                                                         float* __restrict__ part) {
-  const int t = threadIdx.x;
-  const int co = t % kC, ci = t / kC;
-  const int64_t G3 = (int64_t)G * G * G;
-  const int64_t p0 = (int64_t)blockIdx.x * chunk, p1 = p0 + chunk < total ? p0 + chunk : total;
-  float acc[27];
-#pragma unroll
-  for (int d = 0; d < 27; ++d) acc[d] = 0.0f;
-  float gb = 0.0f;
-  for (int64_t gp = p0; gp < p1; ++gp) {
-    const float gv = (float)g[gp * kC + co];
-    gb += gv;
-    const int64_t base = gp - gp % G3;
-    const int p = (int)(gp - base);
-    const int gx = p % G, gy = (p / G) % G, gz = p / (G * G);
-#pragma unroll
-    for (int d = 0; d < 27; ++d) {
-      const int q = neighbour(gx, gy, gz, d, G, 1);
-      if (q >= 0) acc[d] = fmaf(gv, (float)a[(base + q) * kC + ci], acc[d]);
-    }
-  }
-  float* row = part + (int64_t)blockIdx.x * kSegMid;
-#pragma unroll
-  for (int d = 0; d < 27; ++d) row[(co * kC + ci) * 27 + d] = acc[d];
-  if (ci == 0) row[kC * kC * 27 + co] = gb;
+// dst[p] = src[p + sh] as FP16, zero where x + sh leaves the grid line
+template <typename T>
+__global__ __launch_bounds__(kT) void scalar_octets_kernel(const T* __restrict__ src, int G,
+                                                           int64_t np, int sh,
+                                                           _Float16* __restrict__ dst) {
+  const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (p >= np) return;
+  const int xs = (int)(p % G) + sh;
+  dst[p] = (xs >= 0 && xs < G) ? (_Float16)src[p + sh] : (_Float16)0.0f;
 }
 
-__global__ __launch_bounds__(896) void in_wgrad_kernel(const _Float16* __restrict__ x,
-                                                       const _Float16* __restrict__ g1, int G,
-                                                       int64_t total, int64_t chunk,
-                                                       float* __restrict__ part) {
-  const int t = threadIdx.x;
-  if (t >= kSegIn) return;
-  const bool is_bias = t >= kC * 27;
-  const int co = is_bias ? t - kC * 27 : t / 27, d = t % 27;
+__device__ __forceinline__ h8 load_octet(const _Float16* p) {
+  return *reinterpret_cast<const h8*>(p);
+}
+
+// KIND 0: layers 2, 3 (At = g^T, Bs = shifted a^T copies, bstride = np * 32)
+// KIND 1: layer 1 (At = g1^T, Bs = shifted x copies, bstride = np)
+// KIND 2: layer 4 (At = a3^T, Bs = shifted g4 copies, bstride = np)
+// A step is 32 points (4 octets, one per lane group); block b takes steps
+// [b spb, (b + 1) spb).  KIND 0 (512 threads): the eight waves share the
+// steps and split the 27 taps and the bias (at most 4 each, 64 accumulators
+// per lane); KINDs 1 and 2 (256 threads): the waves split the steps and sum
+// through LDS.  One partial row per block.
+constexpr int kWgradMidThreads = 512;
+template <int KIND>
+__global__ __launch_bounds__(KIND == 0 ? kWgradMidThreads : kT) void wgrad_mfma_kernel(const _Float16* __restrict__ At,
+                                                        const _Float16* __restrict__ Bs,
+                                                        int64_t bstride, int G, int64_t nsteps,
+                                                        int64_t spb, float* __restrict__ part) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int i = lane & 15, h = lane >> 4;
   const int64_t G3 = (int64_t)G * G * G;
-  const int64_t p0 = (int64_t)blockIdx.x * chunk, p1 = p0 + chunk < total ? p0 + chunk : total;
-  float acc = 0.0f;
-  for (int64_t gp = p0; gp < p1; ++gp) {
-    const float gv = (float)g1[gp * kC + co];
-    if (is_bias) {
-      acc += gv;
-      continue;
+  const int64_t s0 = (int64_t)blockIdx.x * spb;
+  const int64_t s1 = s0 + spb < nsteps ? s0 + spb : nsteps;
+  const h8 ones = h8{1, 1, 1, 1, 1, 1, 1, 1};
+  const int64_t oy = G / 8, oz = (int64_t)G * G / 8;  // octets per y and z step
+
+  if constexpr (KIND == 0) {
+    constexpr int kSeg = kC * kC * 27 + kC;
+    constexpr int W = kWgradMidThreads / 64, TPW = (28 + W - 1) / W;  // taps (+ bias) per wave
+    f4 acc[TPW][2][2], accb[2];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) acc[t][a][0] = acc[t][a][1] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    accb[0] = accb[1] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int64_t st = s0; st < s1; ++st) {
+      const int64_t o = 4 * st + h;
+      const int64_t pp = (8 * o) % G3;
+      const int y = (int)((pp / G) % G), z = (int)(pp / ((int64_t)G * G));
+      const h8 A0 = load_octet(At + (o * kC + i) * 8);
+      const h8 A1 = load_octet(At + (o * kC + 16 + i) * 8);
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+        const int d = wave + W * t;
+        if (d < 27) {
+          const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
+          const bool ok = (unsigned)(y + dy) < (unsigned)G && (unsigned)(z + dz) < (unsigned)G;
+          const _Float16* b = Bs + (dx + 1) * bstride + ((o + dy * oy + dz * oz) * kC + i) * 8;
+          const h8 B0 = load_octet(ok ? b : g_zero_octet);
+          const h8 B1 = load_octet(ok ? b + 16 * 8 : g_zero_octet);
+          acc[t][0][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A0, B0, acc[t][0][0], 0, 0, 0);
+          acc[t][0][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A0, B1, acc[t][0][1], 0, 0, 0);
+          acc[t][1][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A1, B0, acc[t][1][0], 0, 0, 0);
+          acc[t][1][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A1, B1, acc[t][1][1], 0, 0, 0);
+        } else if (d == 27) {
+          accb[0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A0, ones, accb[0], 0, 0, 0);
+          accb[1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A1, ones, accb[1], 0, 0, 0);
+        }
+      }
     }
-    const int64_t base = gp - gp % G3;
-    const int p = (int)(gp - base);
-    const int q = neighbour(p % G, (p / G) % G, p / (G * G), d, G, 1);
-    if (q >= 0) acc = fmaf(gv, (float)x[base + q], acc);
+    float* row = part + (int64_t)blockIdx.x * kSeg;
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const int d = wave + W * t;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int co = a * 16 + 4 * h + r;
+          if (d < 27) {
+            row[(co * kC + i) * 27 + d] = acc[t][a][0][r];
+            row[(co * kC + 16 + i) * 27 + d] = acc[t][a][1][r];
+          } else if (d == 27 && i == 0) {
+            row[kC * kC * 27 + co] = accb[a][r];
+          }
+        }
+    }
+  } else {
+    constexpr int kSeg = KIND == 1 ? kC * 27 + kC : kC * 27 + 1;
+    __shared__ float s_red[3][20][64];
+    f4 acc[2][2], accb;
+    acc[0][0] = acc[0][1] = acc[1][0] = acc[1][1] = accb = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    // this lane's tap in each of the two column blocks
+    int dxs[2], dys[2], dzs[2];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+      const int d = nb * 16 + i;
+      dxs[nb] = d % 3 - 1;
+      dys[nb] = (d / 3) % 3 - 1;
+      dzs[nb] = d / 9 - 1;
+    }
+    for (int64_t st = s0 + wave; st < s1; st += kT / 64) {
+      const int64_t o = 4 * st + h;
+      const int64_t pp = (8 * o) % G3;
+      const int y = (int)((pp / G) % G), z = (int)(pp / ((int64_t)G * G));
+      const h8 A0 = load_octet(At + (o * kC + i) * 8);
+      const h8 A1 = load_octet(At + (o * kC + 16 + i) * 8);
+      h8 B[2];
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        const int d = nb * 16 + i;
+        // layer 1 reads x at p + tap, layer 4 reads g4 at q - tap
+        const int sg = KIND == 1 ? 1 : -1;
+        const int dx = sg * dxs[nb], dy = sg * dys[nb], dz = sg * dzs[nb];
+        const bool ok = d < 27 && (unsigned)(y + dy) < (unsigned)G &&
+                        (unsigned)(z + dz) < (unsigned)G;
+        const _Float16* b = Bs + (dx + 1) * bstride + (o + dy * oy + dz * oz) * 8;
+        B[nb] = load_octet(ok ? b : g_zero_octet);
+        if (KIND == 1 && d == 27) B[nb] = ones;
+      }
+      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A0, B[0], acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A0, B[1], acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A1, B[0], acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A1, B[1], acc[1][1], 0, 0, 0);
+      if constexpr (KIND == 2)
+        accb = __builtin_amdgcn_mfma_f32_16x16x32_f16(ones, B[0], accb, 0, 0, 0);
+    }
+    // sum the four waves' accumulators through LDS, wave 0 writes the row
+    if (wave > 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        s_red[wave - 1][0 + r][lane] = acc[0][0][r];
+        s_red[wave - 1][4 + r][lane] = acc[0][1][r];
+        s_red[wave - 1][8 + r][lane] = acc[1][0][r];
+        s_red[wave - 1][12 + r][lane] = acc[1][1][r];
+        s_red[wave - 1][16 + r][lane] = accb[r];
+      }
+    }
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int w = 0; w < 3; ++w)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        acc[0][0][r] += s_red[w][0 + r][lane];
+        acc[0][1][r] += s_red[w][4 + r][lane];
+        acc[1][0][r] += s_red[w][8 + r][lane];
+        acc[1][1][r] += s_red[w][12 + r][lane];
+        accb[r] += s_red[w][16 + r][lane];
+      }
+    float* row = part + (int64_t)blockIdx.x * kSeg;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = a * 16 + 4 * h + r;  // output channel (layer 1) / input channel (4)
+          const int d = nb * 16 + i;
+          if (d < 27) row[m * 27 + d] = acc[a][nb][r];
+          else if (KIND == 1 && d == 27) row[kC * 27 + m] = acc[a][nb][r];
+        }
+    if (KIND == 2 && lane == 13) row[kC * 27] = accb[0];
   }
-  part[(int64_t)blockIdx.x * kSegIn + t] = acc;
 }
 
 __global__ __launch_bounds__(kT) void reduce_rows_kernel(const float* __restrict__ part, int seg,
@@ -523,7 +658,7 @@ __global__ __launch_bounds__(kT) void reduce_rows_kernel(const float* __restrict
   const int i = blockIdx.x * kT + threadIdx.x;
   if (i >= seg) return;
   float s = 0.0f;
-  for (int b = 0; b < kWgradBlocks; ++b) s += part[(int64_t)b * seg + i];
+  for (int b = 0; b < kWgradRows; ++b) s += part[(int64_t)b * seg + i];
   const float tot = sums[1];
   grad[i] = tot > 0.0f ? sigma2 * s / tot : 0.0f;
 }
@@ -685,30 +820,49 @@ hipError_t launch_out_bwd(const float* g4, const _Float16* a3, int G, int ns, co
   return hipGetLastError();
 }
 
-static int64_t chunk_of(int64_t total) { return (total + kWgradBlocks - 1) / kWgradBlocks; }
-
-hipError_t launch_out_wgrad(const _Float16* a3, const float* g4, int G, int ns, float* part,
-                            hipStream_t s) {
-  const int64_t total = (int64_t)ns * G * G * G;
-  hipLaunchKernelGGL(out_wgrad_kernel, dim3(kWgradBlocks), dim3(896), 0, s, a3, g4, G, total,
-                     chunk_of(total), part);
+// octet copies for one layer's weight gradient and the MFMA kernel
+template <int KIND>
+static hipError_t wgrad(const _Float16* At, const _Float16* Bs, int64_t bstride, int G,
+                        int64_t np, float* part, hipStream_t s) {
+  const int64_t nsteps = np / 32;
+  const int64_t spb = (nsteps + kWgradRows - 1) / kWgradRows;
+  hipLaunchKernelGGL(wgrad_mfma_kernel<KIND>, dim3(kWgradRows),
+                     dim3(KIND == 0 ? kWgradMidThreads : kT), 0, s, At, Bs, bstride,
+                     G, nsteps, spb, part);
   return hipGetLastError();
 }
 
-hipError_t launch_mid_wgrad(const _Float16* a, const _Float16* g, int G, int ns, float* part,
-                            hipStream_t s) {
-  const int64_t total = (int64_t)ns * G * G * G;
-  hipLaunchKernelGGL(mid_wgrad_kernel, dim3(kWgradBlocks), dim3(1024), 0, s, a, g, G, total,
-                     chunk_of(total), part);
-  return hipGetLastError();
+hipError_t launch_out_wgrad(const _Float16* a3, const float* g4, int G, int ns,
+                            const WgradBufs& w, float* part, hipStream_t s) {
+  const int64_t np = (int64_t)ns * G * G * G, noct = np / 8;
+  hipLaunchKernelGGL(octets_kernel, dim3(blocks_for(noct * 4)), dim3(kT), 0, s, a3, G, noct, 0,
+                     w.ot);
+  for (int sh = -1; sh <= 1; ++sh)
+    hipLaunchKernelGGL(scalar_octets_kernel<float>, dim3(blocks_for(np)), dim3(kT), 0, s, g4, G,
+                       np, sh, w.os + (sh + 1) * np);
+  return wgrad<2>(w.ot, w.os, np, G, np, part, s);
 }
 
-hipError_t launch_in_wgrad(const _Float16* x, const _Float16* g1, int G, int ns, float* part,
-                           hipStream_t s) {
-  const int64_t total = (int64_t)ns * G * G * G;
-  hipLaunchKernelGGL(in_wgrad_kernel, dim3(kWgradBlocks), dim3(896), 0, s, x, g1, G, total,
-                     chunk_of(total), part);
-  return hipGetLastError();
+hipError_t launch_mid_wgrad(const _Float16* a, const _Float16* g, int G, int ns,
+                            const WgradBufs& w, float* part, hipStream_t s) {
+  const int64_t np = (int64_t)ns * G * G * G, noct = np / 8;
+  hipLaunchKernelGGL(octets_kernel, dim3(blocks_for(noct * 4)), dim3(kT), 0, s, g, G, noct, 0,
+                     w.ot);
+  for (int sh = -1; sh <= 1; ++sh)
+    hipLaunchKernelGGL(octets_kernel, dim3(blocks_for(noct * 4)), dim3(kT), 0, s, a, G, noct, sh,
+                       w.os + (sh + 1) * np * kC);
+  return wgrad<0>(w.ot, w.os, np * kC, G, np, part, s);
+}
+
+hipError_t launch_in_wgrad(const _Float16* x, const _Float16* g1, int G, int ns,
+                           const WgradBufs& w, float* part, hipStream_t s) {
+  const int64_t np = (int64_t)ns * G * G * G, noct = np / 8;
+  hipLaunchKernelGGL(octets_kernel, dim3(blocks_for(noct * 4)), dim3(kT), 0, s, g1, G, noct, 0,
+                     w.ot);
+  for (int sh = -1; sh <= 1; ++sh)
+    hipLaunchKernelGGL(scalar_octets_kernel<_Float16>, dim3(blocks_for(np)), dim3(kT), 0, s, x,
+                       G, np, sh, w.os + (sh + 1) * np);
+  return wgrad<1>(w.ot, w.os, np, G, np, part, s);
 }
 
 hipError_t launch_reduce_rows(const float* part, int seg, const float* sums, float sigma,

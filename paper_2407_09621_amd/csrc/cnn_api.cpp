@@ -33,13 +33,14 @@ struct sipg_cnn {
   bool ws_train = false;
   _Float16 *x16 = nullptr, *a1 = nullptr, *a2 = nullptr, *a3 = nullptr;
   _Float16 *g1 = nullptr, *g2 = nullptr, *g3 = nullptr;
+  _Float16 *ot = nullptr, *os = nullptr;  // weight-gradient octet copies (np * 32, 3 np * 32)
   float *y = nullptr, *g4 = nullptr, *xin = nullptr, *tgt = nullptr, *msk = nullptr;
 };
 
 namespace {
 
 void free_ws(sipg_cnn* c) {
-  for (_Float16** p : {&c->x16, &c->a1, &c->a2, &c->a3, &c->g1, &c->g2, &c->g3}) {
+  for (_Float16** p : {&c->x16, &c->a1, &c->a2, &c->a3, &c->g1, &c->g2, &c->g3, &c->ot, &c->os}) {
     if (*p) hipFree(*p);
     *p = nullptr;
   }
@@ -66,6 +67,8 @@ sipg_status ensure_ws(sipg_cnn* c, int64_t points, bool train) {
     SIPG_TRY(dev_alloc(&c->g1, pc));
     SIPG_TRY(dev_alloc(&c->g2, pc));
     SIPG_TRY(dev_alloc(&c->g3, pc));
+    SIPG_TRY(dev_alloc(&c->ot, pc));
+    SIPG_TRY(dev_alloc(&c->os, 3 * pc));
     SIPG_TRY(dev_alloc(&c->g4, (size_t)np));
     SIPG_TRY(dev_alloc(&c->xin, (size_t)np));
     SIPG_TRY(dev_alloc(&c->tgt, (size_t)np));
@@ -97,15 +100,16 @@ sipg_status forward(sipg_cnn* c, int G, int ns, float* y, float scale, hipStream
 sipg_status backward_from_output(sipg_cnn* c, int G, int ns, float* grad, hipStream_t s) {
   const float sig = c->sigma > 0.0f ? c->sigma : 1.0f;
   SIPG_HIP(C::launch_out_bwd(c->g4, c->a3, G, ns, c->prm, c->g3, s));
-  SIPG_HIP(C::launch_out_wgrad(c->a3, c->g4, G, ns, c->part, s));
+  const C::WgradBufs wb{c->ot, c->os};
+  SIPG_HIP(C::launch_out_wgrad(c->a3, c->g4, G, ns, wb, c->part, s));
   SIPG_HIP(C::launch_reduce_rows(c->part, C::kSegOut, c->sums, sig, grad + C::kW4, s));
-  SIPG_HIP(C::launch_mid_wgrad(c->a2, c->g3, G, ns, c->part, s));
+  SIPG_HIP(C::launch_mid_wgrad(c->a2, c->g3, G, ns, wb, c->part, s));
   SIPG_HIP(C::launch_reduce_rows(c->part, C::kSegMid, c->sums, sig, grad + C::kW3, s));
   SIPG_HIP(C::launch_mid(1, c->g3, c->packed + 3 * C::kPacked, nullptr, c->a2, c->g2, G, ns, s));
-  SIPG_HIP(C::launch_mid_wgrad(c->a1, c->g2, G, ns, c->part, s));
+  SIPG_HIP(C::launch_mid_wgrad(c->a1, c->g2, G, ns, wb, c->part, s));
   SIPG_HIP(C::launch_reduce_rows(c->part, C::kSegMid, c->sums, sig, grad + C::kW2, s));
   SIPG_HIP(C::launch_mid(1, c->g2, c->packed + 2 * C::kPacked, nullptr, c->a1, c->g1, G, ns, s));
-  SIPG_HIP(C::launch_in_wgrad(c->x16, c->g1, G, ns, c->part, s));
+  SIPG_HIP(C::launch_in_wgrad(c->x16, c->g1, G, ns, wb, c->part, s));
   SIPG_HIP(C::launch_reduce_rows(c->part, C::kSegIn, c->sums, sig, grad + C::kW1, s));
   return SIPG_OK;
 }
@@ -275,7 +279,7 @@ sipg_status sipg_cnn_create(sipg_cnn** out) {
   if (st == SIPG_OK) st = dev_alloc(&c->av, C::kParams);
   if (st == SIPG_OK) st = dev_alloc(&c->grad, C::kParams);
   if (st == SIPG_OK) st = dev_alloc(&c->packed, 4 * (size_t)C::kPacked);
-  if (st == SIPG_OK) st = dev_alloc(&c->part, (size_t)C::kWgradBlocks * C::kSegMid);
+  if (st == SIPG_OK) st = dev_alloc(&c->part, (size_t)C::kWgradRows * C::kSegMid);
   if (st == SIPG_OK) st = dev_alloc(&c->lpart, 2 * 1024);
   if (st == SIPG_OK) st = dev_alloc(&c->sums, 2);
   if (st == SIPG_OK) {

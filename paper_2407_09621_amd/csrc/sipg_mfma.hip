@@ -31,6 +31,12 @@ namespace sipg {
 
 namespace {
 
+// 512 zeros (one degree-7 cell, or the 8 cells of a degree-3 row): the
+// loads of a missing face neighbour read here, so the loaded values need
+// no per-value select.  The choice of pointer is wave-uniform (scalar).
+// Never written.
+__device__ __align__(16) double g_zero_cells[512];
+
 constexpr int kT = 256;  // 4 waves per workgroup
 
 __device__ __forceinline__ double mma(double a, double b, double c) {
@@ -121,32 +127,26 @@ __global__ __launch_bounds__(kT) void apply_mfma4_kernel(Batch<double> B,
 
   // ---- loads: the row's cells, the two row ends' outer x-neighbours, each
   // cell's z neighbours (x,y,z) and y neighbours (x,z,y).  All loads are
-  // unconditional (a missing neighbour reads the cell itself and is zeroed
-  // after the load): one basic block the compiler can schedule freely.
+  // unconditional (a missing neighbour row reads the cells of zeros): one
+  // basic block the compiler can schedule freely.
   const double* pc = u + (size_t)c0 * 64;
-  const ptrdiff_t dym = cy > 0 ? -(ptrdiff_t)n * 64 : 0, dyp = cy < n - 1 ? (ptrdiff_t)n * 64 : 0;
-  const ptrdiff_t dzm = cz > 0 ? -(ptrdiff_t)nn * 64 : 0, dzp = cz < n - 1 ? (ptrdiff_t)nn * 64 : 0;
+  const double* zc = g_zero_cells;
+  const double* pym = cy > 0 ? pc - (ptrdiff_t)n * 64 : zc;
+  const double* pyp = cy < n - 1 ? pc + (ptrdiff_t)n * 64 : zc;
+  const double* pzm = cz > 0 ? pc - (ptrdiff_t)nn * 64 : zc;
+  const double* pzp = cz < n - 1 ? pc + (ptrdiff_t)nn * 64 : zc;
   double u0[CPW], uym[CPW], uyp[CPW], uzm[CPW], uzp[CPW], b0[CPW];
 #pragma unroll
   for (int q = 0; q < CPW; ++q) {
     u0[q] = pc[q * 64 + lane];
-    uym[q] = pc[q * 64 + oXZY + dym];
-    uyp[q] = pc[q * 64 + oXZY + dyp];
-    uzm[q] = pc[q * 64 + lane + dzm];
-    uzp[q] = pc[q * 64 + lane + dzp];
+    uym[q] = pym[q * 64 + oXZY];
+    uyp[q] = pyp[q * 64 + oXZY];
+    uzm[q] = pzm[q * 64 + lane];
+    uzp[q] = pzp[q * 64 + lane];
     b0[q] = RES ? bv[(size_t)(c0 + q) * 64 + lane] : 0.0;
   }
-  double uxm0 = pc[lane + (cx0 > 0 ? -64 : 0)];
-  double uxpE = pc[lane + (cx0 + CPW < n ? CPW * 64 : (CPW - 1) * 64)];
-#pragma unroll
-  for (int q = 0; q < CPW; ++q) {
-    uym[q] = cy > 0 ? uym[q] : 0.0;
-    uyp[q] = cy < n - 1 ? uyp[q] : 0.0;
-    uzm[q] = cz > 0 ? uzm[q] : 0.0;
-    uzp[q] = cz < n - 1 ? uzp[q] : 0.0;
-  }
-  uxm0 = cx0 > 0 ? uxm0 : 0.0;
-  uxpE = cx0 + CPW < n ? uxpE : 0.0;
+  const double uxm0 = (cx0 > 0 ? pc - 64 : zc)[lane];
+  const double uxpE = (cx0 + CPW < n ? pc + CPW * 64 : zc)[lane];
 
   // ---- matrix operands (uniform tables; the same registers serve as A and B)
   auto var = [&](int q) { return (q == 0 ? 1 : 0) | (q == n - 1 ? 2 : 0); };
@@ -285,10 +285,6 @@ __device__ __forceinline__ void load8(const double* __restrict__ q, double* a) {
   for (int r = 0; r < 8; ++r) a[r] = q[reg_off8(r)];
 }
 
-__device__ __forceinline__ void zero_if(bool z, double* a) {
-#pragma unroll
-  for (int r = 0; r < 8; ++r) a[r] = z ? 0.0 : a[r];
-}
 
 __device__ __forceinline__ void permute8(const double* a, double* b, int src) {
 #pragma unroll
@@ -330,19 +326,14 @@ __global__ __launch_bounds__(kT) void apply_mfma8_kernel(Batch<double> B,
   // and is zeroed after the load), so they form one basic block that the
   // compiler may schedule ahead of the products.
   double u0[8], zm[8], zp[8], xm[8], xp[8], ym[8], yp[8];
+  const double* zc = g_zero_cells;
   load8(pc + oXYZ, u0);
-  load8(pc + oXYZ + (cz > 0 ? -sz : 0), zm);
-  load8(pc + oXYZ + (cz < n - 1 ? sz : 0), zp);
-  load8(pc + oXYZ + (cx > 0 ? -sx : 0), xm);
-  load8(pc + oXYZ + (cx < n - 1 ? sx : 0), xp);
-  load8(pc + oXYZ + (cy > 0 ? -sy : 0), ym);
-  load8(pc + oXYZ + (cy < n - 1 ? sy : 0), yp);
-  zero_if(cz == 0, zm);
-  zero_if(cz == n - 1, zp);
-  zero_if(cx == 0, xm);
-  zero_if(cx == n - 1, xp);
-  zero_if(cy == 0, ym);
-  zero_if(cy == n - 1, yp);
+  load8((cz > 0 ? pc - sz : zc) + oXYZ, zm);
+  load8((cz < n - 1 ? pc + sz : zc) + oXYZ, zp);
+  load8((cx > 0 ? pc - sx : zc) + oXYZ, xm);
+  load8((cx < n - 1 ? pc + sx : zc) + oXYZ, xp);
+  load8((cy > 0 ? pc - sy : zc) + oXYZ, ym);
+  load8((cy < n - 1 ? pc + sy : zc) + oXYZ, yp);
 
   double t3[8], w[8], s[8], a[8];
   {  // t3 = My Mx Lz~ u
@@ -364,8 +355,6 @@ __global__ __launch_bounds__(kT) void apply_mfma8_kernel(Batch<double> B,
     mul_swapped<0>(LR, a, w, true);   // (x, z, y)
     mul_swapped<1>(M, w, s, false);   // My -> (y, z, x)
   }
-  zero_if(cy == 0, ym);
-  zero_if(cy == n - 1, yp);
   {  // s2 = Mx Ly~ u, added to s1
     const Op8 Ly = load_op8(tab + lay.lcell + var(cy) * 64, lane);
     permute8(u0, a, s12);             // (x, z, y)
@@ -531,19 +520,18 @@ void apply_mfma8eo_kernel(Batch<double> B, const double* __restrict__ tab, Table
   const double R0 = a_operand(eo + 64, lane), R1 = a_operand(eo + 80, lane);
   const double R2 = a_operand(eo + 96, lane), R3 = a_operand(eo + 112, lane);
 
-  // unconditional loads (a missing neighbour reads the cell and is zeroed)
+  // unconditional loads (a missing neighbour reads the cell of zeros)
   double u0[8], zm[8], zp[8], xm[8], xp[8], ym[8], yp[8];
   auto load = [&](const double* q, double* a) {
 #pragma unroll
     for (int r = 0; r < 8; ++r) a[r] = q[off[r]];
   };
+  const double* zc = g_zero_cells;
   load(pc, u0);
-  load(pc + (cz > 0 ? -sz : 0), zm);
-  load(pc + (cz < n - 1 ? sz : 0), zp);
-  load(pc + (cx > 0 ? -sx : 0), xm);
-  load(pc + (cx < n - 1 ? sx : 0), xp);
-  zero_if(cz == 0, zm);
-  zero_if(cz == n - 1, zp);
+  load(cz > 0 ? pc - sz : zc, zm);
+  load(cz < n - 1 ? pc + sz : zc, zp);
+  load(cx > 0 ? pc - sx : zc, xm);
+  load(cx < n - 1 ? pc + sx : zc, xp);
 
   double t3[8], w[8], s[8], a[8], b[8];
   {  // t3 = My Mx Lz~ u
@@ -564,10 +552,8 @@ void apply_mfma8eo_kernel(Batch<double> B, const double* __restrict__ tab, Table
   // the y neighbours are read after the z term: holding them through it
   // would not fit three waves per SIMD
   __builtin_amdgcn_sched_barrier(0);
-  load(pc + (cy > 0 ? -sy : 0), ym);
-  load(pc + (cy < n - 1 ? sy : 0), yp);
-  zero_if(cx == 0, xm);
-  zero_if(cx == n - 1, xp);
+  load(cy > 0 ? pc - sy : zc, ym);
+  load(cy < n - 1 ? pc + sy : zc, yp);
   {  // s1 = My Lx~ u
 #pragma unroll
     for (int r = 0; r < 8; ++r) b[r] = u0[r];
@@ -583,8 +569,6 @@ void apply_mfma8eo_kernel(Batch<double> B, const double* __restrict__ tab, Table
     split8<1>(w);
     mul_sym<1, true>(Me, Mo, w, s, false);  // My -> (y,z,x)
   }
-  zero_if(cy == 0, ym);
-  zero_if(cy == n - 1, yp);
   {  // s2 = Mx Ly~ u, added to s1
 #pragma unroll
     for (int r = 0; r < 8; ++r) b[r] = u0[r];

@@ -357,11 +357,13 @@ __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
   if constexpr (COAL) {
     // unconditional loads, one basic block: a missing neighbour is read from
     // a cell of zeros, so no value needs a select after its load; idle lanes
-    // read the tile's first cell and use nothing.  The cells staged through
-    // LDS (own, x and y neighbours) are copied in 16-byte pieces where a
-    // cell splits evenly into them (lane ln moves pieces ln + N^2 r, in
-    // memory order); the z neighbours are read as z-lines, which is the
+    // read the first line of the tile's first cell (lnl = 0) and use
+    // nothing, so every address stays inside one cell.  The cells staged
+    // through LDS (own, x and y neighbours) are copied in 16-byte pieces
+    // where a cell splits evenly into them (lane ln moves pieces ln + N^2 r,
+    // in memory order); the z neighbours are read as z-lines, which is the
     // layout their face traces need.
+    const int lnl = act ? ln : 0;
     const T* zc = zero_cell<T>();
     const T* cp = u + (size_t)c * N3;
     const ptrdiff_t sx = N3, sy = (ptrdiff_t)n * N3, sz = (ptrdiff_t)nn * N3;
@@ -369,8 +371,8 @@ __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
     const T* pxh = hx1 ? cp + sx : zc;
     const T* pyl = hy0 ? cp - sy : zc;
     const T* pyh = hy1 ? cp + sy : zc;
-    const T* pzl = (hz0 ? cp - sz : zc) + ln;
-    const T* pzh = (hz1 ? cp + sz : zc) + ln;
+    const T* pzl = (hz0 ? cp - sz : zc) + lnl;
+    const T* pzh = (hz1 ? cp + sz : zc) + lnl;
 #pragma unroll
     for (int a = 0; a < N; ++a) {
       zlo[a] = pzl[a * N2];
@@ -382,7 +384,7 @@ __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
       P16 qo[NP], ql[NP], qh[NP], yl[NP], yh[NP];
 #pragma unroll
       for (int r = 0; r < NP; ++r) {
-        const int o = (ln + N2 * r) * P16::kPer;
+        const int o = (lnl + N2 * r) * P16::kPer;
         qo[r] = P16::load(cp + o);
         ql[r] = P16::load(pxl + o);
         qh[r] = P16::load(pxh + o);
@@ -422,11 +424,11 @@ __global__ __launch_bounds__(kThreads) void apply_wave_kernel(
     } else {
 #pragma unroll
       for (int a = 0; a < N; ++a) {
-        own[a] = cp[ln + a * N2];
-        xlo[a] = pxl[ln + a * N2];
-        xhi[a] = pxh[ln + a * N2];
-        ylo[a] = pyl[ln + a * N2];
-        yhi[a] = pyh[ln + a * N2];
+        own[a] = cp[lnl + a * N2];
+        xlo[a] = pxl[lnl + a * N2];
+        xhi[a] = pxh[lnl + a * N2];
+        ylo[a] = pyl[lnl + a * N2];
+        yhi[a] = pyh[lnl + a * N2];
       }
       // own and x-neighbours: z-lines -> x-lines (j, l) = (lp, lq)
       if (act) {

@@ -78,6 +78,33 @@ def test_apply_full_size(k, n):
     np.testing.assert_allclose(v[rows], samp, rtol=0, atol=1e-12 * np.abs(ref).max())
 
 
+@pytest.mark.parametrize("k,n", [(5, 64), (4, 64)])
+def test_apply_vectors_ending_on_a_page_boundary(k, n):
+    """Regression: the idle lanes of the last workgroup tile (64^3 cells do
+    not fill whole 7- or 10-cell tiles) must load inside one cell.  At k = 5
+    the FP64 vector is exactly 216 x 2 MiB, so a load past its end leaves
+    the allocation.  Apply and residual form, sampled rows including the
+    last cells, against the oracle's row formula."""
+    import torch
+    from paper_2407_09621_amd import Problem
+    announce("apply ending on a page boundary", k, n)
+    P = Problem(k, n, n_levels=1)
+    nd = P.n_dofs()
+    u = inputs.uniform_vector(nd, seed=7 + k)
+    ug = to_gpu(u)
+    v = P.apply(ug)
+    b = torch.ones_like(ug)
+    r = P.residual(b, ug)
+    torch.cuda.synchronize()
+    N3 = (k + 1) ** 3
+    rng = np.random.default_rng(k)
+    rows = np.concatenate([rng.choice(nd, 48, replace=False), np.arange(nd - 2 * N3, nd, 37)])
+    samp = sipg.apply_rows(u, n, k, rows)
+    scale = np.abs(samp).max()
+    np.testing.assert_allclose(to_cpu(v)[rows], samp, rtol=0, atol=1e-12 * scale)
+    np.testing.assert_allclose(to_cpu(r)[rows], 1.0 - samp, rtol=0, atol=1e-12 * scale)
+
+
 @pytest.mark.parametrize("k,n", [(3, 3), (3, 9), (7, 2), (7, 5), (5, 4), (1, 6)])
 def test_apply_units_match_assembled_matrix(k, n):
     """sipg_apply_units: the FP64 vector-unit kernel (every degree) and the
