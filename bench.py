@@ -235,16 +235,16 @@ VCYCLE_BYTES_PER_DOF = {8: 940.0, 4: 470.0}
 def run_vcycles(configs=((3, 64), (5, 32), (7, 32)), reps=5):
     """One V(2,2) from zero (HIP events, mean of `reps`) in FP64, FP32 and
     FP16-EC against the model's bytes per fine DoF (HBM roofline); FP64 and
-    FP32 also with a separate residual launch per smoother colour instead of
-    the fused colour step."""
+    FP32 also with the fused colour step (one launch per smoother colour)
+    instead of a residual launch and the patch solves."""
     import torch
     from paper_2407_09621_amd import Problem, inputs
     out = {}
     for k, n in configs:
         for prec, ec, es, sm in (("f64", 0, 8, "multiplicative"),
-                                 ("f64", 0, 8, "multiplicative_separate"),
+                                 ("f64", 0, 8, "multiplicative_fused"),
                                  ("f32", 0, 4, "multiplicative"),
-                                 ("f32", 0, 4, "multiplicative_separate"),
+                                 ("f32", 0, 4, "multiplicative_fused"),
                                  ("f16", 1, 4, "multiplicative")):
             P = Problem(k, n, mg_precision=prec, error_correction=ec, smoother=sm)
             b = torch.from_numpy(inputs.uniform_vector(P.n_dofs(), 5)).cuda()
@@ -260,7 +260,7 @@ def run_vcycles(configs=((3, 64), (5, 32), (7, 32)), reps=5):
             e1.synchronize()
             ms = e0.elapsed_time(e1) / reps
             model = VCYCLE_BYTES_PER_DOF[es] * P.n_dofs()
-            out[f"k{k}_n{n}_{prec}{'_ec' if ec else ''}{'_separate' if 'sep' in sm else ''}"] = {
+            out[f"k{k}_n{n}_{prec}{'_ec' if ec else ''}{'_fused' if 'fused' in sm else ''}"] = {
                 "ms": round(ms, 4), "model_bytes": model,
                 "model_gb_s": round(model / ms / 1e6, 1),
                 "hbm_frac": round(model / ms / 1e6 / HBM_PEAK_GBS, 4)}
@@ -557,8 +557,10 @@ def main():
     ap.add_argument("--cnn-chains", type=int, default=CNN_CHAINS,
                     help="right-hand sides for the learned stage's training (4 pairs each)")
     ap.add_argument("--mode", choices=["bench", "profile"], default="bench",
-                    help="profile: a few applies per degree and a plain copy of a known size "
-                         "(for rocprofv3 kernel traces and HBM counters)")
+                    help="profile: a few applies per degree (matrix and vector units, "
+                         "patch-wise, FP16/BF16-EC), three k=3 solves, two short training "
+                         "runs, network forwards and a plain copy of a known size (for "
+                         "rocprofv3 kernel traces and counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -610,7 +612,7 @@ def main():
             torch.cuda.synchronize()
             del u32, v32
             print(f"profiled low-precision apply k={k} n={n}: 3 launches each", flush=True)
-        for prec, ec, sm in (("f64", 0, "multiplicative"), ("f64", 0, "multiplicative_separate"),
+        for prec, ec, sm in (("f64", 0, "multiplicative"), ("f64", 0, "multiplicative_fused"),
                              ("f16", 1, "multiplicative")):
             Ps = Problem(3, 32, mg_precision=prec, error_correction=bool(ec), smoother=sm)
             amps, pqr = inputs.single_sine_modes()
@@ -619,6 +621,12 @@ def main():
                   f"{info['iterations']} iterations", flush=True)
             Ps.close()
         from paper_2407_09621_amd import Network
+        Pt = Problem(3, 32)
+        for loss in ("residual", "mse"):
+            tr = Network(seed=1).train(Pt, n_chains=5, chain_length=4, crops_per_pair=8, crop=32,
+                                       lr=1e-3, seed=2, loss=loss)
+            print(f"profiled training k=3 n=32 ({loss} loss): {tr['steps']} pairs", flush=True)
+        Pt.close()
         net = Network(seed=1)
         net.set_params(net.get_params()[0], 1.0)
         g = torch.rand((1, 128, 128, 128), device=dev, dtype=torch.float32)

@@ -75,18 +75,17 @@ typedef struct {
   int nu_pre;            /* pre-smoothing sweeps (2 for V(2,2)) */
   int nu_post;           /* post-smoothing sweeps */
   int smoother;          /* 0: multiplicative vertex-patch smoother (colour by
-                            colour, the paper's choice, Sec. 7.1), each colour
-                            step one fused launch: the new patch values are the
-                            local solve with the right-hand side minus the face
-                            couplings of the outside neighbours, which equals
-                            x_P + inv(A_PP) (b - A x)_P (FP64 / FP32 V-cycles;
-                            FP16 / BF16, and k = 3 in FP64, whose residual and
-                            patch kernels run on the matrix cores, take
-                            form 2); 1: additive (one residual
-                            per sweep, all patch corrections summed and damped;
-                            FP64 V-cycles only); 2: multiplicative with a
-                            separate residual launch per colour (same result to
-                            rounding) */
+                            colour, the paper's choice, Sec. 7.1): per colour a
+                            residual launch, then the patch solves; 1: additive
+                            (one residual per sweep, all patch corrections
+                            summed and damped; FP64 V-cycles only); 2:
+                            multiplicative with one fused launch per colour
+                            step: the new patch values are the local solve
+                            with the right-hand side minus the face couplings
+                            of the outside neighbours, which equals
+                            x_P + inv(A_PP) (b - A x)_P (same result as 0 to
+                            rounding; FP64 / FP32 V-cycles, FP16 / BF16 take
+                            form 0) */
   double damping;        /* additive smoother: x += damping * sum_P corrections
                             (0 means 1/8: every cell lies in 8 patches) */
   double penalty_scale;  /* penalty gamma = penalty_scale * k(k+1)(1/h+ + 1/h-)

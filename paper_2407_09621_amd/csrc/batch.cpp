@@ -121,50 +121,12 @@ sipg_status b_patch(sipg_batch* B, const Vecs& v, const std::vector<Item>& items
   });
 }
 
-// One fused colour step (FP64 / FP32 problems; see sipg_config.smoother):
-// the new patch values go from `in` (X or R of each problem, by `to_r`) to
-// the other vector, and the cells outside the colour's patches are copied.
-sipg_status b_fused_step(sipg_batch* B, const Vecs& v, const std::vector<Item>& items, int colour,
-                         bool to_r, hipStream_t s) {
-  const int prec = B->prec == SIPG_F64 ? 0 : 1;
-  return for_groups(B, items, [&](int N, const Item* it, int cnt) -> sipg_status {
-    PatchJob jobs[kMaxBatch];
-    int m = 0;
-    for (int i = 0; i < cnt; ++i) {
-      const sipg_problem* q = B->P[it[i].p];
-      const int l = it[i].l;
-      if (q->n[l] < 2) continue;
-      void* xv = X(B, v, it[i].p, l);
-      void* rv = R(B, it[i].p, l);
-      const void* in = to_r ? xv : rv;
-      void* out = to_r ? rv : xv;
-      jobs[m++] = PatchJob{in, out, q->n[l], level_h(q, l), Bv(B, v, it[i].p, l)};
-      SIPG_HIP(launch_copy_uncovered(prec, N, colour, in, out, q->n[l], s));
-    }
-    if (m == 0) return SIPG_OK;
-    SIPG_HIP(launch_patch_fd_batch(prec, N, colour, jobs, m, B->P[it[0].p]->tab, s));
-    return SIPG_OK;
-  });
-}
-
 sipg_status b_smooth(sipg_batch* B, const Vecs& v, const std::vector<Item>& items, int sweeps,
                      hipStream_t s) {
-  // degrees whose colour step runs fused (X and R in turn, back in X after
-  // the 8 colours) and degrees that take a residual launch per colour
-  std::vector<Item> fused, split;
-  const int prec = B->prec == SIPG_F64 ? 0 : 1;
-  for (const Item& it : items) {
-    const bool f = (B->prec == SIPG_F64 || B->prec == SIPG_F32) &&
-                   fused_colour_step(prec, B->P[it.p]->N);
-    (f ? fused : split).push_back(it);
-  }
   for (int sw = 0; sw < sweeps; ++sw)
     for (int c = 0; c < 8; ++c) {
-      if (!fused.empty()) SIPG_TRY(b_fused_step(B, v, fused, c, c % 2 == 0, s));
-      if (!split.empty()) {
-        SIPG_TRY(b_residual(B, v, split, s));
-        SIPG_TRY(b_patch(B, v, split, c, s));
-      }
+      SIPG_TRY(b_residual(B, v, items, s));
+      SIPG_TRY(b_patch(B, v, items, c, s));
     }
   return SIPG_OK;
 }

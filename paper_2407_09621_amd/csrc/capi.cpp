@@ -52,8 +52,7 @@ sipg_status smooth(sipg_problem* p, int l, double* x, const double* b, int sweep
     }
     return SIPG_OK;
   }
-  if (p->cfg.smoother == 0 && fused_colour_step(0, p->N)) {
-    // fused colour steps, x and wr[l] in turn (8 per sweep)
+  if (p->cfg.smoother == 2) {  // fused colour steps, x and wr[l] in turn (8 per sweep)
     double* cur = x;
     double* other = p->wr[l];
     for (int sw = 0; sw < sweeps; ++sw)
@@ -98,8 +97,7 @@ sipg_status patch_lp(sipg_problem* p, int l, int colour, const float* r, float* 
 sipg_status smooth_lp(sipg_problem* p, int l, float* x, const float* b, int sweeps,
                       hipStream_t s) {
   if (p->n[l] < 2) return SIPG_OK;
-  if (p->prec == SIPG_F32 && p->cfg.smoother == 0 && fused_colour_step(1, p->N)) {
-    // fused colour steps (see smooth)
+  if (p->prec == SIPG_F32 && p->cfg.smoother == 2) {  // fused colour steps (see smooth)
     float* cur = x;
     float* other = p->fr[l];
     for (int sw = 0; sw < sweeps; ++sw)

@@ -37,14 +37,6 @@ hipError_t launch_patch_fd_f32(int N, int colour, const float* r, float* x, cons
 hipError_t launch_copy_uncovered(int prec, int N, int colour, const void* in, void* out, int n,
                                  hipStream_t s);
 
-// Whether the multiplicative smoother's colour step runs fused (one patch
-// launch with the outside face couplings, then launch_copy_uncovered) or as
-// a residual launch followed by the patch solve.  Both give the same result
-// to rounding; the split form wins where its two kernels run on the matrix
-// cores (N = 4, FP64 vectors: 13 + 14 us per colour at 32^3 cells against
-// 49 us for the fused vector kernel).
-inline bool fused_colour_step(int prec, int N) { return !(prec == 0 && N == 4); }
-
 // Patch-wise evaluation: v_P += (patch operator) u_P for the vertex patches
 // of `colour` (FP64, vector units); summed over the 8 colours v = A u.
 hipError_t launch_patch_apply_f64(int N, int colour, const double* u, double* v, const DevTab& t,

@@ -30,7 +30,7 @@ class SipgError(RuntimeError):
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 DEALLOC_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
-SMOOTHER = {"multiplicative": 0, "additive": 1, "multiplicative_separate": 2}
+SMOOTHER = {"multiplicative": 0, "additive": 1, "multiplicative_fused": 2}
 VARIANT = {"fgmres": 0, "gmres": 1}
 
 

@@ -96,10 +96,10 @@ def test_vcycle_matches(k, n):
 
 @pytest.mark.parametrize("k,n", [(2, 5), (3, 4), (3, 5), (5, 3), (7, 2), (1, 3), (6, 4)])
 def test_fused_and_separate_smoothers_match_oracle(k, n):
-    """Both forms of the multiplicative smoother: the fused colour step
-    (new patch values = local solve of b_P minus the outside neighbours'
-    face couplings, written to a second vector, uncovered layers copied) and
-    the separate residual per colour, against the oracle's sweeps; odd and
+    """Both forms of the multiplicative smoother: the separate residual per
+    colour (the default) and the fused colour step (new patch values = local
+    solve of b_P minus the outside neighbours' face couplings, written to a
+    second vector, uncovered layers copied), against the oracle's sweeps; odd and
     even n (different uncovered layers per colour), n = 2 (colours without
     patches), two sweeps."""
     from paper_2407_09621_amd import Problem
@@ -108,7 +108,7 @@ def test_fused_and_separate_smoothers_match_oracle(k, n):
     b = inputs.uniform_vector(sipg.n_dofs(n, k), 80 + k)
     x0 = inputs.uniform_vector(sipg.n_dofs(n, k), 90 + k)
     ref = multigrid.smooth(lev, x0, b, 2)
-    for form in ("multiplicative", "multiplicative_separate"):
+    for form in ("multiplicative", "multiplicative_fused"):
         P = Problem(k, n, n_levels=1, smoother=form)
         x = to_gpu(x0)
         P.smooth(x, to_gpu(b), 2)
@@ -127,7 +127,7 @@ def test_fused_smoother_in_fp32_vcycle(k, n):
     b = torch.from_numpy(inputs.uniform_vector(sipg.n_dofs(n, k), 11)).cuda()
     x64 = torch.zeros_like(b)
     Problem(k, n).vcycle(x64, b)
-    for form in ("multiplicative", "multiplicative_separate"):
+    for form in ("multiplicative", "multiplicative_fused"):
         x = torch.zeros_like(b)
         Problem(k, n, mg_precision="f32", smoother=form).vcycle(x, b)
         assert rel_l2(to_cpu(x), to_cpu(x64)) < 64 * 2.0 ** -24, form
