@@ -427,8 +427,8 @@ def run_learned(chains=CNN_CHAINS, loss="residual"):
     per pair; loss "residual": what the correction leaves of the post-V-cycle
     residual, on the whole grid; "mse": the pointwise error on 8 random 32^3
     crops), measure on 3 held-out pairs the fraction of the residual the
-    correction leaves (sqrt of the residual loss, no line search) before and
-    after training, then solve held-out right-hand sides (4 sine modes, seeds
+    stage leaves (sqrt of the residual loss, with the stage's own step
+    length) before and after training, then solve held-out right-hand sides (4 sine modes, seeds
     100000..100003) to rtol 1e-10 with and without the stage.  Also times
     the network forward on the full grid (FP16 matrix cores;
     2 x 32 x 32 x 27 x 2 flop per point in each 32 -> 32 layer)."""

@@ -393,10 +393,12 @@ sipg_status sipg_cnn_gradient(sipg_cnn* c, int G, int batch, const float* in,
  * should cancel the residual the V-cycle leaves, and A amplifies the
  * high-frequency part of any pointwise error in e): for the scaled residual
  * rho (device FP64 cell vector of the finest level, e.g. rho / s of a
- * training pair), c = sigma net(grid(rho)) mapped to cells,
- * L = ||rho - A c||^2 / ||rho||^2; grad (device, SIPG_CNN_PARAMS floats) =
- * dL/dparameters through dL/dy = -2 sigma grid(A (rho - A c)) / ||rho||^2;
- * *loss (device float, may be NULL) = L.  sigma must be set (> 0). */
+ * training pair), c = sigma net(grid(rho)) mapped to cells, q = A c, the
+ * stage's own step alpha = (rho . q) / (q . q) (0 if q = 0) and
+ * r = rho - alpha q: L = ||r||^2 / ||rho||^2 (independent of sigma);
+ * grad (device, SIPG_CNN_PARAMS floats) = dL/dparameters through
+ * dL/dy = -2 sigma alpha grid(A r) / ||rho||^2; *loss (device float, may
+ * be NULL) = L.  sigma must be set (> 0). */
 sipg_status sipg_cnn_gradient_residual(sipg_cnn* c, sipg_problem* p, const double* rho,
                                        float* grad, float* loss, hipStream_t stream);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with the
@@ -421,9 +423,9 @@ typedef struct {
   int log_every;       /* read the loss back every this many steps (0: first/last) */
   uint64_t seed;       /* seed of the draws (modes, crop offsets) */
   int loss;            /* 0: masked MSE on the error, on random crops (crop,
-                          crops_per_pair); 1: the residual the correction leaves,
-                          ||rho/s - A c||^2 / ||rho/s||^2 with c = sigma net(rho/s),
-                          on the whole grid (sipg_cnn_gradient_residual) */
+                          crops_per_pair); 1: the residual the correction leaves
+                          after the stage's own step length, on the whole grid
+                          (sipg_cnn_gradient_residual on rho/s) */
 } sipg_cnn_train_opts;
 typedef struct {
   int steps;

@@ -171,20 +171,29 @@ def _backprop(params, acts, gy):
 def residual_loss_and_grads(params, sigma, A, rho_grids, n, k):
     """Residual-aware loss of the stage (a project reading: the stage should
     cancel the post-V-cycle residual, not match the error pointwise, since A
-    amplifies the high-frequency part of any error in e): for scaled
-    residual grids rho_p (input), the correction c_p = sigma net(rho_p)
-    mapped to cells and L = sum_p ||rho_p - A c_p||^2 / sum_p ||rho_p||^2
-    (cell vectors), with its exact gradient: dL/dy_p = -2 sigma
-    grid(A r_p) / sum_p ||rho_p||^2, r_p = rho_p - A c_p (A symmetric),
-    propagated through the network as in loss_and_grads."""
+    amplifies the high-frequency part of any error in e).  For scaled
+    residual grids rho_p (input) the correction c_p = sigma net(rho_p) is
+    mapped to cells, q_p = A c_p, and the loss is what the stage itself
+    leaves, with its own step length alpha_p = (rho_p . q_p) / (q_p . q_p)
+    (0 when q_p = 0), the minimiser of ||rho_p - alpha q_p||:
+        L = sum_p ||r_p||^2 / sum_p ||rho_p||^2,  r_p = rho_p - alpha_p q_p.
+    Gradient: at the minimising alpha the derivative in alpha vanishes, so
+    dL/dq_p = -2 alpha_p r_p / sum ||rho||^2 and, A being symmetric,
+    dL/dy_p = -2 sigma alpha_p grid(A r_p) / sum_p ||rho_p||^2, propagated
+    through the network as in loss_and_grads.  The loss does not depend on
+    sigma (alpha absorbs any scale of the output)."""
     total = float(sum(np.sum(np.asarray(g) ** 2) for g in rho_grids))
     loss = 0.0
     grads = {key: np.zeros_like(v) for key, v in params.items()}
     for g in rho_grids:
         y, acts = forward(params, g)
-        r = grid_to_cells(g, n, k) - A @ (sigma * grid_to_cells(y, n, k))
+        rho = grid_to_cells(g, n, k)
+        q = A @ (sigma * grid_to_cells(y, n, k))
+        qq = float(q @ q)
+        alpha = float(rho @ q) / qq if qq > 0.0 else 0.0
+        r = rho - alpha * q
         loss += float(r @ r) / total
-        gy = (-2.0 * sigma / total) * cells_to_grid(A @ r, n, k)
+        gy = (-2.0 * sigma * alpha / total) * cells_to_grid(A @ r, n, k)
         for name, gg in _backprop(params, acts, gy).items():
             grads[name] += gg
     return loss, grads

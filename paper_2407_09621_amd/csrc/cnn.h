@@ -75,10 +75,12 @@ hipError_t launch_div_scale(const double* v, const double* scale, double* out, i
                             hipStream_t s);
 
 // ---- training -----------------------------------------------------------------
-// Residual loss: sums[0] = rr / pp, sums[1] = sigma pp / (2 S) for the output
-// gradient g4 = -grid(A r) / S (device scalars rr = ||r||^2, pp = ||rho||^2)
-hipError_t launch_residual_sums(const double* rr, const double* pp, const double* S, float sigma,
-                                float* sums, hipStream_t s);
+// Residual loss: sums[0] = rr / pp, sums[1] = sigma pp b / (2 a S) for the
+// output gradient g4 = -grid(A r) / S, r = rho - (a / b) q (device scalars
+// rr = ||r||^2, pp = ||rho||^2, ab = [rho . q, q . q]; sums[1] = 0 when
+// a = 0 or b = 0: no gradient)
+hipError_t launch_residual_sums(const double* rr, const double* pp, const double* S,
+                                const double* ab, float sigma, float* sums, hipStream_t s);
 // Loss L = sum m (sigma y - t)^2 / sum m.  g4 = 2 m (y - t / sigma), which is
 // dL/dy times sum(m) / sigma^2 (kept O(1) for the FP16 backward pass);
 // sums[0] = L, sums[1] = sum m (two-pass, partial holds >= 2 * 1024 floats)

@@ -332,12 +332,14 @@ __global__ __launch_bounds__(kT) void div_scale_kernel(const double* __restrict_
 // (the normalisation that turns the scaled output gradient -grid(A r) / S
 // into dL/dy, see launch_reduce_rows)
 __global__ void residual_sums_kernel(const double* __restrict__ rr, const double* __restrict__ pp,
-                                     const double* __restrict__ S, float sigma,
-                                     float* __restrict__ sums) {
+                                     const double* __restrict__ S, const double* __restrict__ ab,
+                                     float sigma, float* __restrict__ sums) {
   if (threadIdx.x == 0) {
-    const double p = pp[0], sc = S[0];
+    const double p = pp[0], sc = S[0], a = ab[0], b = ab[1];
     sums[0] = p > 0.0 ? (float)(rr[0] / p) : 0.0f;
-    sums[1] = (p > 0.0 && sc > 0.0) ? (float)(sigma * p / (2.0 * sc)) : 1.0f;
+    // gradient factor 2 sigma alpha S / p with alpha = a / b; 0: no gradient
+    sums[1] = (p > 0.0 && sc > 0.0 && a != 0.0 && b > 0.0)
+                  ? (float)(sigma * p * b / (2.0 * a * sc)) : 0.0f;
   }
 }
 
@@ -660,7 +662,7 @@ __global__ __launch_bounds__(kT) void reduce_rows_kernel(const float* __restrict
   float s = 0.0f;
   for (int b = 0; b < kWgradRows; ++b) s += part[(int64_t)b * seg + i];
   const float tot = sums[1];
-  grad[i] = tot > 0.0f ? sigma2 * s / tot : 0.0f;
+  grad[i] = tot != 0.0f ? sigma2 * s / tot : 0.0f;
 }
 
 __global__ __launch_bounds__(kT) void adam_kernel(float* __restrict__ prm, float* __restrict__ m,
@@ -789,9 +791,9 @@ hipError_t launch_div_scale(const double* v, const double* scale, double* out, i
   return hipGetLastError();
 }
 
-hipError_t launch_residual_sums(const double* rr, const double* pp, const double* S, float sigma,
-                                float* sums, hipStream_t s) {
-  hipLaunchKernelGGL(residual_sums_kernel, dim3(1), dim3(64), 0, s, rr, pp, S, sigma, sums);
+hipError_t launch_residual_sums(const double* rr, const double* pp, const double* S,
+                                const double* ab, float sigma, float* sums, hipStream_t s) {
+  hipLaunchKernelGGL(residual_sums_kernel, dim3(1), dim3(64), 0, s, rr, pp, S, ab, sigma, sums);
   return hipGetLastError();
 }
 

@@ -124,10 +124,12 @@ sipg_status backward(sipg_cnn* c, int G, int ns, float* grad, hipStream_t s) {
 }
 
 // Residual-aware loss on the problem's finest level for the scaled residual
-// rho_s (FP64 cell vector): c = sigma net(grid(rho_s)), r = rho_s - A c,
+// rho_s (FP64 cell vector): c = sigma net(grid(rho_s)), q = A c, the stage's
+// step alpha = (rho_s . q) / (q . q), r = rho_s - alpha q,
 // L = ||r||^2 / ||rho_s||^2 into c->sums[0] and dL/dparameters into grad,
-// through dL/dy = -2 sigma grid(A r) / ||rho_s||^2 (A symmetric).  wc, wq:
-// two cell vectors of workspace; p->d_small[440..444] hold device scalars.
+// through dL/dy = -2 sigma alpha grid(A r) / ||rho_s||^2 (A symmetric; the
+// derivative in alpha vanishes at the minimising alpha).  wc, wq: two cell
+// vectors of workspace; p->d_small[440..445] hold device scalars.
 sipg_status residual_backward(sipg_cnn* c, sipg_problem* p, const double* rho_s, double* wc,
                               double* wq, float* grad, hipStream_t s) {
   const int L = p->L - 1;
@@ -138,19 +140,23 @@ sipg_status residual_backward(sipg_cnn* c, sipg_problem* p, const double* rho_s,
   double* rr = p->d_small + 441;
   double* pp = p->d_small + 442;
   double* S = p->d_small + 443;
+  double* ab = p->d_small + 444;  // [rho . q, q . q]
   SIPG_HIP(launch_fill(one, 1.0, 1, s));
   SIPG_HIP(C::launch_gather_f16(rho_s, n, N, one, c->x16, s));
   SIPG_TRY(forward(c, G, 1, nullptr, 0.0f, s));
   SIPG_HIP(launch_fill(wc, 0.0, nd, s));
   SIPG_HIP(C::launch_out_scatter(c->a3, n, N, c->prm, sig, one, wc, s));  // c
-  SIPG_TRY(sipg_apply(p, L, wc, wq, s));                                   // A c
-  SIPG_HIP(launch_axpy(-1.0, rho_s, wq, nd, s));                           // -r
-  SIPG_HIP(launch_mdot(wq, nd, 1, wq, nd, p->d_partial, rr, s));
+  SIPG_TRY(sipg_apply(p, L, wc, wq, s));                                   // q = A c
+  SIPG_HIP(launch_mdot(rho_s, nd, 1, wq, nd, p->d_partial, ab, s));
+  SIPG_HIP(launch_mdot(wq, nd, 1, wq, nd, p->d_partial, ab + 1, s));
+  SIPG_HIP(launch_scale_copy(rho_s, -1.0, wc, nd, s));
+  SIPG_HIP(C::launch_axpy_ratio(ab, ab + 1, wq, wc, nd, s));              // -r = alpha q - rho
+  SIPG_HIP(launch_mdot(wc, nd, 1, wc, nd, p->d_partial, rr, s));
   SIPG_HIP(launch_mdot(rho_s, nd, 1, rho_s, nd, p->d_partial, pp, s));
-  SIPG_TRY(sipg_apply(p, L, wq, wc, s));                                   // -A r
-  SIPG_HIP(C::launch_pow2_absmax(wc, nd, p->d_partial, S, s));
-  SIPG_HIP(C::launch_gather_f32(wc, n, N, S, c->g4, s));                  // -grid(A r) / S
-  SIPG_HIP(C::launch_residual_sums(rr, pp, S, sig, c->sums, s));
+  SIPG_TRY(sipg_apply(p, L, wc, wq, s));                                   // -A r
+  SIPG_HIP(C::launch_pow2_absmax(wq, nd, p->d_partial, S, s));
+  SIPG_HIP(C::launch_gather_f32(wq, n, N, S, c->g4, s));                  // -grid(A r) / S
+  SIPG_HIP(C::launch_residual_sums(rr, pp, S, ab, sig, c->sums, s));
   return backward_from_output(c, G, 1, grad, s);
 }
 

@@ -574,8 +574,8 @@ class Network:
 
     def gradient_residual(self, problem, rho, stream=None):
         """(gradient tensor [n_params], loss) of the residual-aware loss
-        ||rho - A c||^2 / ||rho||^2, c = sigma net(rho), on the problem's
-        finest level (rho: FP64 cell vector)."""
+        min_alpha ||rho - alpha A c||^2 / ||rho||^2, c = sigma net(rho), on the
+        problem's finest level (rho: FP64 cell vector)."""
         import torch
         grad = torch.empty(self.n_params, dtype=torch.float32, device=rho.device)
         loss = torch.empty(1, dtype=torch.float32, device=rho.device)

@@ -244,10 +244,11 @@ def test_fallback_on_stagnation_and_non_finite():
 
 
 def test_residual_loss_gradients_match_central_differences():
-    """The residual-aware loss ||rho - A c||^2 / ||rho||^2 (c = sigma net(rho)
-    in cells, A the SIPG operator of a 2^3 mesh of degree 1, 4^3 grid):
-    every sampled parameter's exact gradient against central differences,
-    and the loss against its definition written out."""
+    """The residual-aware loss min_alpha ||rho - alpha A c||^2 / ||rho||^2
+    (c = sigma net(rho) in cells, A the SIPG operator of a 2^3 mesh of
+    degree 1, 4^3 grid): every sampled parameter's exact gradient against
+    central differences, and the loss against a brute-force minimisation
+    over alpha."""
     C, n, k, sigma = 3, 2, 1, 0.25
     rng = np.random.default_rng(5)
     params = _tiny_net(C, 6)
@@ -255,13 +256,20 @@ def test_residual_loss_gradients_match_central_differences():
     G = n * (k + 1)
     rhos = [rng.standard_normal((G, G, G)) for _ in range(2)]
     loss, grads = L.residual_loss_and_grads(params, sigma, A, rhos, n, k)
+    from scipy.optimize import minimize_scalar
     num = 0.0
     for g in rhos:
         c = sigma * L.grid_to_cells(L.forward(params, g)[0], n, k)
-        r = L.grid_to_cells(g, n, k) - A @ c
-        num += float(r @ r)
+        rho = L.grid_to_cells(g, n, k)
+        q = A @ c
+        best = minimize_scalar(lambda a: float(np.sum((rho - a * q) ** 2)),
+                               bracket=(-10.0, 10.0), tol=1e-12)
+        num += best.fun
     den = sum(float(np.sum(g * g)) for g in rhos)
-    assert abs(loss - num / den) < 1e-14 * max(1.0, loss)
+    assert abs(loss - num / den) < 1e-10 * max(1.0, loss)
+    # no dependence on the output scale: alpha absorbs it
+    assert abs(L.residual_loss_and_grads(params, 4.0 * sigma, A, rhos, n, k)[0] - loss) \
+        < 1e-13 * max(1.0, loss)
     flat, gflat = L.flatten(params), L.flatten(grads)
 
     def f(th):
@@ -278,7 +286,8 @@ def test_residual_loss_gradients_match_central_differences():
 def test_residual_loss_is_zero_for_the_exact_correction():
     """A network whose output is the exact error A^{-1} rho (a linear map, here
     emulated by a zero network plus the closed form) leaves no residual: the
-    loss of c = A^{-1} rho is 0 and of c = 0 is 1."""
+    loss of c = A^{-1} rho is 0 (the step length is 1) and of c = 0 is 1
+    (q = 0: step length 0)."""
     n, k = 2, 1
     A = sipg.assemble(n, k).toarray()
     rho = np.random.default_rng(1).standard_normal(A.shape[0])
