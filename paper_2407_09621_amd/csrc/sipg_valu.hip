@@ -175,6 +175,54 @@ __device__ __forceinline__ void matvec_rows_t(const T* __restrict__ A, const T (
   }
 }
 
+// Patch transforms of the interior patch type in even-odd form: YE, YO are
+// H x H (H = G/2; row = node a < H, column = eigenvector, 1/sqrt 2 folded
+// in).  Forward c = S^T x with c = [even eigen-indices, odd ones], from
+// e = x_a + x_{G-1-a} and o = x_a - x_{G-1-a}; backward x = S c, with
+// x_a = (YE c_E)_a + (YO c_O)_a and x_{G-1-a} = (YE c_E)_a - (YO c_O)_a.
+// 2 H^2 products instead of G^2; one row per scheduling region as in
+// matvec_rows (the matrices are in LDS).
+template <int G, typename T>
+__device__ __forceinline__ void fd_fwd_eo(const T* __restrict__ YE, const T* __restrict__ YO,
+                                          const T (&x)[G], T (&y)[G]) {
+  constexpr int H = G / 2;
+  T e[H], o[H];
+#pragma unroll
+  for (int a = 0; a < H; ++a) {
+    e[a] = x[a] + x[G - 1 - a];
+    o[a] = x[a] - x[G - 1 - a];
+  }
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+    T se = 0, so = 0;
+#pragma unroll
+    for (int a = 0; a < H; ++a) {
+      se = fma(YE[a * H + k], e[a], se);
+      so = fma(YO[a * H + k], o[a], so);
+    }
+    y[k] = se;
+    y[H + k] = so;
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+template <int G, typename T>
+__device__ __forceinline__ void fd_bwd_eo(const T* __restrict__ YE, const T* __restrict__ YO,
+                                          const T (&c)[G], T (&x)[G]) {
+  constexpr int H = G / 2;
+#pragma unroll
+  for (int a = 0; a < H; ++a) {
+    T ye = 0, yo = 0;
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      ye = fma(YE[a * H + k], c[k], ye);
+      yo = fma(YO[a * H + k], c[H + k], yo);
+    }
+    x[a] = ye + yo;
+    x[G - 1 - a] = ye - yo;
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 // Face coupling to the lower neighbour (its high-end value f and derivative
 // g = d1 . u) and to the upper neighbour (low-end value f, g = d0 . u).
 template <int N, typename T>
@@ -658,6 +706,8 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
   constexpr int PPB = (kThreads / G2) > 0 ? kThreads / G2 : 1;
   __shared__ T s_S[4 * G2];
   __shared__ T s_l[4 * G];
+  // interior type in even-odd form: YE, YO [G/2 x G/2], lamE, lamO
+  __shared__ T s_eo[G2 / 2 + G];
   __shared__ T s_X[PPB * G3];
   // face traces [patch][face 2 d + side][value, derivative][G2] and the
   // face tables d0, d1, mass
@@ -676,6 +726,9 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
   if (np <= 0) return;
   for (int i = tid; i < 4 * G2; i += kThreads) s_S[i] = tab[lay.fd_s + i];
   for (int i = tid; i < 4 * G; i += kThreads) s_l[i] = tab[lay.fd_l + i];
+  const bool eo_ok = lay.fd_eo_ok != 0;
+  if (eo_ok)
+    for (int i = tid; i < G2 / 2 + G; i += kThreads) s_eo[i] = tab[lay.fd_eo + i];
   if constexpr (FUSED) {
     for (int i = tid; i < N; i += kThreads) {
       s_fd[i] = tab[lay.d0 + i];
@@ -834,12 +887,22 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
   const int la = ln % G, lb = ln / G;
   // offsets of line ln in direction d: start and stride
   const int o0 = la * G + lb * G2, o1 = la + lb * G2, o2 = la + lb * G;
+  // interior directions (type 0) in even-odd form when the table has it;
+  // their eigen-indices then run [even, odd] and so do their eigenvalues
+  constexpr int HH = (G / 2) * (G / 2);
+  const T* s_YE = s_eo;
+  const T* s_YO = s_eo + HH;
+  const bool ex = eo_ok && tx == 0, ey = eo_ok && ty == 0, ez = eo_ok && tz == 0;
+  const T* lx = ex ? s_eo + 2 * HH : s_l + tx * G;
+  const T* ly = ey ? s_eo + 2 * HH : s_l + ty * G;
+  const T* lz = ez ? s_eo + 2 * HH : s_l + tz * G;
   T in[G], out[G];
   // forward: S^T along x, y, z
   if (act) {
 #pragma unroll
     for (int a = 0; a < G; ++a) in[a] = X[o0 + a];
-    matvec_rows_t<G>(s_S + tx * G2, in, out);
+    if (ex) fd_fwd_eo<G>(s_YE, s_YO, in, out);
+    else matvec_rows_t<G>(s_S + tx * G2, in, out);
 #pragma unroll
     for (int a = 0; a < G; ++a) X[o0 + a] = out[a];
   }
@@ -847,7 +910,8 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
   if (act) {
 #pragma unroll
     for (int a = 0; a < G; ++a) in[a] = X[o1 + a * G];
-    matvec_rows_t<G>(s_S + ty * G2, in, out);
+    if (ey) fd_fwd_eo<G>(s_YE, s_YO, in, out);
+    else matvec_rows_t<G>(s_S + ty * G2, in, out);
 #pragma unroll
     for (int a = 0; a < G; ++a) X[o1 + a * G] = out[a];
   }
@@ -855,12 +919,14 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
   if (act) {
 #pragma unroll
     for (int a = 0; a < G; ++a) in[a] = X[o2 + a * G2];
-    matvec_rows_t<G>(s_S + tz * G2, in, out);
+    if (ez) fd_fwd_eo<G>(s_YE, s_YO, in, out);
+    else matvec_rows_t<G>(s_S + tz * G2, in, out);
     // eigenvalue scaling: line (la, lb) = (i', j'), running over l'
-    const T lij = s_l[tx * G + la] + s_l[ty * G + lb];
+    const T lij = lx[la] + ly[lb];
 #pragma unroll
-    for (int a = 0; a < G; ++a) in[a] = out[a] / (h * (lij + s_l[tz * G + a]));
-    matvec_rows<G>(s_S + tz * G2, in, out);
+    for (int a = 0; a < G; ++a) in[a] = out[a] / (h * (lij + lz[a]));
+    if (ez) fd_bwd_eo<G>(s_YE, s_YO, in, out);
+    else matvec_rows<G>(s_S + tz * G2, in, out);
 #pragma unroll
     for (int a = 0; a < G; ++a) X[o2 + a * G2] = out[a];
   }
@@ -868,7 +934,8 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
   if (act) {
 #pragma unroll
     for (int a = 0; a < G; ++a) in[a] = X[o1 + a * G];
-    matvec_rows<G>(s_S + ty * G2, in, out);
+    if (ey) fd_bwd_eo<G>(s_YE, s_YO, in, out);
+    else matvec_rows<G>(s_S + ty * G2, in, out);
 #pragma unroll
     for (int a = 0; a < G; ++a) X[o1 + a * G] = out[a];
   }
@@ -876,7 +943,8 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
   if (act) {
 #pragma unroll
     for (int a = 0; a < G; ++a) in[a] = X[o0 + a];
-    matvec_rows<G>(s_S + tx * G2, in, out);
+    if (ex) fd_bwd_eo<G>(s_YE, s_YO, in, out);
+    else matvec_rows<G>(s_S + tx * G2, in, out);
 #pragma unroll
     for (int a = 0; a < G; ++a) X[o0 + a] = out[a];
   }

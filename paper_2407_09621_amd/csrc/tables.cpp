@@ -433,6 +433,43 @@ void window_matrices(const Tables1D& t, double* out) {
   }
 }
 
+// Even-odd form of the fast diagonalization of a G x G patch pencil (L, M)
+// that is symmetric under the reversal J of its G nodes: the eigenvectors
+// split into J-even ones, s = P y with P = [I; J] / sqrt 2, and J-odd ones,
+// s = Q y with Q = [I; -J] / sqrt 2, where y solves the H x H pencil
+// (P^T L P, P^T M P) (entries L[a][b] + L[a][G-1-b]) or (Q^T L Q, Q^T M Q)
+// (L[a][b] - L[a][G-1-b]).  Stores YE / sqrt 2, YO / sqrt 2, lamE, lamO.
+// Returns false when the pencil is not reversal-symmetric (to 1e-12).
+bool fd_even_odd(int G, const std::vector<double>& Lm, const std::vector<double>& Mm,
+                 double* out) {
+  const int H = G / 2;
+  double scale = 0.0;
+  for (double v : Lm) scale = std::max(scale, std::fabs(v));
+  for (int i = 0; i < G; ++i)
+    for (int j = 0; j < G; ++j) {
+      const int ri = G - 1 - i, rj = G - 1 - j;
+      if (std::fabs(Lm[ri * G + rj] - Lm[i * G + j]) > 1e-12 * scale ||
+          std::fabs(Mm[ri * G + rj] - Mm[i * G + j]) > 1e-12)
+        return false;
+    }
+  std::vector<double> LE(H * H), ME(H * H), LO(H * H), MO(H * H), Y, lam;
+  for (int a = 0; a < H; ++a)
+    for (int b = 0; b < H; ++b) {
+      LE[a * H + b] = Lm[a * G + b] + Lm[a * G + G - 1 - b];
+      LO[a * H + b] = Lm[a * G + b] - Lm[a * G + G - 1 - b];
+      ME[a * H + b] = Mm[a * G + b] + Mm[a * G + G - 1 - b];
+      MO[a * H + b] = Mm[a * G + b] - Mm[a * G + G - 1 - b];
+    }
+  const double r2 = 1.0 / std::sqrt(2.0);
+  if (!generalized_eig(H, LE, ME, Y, lam)) return false;
+  for (int i = 0; i < H * H; ++i) out[i] = Y[i] * r2;
+  for (int i = 0; i < H; ++i) out[2 * H * H + i] = lam[i];
+  if (!generalized_eig(H, LO, MO, Y, lam)) return false;
+  for (int i = 0; i < H * H; ++i) out[H * H + i] = Y[i] * r2;
+  for (int i = 0; i < H; ++i) out[2 * H * H + H + i] = lam[i];
+  return true;
+}
+
 std::vector<double> build_device_table(int k, int n0, TableLayout& lay, double penalty_scale) {
   Tables1D t = make_tables_1d(k, penalty_scale);
   const int N = t.N, G = 2 * N, Gc = (n0 >= 1 && n0 <= 3) ? n0 * N : 0;
@@ -455,6 +492,7 @@ std::vector<double> build_device_table(int k, int n0, TableLayout& lay, double p
   lay.lr = take(N * N);
   lay.rl = take(N * N);
   lay.eo = take(N == 8 ? 12 * 16 : 0);
+  lay.fd_eo = take(2 * (G / 2) * (G / 2) + G);
   lay.pw_l = take(4 * G * G);
   lay.sym = take(2 * (((N + 1) / 2) * ((N + 1) / 2) + (N / 2) * (N / 2)));
   lay.total = off;
@@ -477,6 +515,7 @@ std::vector<double> build_device_table(int k, int n0, TableLayout& lay, double p
     if (!generalized_eig(G, Lm, Mm, S, lam)) throw std::runtime_error("patch mass not SPD");
     for (int i = 0; i < G * G; ++i) tab[lay.fd_s + type * G * G + i] = S[i];
     for (int i = 0; i < G; ++i) tab[lay.fd_l + type * G + i] = lam[i];
+    if (type == 0) lay.fd_eo_ok = fd_even_odd(G, Lm, Mm, &tab[lay.fd_eo]) ? 1 : 0;
   }
   if (Gc > 0) {  // exact coarse solve only for 1, 2 or 3 coarse cells per direction
     line_matrices(t, n0, true, true, Lm, Mm);

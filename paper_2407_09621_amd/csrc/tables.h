@@ -35,6 +35,11 @@ struct TableLayout {
   int eo_ok = 0;
   int sym = 0;    // even-odd half-blocks of Mh and of the interior Lh block:
                   // ME [PE x PE], MO [P x P], LE, LO (P = N/2, PE = (N+1)/2)
+  int fd_eo = 0;  // patch fast diagonalization of the interior type 0 in even-odd form
+                  // (H = G/2): YE, YO [H x H] (row = node a < H, column = eigenvector,
+                  // scaled by 1/sqrt 2), lamE [H], lamO [H]; fd_eo_ok = 1 when the
+                  // type-0 patch matrices are symmetric under reversal
+  int fd_eo_ok = 0;
   int pw_l = 0;   // patch-wise evaluation: window stiffness-plus-face matrices [4][G x G]
                   // by window type (bit0: lower cell first of the line, bit1: upper
                   // cell last); the window mass is the cell mass times 1/2 or 1

@@ -58,7 +58,8 @@ extern "C" int shim_even_odd(int k, double pen, double* out) {
   std::memcpy(out, t.data() + L.eo, 12 * 16 * sizeof(double)); return L.eo_ok; }
 extern "C" void shim_extra(int k, int n0, int* out) {
   TableLayout L; build_device_table(k, n0, L);
-  out[0] = L.eo; out[1] = L.eo_ok; out[2] = L.pw_l; out[3] = L.sym; }
+  out[0] = L.eo; out[1] = L.eo_ok; out[2] = L.pw_l; out[3] = L.sym; out[4] = L.fd_eo;
+  out[5] = L.fd_eo_ok; }
 extern "C" void shim_offdiag(int k, double* lr, double* rl) {
   Tables1D t = make_tables_1d(k);
   std::memcpy(lr, t.lr.data(), t.lr.size() * 8); std::memcpy(rl, t.rl.data(), t.rl.size() * 8); }
@@ -90,9 +91,9 @@ def host_tables(tmp_path_factory):
         lib.shim_offdiag(k, lr.ctypes.data_as(ctypes.c_void_p), rl.ctypes.data_as(ctypes.c_void_p))
         return L, buf, lr.reshape(N, N), rl.reshape(N, N)
     def extra(k, n0=2):
-        out = (ctypes.c_int * 4)()
+        out = (ctypes.c_int * 6)()
         lib.shim_extra(k, n0, out)
-        return dict(zip(["eo", "eo_ok", "pw_l", "sym"], list(out)))
+        return dict(zip(["eo", "eo_ok", "pw_l", "sym", "fd_eo", "fd_eo_ok"], list(out)))
     get.lib = lib
     get.layout_extra = extra
     return get
@@ -148,6 +149,38 @@ def test_host_fast_diagonalization_pairs(host_tables, k):
         lam = t[L["fdc_l"]:L["fdc_l"] + Gc]
         np.testing.assert_allclose(S.T @ (M * n0) @ S, np.eye(Gc), atol=1e-9)
         np.testing.assert_allclose(S.T @ (Lg / n0) @ S, np.diag(lam), atol=1e-9 * np.abs(lam).max())
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7])
+def test_host_even_odd_patch_diagonalization(host_tables, k):
+    """The interior patch type in even-odd form: the eigenvectors rebuilt
+    from YE, YO (s = [y; J y] / sqrt 2 and [y; -J y] / sqrt 2) diagonalise
+    the oracle's interior patch pencil, S^T M_P S = I and
+    S^T L_P S = diag(lamE, lamO), and the even-odd patch inverse
+    S diag(1/lam) S^T equals L_P^{-1}."""
+    from oracle import sipg as osipg
+    L, t, _, _ = host_tables(k)
+    X = host_tables.layout_extra(k)
+    assert X["fd_eo_ok"] == 1
+    N = k + 1
+    G, H = 2 * N, N
+    n = 4
+    M, Lg = osipg.global_1d(n, k)
+    sl = slice(N, 3 * N)  # cells 1 and 2 of 4: both faces interior
+    Mp, Lp = M[sl, sl] * n, Lg[sl, sl] / n
+    o = X["fd_eo"]
+    YE = t[o:o + H * H].reshape(H, H)
+    YO = t[o + H * H:o + 2 * H * H].reshape(H, H)
+    lam = t[o + 2 * H * H:o + 2 * H * H + G]
+    J = np.eye(H)[::-1]
+    S = np.zeros((G, G))
+    S[:H, :H], S[H:, :H] = YE, J @ YE
+    S[:H, H:], S[H:, H:] = YO, -J @ YO
+    np.testing.assert_allclose(S.T @ Mp @ S, np.eye(G), atol=1e-9)
+    np.testing.assert_allclose(S.T @ Lp @ S, np.diag(lam), atol=1e-9 * np.abs(lam).max())
+    Linv = np.linalg.inv(Lp)
+    np.testing.assert_allclose(S @ np.diag(1.0 / lam) @ S.T, Linv,
+                               atol=1e-9 * np.abs(Linv).max())
 
 
 @pytest.mark.parametrize("k", [1, 3, 6])
