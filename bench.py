@@ -558,7 +558,8 @@ def main():
                     help="right-hand sides for the learned stage's training (4 pairs each)")
     ap.add_argument("--mode", choices=["bench", "profile"], default="bench",
                     help="profile: a few applies per degree (matrix and vector units, "
-                         "patch-wise, FP16/BF16-EC), three k=3 solves, two short training "
+                         "patch-wise, FP16/BF16-EC), three k=3 solves, V-cycles of k=5 and 7, "
+                         "two short training "
                          "runs, network forwards and a plain copy of a known size (for "
                          "rocprofv3 kernel traces and counters)")
     args = ap.parse_args()
@@ -620,6 +621,18 @@ def main():
             print(f"profiled solve k=3 n=32 {prec}{'_ec' if ec else ''} {sm}: "
                   f"{info['iterations']} iterations", flush=True)
             Ps.close()
+        for kv in (5, 7):  # V(2,2) cycles of the vector-unit patch solves
+            for prec in ("f64", "f32"):
+                Pv = Problem(kv, 32, mg_precision=prec)
+                bv = torch.from_numpy(inputs.uniform_vector(Pv.n_dofs(), 5)).to(dev)
+                xv = torch.zeros_like(bv)
+                for _ in range(2):
+                    xv.zero_()
+                    Pv.vcycle(xv, bv)
+                torch.cuda.synchronize()
+                print(f"profiled V-cycles k={kv} n=32 {prec}: 2", flush=True)
+                Pv.close()
+                del bv, xv
         from paper_2407_09621_amd import Network
         Pt = Problem(3, 32)
         for loss in ("residual", "mse"):

@@ -767,8 +767,10 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
     s_cb[q] = (vx - 1) + n * (vy - 1) + nn * (vz - 1);
   }
   __syncthreads();
-  // gather r_P (fused: b_P)
+  // gather b_P (fused form; the plain form reads r_P line by line in the
+  // first transform below)
   const T* __restrict__ src = FUSED ? B.d[pb].aux : r;
+  if constexpr (FUSED)
   for (int w = w_first; w < w_hi; w += w_step) {
     const int pl = w / G3, rr = w - pl * G3;
     const int cell8 = rr / N3, loc = rr - cell8 * N3;
@@ -897,10 +899,24 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
   const T* ly = ey ? s_eo + 2 * HH : s_l + ty * G;
   const T* lz = ez ? s_eo + 2 * HH : s_l + tz * G;
   T in[G], out[G];
+  // x-line (j', l') = (la, lb) of the patch in global memory: the matching
+  // x-lines of the cells dx = 0 and dx = 1 (N contiguous values each)
+  const int ldy = la / N, lj = la - ldy * N, ldz = lb / N, ll = lb - ldz * N;
+  const size_t line0 =
+      (size_t)(s_cb[pl] + n * ldy + nn * ldz) * N3 + (size_t)(lj * N + ll * N2);
   // forward: S^T along x, y, z
   if (act) {
+    if constexpr (FUSED) {
 #pragma unroll
-    for (int a = 0; a < G; ++a) in[a] = X[o0 + a];
+      for (int a = 0; a < G; ++a) in[a] = X[o0 + a];
+    } else {  // straight from r: the gather of the plain form
+      const T* r0 = r + line0;
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        in[a] = r0[a];
+        in[N + a] = r0[N3 + a];
+      }
+    }
     if (ex) fd_fwd_eo<G>(s_YE, s_YO, in, out);
     else matvec_rows_t<G>(s_S + tx * G2, in, out);
 #pragma unroll
@@ -945,11 +961,21 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
     for (int a = 0; a < G; ++a) in[a] = X[o0 + a];
     if (ex) fd_bwd_eo<G>(s_YE, s_YO, in, out);
     else matvec_rows<G>(s_S + tx * G2, in, out);
+    if constexpr (FUSED) {
 #pragma unroll
-    for (int a = 0; a < G; ++a) X[o0 + a] = out[a];
+      for (int a = 0; a < G; ++a) X[o0 + a] = out[a];
+    } else {  // add the correction to x line by line (patches of a colour are disjoint)
+      T* x0 = x + line0;
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        x0[a] += out[a];
+        x0[N3 + a] += out[N + a];
+      }
+    }
   }
+  if constexpr (!FUSED) return;
   psync();
-  // scatter-add into x (fused: the new values, stored)
+  // fused form: store the new values
   for (int w = w_first; w < w_hi; w += w_step) {
     const int q = w / G3, rr = w - q * G3;
     const int cell8 = rr / N3, loc = rr - cell8 * N3;
