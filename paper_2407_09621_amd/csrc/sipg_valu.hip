@@ -704,10 +704,16 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
     Batch<T> B, const T* __restrict__ tab, TableLayout lay, int bx, int by, int bz) {
   constexpr int G = 2 * N, G2 = G * G, G3 = G2 * G, N2 = N * N, N3 = N2 * N;
   constexpr int PPB = (kThreads / G2) > 0 ? kThreads / G2 : 1;
-  __shared__ T s_S[4 * G2];
-  __shared__ T s_l[4 * G];
-  // interior type in even-odd form: YE, YO [G/2 x G/2], lamE, lamO
-  __shared__ T s_eo[G2 / 2 + G];
+  // One patch per workgroup (N >= 6): only the three matrices of its
+  // direction types are staged, which keeps N = 8 in FP64 under 40 KB of LDS
+  // (four workgroups per CU).  Several patches: all four types.
+  constexpr bool ONE = PPB == 1;
+  constexpr int NS = ONE ? 3 : 4;
+  __shared__ T s_S[NS * G2];
+  // eigenvalues by type, then those of the interior type in even-odd order
+  __shared__ T s_l[5 * G];
+  // interior type in even-odd form: YE, YO [G/2 x G/2]
+  __shared__ T s_eo[G2 / 2];
   __shared__ T s_X[PPB * G3];
   // face traces [patch][face 2 d + side][value, derivative][G2] and the
   // face tables d0, d1, mass
@@ -724,11 +730,35 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
   const int p0 = (bi - B.start[pb]) * PPB;
   const int np = min(PPB, npatch - p0);
   if (np <= 0) return;
-  for (int i = tid; i < 4 * G2; i += kThreads) s_S[i] = tab[lay.fd_s + i];
+  const int nn = n * n;
+  // vertex of a patch and its first cell
+  auto vertex = [&](int pl, int& vx, int& vy, int& vz) {
+    const int p = p0 + pl;
+    const int px = p % npx, py = (p / npx) % npy, pz = p / (npx * npy);
+    vx = 2 * px + (bx ? 1 : 2);
+    vy = 2 * py + (by ? 1 : 2);
+    vz = 2 * pz + (bz ? 1 : 2);
+  };
+  auto vtype = [&](int v) { return (v == 1 ? 1 : 0) | (v == n - 1 ? 2 : 0); };
+  int ts[3] = {0, 1, 2};
+  if constexpr (ONE) {
+    int vx, vy, vz;
+    vertex(0, vx, vy, vz);
+    ts[0] = vtype(vx);
+    ts[1] = vtype(vy);
+    ts[2] = vtype(vz);
+  }
+  for (int i = tid; i < NS * G2; i += kThreads) {
+    const int d = i / G2, e = i - d * G2;
+    s_S[i] = tab[lay.fd_s + (ONE ? ts[d] : d) * G2 + e];
+  }
   for (int i = tid; i < 4 * G; i += kThreads) s_l[i] = tab[lay.fd_l + i];
   const bool eo_ok = lay.fd_eo_ok != 0;
-  if (eo_ok)
-    for (int i = tid; i < G2 / 2 + G; i += kThreads) s_eo[i] = tab[lay.fd_eo + i];
+  constexpr int HH = (G / 2) * (G / 2);
+  if (eo_ok) {
+    for (int i = tid; i < 2 * HH; i += kThreads) s_eo[i] = tab[lay.fd_eo + i];
+    for (int i = tid; i < G; i += kThreads) s_l[4 * G + i] = tab[lay.fd_eo + 2 * HH + i];
+  }
   if constexpr (FUSED) {
     for (int i = tid; i < N; i += kThreads) {
       s_fd[i] = tab[lay.d0 + i];
@@ -749,15 +779,6 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
   const int w_hi = WL ? min(np * G3, w_lo + (G2 <= 64 ? 64 / G2 : 1) * G3) : np * G3;
   const int w_first = WL ? w_lo + lane : tid, w_step = WL ? 64 : kThreads;
 
-  // vertex of a patch and its first cell
-  auto vertex = [&](int pl, int& vx, int& vy, int& vz) {
-    const int p = p0 + pl;
-    const int px = p % npx, py = (p / npx) % npy, pz = p / (npx * npy);
-    vx = 2 * px + (bx ? 1 : 2);
-    vy = 2 * py + (by ? 1 : 2);
-    vz = 2 * pz + (bz ? 1 : 2);
-  };
-  const int nn = n * n;
   // first cell of each patch of the block, computed once per patch (the
   // gather and scatter loops below then divide only by compile-time sizes)
   __shared__ int s_cb[PPB];
@@ -882,22 +903,22 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
   const int pl = act ? tid / G2 : 0, ln = tid - pl * G2;
   int vx = 1, vy = 1, vz = 1;
   if (act) vertex(pl, vx, vy, vz);
-  const int tx = (vx == 1 ? 1 : 0) | (vx == n - 1 ? 2 : 0);
-  const int ty = (vy == 1 ? 1 : 0) | (vy == n - 1 ? 2 : 0);
-  const int tz = (vz == 1 ? 1 : 0) | (vz == n - 1 ? 2 : 0);
+  const int tx = vtype(vx), ty = vtype(vy), tz = vtype(vz);
+  const T* Sx = s_S + (ONE ? 0 : tx) * G2;
+  const T* Sy = s_S + (ONE ? 1 : ty) * G2;
+  const T* Sz = s_S + (ONE ? 2 : tz) * G2;
   T* X = s_X + pl * G3;
   const int la = ln % G, lb = ln / G;
   // offsets of line ln in direction d: start and stride
   const int o0 = la * G + lb * G2, o1 = la + lb * G2, o2 = la + lb * G;
   // interior directions (type 0) in even-odd form when the table has it;
   // their eigen-indices then run [even, odd] and so do their eigenvalues
-  constexpr int HH = (G / 2) * (G / 2);
   const T* s_YE = s_eo;
   const T* s_YO = s_eo + HH;
   const bool ex = eo_ok && tx == 0, ey = eo_ok && ty == 0, ez = eo_ok && tz == 0;
-  const T* lx = ex ? s_eo + 2 * HH : s_l + tx * G;
-  const T* ly = ey ? s_eo + 2 * HH : s_l + ty * G;
-  const T* lz = ez ? s_eo + 2 * HH : s_l + tz * G;
+  const T* lx = s_l + (ex ? 4 : tx) * G;
+  const T* ly = s_l + (ey ? 4 : ty) * G;
+  const T* lz = s_l + (ez ? 4 : tz) * G;
   T in[G], out[G];
   // x-line (j', l') = (la, lb) of the patch in global memory: the matching
   // x-lines of the cells dx = 0 and dx = 1 (N contiguous values each)
@@ -918,7 +939,7 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
       }
     }
     if (ex) fd_fwd_eo<G>(s_YE, s_YO, in, out);
-    else matvec_rows_t<G>(s_S + tx * G2, in, out);
+    else matvec_rows_t<G>(Sx, in, out);
 #pragma unroll
     for (int a = 0; a < G; ++a) X[o0 + a] = out[a];
   }
@@ -927,7 +948,7 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
 #pragma unroll
     for (int a = 0; a < G; ++a) in[a] = X[o1 + a * G];
     if (ey) fd_fwd_eo<G>(s_YE, s_YO, in, out);
-    else matvec_rows_t<G>(s_S + ty * G2, in, out);
+    else matvec_rows_t<G>(Sy, in, out);
 #pragma unroll
     for (int a = 0; a < G; ++a) X[o1 + a * G] = out[a];
   }
@@ -936,13 +957,13 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
 #pragma unroll
     for (int a = 0; a < G; ++a) in[a] = X[o2 + a * G2];
     if (ez) fd_fwd_eo<G>(s_YE, s_YO, in, out);
-    else matvec_rows_t<G>(s_S + tz * G2, in, out);
+    else matvec_rows_t<G>(Sz, in, out);
     // eigenvalue scaling: line (la, lb) = (i', j'), running over l'
     const T lij = lx[la] + ly[lb];
 #pragma unroll
     for (int a = 0; a < G; ++a) in[a] = out[a] / (h * (lij + lz[a]));
     if (ez) fd_bwd_eo<G>(s_YE, s_YO, in, out);
-    else matvec_rows<G>(s_S + tz * G2, in, out);
+    else matvec_rows<G>(Sz, in, out);
 #pragma unroll
     for (int a = 0; a < G; ++a) X[o2 + a * G2] = out[a];
   }
@@ -951,7 +972,7 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
 #pragma unroll
     for (int a = 0; a < G; ++a) in[a] = X[o1 + a * G];
     if (ey) fd_bwd_eo<G>(s_YE, s_YO, in, out);
-    else matvec_rows<G>(s_S + ty * G2, in, out);
+    else matvec_rows<G>(Sy, in, out);
 #pragma unroll
     for (int a = 0; a < G; ++a) X[o1 + a * G] = out[a];
   }
@@ -960,7 +981,7 @@ __global__ __launch_bounds__(kThreads) void patch_fd_kernel(
 #pragma unroll
     for (int a = 0; a < G; ++a) in[a] = X[o0 + a];
     if (ex) fd_bwd_eo<G>(s_YE, s_YO, in, out);
-    else matvec_rows<G>(s_S + tx * G2, in, out);
+    else matvec_rows<G>(Sx, in, out);
     if constexpr (FUSED) {
 #pragma unroll
       for (int a = 0; a < G; ++a) X[o0 + a] = out[a];
