@@ -16,6 +16,9 @@ Tensor-Product Operations with Tensor Cores", arXiv 2407.09621, it follows):
                   the bilinear form (Sec. 2, eq. bilinear_form), and a second,
                   independent derivation through the Kronecker-sum identity on
                   Cartesian meshes (Sec. 2.1, eq. tensorproduct_3d).
+* ``mapped``    - the SIPG matrix on trilinear hexahedra (general geometry:
+                  mapped cell integrals with per-point Jacobians, Sec. 2.1,
+                  and physical face normals), by quadrature cell by cell.
 * ``rhs``       - right-hand side and L2 error by tensor Gauss quadrature
                   (Sec. 7.2 manufactured solution).
 * ``multigrid`` - transfers, multiplicative vertex-patch smoother with dense

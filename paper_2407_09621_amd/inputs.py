@@ -39,3 +39,46 @@ def batch_problems(seed, count=64, edges=(16, 24, 32, 48, 64), degrees=(2, 3, 4,
     ns = rng.choice(np.asarray(edges), size=count)
     ks = rng.choice(np.asarray(degrees), size=count)
     return [(int(a), int(b)) for a, b in zip(ns, ks)]
+
+
+def mesh_vertices(n, kind="identity", amplitude=0.0, seed=0, affine=None, shift=None):
+    """Vertex positions of a structured mesh of n^3 hexahedra, array
+    [n+1, n+1, n+1, 3] indexed [vz, vy, vx] (x, y, z last).
+
+    kind "identity": the uniform grid of the unit cube.
+    kind "smooth":   the grid moved by amplitude * s(x) * c, with
+                     s = sin(pi x) sin(pi y) sin(pi z) (zero on the boundary)
+                     and a seeded direction c in [-1, 1]^3.
+    kind "jitter":   interior vertices moved by seeded offsets in
+                     [-amplitude h, amplitude h]^3 (h = 1/n); boundary
+                     vertices stay.
+    Then x <- affine @ x + shift when given (a 3 x 3 matrix, a 3-vector)."""
+    t = np.arange(n + 1, dtype=np.float64) / n
+    Z, Y, X = np.meshgrid(t, t, t, indexing="ij")
+    P = np.stack([X, Y, Z], axis=-1)
+    rng = np.random.default_rng(seed)
+    if kind == "smooth":
+        c = rng.uniform(-1.0, 1.0, 3)
+        s = np.sin(np.pi * X) * np.sin(np.pi * Y) * np.sin(np.pi * Z)
+        P = P + amplitude * s[..., None] * c
+    elif kind == "jitter":
+        d = rng.uniform(-amplitude / n, amplitude / n, P.shape)
+        inner = np.zeros(P.shape[:3], dtype=bool)
+        inner[1:-1, 1:-1, 1:-1] = True
+        P = P + d * inner[..., None]
+    elif kind != "identity":
+        raise ValueError("kind must be identity, smooth or jitter")
+    if affine is not None:
+        P = P @ np.asarray(affine, dtype=np.float64).T
+    if shift is not None:
+        P = P + np.asarray(shift, dtype=np.float64)
+    return np.ascontiguousarray(P)
+
+
+def rotation(seed):
+    """A seeded proper rotation (QR of a Gaussian matrix, det +1)."""
+    q, r = np.linalg.qr(np.random.default_rng(seed).standard_normal((3, 3)))
+    q = q * np.sign(np.diag(r))
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    return q
