@@ -127,6 +127,29 @@ int64_t sipg_n_dofs(const sipg_problem* p, int level);
 sipg_status sipg_apply(sipg_problem* p, int level, const double* u, double* v,
                        hipStream_t stream);
 
+/* General geometry (Sec. 2 and Sec. 2.1: cells mapped from the reference
+ * cube, A^K = G^T W G with per-point Jacobians).  Replaces the Cartesian
+ * unit-cube mesh of every level by trilinear hexahedra through the given
+ * vertex positions: `vertices` is a HOST array of (n+1)^3 * 3 doubles (n =
+ * finest cells per direction), vertex (vx, vy, vz) at index
+ * ((vz * (n+1) + vy) * (n+1) + vx) * 3 (x, y, z); level l takes every
+ * 2^(L-1-l)-th vertex.  The caller keeps ownership; the library copies it.
+ * Quadrature is N-point Gauss per direction on cells and N x N on faces;
+ * the penalty of a face is k(k+1)(1/h- + 1/h+) times penalty_scale with h
+ * the cell volume over the face area (boundary faces 2k(k+1)/h-).
+ * Afterwards sipg_apply, sipg_residual, sipg_smooth, sipg_vcycle and
+ * sipg_fgmres use the mapped operator; the smoother's patch solves and the
+ * coarse solve keep the Cartesian fast diagonalization (an approximate
+ * inverse on mapped cells; the outer FGMRES corrects for it).  NULL
+ * restores the Cartesian mesh.  SIPG_ERR_UNSUPPORTED unless mg_precision is
+ * SIPG_F64 and the smoother is 0 or 1; while a geometry is set,
+ * sipg_apply_units, sipg_apply_patchwise, sipg_apply_lp, sipg_autotune,
+ * sipg_rhs_sines, the L2 errors, the learned stage and the network training
+ * return SIPG_ERR_UNSUPPORTED (they are Cartesian).  SIPG_ERR_ARG when a
+ * cell has a non-positive Jacobian determinant at a Gauss point or corner
+ * (the previous geometry is kept).  Synchronizes `stream`. */
+sipg_status sipg_set_geometry(sipg_problem* p, const double* vertices, hipStream_t stream);
+
 /* Execution units of the FP64 apply (the paper's comparison of tensor-core
  * and CUDA-core kernels, Sec. 4 and App. A, on gfx950's matrix and vector
  * units). */

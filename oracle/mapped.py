@@ -32,6 +32,8 @@ Vertex array: V[vz, vy, vx, :] = (x, y, z); cell (cx, cy, cz) has vertex
 (a, b, c) in {0, 1}^3 at V[cz + c, cy + b, cx + a], numbered a + 2b + 4c.
 Degree-of-freedom layout as in ``oracle.sipg``.
 """
+import functools
+
 import numpy as np
 import scipy.sparse as sp
 
@@ -70,6 +72,22 @@ def _cell_rule(k):
     return P, W
 
 
+@functools.lru_cache(maxsize=None)
+def _cell_basis(k):
+    """Gauss points, weights and the reference basis (values, gradients)
+    there; the same for every cell."""
+    P, W = _cell_rule(k)
+    v, g = _tensor_basis_at(k, P, 1.0)
+    return P, W, v, g
+
+
+@functools.lru_cache(maxsize=None)
+def _face_basis(k, d, side):
+    pts, wq = _face_points(k, d, float(side))
+    v, g = _tensor_basis_at(k, pts, 1.0)
+    return pts, wq, v, g
+
+
 def _physical(gref, J):
     """Physical gradients grad phi = J^{-T} grad_xi phi: [Q, N^3, 3]."""
     Jinv = np.linalg.inv(J)                       # [Q, d, i]
@@ -94,19 +112,18 @@ def face_area(k, X, d, side):
 
 def cell_matrix_mapped(k, X):
     """int_K grad phi_I . grad phi_J dx on the trilinear cell X (Sec. 2.1)."""
-    P, W = _cell_rule(k)
-    _, gref = _tensor_basis_at(k, P, 1.0)
+    P, W, _, gref = _cell_basis(k)
     _, J = trilinear(X, P)
     g = _physical(gref, J)
     wd = W * np.linalg.det(J)
-    return sum(g[:, :, i].T @ (wd[:, None] * g[:, :, i]) for i in range(3))
+    gi = [np.ascontiguousarray(g[:, :, i]) for i in range(3)]
+    return sum(gi[i].T @ (wd[:, None] * gi[i]) for i in range(3))
 
 
 def _face_side(k, X, d, side):
     """Values, physical gradients and positions of the basis of the cell X on
     its face xi_d = side, and n dsigma / dA there (outward)."""
-    pts, wq = _face_points(k, d, float(side))
-    v, gref = _tensor_basis_at(k, pts, 1.0)
+    pts, wq, v, gref = _face_basis(k, d, side)
     x, J = trilinear(X, pts)
     g = _physical(gref, J)
     sign = 1.0 if side == 1 else -1.0
@@ -135,12 +152,15 @@ def interior_face_blocks_mapped(k, Xm, Xp, d, penalty_scale=1.0):
         vt, gt, nt = side[t]
         for s in '-+':
             vs, gs, ns = side[s]
+            # sum over the face points q of w_q times
+            #   gamma [[phi_J]].[[phi_I]] - {grad phi_J}.[[phi_I]] - [[phi_J]].{grad phi_I}
+            # written as products over q (rows I: test functions on K_t)
             nn = np.einsum("qi,qi->q", ns, nt)
-            jump_jump = nn[:, None, None] * vs[:, None, :] * vt[:, :, None]
-            avg_u_jump_v = 0.5 * np.einsum("qJi,qi->qJ", gs, nt)[:, None, :] * vt[:, :, None]
-            jump_u_avg_v = 0.5 * vs[:, None, :] * np.einsum("qIi,qi->qI", gt, ns)[:, :, None]
-            integrand = gamma * jump_jump - avg_u_jump_v - jump_u_avg_v
-            blocks[(t, s)] = np.tensordot(w, integrand, axes=(0, 0))
+            gs_nt = np.einsum("qJi,qi->qJ", gs, nt)
+            gt_ns = np.einsum("qIi,qi->qI", gt, ns)
+            blocks[(t, s)] = (gamma * vt.T @ ((w * nn)[:, None] * vs)
+                              - 0.5 * vt.T @ (w[:, None] * gs_nt)
+                              - 0.5 * gt_ns.T @ (w[:, None] * vs))
     return blocks
 
 
@@ -153,10 +173,10 @@ def boundary_face_block_mapped(k, X, d, side, penalty_scale=1.0):
     h = cell_volume(k, X) / float(wq @ ds)
     gamma = penalty_scale * 2.0 * k * (k + 1) / h
     gn = np.einsum("qIi,qi->qI", g, n)
-    integrand = (gamma * v[:, :, None] * v[:, None, :]
-                 - v[:, :, None] * gn[:, None, :]
-                 - gn[:, :, None] * v[:, None, :])
-    return np.tensordot(wq * ds, integrand, axes=(0, 0))
+    w = wq * ds
+    # sum over q of w_q (gamma phi_I phi_J - phi_I dn phi_J - dn phi_I phi_J)
+    return (gamma * v.T @ (w[:, None] * v) - v.T @ (w[:, None] * gn)
+            - gn.T @ (w[:, None] * v))
 
 
 def _check(V, n):

@@ -31,11 +31,36 @@ int tile_order(const sipg_problem* p, int l) {
   return (l < (int)p->order.size()) ? p->order[l] : 0;
 }
 
-sipg_status residual(sipg_problem* p, int l, const double* b, const double* x, double* r,
+// v = A_l u, or v = b - A_l u when b != nullptr: the Cartesian kernels, or the
+// trilinear-cell kernel once a geometry is set
+sipg_status op_apply(sipg_problem* p, int l, const double* u, double* v, const double* b,
                      hipStream_t s) {
-  ApplyJob j{x, r, b, p->n[l], level_h(p, l), tile_order(p, l)};
+  if (p->mapped) {
+    MappedLevel g;
+    g.vert = p->geo_vert[l];
+    g.gam = p->geo_gam[l];
+    g.n = p->n[l];
+    SIPG_HIP(launch_apply_mapped(p->N, u, v, b, g, p->d_mtab, s));
+    return SIPG_OK;
+  }
+  ApplyJob j{u, v, b, p->n[l], level_h(p, l), tile_order(p, l)};
   SIPG_HIP(launch_apply_batch(0, p->N, &j, 1, p->tab, s));
   return SIPG_OK;
+}
+
+sipg_status residual(sipg_problem* p, int l, const double* b, const double* x, double* r,
+                     hipStream_t s) {
+  return op_apply(p, l, x, r, b, s);
+}
+
+void free_geometry(sipg_problem* p) {
+  for (auto q : p->geo_vert) prob_free(p, q);
+  for (auto q : p->geo_gam) prob_free(p, q);
+  p->geo_vert.clear();
+  p->geo_gam.clear();
+  prob_free(p, p->d_mtab);
+  p->d_mtab = nullptr;
+  p->mapped = false;
 }
 
 sipg_status smooth(sipg_problem* p, int l, double* x, const double* b, int sweeps,
@@ -382,6 +407,7 @@ void sipg_destroy(sipg_problem* p) {
   for (auto q : p->fr) prob_free(p, q);
   prob_free(p, p->stage_c);
   prob_free(p, p->stage_q);
+  free_geometry(p);
   if (p->h_pinned) hipHostFree(p->h_pinned);
   delete p;
 }
@@ -402,14 +428,73 @@ sipg_status sipg_apply(sipg_problem* p, int level, const double* u, double* v, h
   SIPG_TRY(check_level(p, level));
   if (!u || !v) return fail(SIPG_ERR_ARG, "NULL vector");
   if (u == v) return fail(SIPG_ERR_ARG, "u and v must not alias");
-  ApplyJob j{u, v, nullptr, p->n[level], level_h(p, level), tile_order(p, level)};
-  SIPG_HIP(launch_apply_batch(0, p->N, &j, 1, p->tab, s));
+  return op_apply(p, level, u, v, nullptr, s);
+}
+
+sipg_status sipg_set_geometry(sipg_problem* p, const double* vertices, hipStream_t s) {
+  if (!p) return fail(SIPG_ERR_ARG, "NULL handle");
+  if (!vertices) {
+    SIPG_HIP(hipStreamSynchronize(s));
+    free_geometry(p);
+    return SIPG_OK;
+  }
+  if (p->prec != SIPG_F64 || p->cfg.smoother == 2)
+    return fail(SIPG_ERR_UNSUPPORTED,
+                "general geometry needs mg_precision SIPG_F64 and smoother 0 or 1");
+  const int L = p->L, nf = p->n[L - 1];
+  const size_t nf1 = (size_t)nf + 1;
+  std::vector<std::vector<double>> verts(L), gams(L);
+  for (int l = 0; l < L; ++l) {
+    const int nl = p->n[l], stp = nf / nl;
+    const size_t n1 = (size_t)nl + 1;
+    std::vector<double>& V = verts[l];
+    V.resize(n1 * n1 * n1 * 3);
+    for (size_t z = 0; z < n1; ++z)
+      for (size_t y = 0; y < n1; ++y)
+        for (size_t x = 0; x < n1; ++x)
+          for (int i = 0; i < 3; ++i)
+            V[((z * n1 + y) * n1 + x) * 3 + i] =
+                vertices[(((z * stp) * nf1 + y * stp) * nf1 + x * stp) * 3 + i];
+    for (double d : V)
+      if (!std::isfinite(d)) return fail(SIPG_ERR_ARG, "vertex positions must be finite");
+    std::string err;
+    if (!mapped_penalties(p->k, nl, V.data(), p->cfg.penalty_scale, gams[l], err))
+      return fail(SIPG_ERR_ARG, "level " + std::to_string(l) + ": " + err);
+  }
+  SIPG_HIP(hipStreamSynchronize(s));
+  free_geometry(p);
+  const std::vector<double> mt = mapped_table(p->k);
+  sipg_status st = prob_alloc(p, &p->d_mtab, mt.size());
+  p->geo_vert.assign(L, nullptr);
+  p->geo_gam.assign(L, nullptr);
+  for (int l = 0; l < L && st == SIPG_OK; ++l) {
+    st = prob_alloc(p, &p->geo_vert[l], verts[l].size());
+    if (st == SIPG_OK) st = prob_alloc(p, &p->geo_gam[l], gams[l].size());
+  }
+  if (st != SIPG_OK) {
+    std::string msg = g_err;
+    free_geometry(p);
+    return fail(st, msg);
+  }
+  bool ok = hipMemcpyAsync(p->d_mtab, mt.data(), mt.size() * sizeof(double),
+                           hipMemcpyHostToDevice, s) == hipSuccess;
+  for (int l = 0; l < L && ok; ++l)
+    ok = hipMemcpyAsync(p->geo_vert[l], verts[l].data(), verts[l].size() * sizeof(double),
+                        hipMemcpyHostToDevice, s) == hipSuccess &&
+         hipMemcpyAsync(p->geo_gam[l], gams[l].data(), gams[l].size() * sizeof(double),
+                        hipMemcpyHostToDevice, s) == hipSuccess;
+  if (!ok || hipStreamSynchronize(s) != hipSuccess) {
+    free_geometry(p);
+    return fail(SIPG_ERR_HIP, "geometry upload failed");
+  }
+  p->mapped = true;
   return SIPG_OK;
 }
 
 sipg_status sipg_apply_units(sipg_problem* p, int level, const double* u, double* v, int units,
                              hipStream_t s) {
   SIPG_TRY(check_level(p, level));
+  SIPG_TRY(cartesian_only(p, "sipg_apply_units"));
   if (!u || !v) return fail(SIPG_ERR_ARG, "NULL vector");
   if (u == v) return fail(SIPG_ERR_ARG, "u and v must not alias");
   if (units < SIPG_UNITS_AUTO || units > SIPG_UNITS_MATRIX)
@@ -425,6 +510,7 @@ sipg_status sipg_apply_units(sipg_problem* p, int level, const double* u, double
 sipg_status sipg_apply_patchwise(sipg_problem* p, int level, const double* u, double* v,
                                  hipStream_t s) {
   SIPG_TRY(check_level(p, level));
+  SIPG_TRY(cartesian_only(p, "sipg_apply_patchwise"));
   if (!u || !v) return fail(SIPG_ERR_ARG, "NULL vector");
   if (u == v) return fail(SIPG_ERR_ARG, "u and v must not alias");
   if (p->n[level] < 2) return fail(SIPG_ERR_ARG, "patch-wise evaluation needs n >= 2 cells");
@@ -519,6 +605,7 @@ sipg_status sipg_vcycle(sipg_problem* p, int level, double* x, const double* b, 
 sipg_status sipg_autotune(sipg_problem* p, int level, const double* u, double* v, int* best,
                           hipStream_t s) {
   SIPG_TRY(check_level(p, level));
+  SIPG_TRY(cartesian_only(p, "sipg_autotune"));
   if (!u || !v || u == v) return fail(SIPG_ERR_ARG, "need two distinct vectors");
   const int nl = p->n[level];
   const int cand[4] = {1, 2, 4, 8};
@@ -553,6 +640,7 @@ sipg_status sipg_autotune(sipg_problem* p, int level, const double* u, double* v
 sipg_status sipg_apply_lp(sipg_problem* p, int level, const float* u, float* v, int precision,
                           int ec, hipStream_t s) {
   SIPG_TRY(check_level(p, level));
+  SIPG_TRY(cartesian_only(p, "sipg_apply_lp"));
   if (!u || !v) return fail(SIPG_ERR_ARG, "NULL vector");
   if (u == v) return fail(SIPG_ERR_ARG, "u and v must not alias");
   if (precision == SIPG_F32) {
@@ -575,6 +663,7 @@ sipg_status sipg_fgmres(sipg_problem* p, double* x, const double* b, const sipg_
   if (o->max_iters < 1) return fail(SIPG_ERR_ARG, "max_iters must be >= 1");
   if (!(o->rtol > 0.0)) return fail(SIPG_ERR_ARG, "rtol must be > 0");
   if (o->use_learned && !p->cnn) return fail(SIPG_ERR_ARG, "use_learned set but no network attached");
+  if (o->use_learned) SIPG_TRY(cartesian_only(p, "the learned stage"));
   if (o->variant != SIPG_FGMRES && o->variant != SIPG_GMRES)
     return fail(SIPG_ERR_ARG, "variant must be SIPG_FGMRES or SIPG_GMRES");
   if (o->variant == SIPG_GMRES && o->use_learned)
@@ -642,8 +731,7 @@ sipg_status sipg_fgmres(sipg_problem* p, double* x, const double* b, const sipg_
         if (mode < 2) SIPG_TRY(vcycle_any(p, L, Zj, Vj, s));
         else SIPG_HIP(launch_scale_copy(Vj, 1.0, Zj, n, s));
         if (mode == 0 && learned) SIPG_TRY(cnn_stage(p, Vj, Zj, s));
-        ApplyJob aj{Zj, w, nullptr, p->n[L], level_h(p, L), tile_order(p, L)};
-        SIPG_HIP(launch_apply_batch(0, p->N, &aj, 1, p->tab, s));
+        SIPG_TRY(op_apply(p, L, Zj, w, nullptr, s));
         // classical Gram-Schmidt, twice; the Hessenberg column and ||w||^2
         // come back in one stream-ordered copy (a NaN or Inf in z shows up
         // there, so no separate check is needed)
@@ -729,6 +817,7 @@ sipg_status sipg_fgmres(sipg_problem* p, double* x, const double* b, const sipg_
 sipg_status sipg_rhs_sines(sipg_problem* p, int level, int n_modes, const double* amps,
                            const int* pqr, double* b, hipStream_t s) {
   SIPG_TRY(check_level(p, level));
+  SIPG_TRY(cartesian_only(p, "sipg_rhs_sines"));
   if (n_modes < 1 || n_modes > 64 || !amps || !pqr || !b) return fail(SIPG_ERR_ARG, "bad modes");
   const int N = p->N, nl = p->n[level];
   const double h = 1.0 / nl;
@@ -768,6 +857,7 @@ sipg_status sipg_rhs_sines(sipg_problem* p, int level, int n_modes, const double
 sipg_status sipg_l2_error_sines(sipg_problem* p, int level, int n_modes, const double* amps,
                                 const int* pqr, const double* x, double* err, hipStream_t s) {
   SIPG_TRY(check_level(p, level));
+  SIPG_TRY(cartesian_only(p, "sipg_l2_error_sines"));
   if (n_modes < 1 || n_modes > 64 || !amps || !pqr || !x || !err)
     return fail(SIPG_ERR_ARG, "bad modes");
   const int N = p->N, nl = p->n[level], nq = p->k + 3;
@@ -788,6 +878,7 @@ sipg_status sipg_l2_error_sines_noalloc(sipg_problem* p, int level, int n_modes,
                                         const double* amps, const int* pqr, const double* x,
                                         double* err, hipStream_t s) {
   SIPG_TRY(check_level(p, level));
+  SIPG_TRY(cartesian_only(p, "sipg_l2_error_sines_noalloc"));
   if (n_modes < 1 || n_modes > 64 || !amps || !pqr || !x || !err)
     return fail(SIPG_ERR_ARG, "bad modes");
   const int N = p->N, nl = p->n[level], nq = p->k + 3;

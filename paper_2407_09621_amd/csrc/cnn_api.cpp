@@ -232,6 +232,7 @@ void free_pair_bufs(PairBufs& w) {
 }
 
 sipg_status check_problem_grid(const sipg_problem* p) {
+  SIPG_TRY(cartesian_only(p, "the learned stage"));
   const int G = p->n[p->L - 1] * p->N;
   if (G % C::kTile) return fail(SIPG_ERR_UNSUPPORTED, "n (k+1) must be a multiple of 16");
   return SIPG_OK;
@@ -451,6 +452,7 @@ sipg_status sipg_cnn_make_pairs(sipg_problem* p, const double* x0, int count, fl
                                 float* e_grids, double* scales, hipStream_t s) {
   if (!p || !x0 || !rho_grids || !e_grids) return fail(SIPG_ERR_ARG, "NULL argument");
   if (count < 1) return fail(SIPG_ERR_ARG, "count must be >= 1");
+  SIPG_TRY(cartesian_only(p, "the learned stage"));
   const int L = p->L - 1;
   const int64_t n = p->ndofs[L];
   PairBufs w;

@@ -5,6 +5,7 @@
 #include <cstdint>
 
 #include "batch.h"
+#include "geometry.h"
 #include "tables.h"
 
 namespace sipg {
@@ -130,5 +131,16 @@ hipError_t launch_l2_sines(int N, int nq, int n, int n_modes, const double* amps
 constexpr size_t kL2ScratchDoubles = 131072;  // 1 MiB
 constexpr int kMaxDevices = 64;
 hipError_t l2_scratch(double** out);
+
+// General geometry (trilinear hexahedra): the device data of one level.
+struct MappedLevel {
+  const double* vert = nullptr;  // (n+1)^3 x 3 vertex positions, [vz][vy][vx][xyz]
+  const double* gam = nullptr;   // n^3 x 6 face penalties, face 2 d + side
+  int n = 0;
+};
+// v = A u (or v = b - A u when b != nullptr) on the trilinear cells of g;
+// mtab is the device copy of mapped_table(k).  u and v must not alias.
+hipError_t launch_apply_mapped(int N, const double* u, double* v, const double* b,
+                               const MappedLevel& g, const double* mtab, hipStream_t s);
 
 }  // namespace sipg

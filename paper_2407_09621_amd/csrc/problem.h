@@ -76,10 +76,20 @@ struct sipg_problem {
   sipg_cnn* cnn = nullptr;  // learned correction stage (borrowed; see sipg_cnn_attach)
   double* stage_c = nullptr;  // the stage's correction and its image under A (finest level)
   double* stage_q = nullptr;
+  // general geometry (sipg_set_geometry): per-level vertices and face penalties
+  bool mapped = false;
+  double* d_mtab = nullptr;
+  std::vector<double*> geo_vert, geo_gam;
 };
 
 namespace sipg {
 inline double level_h(const sipg_problem* p, int l) { return 1.0 / p->n[l]; }
+
+inline sipg_status cartesian_only(const sipg_problem* p, const char* what) {
+  if (p && p->mapped)
+    return fail(SIPG_ERR_UNSUPPORTED, std::string(what) + " needs the Cartesian mesh (a geometry is set)");
+  return SIPG_OK;
+}
 
 // Workspace of a problem handle: through the caller's allocator callbacks
 // when the configuration names them, else hipMalloc / hipFree.

@@ -1,0 +1,355 @@
+// Operator apply on trilinear hexahedra (general geometry, Sec. 2.1): every
+// cell is the image of the reference cube under the trilinear map of its 8
+// vertices, and the cell integral becomes
+//   A^K = G^T W G,   W = w_q det J J^{-1} J^{-T}  at each quadrature point,
+// with G the values / reference gradients of the basis at the points (sum
+// factorization along x, y, z).  The face terms of eq. bilinear_form use the
+// physical normal and surface measure: on the reference face
+//   n dsigma = det J J^{-T} n_hat dA = C n_hat dA,  C = cof(J),
+// so that grad u . n dsigma = grad_xi u . (C^T nu / det J) with nu = C n_hat w.
+//
+// Quadrature is N-point Gauss per direction on cells and N x N on faces (the
+// rule of the Cartesian operator, exact on affine cells).  The penalty of a
+// face is k(k+1)(1/h- + 1/h+) with h = |K| / |e| on each side (2k(k+1)/h-
+// on the boundary), computed once per face on the host.
+//
+// One workgroup per cell: the cell's block and the stage arrays live in LDS,
+// the 16 one-dimensional contractions of the cell term and the two-
+// dimensional contractions of the six face terms run over the workgroup's
+// threads.  The Jacobians are computed on the fly from the 8 vertices at
+// every quadrature point (a few dozen flops per point instead of 48 B per
+// point of stored metric terms), so the kernel reads the vector once (plus
+// its neighbours' blocks, mostly from L2) and 72 B of geometry per cell.
+// Workgroups are mapped to cells in contiguous chunks per XCD so that a
+// cell's neighbours are likely in the same L2.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace sipg {
+
+namespace {
+
+// dx_i / dxi_d of the trilinear map through X (vertex a + 2b + 4c at
+// X[3 (a + 2b + 4c) + i]) at the reference point (x0, x1, x2)
+__device__ __forceinline__ void trilinear_jacobian(const double* X, double x0, double x1,
+                                                   double x2, double J[3][3]) {
+  const double a0 = 1.0 - x0, a1 = 1.0 - x1, a2 = 1.0 - x2;
+  for (int i = 0; i < 3; ++i) {
+    J[i][0] = (X[3 + i] - X[i]) * a1 * a2 + (X[9 + i] - X[6 + i]) * x1 * a2 +
+              (X[15 + i] - X[12 + i]) * a1 * x2 + (X[21 + i] - X[18 + i]) * x1 * x2;
+    J[i][1] = (X[6 + i] - X[i]) * a0 * a2 + (X[9 + i] - X[3 + i]) * x0 * a2 +
+              (X[18 + i] - X[12 + i]) * a0 * x2 + (X[21 + i] - X[15 + i]) * x0 * x2;
+    J[i][2] = (X[12 + i] - X[i]) * a0 * a1 + (X[15 + i] - X[3 + i]) * x0 * a1 +
+              (X[18 + i] - X[6 + i]) * a0 * x1 + (X[21 + i] - X[9 + i]) * x0 * x1;
+  }
+}
+
+// cofactor matrix C (J^{-T} = C / det J) and the determinant
+__device__ __forceinline__ double cofactor(const double J[3][3], double C[3][3]) {
+  C[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+  C[0][1] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+  C[0][2] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+  C[1][0] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+  C[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+  C[1][2] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+  C[2][0] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+  C[2][1] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+  C[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  return J[0][0] * C[0][0] + J[0][1] * C[0][1] + J[0][2] * C[0][2];
+}
+
+template <int N>
+constexpr int mapped_threads() {
+  return N <= 4 ? 64 : 256;
+}
+
+// dst[p] (+)= sum_a M'[o][a] src[p with its index o along DIR replaced by a]
+// over the N^3 points of a cell block (x fastest); M' = M (row-major
+// M[o * N + a]) or, for TR, its transpose
+template <int N, int T, int DIR, bool TR, bool ACC>
+__device__ __forceinline__ void line3(const double* M, const double* src, double* dst, int tid) {
+  constexpr int st = DIR == 0 ? 1 : (DIR == 1 ? N : N * N);
+  for (int p = tid; p < N * N * N; p += T) {
+    const int o = (p / st) % N;
+    const int base = p - o * st;
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < N; ++a) s += (TR ? M[a * N + o] : M[o * N + a]) * src[base + a * st];
+    dst[p] = ACC ? dst[p] + s : s;
+  }
+}
+
+// the same on the six N x N face arrays (index t1 + N t2, face-major);
+// DIR 0 contracts along t1, 1 along t2
+template <int N, int T, int DIR, bool TR, bool ACC>
+__device__ __forceinline__ void line2(const double* M, const double* src, double* dst, int tid) {
+  constexpr int st = DIR == 0 ? 1 : N;
+  for (int it = tid; it < 6 * N * N; it += T) {
+    const int p = it % (N * N);
+    const int o = (p / st) % N;
+    const int base = it - o * st;
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < N; ++a) s += (TR ? M[a * N + o] : M[o * N + a]) * src[base + a * st];
+    dst[it] = ACC ? dst[it] + s : s;
+  }
+}
+
+// v = A u, or v = b - A u when b != nullptr.  mtab: S [N x N] (basis at the
+// Gauss points, S[q * N + a] = phi_a(g_q)), D [N x N] (derivatives), Gauss
+// weights [N], Gauss points [N], phi'(0) [N], phi'(1) [N].  Cell c of the
+// launch is (blockIdx % 8) * chunk + blockIdx / 8 (contiguous chunks of
+// cells per XCD); blocks beyond n^3 cells return at once.
+template <int N>
+__global__ __launch_bounds__(mapped_threads<N>()) void apply_mapped_kernel(
+    const double* __restrict__ u, double* __restrict__ v, const double* __restrict__ b,
+    const double* __restrict__ vert, const double* __restrict__ gam,
+    const double* __restrict__ mtab, int n, int chunk) {
+  constexpr int T = mapped_threads<N>();
+  constexpr int N2 = N * N, N3 = N * N * N, F = 6 * N2;
+  constexpr int RA = (5 * N3 > 6 * F) ? 5 * N3 : 6 * F;
+  __shared__ double s_tab[2 * N2 + 4 * N];
+  __shared__ double s_X[24];
+  __shared__ double s_Xn[6 * 24];
+  __shared__ double s_gam[6];
+  __shared__ double s_u[N3];
+  __shared__ double s_v[N3];
+  __shared__ double s_a[RA];     // cell stage arrays, then face region 2 (6 arrays)
+  __shared__ double s_r1[8 * F]; // face region 1 (8 arrays)
+  const int tid = threadIdx.x;
+  const int nc = n * n * n;
+  const int c = (int)(blockIdx.x % 8) * chunk + (int)(blockIdx.x / 8);
+  if (c >= nc) return;  // the whole workgroup, before any barrier
+  const int pos[3] = {c % n, (c / n) % n, c / (n * n)};
+  const int cstride[3] = {1, n, n * n};
+  const size_t n1 = (size_t)n + 1;
+  auto vtx = [&](int x, int y, int z, int i) { return vert[((z * n1 + y) * n1 + x) * 3 + i]; };
+
+  for (int i = tid; i < 2 * N2 + 4 * N; i += T) s_tab[i] = mtab[i];
+  if (tid < 24) {
+    const int w = tid / 3, i = tid % 3;
+    s_X[tid] = vtx(pos[0] + (w & 1), pos[1] + ((w >> 1) & 1), pos[2] + (w >> 2), i);
+  }
+  for (int it = tid; it < 6 * 24; it += T) {
+    const int f = it / 24, r = it % 24, d = f >> 1, side = f & 1;
+    int q[3] = {pos[0], pos[1], pos[2]};
+    q[d] += side ? 1 : -1;
+    double val = 0.0;
+    if (q[d] >= 0 && q[d] < n) {
+      const int w = r / 3, i = r % 3;
+      val = vtx(q[0] + (w & 1), q[1] + ((w >> 1) & 1), q[2] + (w >> 2), i);
+    }
+    s_Xn[it] = val;
+  }
+  if (tid < 6) s_gam[tid] = gam[(size_t)c * 6 + tid];
+  const double* __restrict__ uc = u + (size_t)c * N3;
+  for (int p = tid; p < N3; p += T) s_u[p] = uc[p];
+  __syncthreads();
+
+  const double* S = s_tab;
+  const double* D = s_tab + N2;
+  const double* W = s_tab + 2 * N2;
+  const double* G = W + N;
+  const double* D0 = G + N;
+  const double* D1 = D0 + N;
+
+  // ---- cell term: reference gradient at the Gauss points, metric, transpose
+  double* t0 = s_a;
+  double* t1 = s_a + N3;
+  double* p1 = s_a + 2 * N3;
+  double* p2 = s_a + 3 * N3;
+  double* p3 = s_a + 4 * N3;
+  line3<N, T, 0, false, false>(S, s_u, t0, tid);
+  line3<N, T, 0, false, false>(D, s_u, t1, tid);
+  __syncthreads();
+  line3<N, T, 1, false, false>(S, t1, p1, tid);  // d/dxi0 branch
+  line3<N, T, 1, false, false>(D, t0, p2, tid);  // d/dxi1 branch
+  line3<N, T, 1, false, false>(S, t0, p3, tid);  // d/dxi2 branch
+  __syncthreads();
+  line3<N, T, 2, false, false>(S, p1, t0, tid);
+  line3<N, T, 2, false, false>(S, p2, t1, tid);
+  line3<N, T, 2, false, false>(D, p3, s_v, tid);
+  __syncthreads();
+  for (int p = tid; p < N3; p += T) {
+    const int qx = p % N, qy = (p / N) % N, qz = p / N2;
+    double J[3][3], C[3][3];
+    trilinear_jacobian(s_X, G[qx], G[qy], G[qz], J);
+    const double det = cofactor(J, C);
+    const double g0 = t0[p], g1 = t1[p], g2 = s_v[p];
+    double h[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) h[i] = C[i][0] * g0 + C[i][1] * g1 + C[i][2] * g2;
+    const double w = W[qx] * W[qy] * W[qz] / det;
+    t0[p] = w * (C[0][0] * h[0] + C[1][0] * h[1] + C[2][0] * h[2]);
+    t1[p] = w * (C[0][1] * h[0] + C[1][1] * h[1] + C[2][1] * h[2]);
+    s_v[p] = w * (C[0][2] * h[0] + C[1][2] * h[1] + C[2][2] * h[2]);
+  }
+  __syncthreads();
+  line3<N, T, 2, true, false>(S, t0, p1, tid);
+  line3<N, T, 2, true, false>(S, t1, p2, tid);
+  line3<N, T, 2, true, false>(D, s_v, p3, tid);
+  __syncthreads();
+  line3<N, T, 1, true, false>(S, p1, t0, tid);
+  line3<N, T, 1, true, false>(D, p2, t1, tid);
+  line3<N, T, 1, true, true>(S, p3, t1, tid);
+  __syncthreads();
+  line3<N, T, 0, true, false>(D, t0, s_v, tid);
+  line3<N, T, 0, true, true>(S, t1, s_v, tid);
+  __syncthreads();
+
+  // ---- face terms of the six faces (face f = 2 d + side, side 1 at xi_d = 1)
+  double* R1 = s_r1;
+  double* R2 = s_a;
+  auto tdirs = [](int d, int& a, int& bb) {
+    a = d == 0 ? 1 : 0;
+    bb = d == 2 ? 1 : 2;
+  };
+  const int st3[3] = {1, N, N2};
+  for (int it = tid; it < F; it += T) {  // traces at the face nodes
+    const int f = it / N2, t = it % N2, d = f >> 1, side = f & 1;
+    int d1, d2;
+    tdirs(d, d1, d2);
+    const int base = (t % N) * st3[d1] + (t / N) * st3[d2];
+    const double* Ds = side ? D1 : D0;
+    double lm = s_u[base + (side ? N - 1 : 0) * st3[d]], dm = 0.0;
+#pragma unroll
+    for (int e = 0; e < N; ++e) dm += Ds[e] * s_u[base + e * st3[d]];
+    double lp = 0.0, dp = 0.0;
+    const int qd = pos[d] + (side ? 1 : -1);
+    if (qd >= 0 && qd < n) {
+      const double* __restrict__ un = u + (size_t)(c + (side ? 1 : -1) * cstride[d]) * N3 + base;
+      const double* Do = side ? D0 : D1;
+      lp = un[(side ? 0 : N - 1) * st3[d]];
+#pragma unroll
+      for (int e = 0; e < N; ++e) dp += Do[e] * un[e * st3[d]];
+    }
+    R1[it] = lm;
+    R1[F + it] = dm;
+    R1[2 * F + it] = lp;
+    R1[3 * F + it] = dp;
+  }
+  __syncthreads();
+  line2<N, T, 0, false, false>(S, R1, R2, tid);                  // minus value, along t1
+  line2<N, T, 0, false, false>(D, R1, R2 + F, tid);              // minus d/dt1
+  line2<N, T, 0, false, false>(S, R1 + F, R2 + 2 * F, tid);      // minus d/dn
+  line2<N, T, 0, false, false>(S, R1 + 2 * F, R2 + 3 * F, tid);  // plus value
+  line2<N, T, 0, false, false>(D, R1 + 2 * F, R2 + 4 * F, tid);  // plus d/dt1
+  line2<N, T, 0, false, false>(S, R1 + 3 * F, R2 + 5 * F, tid);  // plus d/dn
+  __syncthreads();
+  line2<N, T, 1, false, false>(S, R2, R1, tid);                  // u-
+  line2<N, T, 1, false, false>(S, R2 + F, R1 + F, tid);          // du-/dt1
+  line2<N, T, 1, false, false>(D, R2, R1 + 2 * F, tid);          // du-/dt2
+  line2<N, T, 1, false, false>(S, R2 + 2 * F, R1 + 3 * F, tid);  // du-/dn
+  line2<N, T, 1, false, false>(S, R2 + 3 * F, R1 + 4 * F, tid);  // u+
+  line2<N, T, 1, false, false>(S, R2 + 4 * F, R1 + 5 * F, tid);  // du+/dt1
+  line2<N, T, 1, false, false>(D, R2 + 3 * F, R1 + 6 * F, tid);  // du+/dt2
+  line2<N, T, 1, false, false>(S, R2 + 5 * F, R1 + 7 * F, tid);  // du+/dn
+  __syncthreads();
+  for (int it = tid; it < F; it += T) {  // integrand at the face quadrature points
+    const int f = it / N2, t = it % N2, d = f >> 1, side = f & 1;
+    int d1, d2;
+    tdirs(d, d1, d2);
+    double xi[3];
+    xi[d] = side;
+    xi[d1] = G[t % N];
+    xi[d2] = G[t / N];
+    const double wf = W[t % N] * W[t / N];
+    double J[3][3], C[3][3];
+    trilinear_jacobian(s_X, xi[0], xi[1], xi[2], J);
+    const double det = cofactor(J, C);
+    const double sg = side ? wf : -wf;
+    const double nu[3] = {sg * C[0][d], sg * C[1][d], sg * C[2][d]};
+    const double ds = sqrt(nu[0] * nu[0] + nu[1] * nu[1] + nu[2] * nu[2]);
+    double mm[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) mm[e] = (C[0][e] * nu[0] + C[1][e] * nu[1] + C[2][e] * nu[2]) / det;
+    double gm[3];
+    gm[d] = R1[3 * F + it];
+    gm[d1] = R1[F + it];
+    gm[d2] = R1[2 * F + it];
+    const double um = R1[it];
+    const double gmm = gm[0] * mm[0] + gm[1] * mm[1] + gm[2] * mm[2];
+    const double gmf = s_gam[f];
+    double cv, cs;  // value coefficient, scale of m- in the gradient coefficient
+    const int qd = pos[d] + (side ? 1 : -1);
+    if (qd >= 0 && qd < n) {
+      xi[d] = 1 - side;
+      trilinear_jacobian(s_Xn + 24 * f, xi[0], xi[1], xi[2], J);
+      const double detp = cofactor(J, C);
+      double gp[3];
+      gp[d] = R1[7 * F + it];
+      gp[d1] = R1[5 * F + it];
+      gp[d2] = R1[6 * F + it];
+      double gpm = 0.0;
+#pragma unroll
+      for (int e = 0; e < 3; ++e)
+        gpm += gp[e] * (C[0][e] * nu[0] + C[1][e] * nu[1] + C[2][e] * nu[2]);
+      gpm /= detp;
+      const double jump = um - R1[4 * F + it];
+      cv = gmf * ds * jump - 0.5 * (gmm + gpm);
+      cs = -0.5 * jump;
+    } else {
+      cv = gmf * ds * um - gmm;
+      cs = -um;
+    }
+    R2[it] = cv;
+    R2[F + it] = cs * mm[d1];
+    R2[2 * F + it] = cs * mm[d2];
+    R2[3 * F + it] = cs * mm[d];
+  }
+  __syncthreads();
+  line2<N, T, 1, true, false>(S, R2, R1, tid);
+  line2<N, T, 1, true, true>(D, R2 + 2 * F, R1, tid);
+  line2<N, T, 1, true, false>(S, R2 + F, R1 + F, tid);
+  line2<N, T, 1, true, false>(S, R2 + 3 * F, R1 + 2 * F, tid);
+  __syncthreads();
+  line2<N, T, 0, true, false>(S, R1, R2, tid);
+  line2<N, T, 0, true, true>(D, R1 + F, R2, tid);
+  line2<N, T, 0, true, false>(S, R1 + 2 * F, R2 + F, tid);
+  __syncthreads();
+  const double* __restrict__ bc = b ? b + (size_t)c * N3 : nullptr;
+  double* __restrict__ vc = v + (size_t)c * N3;
+  for (int p = tid; p < N3; p += T) {
+    const int id[3] = {p % N, (p / N) % N, p / N2};
+    double val = s_v[p];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      const int d = f >> 1, side = f & 1;
+      int d1, d2;
+      tdirs(d, d1, d2);
+      const int t = f * N2 + id[d1] + N * id[d2];
+      if (id[d] == (side ? N - 1 : 0)) val += R2[t];
+      val += (side ? D1 : D0)[id[d]] * R2[F + t];
+    }
+    vc[p] = bc ? bc[p] - val : val;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_apply_mapped(int N, const double* u, double* v, const double* b,
+                               const MappedLevel& g, const double* mtab, hipStream_t s) {
+  if (N < 2 || N > kMaxN || g.n < 1 || g.n > 1024 || !u || !v || !g.vert || !g.gam || !mtab)
+    return hipErrorInvalidValue;
+  const int nc = g.n * g.n * g.n;
+  const int chunk = (nc + 7) / 8;
+  const dim3 grid(8 * chunk);
+#define LAUNCH(NN)                                                                          \
+  hipLaunchKernelGGL(apply_mapped_kernel<NN>, grid, dim3(mapped_threads<NN>()), 0, s, u, v, \
+                     b, g.vert, g.gam, mtab, g.n, chunk)
+  switch (N) {
+    case 2: LAUNCH(2); break;
+    case 3: LAUNCH(3); break;
+    case 4: LAUNCH(4); break;
+    case 5: LAUNCH(5); break;
+    case 6: LAUNCH(6); break;
+    case 7: LAUNCH(7); break;
+    case 8: LAUNCH(8); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef LAUNCH
+  return hipGetLastError();
+}
+
+}  // namespace sipg

@@ -130,6 +130,7 @@ def load_library(path=None):
         "sipg_level_cells": (i32, [vp, i32]),
         "sipg_n_dofs": (i64, [vp, i32]),
         "sipg_apply": (i32, [vp, i32, vp, vp, vp]),
+        "sipg_set_geometry": (i32, [vp, vp, vp]),
         "sipg_apply_units": (i32, [vp, i32, vp, vp, i32, vp]),
         "sipg_apply_patchwise": (i32, [vp, i32, vp, vp, vp]),
         "sipg_residual": (i32, [vp, i32, vp, vp, vp, vp]),
@@ -240,6 +241,20 @@ class Problem:
     def new_vector(self, level=-1, dtype=None):
         import torch
         return torch.zeros(self.n_dofs(level), dtype=dtype or torch.float64, device="cuda")
+
+    def set_geometry(self, vertices, stream=None):
+        """Trilinear hexahedra through the finest level's vertex positions
+        (sipg_set_geometry): a float64 array of shape (n+1, n+1, n+1, 3)
+        indexed [vz, vy, vx]; None restores the Cartesian mesh."""
+        import numpy as np
+        if vertices is None:
+            _check(_lib.sipg_set_geometry(self._h, None, _stream(stream)))
+            return
+        n = self.cells[-1]
+        V = np.ascontiguousarray(vertices, dtype=np.float64)
+        if V.shape != (n + 1, n + 1, n + 1, 3):
+            raise ValueError(f"vertices must have shape {(n + 1,) * 3 + (3,)}")
+        _check(_lib.sipg_set_geometry(self._h, V.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
 
     def apply(self, u, v=None, level=-1, stream=None, units=None):
         """v = A u in FP64; units "vector" or "matrix" picks the execution
