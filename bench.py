@@ -358,6 +358,76 @@ def run_patchwise(stream, reps=10):
     return out
 
 
+def mapped_flops_per_dof(k):
+    """Model count of the trilinear-cell apply as implemented (FP64 vector
+    units): 16 sum-factorized N x N line products per cell (32 N flop/DoF),
+    ~206 flop per quadrature point for the Jacobian, its cofactors and the
+    metric product, and per cell 6 N^2 face points that each take
+    46 N flop of face-trace products and ~400 flop of two Jacobians, normals
+    and the flux terms, plus the expansion into the cell
+    (= 32 N + 500 + 2400 / N per DoF)."""
+    N = k + 1
+    return 32 * N + 500 + 2400 / N
+
+
+MAPPED_AMPLITUDE = 0.08
+
+
+def run_mapped(stream, reps=10):
+    """General geometry (trilinear hexahedra, Sec. 2.1 mapped integrals):
+    the apply at the benchmark sizes on the unit cube moved by a smooth
+    interior deformation (amplitude 0.08, seeded), timed with HIP events
+    beside the Cartesian apply on the same problem; then FGMRES + V(2,2)
+    solves (the Cartesian patch smoother and coarse solve as an approximate
+    inverse) on mapped and Cartesian meshes with the same seeded random
+    right-hand side, to rtol 1e-10."""
+    import torch
+    from paper_2407_09621_amd import Problem, inputs
+    out = {"mesh": f"unit cube, smooth deformation amplitude {MAPPED_AMPLITUDE}, seed 1"}
+    for k, n in ((3, 64), (5, 40), (7, 32)):
+        P = Problem(k, n, n_levels=1)
+        nd = P.n_dofs()
+        us = [torch.from_numpy(inputs.uniform_vector(nd, seed=60 + k + i)).cuda() for i in range(2)]
+        vs = [torch.empty_like(us[0]) for _ in range(2)]
+        mc = _event_ms(lambda i: P.apply(us[i % 2], vs[i % 2], stream=stream), reps, stream)
+        t0 = time.perf_counter()
+        P.set_geometry(inputs.mesh_vertices(n, "smooth", MAPPED_AMPLITUDE, seed=1))
+        setup = time.perf_counter() - t0
+        mm = _event_ms(lambda i: P.apply(us[i % 2], vs[i % 2], stream=stream), reps, stream)
+        g = nd / mm / 1e6
+        tf = g * mapped_flops_per_dof(k) / 1e3
+        bpd = BYTES_PER_DOF + 72.0 / (k + 1) ** 3
+        out[f"k{k}_n{n}"] = {
+            "n_dofs": nd, "mapped_ms": round(mm, 4), "mapped_gdof_s": round(g, 2),
+            "cartesian_ms": round(mc, 4), "mapped_over_cartesian_time": round(mm / mc, 2),
+            "flops_per_dof_model": round(mapped_flops_per_dof(k), 1),
+            "tflops_model": round(tf, 2), "frac_fp64_vector_peak": round(tf / FP64_PEAK_TFLOPS, 4),
+            "hbm_gb_s_algorithmic": round(g * bpd, 1),
+            "geometry_setup_s": round(setup, 3)}
+        P.close()
+        del us, vs
+        torch.cuda.empty_cache()
+    solves = {}
+    for k, n in ((3, 32), (7, 16)):
+        for geo in ("cartesian", "mapped"):
+            P = Problem(k, n)
+            if geo == "mapped":
+                P.set_geometry(inputs.mesh_vertices(n, "smooth", MAPPED_AMPLITUDE, seed=1))
+            b = torch.from_numpy(inputs.uniform_vector(P.n_dofs(), seed=77)).cuda()
+            P.fgmres(b, rtol=1e-10, max_iters=200, raise_on_nonconvergence=False)
+            x, info = P.fgmres(b, rtol=1e-10, max_iters=200, raise_on_nonconvergence=False)
+            solves[f"k{k}_n{n}_{geo}"] = {"iterations": info["iterations"],
+                                          "seconds": round(info["seconds"], 5),
+                                          "rel_res_true": info["rel_res_true"],
+                                          "status": info["status"]}
+            P.close()
+            del x, b
+    out["solves"] = solves
+    torch.cuda.empty_cache()
+    progress("general-geometry apply and solves done")
+    return out
+
+
 BATCH_SEED, BATCH_COUNT, BATCH_RESTART = 4, 64, 6
 SMALL_EDGES = (4, 6, 8, 12)
 
@@ -552,6 +622,8 @@ def main():
     ap.add_argument("--batch-count", type=int, default=BATCH_COUNT,
                     help="problems in the batched-solve measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-stage measurement")
+    ap.add_argument("--no-mapped", action="store_true",
+                    help="skip the general-geometry (trilinear cells) measurement")
     ap.add_argument("--cnn-loss", choices=["residual", "mse"], default="residual",
                     help="training loss of the learned stage")
     ap.add_argument("--cnn-chains", type=int, default=CNN_CHAINS,
@@ -633,6 +705,17 @@ def main():
                 print(f"profiled V-cycles k={kv} n=32 {prec}: 2", flush=True)
                 Pv.close()
                 del bv, xv
+        for kv, nv in ((3, 64), (7, 32)):  # applies on trilinear cells
+            Pm = Problem(kv, nv, n_levels=1)
+            Pm.set_geometry(inputs.mesh_vertices(nv, "smooth", MAPPED_AMPLITUDE, seed=1))
+            um = torch.from_numpy(inputs.uniform_vector(Pm.n_dofs(), 6)).to(dev)
+            vm = torch.empty_like(um)
+            for _ in range(3):
+                Pm.apply(um, vm, stream=stream)
+            torch.cuda.synchronize()
+            print(f"profiled general-geometry apply k={kv} n={nv}: 3 launches", flush=True)
+            Pm.close()
+            del um, vm
         from paper_2407_09621_amd import Network
         Pt = Problem(3, 32)
         for loss in ("residual", "mse"):
@@ -744,6 +827,7 @@ def main():
         batch = {"large": run_batch(count=args.batch_count),
                  "small": run_batch(count=args.batch_count, edges=SMALL_EDGES)}
     learned = None if args.no_learned else run_learned(args.cnn_chains, args.cnn_loss)
+    mapped = None if args.no_mapped else run_mapped(stream)
 
     line = {
         "metric": "SIPG apply GDoF/s (FP64/FP16 MFMA); FGMRES-MG solve time at equal L2 error",
@@ -759,6 +843,7 @@ def main():
         "lowprec_apply": lp_rates, "patchwise_sweep": patchwise, "solves": solves,
         "vcycles": vcycles,
         "krylov_smoother_comparison": comparisons, "batch": batch, "learned": learned,
+        "general_geometry": mapped,
     }
     print(json.dumps(line))
 
