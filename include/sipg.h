@@ -143,8 +143,11 @@ sipg_status sipg_apply(sipg_problem* p, int level, const double* u, double* v,
  * inverse on mapped cells; the outer FGMRES corrects for it).  NULL
  * restores the Cartesian mesh.  SIPG_ERR_UNSUPPORTED unless mg_precision is
  * SIPG_F64 and the smoother is 0 or 1; while a geometry is set,
+ * sipg_rhs_sines and sipg_l2_error_sines integrate over the mapped cells
+ * (the same Gauss rules with det J at every point; the sine modes vanish on
+ * the boundary only where it stays on the unit cube's faces), and
  * sipg_apply_units, sipg_apply_patchwise, sipg_apply_lp, sipg_autotune,
- * sipg_rhs_sines, the L2 errors, the learned stage and the network training
+ * sipg_l2_error_sines_noalloc, the learned stage and the network training
  * return SIPG_ERR_UNSUPPORTED (they are Cartesian).  SIPG_ERR_ARG when a
  * cell has a non-positive Jacobian determinant at a Gauss point or corner
  * (the previous geometry is kept).  Synchronizes `stream`. */

@@ -292,3 +292,53 @@ def min_jacobian(n, k, V):
                 _, J = trilinear(cell_vertices(V, cx, cy, cz), pts)
                 m = min(m, float(np.linalg.det(J).min()))
     return m
+
+
+def _mapped_cell_rule(k, nq, X):
+    """Physical points [Q, 3] and weights w_q det J [Q] of the nq-point Gauss
+    rule per direction on the trilinear cell X, and the reference basis
+    values there [Q, N^3]."""
+    N = k + 1
+    xq, wq = basis1d.gauss_rule(nq)
+    P = np.array([(a, b, c) for c in xq for b in xq for a in xq])
+    W = np.array([wa * wb * wc for wc in wq for wb in wq for wa in wq])
+    x, J = trilinear(X, P)
+    Vq = basis1d.lagrange_values(basis1d.gll_nodes(k), xq)
+    qi = np.arange(nq ** 3)
+    a, b, c = qi % nq, (qi // nq) % nq, qi // (nq * nq)
+    loc = np.arange(N ** 3)
+    i, j, l = loc % N, (loc // N) % N, loc // (N * N)
+    Phi = Vq[a][:, i] * Vq[b][:, j] * Vq[c][:, l]
+    return x, W * np.linalg.det(J), Phi
+
+
+def rhs_mapped(problem, n, k, V):
+    """b_I = int_K f phi_I dx on every trilinear cell, (k+2)-point Gauss rule
+    per direction with the per-point det J (the Cartesian rule of
+    ``oracle.rhs`` on the mapped cells); cell-blocked order."""
+    V = _check(V, n)
+    out = []
+    for cz in range(n):
+        for cy in range(n):
+            for cx in range(n):
+                x, w, Phi = _mapped_cell_rule(k, k + 2, cell_vertices(V, cx, cy, cz))
+                out.append((problem.f(x[:, 0], x[:, 1], x[:, 2]) * w) @ Phi)
+    return np.concatenate(out)
+
+
+def l2_error_mapped(problem, uh, n, k, V):
+    """||u - u_h||_L2 over the mapped mesh, (k+3)-point Gauss rule per
+    direction with the per-point det J."""
+    V = _check(V, n)
+    N3 = (k + 1) ** 3
+    uh = np.asarray(uh).reshape(n ** 3, N3)
+    s = 0.0
+    c = 0
+    for cz in range(n):
+        for cy in range(n):
+            for cx in range(n):
+                x, w, Phi = _mapped_cell_rule(k, k + 3, cell_vertices(V, cx, cy, cz))
+                e = problem.u(x[:, 0], x[:, 1], x[:, 2]) - Phi @ uh[c]
+                s += float(w @ (e * e))
+                c += 1
+    return float(np.sqrt(s))

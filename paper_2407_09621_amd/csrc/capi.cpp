@@ -31,16 +31,21 @@ int tile_order(const sipg_problem* p, int l) {
   return (l < (int)p->order.size()) ? p->order[l] : 0;
 }
 
+// the device geometry of level l (sipg_set_geometry)
+MappedLevel mapped_level(const sipg_problem* p, int l) {
+  MappedLevel g;
+  g.vert = p->geo_vert[l];
+  g.gam = p->geo_gam[l];
+  g.n = p->n[l];
+  return g;
+}
+
 // v = A_l u, or v = b - A_l u when b != nullptr: the Cartesian kernels, or the
 // trilinear-cell kernel once a geometry is set
 sipg_status op_apply(sipg_problem* p, int l, const double* u, double* v, const double* b,
                      hipStream_t s) {
   if (p->mapped) {
-    MappedLevel g;
-    g.vert = p->geo_vert[l];
-    g.gam = p->geo_gam[l];
-    g.n = p->n[l];
-    SIPG_HIP(launch_apply_mapped(p->N, u, v, b, g, p->d_mtab, s));
+    SIPG_HIP(launch_apply_mapped(p->N, u, v, b, mapped_level(p, l), p->d_mtab, s));
     return SIPG_OK;
   }
   ApplyJob j{u, v, b, p->n[l], level_h(p, l), tile_order(p, l)};
@@ -212,6 +217,29 @@ sipg_status ensure_aux(sipg_problem* p, size_t count) {
   p->aux_size = 0;
   SIPG_TRY(prob_alloc(p, &p->d_aux, count));
   p->aux_size = count;
+  return SIPG_OK;
+}
+
+// Sine modes and the nq-point quadrature table of the trilinear-cell RHS / L2
+// error in the aux buffer: [n_modes][c, p, q, r] (c = amplitude, times
+// pi^2 (p^2 + q^2 + r^2) for -Laplace u), then quad_table(k, nq).  Returns the
+// offset of the quadrature table.
+sipg_status upload_mapped_modes(sipg_problem* p, int n_modes, const double* amps, const int* pqr,
+                                bool laplace, int nq, size_t* qoff, hipStream_t s) {
+  std::vector<double> host((size_t)4 * n_modes);
+  for (int m = 0; m < n_modes; ++m) {
+    const double pp = pqr[3 * m], qq = pqr[3 * m + 1], rr = pqr[3 * m + 2];
+    host[4 * m] = amps[m] * (laplace ? M_PI * M_PI * (pp * pp + qq * qq + rr * rr) : 1.0);
+    host[4 * m + 1] = pp;
+    host[4 * m + 2] = qq;
+    host[4 * m + 3] = rr;
+  }
+  *qoff = host.size();
+  const std::vector<double> qt = quad_table(p->k, nq);
+  host.insert(host.end(), qt.begin(), qt.end());
+  SIPG_TRY(ensure_aux(p, host.size()));
+  SIPG_HIP(hipMemcpyAsync(p->d_aux, host.data(), host.size() * sizeof(double),
+                          hipMemcpyHostToDevice, s));
   return SIPG_OK;
 }
 
@@ -817,8 +845,15 @@ sipg_status sipg_fgmres(sipg_problem* p, double* x, const double* b, const sipg_
 sipg_status sipg_rhs_sines(sipg_problem* p, int level, int n_modes, const double* amps,
                            const int* pqr, double* b, hipStream_t s) {
   SIPG_TRY(check_level(p, level));
-  SIPG_TRY(cartesian_only(p, "sipg_rhs_sines"));
   if (n_modes < 1 || n_modes > 64 || !amps || !pqr || !b) return fail(SIPG_ERR_ARG, "bad modes");
+  if (p->mapped) {  // trilinear cells: f at every quadrature point, det J weights
+    size_t qoff = 0;
+    SIPG_TRY(upload_mapped_modes(p, n_modes, amps, pqr, true, p->k + 2, &qoff, s));
+    SIPG_HIP(launch_rhs_mapped(p->N, mapped_level(p, level), n_modes, p->d_aux, p->d_aux + qoff,
+                               b, s));
+    SIPG_HIP(hipStreamSynchronize(s));
+    return SIPG_OK;
+  }
   const int N = p->N, nl = p->n[level];
   const double h = 1.0 / nl;
   std::vector<double> nodes = make_tables_1d(p->k).nodes, xq, wq, V;
@@ -857,9 +892,19 @@ sipg_status sipg_rhs_sines(sipg_problem* p, int level, int n_modes, const double
 sipg_status sipg_l2_error_sines(sipg_problem* p, int level, int n_modes, const double* amps,
                                 const int* pqr, const double* x, double* err, hipStream_t s) {
   SIPG_TRY(check_level(p, level));
-  SIPG_TRY(cartesian_only(p, "sipg_l2_error_sines"));
   if (n_modes < 1 || n_modes > 64 || !amps || !pqr || !x || !err)
     return fail(SIPG_ERR_ARG, "bad modes");
+  if (p->mapped) {
+    size_t qoff = 0;
+    SIPG_TRY(upload_mapped_modes(p, n_modes, amps, pqr, false, p->k + 3, &qoff, s));
+    SIPG_HIP(launch_l2_mapped(p->N, mapped_level(p, level), n_modes, p->d_aux, p->d_aux + qoff,
+                              x, p->d_partial, kDotBlocks, p->d_small + 300, s));
+    double e2 = 0.0;
+    SIPG_HIP(hipMemcpyAsync(&e2, p->d_small + 300, sizeof(double), hipMemcpyDeviceToHost, s));
+    SIPG_HIP(hipStreamSynchronize(s));
+    *err = std::sqrt(e2);
+    return SIPG_OK;
+  }
   const int N = p->N, nl = p->n[level], nq = p->k + 3;
   std::vector<double> host(l2_table_size(n_modes, nl, nq, N));
   l2_fill_tables(p, nl, n_modes, amps, pqr, host.data());

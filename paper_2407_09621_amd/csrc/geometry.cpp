@@ -63,6 +63,17 @@ std::vector<double> mapped_table(int k) {
   return out;
 }
 
+std::vector<double> quad_table(int k, int nq) {
+  const Tables1D t = make_tables_1d(k);
+  std::vector<double> g, w, V;
+  gauss_legendre(nq, g, w);
+  lagrange_eval(t.nodes, g, V, nullptr);
+  std::vector<double> out(V);
+  out.insert(out.end(), w.begin(), w.end());
+  out.insert(out.end(), g.begin(), g.end());
+  return out;
+}
+
 bool mapped_penalties(int k, int n, const double* V, double penalty_scale,
                       std::vector<double>& gam, std::string& err) {
   const int N = k + 1;

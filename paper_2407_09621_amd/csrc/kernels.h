@@ -142,5 +142,15 @@ struct MappedLevel {
 // mtab is the device copy of mapped_table(k).  u and v must not alias.
 hipError_t launch_apply_mapped(int N, const double* u, double* v, const double* b,
                                const MappedLevel& g, const double* mtab, hipStream_t s);
+// b = int f phi on the trilinear cells, f a sum of nm sine modes (modes:
+// [nm][coefficient, p, q, r]); qtab = quad_table(k, k + 2).
+hipError_t launch_rhs_mapped(int N, const MappedLevel& g, int nm, const double* modes,
+                             const double* qtab, double* b, hipStream_t s);
+// out[0] = int (u - x)^2 over the trilinear cells, u a sum of nm sine modes
+// (modes: [nm][amplitude, p, q, r]); qtab = quad_table(k, k + 3); partial
+// holds max_blocks doubles.
+hipError_t launch_l2_mapped(int N, const MappedLevel& g, int nm, const double* modes,
+                            const double* qtab, const double* x, double* partial, int max_blocks,
+                            double* out, hipStream_t s);
 
 }  // namespace sipg

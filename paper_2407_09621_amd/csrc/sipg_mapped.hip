@@ -30,18 +30,27 @@ namespace sipg {
 
 namespace {
 
-// dx_i / dxi_d of the trilinear map through X (vertex a + 2b + 4c at
-// X[3 (a + 2b + 4c) + i]) at the reference point (x0, x1, x2)
-__device__ __forceinline__ void trilinear_jacobian(const double* X, double x0, double x1,
-                                                   double x2, double J[3][3]) {
-  const double a0 = 1.0 - x0, a1 = 1.0 - x1, a2 = 1.0 - x2;
+// column `col` of the Jacobian dx_i / dxi_col of the trilinear map through X
+// (vertex a + 2b + 4c at X[3 (a + 2b + 4c) + i]); it depends only on the two
+// other reference coordinates, xa < xb in direction order
+__device__ __forceinline__ void jac_column(const double* X, int col, double xa, double xb,
+                                           double out[3]) {
+  // vertex pairs (hi, lo) along col, ordered by the other two corner bits
+  const int step = col == 0 ? 1 : (col == 1 ? 2 : 4);
+  const int sa = col == 0 ? 2 : 1;          // bit of the first other direction
+  const int sb = col == 2 ? 2 : 4;          // bit of the second
+  const double wa[2] = {1.0 - xa, xa}, wb[2] = {1.0 - xb, xb};
+#pragma unroll
   for (int i = 0; i < 3; ++i) {
-    J[i][0] = (X[3 + i] - X[i]) * a1 * a2 + (X[9 + i] - X[6 + i]) * x1 * a2 +
-              (X[15 + i] - X[12 + i]) * a1 * x2 + (X[21 + i] - X[18 + i]) * x1 * x2;
-    J[i][1] = (X[6 + i] - X[i]) * a0 * a2 + (X[9 + i] - X[3 + i]) * x0 * a2 +
-              (X[18 + i] - X[12 + i]) * a0 * x2 + (X[21 + i] - X[15 + i]) * x0 * x2;
-    J[i][2] = (X[12 + i] - X[i]) * a0 * a1 + (X[15 + i] - X[3 + i]) * x0 * a1 +
-              (X[18 + i] - X[6 + i]) * a0 * x1 + (X[21 + i] - X[9 + i]) * x0 * x1;
+    double s = 0.0;
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int lo = a * sa + bb * sb;
+        s += (X[3 * (lo + step) + i] - X[3 * lo + i]) * wa[a] * wb[bb];
+      }
+    out[i] = s;
   }
 }
 
@@ -117,6 +126,11 @@ __global__ __launch_bounds__(mapped_threads<N>()) void apply_mapped_kernel(
   __shared__ double s_v[N3];
   __shared__ double s_a[RA];     // cell stage arrays, then face region 2 (6 arrays)
   __shared__ double s_r1[8 * F]; // face region 1 (8 arrays)
+  // Jacobian columns at the Gauss points and the ends 0, 1 (extended index
+  // N + side): column c at the extended indices (ea, eb) of the two other
+  // directions, s_J[((3 c + i) * E + eb) * E + ea]
+  constexpr int E = N + 2;
+  __shared__ double s_J[9 * E * E];
   const int tid = threadIdx.x;
   const int nc = n * n * n;
   const int c = (int)(blockIdx.x % 8) * chunk + (int)(blockIdx.x / 8);
@@ -154,6 +168,24 @@ __global__ __launch_bounds__(mapped_threads<N>()) void apply_mapped_kernel(
   const double* D0 = G + N;
   const double* D1 = D0 + N;
 
+  for (int e = tid; e < 9 * E * E; e += T) {
+    const int ea = e % E, eb = (e / E) % E, ci = e / (E * E);
+    const double xa = ea < N ? G[ea] : (double)(ea - N);
+    const double xb = eb < N ? G[eb] : (double)(eb - N);
+    double col[3];
+    jac_column(s_X, ci / 3, xa, xb, col);
+    s_J[e] = col[ci % 3];
+  }
+  // J at the point with extended indices (e0, e1, e2)
+  auto jac_at = [&](int e0, int e1, int e2, double J[3][3]) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      J[i][0] = s_J[((0 * 3 + i) * E + e2) * E + e1];
+      J[i][1] = s_J[((1 * 3 + i) * E + e2) * E + e0];
+      J[i][2] = s_J[((2 * 3 + i) * E + e1) * E + e0];
+    }
+  };
+
   // ---- cell term: reference gradient at the Gauss points, metric, transpose
   double* t0 = s_a;
   double* t1 = s_a + N3;
@@ -174,7 +206,7 @@ __global__ __launch_bounds__(mapped_threads<N>()) void apply_mapped_kernel(
   for (int p = tid; p < N3; p += T) {
     const int qx = p % N, qy = (p / N) % N, qz = p / N2;
     double J[3][3], C[3][3];
-    trilinear_jacobian(s_X, G[qx], G[qy], G[qz], J);
+    jac_at(qx, qy, qz, J);
     const double det = cofactor(J, C);
     const double g0 = t0[p], g1 = t1[p], g2 = s_v[p];
     double h[3];
@@ -250,13 +282,13 @@ __global__ __launch_bounds__(mapped_threads<N>()) void apply_mapped_kernel(
     const int f = it / N2, t = it % N2, d = f >> 1, side = f & 1;
     int d1, d2;
     tdirs(d, d1, d2);
-    double xi[3];
-    xi[d] = side;
-    xi[d1] = G[t % N];
-    xi[d2] = G[t / N];
+    int ex[3];
+    ex[d] = N + side;
+    ex[d1] = t % N;
+    ex[d2] = t / N;
     const double wf = W[t % N] * W[t / N];
     double J[3][3], C[3][3];
-    trilinear_jacobian(s_X, xi[0], xi[1], xi[2], J);
+    jac_at(ex[0], ex[1], ex[2], J);
     const double det = cofactor(J, C);
     const double sg = side ? wf : -wf;
     const double nu[3] = {sg * C[0][d], sg * C[1][d], sg * C[2][d]};
@@ -274,8 +306,13 @@ __global__ __launch_bounds__(mapped_threads<N>()) void apply_mapped_kernel(
     double cv, cs;  // value coefficient, scale of m- in the gradient coefficient
     const int qd = pos[d] + (side ? 1 : -1);
     if (qd >= 0 && qd < n) {
-      xi[d] = 1 - side;
-      trilinear_jacobian(s_Xn + 24 * f, xi[0], xi[1], xi[2], J);
+      // the neighbour's Jacobian on the shared face: the same tangential
+      // columns (the same bilinear face), its own normal column
+      double cn[3];
+      jac_column(s_Xn + 24 * f, d, G[t % N], G[t / N], cn);
+      J[0][d] = cn[0];
+      J[1][d] = cn[1];
+      J[2][d] = cn[2];
       const double detp = cofactor(J, C);
       double gp[3];
       gp[d] = R1[7 * F + it];
@@ -326,6 +363,178 @@ __global__ __launch_bounds__(mapped_threads<N>()) void apply_mapped_kernel(
   }
 }
 
+// Contraction along DIR of a (d0, d1, d2) array (x fastest) with the table
+// M = [NQ][NB] (row-major, basis at the quadrature points): INTERP maps NB
+// nodes to NQ points, out[o] = sum_a M[o NB + a] in[a]; otherwise NQ points
+// to NB nodes, out[o] = sum_a M[a NB + o] in[a] (the transpose).
+template <int T, int DIR, bool INTERP, int NB, int NQ>
+__device__ __forceinline__ void contract_q(const double* M, const double* src, double* dst,
+                                           int d0, int d1, int d2, int tid) {
+  constexpr int IN = INTERP ? NB : NQ, OUT = INTERP ? NQ : NB;
+  const int e0 = DIR == 0 ? OUT : d0, e1 = DIR == 1 ? OUT : d1, e2 = DIR == 2 ? OUT : d2;
+  const int total = e0 * e1 * e2;
+  for (int p = tid; p < total; p += T) {
+    const int o0 = p % e0, o1 = (p / e0) % e1, o2 = p / (e0 * e1);
+    const int o = DIR == 0 ? o0 : (DIR == 1 ? o1 : o2);
+    const int sst = DIR == 0 ? 1 : (DIR == 1 ? d0 : d0 * d1);
+    const int base = (DIR == 0 ? 0 : o0) + (DIR == 1 ? 0 : o1) * d0 + (DIR == 2 ? 0 : o2) * d0 * d1;
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < IN; ++a)
+      acc += (INTERP ? M[o * NB + a] : M[a * NB + o]) * src[base + a * sst];
+    dst[p] = acc;
+  }
+}
+
+// position and det J of the trilinear map through X at (x0, x1, x2)
+__device__ __forceinline__ double map_point(const double* X, double x0, double x1, double x2,
+                                            double pos[3]) {
+  const double w0[2] = {1.0 - x0, x0}, w1[2] = {1.0 - x1, x1}, w2[2] = {1.0 - x2, x2};
+  pos[0] = pos[1] = pos[2] = 0.0;
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    const double w = w0[v & 1] * w1[(v >> 1) & 1] * w2[v >> 2];
+    pos[0] += w * X[3 * v];
+    pos[1] += w * X[3 * v + 1];
+    pos[2] += w * X[3 * v + 2];
+  }
+  double J[3][3], C[3][3], col[3];
+  jac_column(X, 0, x1, x2, col);
+  J[0][0] = col[0]; J[1][0] = col[1]; J[2][0] = col[2];
+  jac_column(X, 1, x0, x2, col);
+  J[0][1] = col[0]; J[1][1] = col[1]; J[2][1] = col[2];
+  jac_column(X, 2, x0, x1, col);
+  J[0][2] = col[0]; J[1][2] = col[1]; J[2][2] = col[2];
+  return cofactor(J, C);
+}
+
+// sum_m s_m[4m] sin(s_m[4m+1] pi x) sin(s_m[4m+2] pi y) sin(s_m[4m+3] pi z)
+__device__ __forceinline__ double sine_modes(const double* m, int nm, const double pos[3]) {
+  double s = 0.0;
+  for (int i = 0; i < nm; ++i)
+    s += m[4 * i] * sin(m[4 * i + 1] * M_PI * pos[0]) * sin(m[4 * i + 2] * M_PI * pos[1]) *
+         sin(m[4 * i + 3] * M_PI * pos[2]);
+  return s;
+}
+
+constexpr int kMappedRhsT = 256;
+
+// b_I = int_K f phi_I dx on every trilinear cell (one workgroup per cell),
+// (N+1)-point Gauss rule per direction with det J at every point.  modes:
+// [nm][coefficient of -Laplace u, p, q, r]; qtab: basis at the points
+// [Q][N], weights [Q], points [Q].
+template <int N>
+__global__ __launch_bounds__(kMappedRhsT) void rhs_mapped_kernel(
+    const double* __restrict__ vert, int n, int nm, const double* __restrict__ modes,
+    const double* __restrict__ qtab, double* __restrict__ b) {
+  constexpr int Q = N + 1, T = kMappedRhsT;
+  __shared__ double s_X[24];
+  __shared__ double s_tab[Q * N + 2 * Q];
+  __shared__ double s_m[4 * 64];
+  __shared__ double s_F[Q * Q * Q];
+  __shared__ double s_T1[N * Q * Q];
+  __shared__ double s_T2[N * N * Q];
+  const int tid = threadIdx.x;
+  const int c = blockIdx.x;
+  const int pos0[3] = {c % n, (c / n) % n, c / (n * n)};
+  const size_t n1 = (size_t)n + 1;
+  if (tid < 24) {
+    const int w = tid / 3, i = tid % 3;
+    s_X[tid] = vert[(((pos0[2] + (w >> 2)) * n1 + pos0[1] + ((w >> 1) & 1)) * n1 + pos0[0] +
+                     (w & 1)) * 3 + i];
+  }
+  for (int i = tid; i < Q * N + 2 * Q; i += T) s_tab[i] = qtab[i];
+  for (int i = tid; i < 4 * nm; i += T) s_m[i] = modes[i];
+  __syncthreads();
+  const double* Vq = s_tab;
+  const double* wq = s_tab + Q * N;
+  const double* xq = wq + Q;
+  for (int q = tid; q < Q * Q * Q; q += T) {
+    const int qa = q % Q, qb = (q / Q) % Q, qc = q / (Q * Q);
+    double pos[3];
+    const double det = map_point(s_X, xq[qa], xq[qb], xq[qc], pos);
+    s_F[q] = wq[qa] * wq[qb] * wq[qc] * det * sine_modes(s_m, nm, pos);
+  }
+  __syncthreads();
+  contract_q<T, 0, false, N, Q>(Vq, s_F, s_T1, Q, Q, Q, tid);
+  __syncthreads();
+  contract_q<T, 1, false, N, Q>(Vq, s_T1, s_T2, N, Q, Q, tid);
+  __syncthreads();
+  contract_q<T, 2, false, N, Q>(Vq, s_T2, b + (size_t)c * N * N * N, N, N, Q, tid);
+}
+
+// Partial sums of int (u - u_h)^2 dx over the trilinear cells, (N+2)-point
+// Gauss rule per direction: workgroup g takes cells g, g + grid, ...;
+// modes: [nm][amplitude, p, q, r].
+template <int N>
+__global__ __launch_bounds__(kMappedRhsT) void l2_mapped_kernel(
+    const double* __restrict__ vert, int n, int nm, const double* __restrict__ modes,
+    const double* __restrict__ qtab, const double* __restrict__ x, double* __restrict__ partial) {
+  constexpr int Q = N + 2, T = kMappedRhsT, N3 = N * N * N;
+  __shared__ double s_X[24];
+  __shared__ double s_tab[Q * N + 2 * Q];
+  __shared__ double s_m[4 * 64];
+  __shared__ double s_U[N3];
+  __shared__ double s_T1[Q * N * N];
+  __shared__ double s_T2[Q * Q * N];
+  __shared__ double s_T3[Q * Q * Q];
+  __shared__ double s_red[T / 64];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < Q * N + 2 * Q; i += T) s_tab[i] = qtab[i];
+  for (int i = tid; i < 4 * nm; i += T) s_m[i] = modes[i];
+  const double* Vq = s_tab;
+  const double* wq = s_tab + Q * N;
+  const double* xq = wq + Q;
+  const int nc = n * n * n;
+  const size_t n1 = (size_t)n + 1;
+  double acc = 0.0;
+  for (int c = blockIdx.x; c < nc; c += gridDim.x) {
+    __syncthreads();
+    const int pos0[3] = {c % n, (c / n) % n, c / (n * n)};
+    if (tid < 24) {
+      const int w = tid / 3, i = tid % 3;
+      s_X[tid] = vert[(((pos0[2] + (w >> 2)) * n1 + pos0[1] + ((w >> 1) & 1)) * n1 + pos0[0] +
+                       (w & 1)) * 3 + i];
+    }
+    for (int i = tid; i < N3; i += T) s_U[i] = x[(size_t)c * N3 + i];
+    __syncthreads();
+    contract_q<T, 0, true, N, Q>(Vq, s_U, s_T1, N, N, N, tid);
+    __syncthreads();
+    contract_q<T, 1, true, N, Q>(Vq, s_T1, s_T2, Q, N, N, tid);
+    __syncthreads();
+    contract_q<T, 2, true, N, Q>(Vq, s_T2, s_T3, Q, Q, N, tid);
+    __syncthreads();
+    for (int q = tid; q < Q * Q * Q; q += T) {
+      const int qa = q % Q, qb = (q / Q) % Q, qc = q / (Q * Q);
+      double pos[3];
+      const double det = map_point(s_X, xq[qa], xq[qb], xq[qc], pos);
+      const double e = sine_modes(s_m, nm, pos) - s_T3[q];
+      acc += wq[qa] * wq[qb] * wq[qc] * det * e * e;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((tid & 63) == 0) s_red[tid >> 6] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+    for (int i = 0; i < T / 64; ++i) s += s_red[i];
+    partial[blockIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(256) void sum_partials_kernel(const double* __restrict__ partial,
+                                                           int nb, double* __restrict__ out) {
+  __shared__ double s_red[4];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) acc += partial[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) out[0] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+}
+
 }  // namespace
 
 hipError_t launch_apply_mapped(int N, const double* u, double* v, const double* b,
@@ -349,6 +558,57 @@ hipError_t launch_apply_mapped(int N, const double* u, double* v, const double* 
     default: return hipErrorInvalidValue;
   }
 #undef LAUNCH
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs_mapped(int N, const MappedLevel& g, int nm, const double* modes,
+                             const double* qtab, double* b, hipStream_t s) {
+  if (N < 2 || N > kMaxN || g.n < 1 || g.n > 1024 || nm < 1 || nm > 64 || !g.vert || !modes ||
+      !qtab || !b)
+    return hipErrorInvalidValue;
+  const dim3 grid(g.n * g.n * g.n);
+#define LAUNCH(NN)                                                                     \
+  hipLaunchKernelGGL(rhs_mapped_kernel<NN>, grid, dim3(kMappedRhsT), 0, s, g.vert, g.n, nm, \
+                     modes, qtab, b)
+  switch (N) {
+    case 2: LAUNCH(2); break;
+    case 3: LAUNCH(3); break;
+    case 4: LAUNCH(4); break;
+    case 5: LAUNCH(5); break;
+    case 6: LAUNCH(6); break;
+    case 7: LAUNCH(7); break;
+    case 8: LAUNCH(8); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef LAUNCH
+  return hipGetLastError();
+}
+
+hipError_t launch_l2_mapped(int N, const MappedLevel& g, int nm, const double* modes,
+                            const double* qtab, const double* x, double* partial, int max_blocks,
+                            double* out, hipStream_t s) {
+  if (N < 2 || N > kMaxN || g.n < 1 || g.n > 1024 || nm < 1 || nm > 64 || !g.vert || !modes ||
+      !qtab || !x || !partial || !out || max_blocks < 1)
+    return hipErrorInvalidValue;
+  const int nc = g.n * g.n * g.n;
+  const int nb = nc < max_blocks ? nc : max_blocks;
+#define LAUNCH(NN)                                                                          \
+  hipLaunchKernelGGL(l2_mapped_kernel<NN>, dim3(nb), dim3(kMappedRhsT), 0, s, g.vert, g.n, nm, \
+                     modes, qtab, x, partial)
+  switch (N) {
+    case 2: LAUNCH(2); break;
+    case 3: LAUNCH(3); break;
+    case 4: LAUNCH(4); break;
+    case 5: LAUNCH(5); break;
+    case 6: LAUNCH(6); break;
+    case 7: LAUNCH(7); break;
+    case 8: LAUNCH(8); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef LAUNCH
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partial, nb, out);
   return hipGetLastError();
 }
 
