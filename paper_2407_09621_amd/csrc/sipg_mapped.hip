@@ -73,14 +73,54 @@ constexpr int mapped_threads() {
   return N <= 4 ? 64 : 256;
 }
 
+// The points a thread of a T-thread workgroup takes in the stage loops over
+// a cell block (p = tid + j T < N^3) with their three coordinates, and over
+// the six faces' N x N arrays (it = tid + j T < 6 N^2) with their two
+// tangential coordinates, computed once instead of in every stage.
+template <int N, int T>
+struct CellPts {
+  static constexpr int PP = (N * N * N + T - 1) / T;
+  int p[PP], o[3][PP];
+  __device__ __forceinline__ explicit CellPts(int tid) {
+#pragma unroll
+    for (int j = 0; j < PP; ++j) {
+      const int q = tid + j * T;
+      p[j] = q;
+      o[0][j] = q % N;
+      o[1][j] = (q / N) % N;
+      o[2][j] = q / (N * N);
+    }
+  }
+  __device__ __forceinline__ bool ok(int j) const { return PP * T == N * N * N || p[j] < N * N * N; }
+};
+
+template <int N, int T>
+struct FacePts {
+  static constexpr int PF = (6 * N * N + T - 1) / T;
+  int p[PF], o[2][PF];
+  __device__ __forceinline__ explicit FacePts(int tid) {
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+      const int q = tid + j * T;
+      p[j] = q;
+      o[0][j] = (q % (N * N)) % N;
+      o[1][j] = (q % (N * N)) / N;
+    }
+  }
+  __device__ __forceinline__ bool ok(int j) const { return PF * T == 6 * N * N || p[j] < 6 * N * N; }
+};
+
 // dst[p] (+)= sum_a M'[o][a] src[p with its index o along DIR replaced by a]
 // over the N^3 points of a cell block (x fastest); M' = M (row-major
 // M[o * N + a]) or, for TR, its transpose
 template <int N, int T, int DIR, bool TR, bool ACC>
-__device__ __forceinline__ void line3(const double* M, const double* src, double* dst, int tid) {
+__device__ __forceinline__ void line3(const double* M, const double* src, double* dst,
+                                      const CellPts<N, T>& P) {
   constexpr int st = DIR == 0 ? 1 : (DIR == 1 ? N : N * N);
-  for (int p = tid; p < N * N * N; p += T) {
-    const int o = (p / st) % N;
+#pragma unroll
+  for (int j = 0; j < CellPts<N, T>::PP; ++j) {
+    if (!P.ok(j)) continue;
+    const int p = P.p[j], o = P.o[DIR][j];
     const int base = p - o * st;
     double s = 0.0;
 #pragma unroll
@@ -92,11 +132,13 @@ __device__ __forceinline__ void line3(const double* M, const double* src, double
 // the same on the six N x N face arrays (index t1 + N t2, face-major);
 // DIR 0 contracts along t1, 1 along t2
 template <int N, int T, int DIR, bool TR, bool ACC>
-__device__ __forceinline__ void line2(const double* M, const double* src, double* dst, int tid) {
+__device__ __forceinline__ void line2(const double* M, const double* src, double* dst,
+                                      const FacePts<N, T>& P) {
   constexpr int st = DIR == 0 ? 1 : N;
-  for (int it = tid; it < 6 * N * N; it += T) {
-    const int p = it % (N * N);
-    const int o = (p / st) % N;
+#pragma unroll
+  for (int j = 0; j < FacePts<N, T>::PF; ++j) {
+    if (!P.ok(j)) continue;
+    const int it = P.p[j], o = P.o[DIR][j];
     const int base = it - o * st;
     double s = 0.0;
 #pragma unroll
@@ -132,6 +174,8 @@ __global__ __launch_bounds__(mapped_threads<N>()) void apply_mapped_kernel(
   constexpr int E = N + 2;
   __shared__ double s_J[9 * E * E];
   const int tid = threadIdx.x;
+  const CellPts<N, T> P3(tid);
+  const FacePts<N, T> P2(tid);
   const int nc = n * n * n;
   const int c = (int)(blockIdx.x % 8) * chunk + (int)(blockIdx.x / 8);
   if (c >= nc) return;  // the whole workgroup, before any barrier
@@ -192,19 +236,21 @@ __global__ __launch_bounds__(mapped_threads<N>()) void apply_mapped_kernel(
   double* p1 = s_a + 2 * N3;
   double* p2 = s_a + 3 * N3;
   double* p3 = s_a + 4 * N3;
-  line3<N, T, 0, false, false>(S, s_u, t0, tid);
-  line3<N, T, 0, false, false>(D, s_u, t1, tid);
+  line3<N, T, 0, false, false>(S, s_u, t0, P3);
+  line3<N, T, 0, false, false>(D, s_u, t1, P3);
   __syncthreads();
-  line3<N, T, 1, false, false>(S, t1, p1, tid);  // d/dxi0 branch
-  line3<N, T, 1, false, false>(D, t0, p2, tid);  // d/dxi1 branch
-  line3<N, T, 1, false, false>(S, t0, p3, tid);  // d/dxi2 branch
+  line3<N, T, 1, false, false>(S, t1, p1, P3);  // d/dxi0 branch
+  line3<N, T, 1, false, false>(D, t0, p2, P3);  // d/dxi1 branch
+  line3<N, T, 1, false, false>(S, t0, p3, P3);  // d/dxi2 branch
   __syncthreads();
-  line3<N, T, 2, false, false>(S, p1, t0, tid);
-  line3<N, T, 2, false, false>(S, p2, t1, tid);
-  line3<N, T, 2, false, false>(D, p3, s_v, tid);
+  line3<N, T, 2, false, false>(S, p1, t0, P3);
+  line3<N, T, 2, false, false>(S, p2, t1, P3);
+  line3<N, T, 2, false, false>(D, p3, s_v, P3);
   __syncthreads();
-  for (int p = tid; p < N3; p += T) {
-    const int qx = p % N, qy = (p / N) % N, qz = p / N2;
+#pragma unroll
+  for (int j = 0; j < CellPts<N, T>::PP; ++j) {
+    if (!P3.ok(j)) continue;
+    const int p = P3.p[j], qx = P3.o[0][j], qy = P3.o[1][j], qz = P3.o[2][j];
     double J[3][3], C[3][3];
     jac_at(qx, qy, qz, J);
     const double det = cofactor(J, C);
@@ -218,16 +264,16 @@ __global__ __launch_bounds__(mapped_threads<N>()) void apply_mapped_kernel(
     s_v[p] = w * (C[0][2] * h[0] + C[1][2] * h[1] + C[2][2] * h[2]);
   }
   __syncthreads();
-  line3<N, T, 2, true, false>(S, t0, p1, tid);
-  line3<N, T, 2, true, false>(S, t1, p2, tid);
-  line3<N, T, 2, true, false>(D, s_v, p3, tid);
+  line3<N, T, 2, true, false>(S, t0, p1, P3);
+  line3<N, T, 2, true, false>(S, t1, p2, P3);
+  line3<N, T, 2, true, false>(D, s_v, p3, P3);
   __syncthreads();
-  line3<N, T, 1, true, false>(S, p1, t0, tid);
-  line3<N, T, 1, true, false>(D, p2, t1, tid);
-  line3<N, T, 1, true, true>(S, p3, t1, tid);
+  line3<N, T, 1, true, false>(S, p1, t0, P3);
+  line3<N, T, 1, true, false>(D, p2, t1, P3);
+  line3<N, T, 1, true, true>(S, p3, t1, P3);
   __syncthreads();
-  line3<N, T, 0, true, false>(D, t0, s_v, tid);
-  line3<N, T, 0, true, true>(S, t1, s_v, tid);
+  line3<N, T, 0, true, false>(D, t0, s_v, P3);
+  line3<N, T, 0, true, true>(S, t1, s_v, P3);
   __syncthreads();
 
   // ---- face terms of the six faces (face f = 2 d + side, side 1 at xi_d = 1)
@@ -238,11 +284,14 @@ __global__ __launch_bounds__(mapped_threads<N>()) void apply_mapped_kernel(
     bb = d == 2 ? 1 : 2;
   };
   const int st3[3] = {1, N, N2};
-  for (int it = tid; it < F; it += T) {  // traces at the face nodes
-    const int f = it / N2, t = it % N2, d = f >> 1, side = f & 1;
+#pragma unroll
+  for (int j = 0; j < FacePts<N, T>::PF; ++j) {  // traces at the face nodes
+    if (!P2.ok(j)) continue;
+    const int it = P2.p[j], f = it / N2, d = f >> 1, side = f & 1;
+    const int t1i = P2.o[0][j], t2i = P2.o[1][j];
     int d1, d2;
     tdirs(d, d1, d2);
-    const int base = (t % N) * st3[d1] + (t / N) * st3[d2];
+    const int base = t1i * st3[d1] + t2i * st3[d2];
     const double* Ds = side ? D1 : D0;
     double lm = s_u[base + (side ? N - 1 : 0) * st3[d]], dm = 0.0;
 #pragma unroll
@@ -262,31 +311,34 @@ __global__ __launch_bounds__(mapped_threads<N>()) void apply_mapped_kernel(
     R1[3 * F + it] = dp;
   }
   __syncthreads();
-  line2<N, T, 0, false, false>(S, R1, R2, tid);                  // minus value, along t1
-  line2<N, T, 0, false, false>(D, R1, R2 + F, tid);              // minus d/dt1
-  line2<N, T, 0, false, false>(S, R1 + F, R2 + 2 * F, tid);      // minus d/dn
-  line2<N, T, 0, false, false>(S, R1 + 2 * F, R2 + 3 * F, tid);  // plus value
-  line2<N, T, 0, false, false>(D, R1 + 2 * F, R2 + 4 * F, tid);  // plus d/dt1
-  line2<N, T, 0, false, false>(S, R1 + 3 * F, R2 + 5 * F, tid);  // plus d/dn
+  line2<N, T, 0, false, false>(S, R1, R2, P2);                  // minus value, along t1
+  line2<N, T, 0, false, false>(D, R1, R2 + F, P2);              // minus d/dt1
+  line2<N, T, 0, false, false>(S, R1 + F, R2 + 2 * F, P2);      // minus d/dn
+  line2<N, T, 0, false, false>(S, R1 + 2 * F, R2 + 3 * F, P2);  // plus value
+  line2<N, T, 0, false, false>(D, R1 + 2 * F, R2 + 4 * F, P2);  // plus d/dt1
+  line2<N, T, 0, false, false>(S, R1 + 3 * F, R2 + 5 * F, P2);  // plus d/dn
   __syncthreads();
-  line2<N, T, 1, false, false>(S, R2, R1, tid);                  // u-
-  line2<N, T, 1, false, false>(S, R2 + F, R1 + F, tid);          // du-/dt1
-  line2<N, T, 1, false, false>(D, R2, R1 + 2 * F, tid);          // du-/dt2
-  line2<N, T, 1, false, false>(S, R2 + 2 * F, R1 + 3 * F, tid);  // du-/dn
-  line2<N, T, 1, false, false>(S, R2 + 3 * F, R1 + 4 * F, tid);  // u+
-  line2<N, T, 1, false, false>(S, R2 + 4 * F, R1 + 5 * F, tid);  // du+/dt1
-  line2<N, T, 1, false, false>(D, R2 + 3 * F, R1 + 6 * F, tid);  // du+/dt2
-  line2<N, T, 1, false, false>(S, R2 + 5 * F, R1 + 7 * F, tid);  // du+/dn
+  line2<N, T, 1, false, false>(S, R2, R1, P2);                  // u-
+  line2<N, T, 1, false, false>(S, R2 + F, R1 + F, P2);          // du-/dt1
+  line2<N, T, 1, false, false>(D, R2, R1 + 2 * F, P2);          // du-/dt2
+  line2<N, T, 1, false, false>(S, R2 + 2 * F, R1 + 3 * F, P2);  // du-/dn
+  line2<N, T, 1, false, false>(S, R2 + 3 * F, R1 + 4 * F, P2);  // u+
+  line2<N, T, 1, false, false>(S, R2 + 4 * F, R1 + 5 * F, P2);  // du+/dt1
+  line2<N, T, 1, false, false>(D, R2 + 3 * F, R1 + 6 * F, P2);  // du+/dt2
+  line2<N, T, 1, false, false>(S, R2 + 5 * F, R1 + 7 * F, P2);  // du+/dn
   __syncthreads();
-  for (int it = tid; it < F; it += T) {  // integrand at the face quadrature points
-    const int f = it / N2, t = it % N2, d = f >> 1, side = f & 1;
+#pragma unroll
+  for (int j = 0; j < FacePts<N, T>::PF; ++j) {  // integrand at the face quadrature points
+    if (!P2.ok(j)) continue;
+    const int it = P2.p[j], f = it / N2, d = f >> 1, side = f & 1;
+    const int q1 = P2.o[0][j], q2 = P2.o[1][j];
     int d1, d2;
     tdirs(d, d1, d2);
     int ex[3];
     ex[d] = N + side;
-    ex[d1] = t % N;
-    ex[d2] = t / N;
-    const double wf = W[t % N] * W[t / N];
+    ex[d1] = q1;
+    ex[d2] = q2;
+    const double wf = W[q1] * W[q2];
     double J[3][3], C[3][3];
     jac_at(ex[0], ex[1], ex[2], J);
     const double det = cofactor(J, C);
@@ -309,7 +361,7 @@ __global__ __launch_bounds__(mapped_threads<N>()) void apply_mapped_kernel(
       // the neighbour's Jacobian on the shared face: the same tangential
       // columns (the same bilinear face), its own normal column
       double cn[3];
-      jac_column(s_Xn + 24 * f, d, G[t % N], G[t / N], cn);
+      jac_column(s_Xn + 24 * f, d, G[q1], G[q2], cn);
       J[0][d] = cn[0];
       J[1][d] = cn[1];
       J[2][d] = cn[2];
@@ -336,19 +388,22 @@ __global__ __launch_bounds__(mapped_threads<N>()) void apply_mapped_kernel(
     R2[3 * F + it] = cs * mm[d];
   }
   __syncthreads();
-  line2<N, T, 1, true, false>(S, R2, R1, tid);
-  line2<N, T, 1, true, true>(D, R2 + 2 * F, R1, tid);
-  line2<N, T, 1, true, false>(S, R2 + F, R1 + F, tid);
-  line2<N, T, 1, true, false>(S, R2 + 3 * F, R1 + 2 * F, tid);
+  line2<N, T, 1, true, false>(S, R2, R1, P2);
+  line2<N, T, 1, true, true>(D, R2 + 2 * F, R1, P2);
+  line2<N, T, 1, true, false>(S, R2 + F, R1 + F, P2);
+  line2<N, T, 1, true, false>(S, R2 + 3 * F, R1 + 2 * F, P2);
   __syncthreads();
-  line2<N, T, 0, true, false>(S, R1, R2, tid);
-  line2<N, T, 0, true, true>(D, R1 + F, R2, tid);
-  line2<N, T, 0, true, false>(S, R1 + 2 * F, R2 + F, tid);
+  line2<N, T, 0, true, false>(S, R1, R2, P2);
+  line2<N, T, 0, true, true>(D, R1 + F, R2, P2);
+  line2<N, T, 0, true, false>(S, R1 + 2 * F, R2 + F, P2);
   __syncthreads();
   const double* __restrict__ bc = b ? b + (size_t)c * N3 : nullptr;
   double* __restrict__ vc = v + (size_t)c * N3;
-  for (int p = tid; p < N3; p += T) {
-    const int id[3] = {p % N, (p / N) % N, p / N2};
+#pragma unroll
+  for (int j = 0; j < CellPts<N, T>::PP; ++j) {
+    if (!P3.ok(j)) continue;
+    const int p = P3.p[j];
+    const int id[3] = {P3.o[0][j], P3.o[1][j], P3.o[2][j]};
     double val = s_v[p];
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
