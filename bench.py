@@ -438,8 +438,9 @@ def run_batch(count=BATCH_COUNT, seed=BATCH_SEED, restart=BATCH_RESTART,
     {16,24,32,48,64}, k in 2..7), right-hand sides from 4 seeded sine modes,
     FGMRES(restart) + FP64 V(2,2) to rtol 1e-10.  Times one batched solve
     with captured V-cycle graphs (after a warm-up solve that captures them),
-    one batched solve without graphs, and the one-problem-at-a-time loop on
-    the same handles.  Aggregate rate = sum over problems of DoFs x
+    one batched solve without graphs, one with the FGMRES scalars on the
+    device and every whole Krylov step a captured graph (after its own
+    warm-up), and the one-problem-at-a-time loop on the same handles.  Aggregate rate = sum over problems of DoFs x
     iterations / wall time.  The Krylov space holds restart + 1 and restart
     vectors per problem, sized so the whole batch fits in HBM (the sine
     right-hand sides converge in <= 3 iterations, so no restart occurs).
@@ -455,7 +456,9 @@ def run_batch(count=BATCH_COUNT, seed=BATCH_SEED, restart=BATCH_RESTART,
     torch.cuda.synchronize()
     res = {}
     for name, kw in [("warmup", dict(use_graph=True)), ("graph", dict(use_graph=True)),
-                     ("eager", dict(use_graph=False)), ("sequential", dict(sequential=True))]:
+                     ("eager", dict(use_graph=False)),
+                     ("warmup_device", dict(use_graph="device")),
+                     ("device", dict(use_graph="device")), ("sequential", dict(sequential=True))]:
         xs = [torch.zeros_like(b) for b in bs]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -468,18 +471,22 @@ def run_batch(count=BATCH_COUNT, seed=BATCH_SEED, restart=BATCH_RESTART,
                      "iterations_total": sum(its), "iterations_max": max(its),
                      "max_rel_res_true": max(i["rel_res_true"] for i in infos),
                      "converged": all(i["status"] == "SIPG_OK" for i in infos)}
-        if name in ("graph", "sequential"):
+        if name in ("graph", "device", "sequential"):
             res[name]["l2_errors"] = [B.l2_error_sines(i, *modes[i], xs[i]) for i in range(count)]
         del xs
         torch.cuda.empty_cache()
     eg, es = res["graph"].pop("l2_errors"), res["sequential"].pop("l2_errors")
+    ed = res["device"].pop("l2_errors")
     out = {"problems": count, "seed": seed, "restart": restart,
            "total_dofs": int(sum(B.sizes)),
            "degrees": sorted({k for k, _ in pairs}), "edges": sorted({n for _, n in pairs}),
            "l2_max_rel_diff_vs_sequential": max(abs(a - b) / b for a, b in zip(eg, es)),
            "speedup_graph_vs_sequential": round(res["sequential"]["seconds"] / res["graph"]["seconds"], 3),
-           "speedup_graph_vs_eager": round(res["eager"]["seconds"] / res["graph"]["seconds"], 3)}
-    out.update({k: v for k, v in res.items() if k != "warmup"})
+           "speedup_graph_vs_eager": round(res["eager"]["seconds"] / res["graph"]["seconds"], 3),
+           "l2_max_rel_diff_device_vs_sequential": max(abs(a - b) / b for a, b in zip(ed, es)),
+           "speedup_device_vs_sequential": round(res["sequential"]["seconds"] / res["device"]["seconds"], 3),
+           "speedup_device_vs_graph": round(res["graph"]["seconds"] / res["device"]["seconds"], 3)}
+    out.update({k: v for k, v in res.items() if not k.startswith("warmup")})
     progress(f"batch of {count} (edges {edges}) done")
     B.close()
     del bs

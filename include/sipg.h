@@ -355,12 +355,19 @@ sipg_status sipg_batch_apply(sipg_batch* b, const double* const* u, double* cons
 /* x_i <- V-cycle(x_i, b_i) on the finest levels, levels aligned by depth. */
 sipg_status sipg_batch_vcycle(sipg_batch* b, double* const* x, const double* const* bvec,
                               hipStream_t stream);
-/* FGMRES for all problems in lockstep (one host synchronization per Krylov
- * step for the whole batch), each with its own Hessenberg system, stopping
- * test and restarts.  use_graph = 1 captures the batched V-cycle of Krylov
- * step j as a HIP graph on an internal stream at its first use and replays
- * it.  infos[count] (HOST) receive per-problem results; `seconds` is the
- * batch wall time.  Blocks until done. */
+/* FGMRES for all problems in lockstep, each with its own Hessenberg system,
+ * stopping test and restarts.  use_graph = 0: batched launches, one host
+ * synchronization per Krylov step for the whole batch; 1: the same with the
+ * batched V-cycle of Krylov step j captured as a HIP graph on an internal
+ * stream at its first use and replayed; 2: the FGMRES scalars on the device
+ * (Gram-Schmidt, Arnoldi normalization, Givens rotations, stopping test and
+ * the triangular solve in batched kernels), each whole Krylov step
+ * (V-cycle, apply, Gram-Schmidt, update) one captured graph over all
+ * problems; between steps the host reads only the problems' active flags
+ * (one small copy) to decide whether to issue the next; restart <= 32.
+ * Problems that stopped ride along with zero vectors.  infos[count] (HOST)
+ * receive per-problem results; `seconds` is the batch wall time.  Blocks
+ * until done.  SIPG_ERR_UNSUPPORTED if a problem has a geometry set. */
 sipg_status sipg_batch_solve(sipg_batch* b, double* const* x, const double* const* bvec,
                              const sipg_solve_opts* opts, sipg_solve_info* infos,
                              int use_graph, hipStream_t stream);

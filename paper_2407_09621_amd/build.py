@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsipg.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["tables.cpp", "sipg_valu.hip", "sipg_mfma.hip", "sipg_lp.hip", "blas.hip", "rhs.hip", "capi.cpp", "batch.cpp", "cnn.hip", "cnn_api.cpp", "sipg_mapped.hip", "geometry.cpp"]
+SOURCES = ["tables.cpp", "sipg_valu.hip", "sipg_mfma.hip", "sipg_lp.hip", "blas.hip", "rhs.hip", "capi.cpp", "batch.cpp", "cnn.hip", "cnn_api.cpp", "sipg_mapped.hip", "geometry.cpp", "krylov.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -28,8 +28,15 @@ struct sipg_batch {
   hipStream_t stream = nullptr;    // internal capture stream (default priority)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   std::map<int, hipGraphExec_t> graphs;  // Krylov index j -> captured V-cycle
+  std::map<int, hipGraphExec_t> steps;   // Krylov index j -> captured whole step (device scalars)
   std::vector<int> graph_gen;            // krylov_gen of every problem at capture
   double* h_pinned = nullptr;            // host scalars of all problems
+  // device-scalar FGMRES: descriptors, state blocks, flags (device and pinned)
+  KrylovDesc* d_kd = nullptr;
+  double* d_st = nullptr;
+  double* d_flags = nullptr;
+  double* h_flags = nullptr;             // 3 slots of P x kFlagCount
+  hipEvent_t ev_flags[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -61,6 +68,14 @@ bool lowp(const sipg_batch* B) { return B->prec != SIPG_F64; }
 void drop_graphs(sipg_batch* B) {
   for (auto& kv : B->graphs) hipGraphExecDestroy(kv.second);
   B->graphs.clear();
+  for (auto& kv : B->steps) hipGraphExecDestroy(kv.second);
+  B->steps.clear();
+}
+
+sipg_status cartesian_batch(const sipg_batch* B) {
+  for (const sipg_problem* q : B->P)
+    if (q->mapped) return fail(SIPG_ERR_UNSUPPORTED, "batches run on Cartesian meshes (a problem has a geometry)");
+  return SIPG_OK;
 }
 
 // level vectors: x, b, r of problem p at level l (the finest x/b are given)
@@ -260,6 +275,168 @@ sipg_status b_apply64(sipg_batch* B, const std::vector<int>& probs,
   });
 }
 
+// FGMRES(m) of every problem with its scalars on the device (krylov.hip):
+// each Krylov step (V-cycle, apply, Gram-Schmidt twice, Arnoldi and Givens
+// update, scaling) is one captured graph over all problems; after a step
+// the host reads only the problems' active flags (one small copy) to decide
+// whether to issue the next one.  (Issuing ahead and reading the flags one
+// step behind was measured slower: the step issued after the last problem
+// stopped costs more than the flag round trip saves.)
+sipg_status device_krylov(sipg_batch* B, double* const* x, const double* const* b,
+                          const sipg_solve_opts* o, const std::vector<double>& nb,
+                          const std::vector<double>& tol, std::vector<int>& conv,
+                          std::vector<int>& its, sipg_solve_info* infos, hipStream_t s) {
+  const int P = (int)B->P.size(), m = o->restart;
+  if (m > kMaxKrylov) return fail(SIPG_ERR_ARG, "device-scalar FGMRES needs restart <= 32");
+  if (!B->d_kd) {
+    KrylovDesc* kd = nullptr;
+    double *st = nullptr, *fl = nullptr, *hf = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool ok =
+        hipMalloc((void**)&kd, sizeof(KrylovDesc) * P) == hipSuccess &&
+        hipMalloc((void**)&st, sizeof(double) * kStateStride * P) == hipSuccess &&
+        hipMalloc((void**)&fl, sizeof(double) * kFlagCount * P) == hipSuccess &&
+        hipHostMalloc((void**)&hf, sizeof(double) * 3 * kFlagCount * P) == hipSuccess &&
+        hipEventCreateWithFlags(&e0, hipEventDisableTiming) == hipSuccess &&
+        hipEventCreateWithFlags(&e1, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+      if (kd) hipFree(kd);
+      if (st) hipFree(st);
+      if (fl) hipFree(fl);
+      if (hf) hipHostFree(hf);
+      if (e0) hipEventDestroy(e0);
+      if (e1) hipEventDestroy(e1);
+      return fail(SIPG_ERR_OOM, "device-scalar FGMRES workspace allocation failed");
+    }
+    B->d_kd = kd;
+    B->d_st = st;
+    B->d_flags = fl;
+    B->h_flags = hf;
+    B->ev_flags[0] = e0;
+    B->ev_flags[1] = e1;
+  }
+  auto n_of = [&](int p) { return B->P[p]->ndofs[B->P[p]->L - 1]; };
+  auto Vj = [&](int p, int j) { return B->P[p]->V + (size_t)j * n_of(p); };
+  auto Zj = [&](int p, int j) { return B->P[p]->Z + (size_t)j * n_of(p); };
+  int64_t nmax = 1;
+  std::vector<KrylovDesc> kd(P);
+  std::vector<double> st0((size_t)kStateStride * P, 0.0);
+  for (int p = 0; p < P; ++p) {
+    sipg_problem* q = B->P[p];
+    kd[p] = KrylovDesc{q->V, q->Z, x[p], q->d_small, q->d_partial, B->d_st + (size_t)p * kStateStride,
+                       n_of(p)};
+    nmax = std::max(nmax, n_of(p));
+    double* t = st0.data() + (size_t)p * kStateStride;
+    t[kSNb] = nb[p];
+    t[kSTol] = tol[p];
+    t[kSMaxIts] = o->max_iters;
+    t[kSConv] = conv[p];
+  }
+  SIPG_HIP(hipMemcpyAsync(B->d_kd, kd.data(), sizeof(KrylovDesc) * P, hipMemcpyHostToDevice, s));
+  SIPG_HIP(hipMemcpyAsync(B->d_st, st0.data(), sizeof(double) * st0.size(), hipMemcpyHostToDevice,
+                          s));
+  SIPG_HIP(hipStreamSynchronize(s));
+  std::vector<int> all(P);
+  for (int p = 0; p < P; ++p) all[p] = p;
+  auto step = [&](int j) -> sipg_status {
+    std::vector<const double*> vin(P), u(P);
+    std::vector<double*> zout(P), out(P);
+    for (int p = 0; p < P; ++p) {
+      vin[p] = Vj(p, j);
+      zout[p] = Zj(p, j);
+      u[p] = Zj(p, j);
+      out[p] = Vj(p, j + 1);
+    }
+    SIPG_TRY(b_precondition(B, all, vin, zout, s));
+    SIPG_TRY(b_apply64(B, all, u, out, {}, s));
+    SIPG_HIP(launch_krylov_dots(B->d_kd, P, 0, j + 1, j + 1, 0, s));
+    SIPG_HIP(launch_krylov_axpy(B->d_kd, P, nmax, j + 1, j + 1, 0, -1, s));
+    SIPG_HIP(launch_krylov_dots(B->d_kd, P, 0, j + 1, j + 1, 80, s));
+    SIPG_HIP(launch_krylov_axpy(B->d_kd, P, nmax, j + 1, j + 1, 80, 0, s));
+    SIPG_HIP(launch_krylov_dots(B->d_kd, P, j + 1, 1, j + 1, kNormSlot, s));
+    SIPG_HIP(launch_krylov_scalars(1, B->d_kd, P, j, m, nullptr, s));
+    SIPG_HIP(launch_krylov_scale(B->d_kd, P, nmax, j + 1, s));
+    return SIPG_OK;
+  };
+  const size_t fbytes = sizeof(double) * kFlagCount * P;
+  auto hflags = [&](int slot) { return B->h_flags + (size_t)slot * kFlagCount * P; };
+  std::vector<int> bad(P, 0);
+  while (true) {
+    bool any = false;
+    for (int p = 0; p < P; ++p) any = any || (!conv[p] && its[p] < o->max_iters);
+    if (!any) break;
+    {  // cycle start: V_0 = b - A x, its norm, g and the scale of V_0
+      std::vector<const double*> u(P), bb(P);
+      std::vector<double*> out(P);
+      for (int p = 0; p < P; ++p) {
+        u[p] = x[p];
+        bb[p] = b[p];
+        out[p] = Vj(p, 0);
+      }
+      SIPG_TRY(b_apply64(B, all, u, out, bb, s));
+      SIPG_HIP(launch_krylov_dots(B->d_kd, P, 0, 1, 0, kNormSlot, s));
+      SIPG_HIP(launch_krylov_scalars(0, B->d_kd, P, 0, m, nullptr, s));
+      SIPG_HIP(launch_krylov_scale(B->d_kd, P, nmax, 0, s));
+    }
+    int issued = 0;
+    for (int j = 0; j < m; ++j) {
+      const int key = m * 64 + j;
+      auto it = B->steps.find(key);
+      if (it == B->steps.end()) {
+        hipGraph_t gr;
+        SIPG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        sipg_status stc = step(j);
+        hipError_t ee = hipStreamEndCapture(s, &gr);
+        if (stc != SIPG_OK) return stc;
+        SIPG_HIP(ee);
+        hipGraphExec_t ex;
+        hipError_t ei = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+        hipGraphDestroy(gr);
+        SIPG_HIP(ei);
+        it = B->steps.emplace(key, ex).first;
+      }
+      SIPG_HIP(hipGraphLaunch(it->second, s));
+      issued = j + 1;
+      if (j + 1 == m) break;
+      // the active flags after step j decide whether step j + 1 is issued
+      SIPG_HIP(launch_krylov_scalars(3, B->d_kd, P, 0, m, B->d_flags, s));
+      SIPG_HIP(hipMemcpyAsync(hflags(j & 1), B->d_flags, fbytes, hipMemcpyDeviceToHost, s));
+      SIPG_HIP(hipEventRecord(B->ev_flags[j & 1], s));
+      SIPG_HIP(hipEventSynchronize(B->ev_flags[j & 1]));
+      const double* f = hflags(j & 1);
+      bool live = false;
+      for (int p = 0; p < P; ++p) live = live || f[(size_t)p * kFlagCount] != 0.0;
+      if (!live) break;
+    }
+    // cycle end: y = R^{-1} g, x += Z y over the steps issued, flags to the host
+    SIPG_HIP(launch_krylov_scalars(2, B->d_kd, P, 0, m, nullptr, s));
+    SIPG_HIP(launch_krylov_update(B->d_kd, P, nmax, issued, s));
+    SIPG_HIP(launch_krylov_scalars(3, B->d_kd, P, 0, m, B->d_flags, s));
+    SIPG_HIP(hipMemcpyAsync(hflags(2), B->d_flags, fbytes, hipMemcpyDeviceToHost, s));
+    SIPG_HIP(hipStreamSynchronize(s));
+    const double* f = hflags(2);
+    for (int p = 0; p < P; ++p) {
+      conv[p] = f[(size_t)p * kFlagCount + (kSConv - kSActive)] != 0.0;
+      its[p] = (int)f[(size_t)p * kFlagCount + (kSIts - kSActive)];
+      bad[p] = f[(size_t)p * kFlagCount + (kSBad - kSActive)] != 0.0;
+      if (bad[p]) return fail(SIPG_ERR_NONFINITE, "Arnoldi vector is not finite");
+    }
+  }
+  std::vector<double> stv((size_t)kStateStride * P);
+  SIPG_HIP(hipMemcpyAsync(stv.data(), B->d_st, sizeof(double) * stv.size(), hipMemcpyDeviceToHost,
+                          s));
+  SIPG_HIP(hipStreamSynchronize(s));
+  for (int p = 0; p < P; ++p) {
+    const double* t = stv.data() + (size_t)p * kStateStride;
+    infos[p].rel_res_est = t[kSEst];
+    if (o->log_history) {
+      const int h = std::min((int)t[kSHist], kHistory);
+      for (int i = 0; i < h; ++i) infos[p].history[i] = t[kSHistory + i];
+    }
+  }
+  return SIPG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -319,6 +496,12 @@ void sipg_batch_destroy(sipg_batch* B) {
   if (B->ev_in) hipEventDestroy(B->ev_in);
   if (B->ev_out) hipEventDestroy(B->ev_out);
   if (B->h_pinned) hipHostFree(B->h_pinned);
+  if (B->h_flags) hipHostFree(B->h_flags);
+  if (B->d_kd) hipFree(B->d_kd);
+  if (B->d_st) hipFree(B->d_st);
+  if (B->d_flags) hipFree(B->d_flags);
+  for (hipEvent_t e : B->ev_flags)
+    if (e) hipEventDestroy(e);
   delete B;
 }
 
@@ -362,6 +545,7 @@ sipg_status sipg_batch_autotune(sipg_batch* B, hipStream_t s) {
 sipg_status sipg_batch_apply(sipg_batch* B, const double* const* u, double* const* v,
                              hipStream_t s) {
   if (!B || !u || !v) return fail(SIPG_ERR_ARG, "NULL argument");
+  SIPG_TRY(cartesian_batch(B));
   std::vector<int> all(B->P.size());
   std::vector<const double*> uu(B->P.size());
   std::vector<double*> vv(B->P.size());
@@ -377,6 +561,7 @@ sipg_status sipg_batch_apply(sipg_batch* B, const double* const* u, double* cons
 sipg_status sipg_batch_vcycle(sipg_batch* B, double* const* x, const double* const* b,
                               hipStream_t s) {
   if (!B || !x || !b) return fail(SIPG_ERR_ARG, "NULL argument");
+  SIPG_TRY(cartesian_batch(B));
   std::vector<int> all(B->P.size());
   Vecs v;
   v.x.assign(B->P.size(), nullptr);
@@ -411,6 +596,8 @@ sipg_status sipg_batch_solve(sipg_batch* B, double* const* x, const double* cons
                              hipStream_t s_user) {
   if (!B || !x || !b || !o || !infos) return fail(SIPG_ERR_ARG, "NULL argument");
   if (o->restart < 1 || o->restart > 64) return fail(SIPG_ERR_ARG, "restart must be in 1..64");
+  if (use_graph < 0 || use_graph > 2) return fail(SIPG_ERR_ARG, "use_graph must be 0, 1 or 2");
+  SIPG_TRY(cartesian_batch(B));
   if (o->max_iters < 1 || !(o->rtol > 0.0)) return fail(SIPG_ERR_ARG, "bad options");
   if (o->use_learned) return fail(SIPG_ERR_UNSUPPORTED, "learned stage not available in batches");
   if (o->variant != SIPG_FGMRES) return fail(SIPG_ERR_UNSUPPORTED, "batches run FGMRES");
@@ -481,7 +668,8 @@ sipg_status sipg_batch_solve(sipg_batch* B, double* const* x, const double* cons
       g(P, std::vector<double>(m + 1));
   bool graphs_ok = use_graph != 0;
   int total_it = 0;
-  while (true) {
+  if (use_graph == 2) SIPG_TRY(device_krylov(B, x, b, o, nb, tol, conv, its, infos, s));
+  while (use_graph != 2) {
     std::vector<int> act;
     for (int p = 0; p < P; ++p)
       if (!conv[p] && its[p] < o->max_iters) act.push_back(p);

@@ -153,4 +153,41 @@ hipError_t launch_l2_mapped(int N, const MappedLevel& g, int nm, const double* m
                             const double* qtab, const double* x, double* partial, int max_blocks,
                             double* out, hipStream_t s);
 
+// ---- flexible GMRES of many problems with device-side scalars (krylov.hip)
+// Per-problem state block (doubles, kStateStride per problem): g, Givens
+// cosines and sines, flags, the triangular factor R (column-major, m x m),
+// y and the residual history.
+constexpr int kMaxKrylov = 32;
+constexpr int kStateStride = 2048;
+constexpr int kSG = 0, kSCs = 64, kSSn = 96;
+constexpr int kSActive = 128, kSJd = 129, kSIts = 130, kSEst = 131, kSConv = 132, kSBad = 133,
+              kSHist = 134;
+constexpr int kFlagCount = 7;  // kSActive .. kSHist, the host's view
+constexpr int kSInv = 140, kSNb = 141, kSTol = 142, kSMaxIts = 143;
+constexpr int kSR = 256, kSY = 1280, kSHistory = 1536, kHistory = 128;
+constexpr int kNormSlot = 160;  // small[] slot of the squared norms
+struct KrylovDesc {
+  double* V;        // Krylov basis, m + 1 vectors of n
+  double* Z;        // preconditioned vectors, m vectors of n
+  double* x;        // solution
+  double* small;    // dot results: h at [0, 33), second pass at [80, 113), norm at kNormSlot
+  double* partial;  // dot partial sums, 256 x 33 doubles
+  double* st;       // state block
+  int64_t n;
+};
+// small[off + i] = V_{first+i} . V_widx for i < nv (every problem of D[0..P))
+hipError_t launch_krylov_dots(const KrylovDesc* D, int P, int first, int nv, int widx, int off,
+                              hipStream_t s);
+// V_widx -= sum_{i<nv} small[coef + i] V_i; small[acc + i] += coef (acc >= 0)
+hipError_t launch_krylov_axpy(const KrylovDesc* D, int P, int64_t nmax, int nv, int widx,
+                              int coef, int acc, hipStream_t s);
+// V_widx *= st[kSInv]
+hipError_t launch_krylov_scale(const KrylovDesc* D, int P, int64_t nmax, int widx, hipStream_t s);
+// x += sum_{i<m} st[kSY + i] Z_i
+hipError_t launch_krylov_update(const KrylovDesc* D, int P, int64_t nmax, int m, hipStream_t s);
+// stage 0: cycle start; 1: Arnoldi step j; 2: cycle end (y, convergence);
+// 3: copy the flags of every problem to flags[P x kFlagCount]
+hipError_t launch_krylov_scalars(int stage, const KrylovDesc* D, int P, int j, int m,
+                                 double* flags, hipStream_t s);
+
 }  // namespace sipg

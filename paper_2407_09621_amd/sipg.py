@@ -490,7 +490,8 @@ class Batch:
         else:
             st = _lib.sipg_batch_solve(self._h, _ptr_array(xs, torch.float64, self.sizes),
                                        _ptr_array(bs, torch.float64, self.sizes), ctypes.byref(opts), infos,
-                                       int(bool(use_graph)), _stream(stream))
+                                       2 if use_graph == "device" else int(bool(use_graph)),
+                                       _stream(stream))
         if st not in (SIPG_OK, 5):
             _check(st)
         return xs, [_info_dict(infos[i], st) for i in range(len(bs))]

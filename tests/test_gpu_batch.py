@@ -112,7 +112,7 @@ def test_batch_vcycle_matches_oracle():
         assert rel_l2(to_cpu(x), H.precondition(to_cpu(b))) < 1e-12, (k, n)
 
 
-@pytest.mark.parametrize("use_graph", [False, True])
+@pytest.mark.parametrize("use_graph", [False, True, "device"])
 def test_batch_solve_matches_sequential(use_graph):
     from paper_2407_09621_amd import Batch
     announce("batch solve", use_graph)
@@ -199,6 +199,55 @@ def test_batch_zero_rhs_and_restart_growth():
         xs, infos = B.solve(bs, xs=xs, rtol=1e-10, restart=restart)
         assert infos[0]["iterations"] == 0 and float(xs[0].abs().max()) == 0.0
         assert infos[1]["rel_res_true"] < 1e-10
+
+
+def test_device_scalar_solves_over_restarts_and_replays():
+    """FGMRES with the scalars on the device and whole Krylov steps as
+    graphs: restart 2 forces several cycles (so problems stop at different
+    steps and cycles), a zero right-hand side rides along, and three solves
+    replay the captured steps with other GPU work and host synchronisations
+    between them; every solve equals the host-scalar solve of the same
+    right-hand side (iterations, iterate, true residual)."""
+    from paper_2407_09621_amd import Batch
+    announce("batch device scalars")
+    import torch
+    probs = [(2, 8), (3, 4), (5, 2), (2, 6), (1, 4)]
+    Bd, Bh = Batch(probs), Batch(probs)
+    for rep in range(3):
+        bs = _vectors(Bd, 140 + 10 * rep)
+        bs[4].zero_()
+        xd, idv = Bd.solve(bs, rtol=1e-9, restart=2, use_graph="device")
+        junk = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
+        (junk * 2.0).sum().item()
+        torch.cuda.synchronize()
+        xh, ih = Bh.solve(bs, rtol=1e-9, restart=2, use_graph=False)
+        for i in range(len(probs)):
+            assert idv[i]["iterations"] == ih[i]["iterations"], (rep, i, idv[i], ih[i])
+            assert rel_l2(to_cpu(xd[i]), to_cpu(xh[i])) < 1e-10, (rep, i)
+            assert idv[i]["rel_res_true"] < 1e-9 or i == 4
+            np.testing.assert_allclose(idv[i]["history"], ih[i]["history"], rtol=1e-6, atol=1e-14)
+        assert float(xd[4].abs().max()) == 0.0 and idv[4]["iterations"] == 0
+
+
+def test_device_scalar_solve_lowprec_and_limits():
+    """FP16-EC V-cycle inside the device-scalar FGMRES; an iteration budget
+    stops every problem at the same count with SIPG_ERR_NOT_CONVERGED
+    reported as a status, and restart above 32 is refused."""
+    from paper_2407_09621_amd import Batch
+    from paper_2407_09621_amd.sipg import SipgError
+    announce("batch device scalars f16")
+    probs = [(3, 8), (2, 12), (5, 4)]
+    B16 = Batch(probs, mg_precision="f16", error_correction=True)
+    bs = _vectors(B16, 160)
+    xd, idv = B16.solve(bs, rtol=1e-10, use_graph="device", restart=8)
+    xh, ih = B16.solve(bs, rtol=1e-10, use_graph=False, restart=8)
+    for i in range(len(probs)):
+        assert idv[i]["rel_res_true"] < 1e-10
+        assert idv[i]["iterations"] == ih[i]["iterations"]
+    xd, idv = B16.solve(bs, rtol=1e-14, use_graph="device", restart=8, max_iters=2)
+    assert all(d["iterations"] == 2 and d["status"] == "SIPG_ERR_NOT_CONVERGED" for d in idv)
+    with pytest.raises(SipgError):
+        B16.solve(bs, restart=40, use_graph="device")
 
 
 @pytest.mark.parametrize("k,n", [(5, 16), (7, 8)])
