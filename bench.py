@@ -101,6 +101,27 @@ def _oracle_apply_round(_=None):
     return total, t
 
 
+def _oracle_mapped_sample():
+    """The oracle's apply on trilinear cells (quadrature blocks cell by cell,
+    one core) on a sample of cells of the benchmark meshes with the smooth
+    deformation: 128 cells at k=3 (64^3) and 16 at k=7 (32^3)."""
+    import numpy as np
+    from oracle import mapped
+    from paper_2407_09621_amd import inputs
+    out = {}
+    for k, n, count in ((3, 64, 128), (7, 32, 16)):
+        V = inputs.mesh_vertices(n, "smooth", MAPPED_AMPLITUDE, seed=1)
+        u = inputs.uniform_vector(n ** 3 * (k + 1) ** 3, seed=60 + k)
+        cells = np.random.default_rng(k).integers(0, n ** 3, count)
+        mapped.apply_cells_mapped(u, n, k, V, cells[:1])   # reference tables
+        t0 = time.perf_counter()
+        mapped.apply_cells_mapped(u, n, k, V, cells)
+        dt = time.perf_counter() - t0
+        out[f"k{k}_n{n}"] = {"value": count * (k + 1) ** 3 / dt / 1e9, "unit": "GDoF/s",
+                             "cores": 1, "sample": f"{count} random cells, {dt:.2f} s"}
+    return out
+
+
 def cpu_baseline(max_workers=16):
     """The oracle's Kronecker-sum apply (numpy/scipy, FP64, single-threaded
     per process) at the full benchmark sizes: one apply per degree on one
@@ -128,7 +149,9 @@ def cpu_baseline(max_workers=16):
             else:
                 os.environ[v] = val
     dofs_all = sum(r[0] for r in res)
+    geo = _oracle_mapped_sample()
     return {"value": dofs_all / wall / 1e9, "unit": "GDoF/s", "cores": W, "kind": "oracle",
+            "general_geometry": geo,
             "sample": f"{W} worker processes at once, each one FP64 apply at k=3 (64^3), "
                       f"k=5 (40^3) and k=7 (32^3) by the oracle's Kronecker-sum path "
                       f"(scipy.sparse, one thread each): {3 * W} applies, "
