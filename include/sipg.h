@@ -365,7 +365,10 @@ sipg_status sipg_batch_vcycle(sipg_batch* b, double* const* x, const double* con
  * (V-cycle, apply, Gram-Schmidt, update) one captured graph over all
  * problems; between steps the host reads only the problems' active flags
  * (one small copy) to decide whether to issue the next; restart <= 32.
- * Problems that stopped ride along with zero vectors.  infos[count] (HOST)
+ * Problems that stopped ride along with zero vectors.  Mode 2 allocates its
+ * small device state (descriptors, a 16 KB state block per problem, flags)
+ * with hipMalloc on first use; it is freed by sipg_batch_destroy.
+ * infos[count] (HOST)
  * receive per-problem results; `seconds` is the batch wall time.  Blocks
  * until done.  SIPG_ERR_UNSUPPORTED if a problem has a geometry set. */
 sipg_status sipg_batch_solve(sipg_batch* b, double* const* x, const double* const* bvec,
