@@ -70,7 +70,7 @@ __device__ __forceinline__ double cofactor(const double J[3][3], double C[3][3])
 
 template <int N>
 constexpr int mapped_threads() {
-  return N <= 4 ? 64 : 256;
+  return N <= 3 ? 64 : (N == 4 ? 128 : 256);
 }
 
 // The points a thread of a T-thread workgroup takes in the stage loops over
