@@ -342,3 +342,49 @@ def l2_error_mapped(problem, uh, n, k, V):
                 s += float(w @ (e * e))
                 c += 1
     return float(np.sqrt(s))
+
+
+def level_vertices(V, n, n_level):
+    """Vertices of the level with n_level cells per direction: every
+    (n / n_level)-th vertex of the finest level's array."""
+    s = n // n_level
+    return np.ascontiguousarray(np.asarray(V)[::s, ::s, ::s])
+
+
+class MappedHierarchy:
+    """The V-cycle (Alg. v_cycle) on trilinear cells.  Reading: the residuals
+    use the mapped operator of each level (its vertices every 2^j-th fine
+    vertex), while the vertex-patch solves and the coarse solve keep the
+    exact inverses of the Cartesian operator's patch and coarse matrices,
+    which are then approximate inverses; the transfers are the Cartesian
+    ones (reference-space embedding of the nested Q_k spaces)."""
+
+    def __init__(self, n, k, V):
+        from . import multigrid
+        self.H = multigrid.Hierarchy(n, k)       # Cartesian patch factors and coarse solve
+        self.A = [assemble_mapped(lev.n, k, level_vertices(V, n, lev.n)) for lev in self.H.levels]
+
+    def _smooth(self, l, x, b, sweeps):
+        from . import multigrid
+        from scipy.linalg import cho_solve
+        lev = self.H.levels[l]
+        x = np.array(x, dtype=np.float64, copy=True)
+        for _ in range(sweeps):
+            for colour in range(8):
+                r = b - self.A[l] @ x
+                for v, c in lev.patches:
+                    if c != colour:
+                        continue
+                    idx = multigrid.patch_dofs(lev.n, lev.k, v)
+                    x[idx] += cho_solve(lev.patch_factor(v), r[idx])
+        return x
+
+    def vcycle(self, l, x, b):
+        if l == 0:
+            return self.H.coarse.solve(b)
+        x = self._smooth(l, x, b, self.H.nu_pre)
+        r = b - self.A[l] @ x
+        rc = self.H.P[l].T @ r
+        ec = self.vcycle(l - 1, np.zeros(rc.shape), rc)
+        x = x + self.H.P[l] @ ec
+        return self._smooth(l, x, b, self.H.nu_post)

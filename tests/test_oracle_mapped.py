@@ -164,3 +164,36 @@ def test_solution_on_deformed_meshes_converges_at_rate_k_plus_1(k):
         errs.append(mapped.l2_error_mapped(prob, u, n, k, V))
     rates = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert rates[-1] > k + 1 - 0.3, (errs, rates)
+
+
+def test_mapped_vcycle_on_the_identity_mesh_is_the_cartesian_vcycle():
+    """With identity vertices the mapped V-cycle (mapped residuals, Cartesian
+    patch and coarse inverses) is the Cartesian V-cycle of the oracle."""
+    from oracle import multigrid
+    n, k = 4, 2
+    H = multigrid.Hierarchy(n, k)
+    M = mapped.MappedHierarchy(n, k, inputs.mesh_vertices(n))
+    b = inputs.uniform_vector(sipg.n_dofs(n, k), 3)
+    L = len(H.levels) - 1
+    x0 = np.zeros_like(b)
+    ref = H.vcycle(L, x0, b)
+    got = M.vcycle(L, x0, b)
+    assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_mapped_vcycle_contracts_on_a_deformed_mesh():
+    """The Cartesian inverses stay good approximate inverses on a mildly
+    deformed mesh: the V-cycle iteration's error contracts."""
+    import scipy.sparse.linalg as spla
+    n, k = 4, 2
+    V = inputs.mesh_vertices(n, "smooth", 0.08, seed=1)
+    M = mapped.MappedHierarchy(n, k, V)
+    A = M.A[-1]
+    b = inputs.uniform_vector(A.shape[0], 4)
+    xs = spla.spsolve(A.tocsc(), b)
+    x = np.zeros_like(b)
+    errs = []
+    for _ in range(4):
+        x = x + M.vcycle(len(M.A) - 1, np.zeros_like(b), b - A @ x)
+        errs.append(np.linalg.norm(x - xs))
+    assert errs[-1] < 0.05 * errs[0] and all(errs[i + 1] < errs[i] for i in range(3))
