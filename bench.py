@@ -101,6 +101,27 @@ def _oracle_apply_round(_=None):
     return total, t
 
 
+def measured_copy_rate(stream, nbytes=1 << 30, reps=20):
+    """Device copy of nbytes (read + write) between two buffers, HIP events
+    on the stream: the achievable HBM rate, GB/s of bytes moved."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").uniform_()
+    b2 = torch.empty_like(a)
+    with torch.cuda.stream(stream):
+        b2.copy_(a)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            b2.copy_(a)
+        e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b2
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
 def _oracle_mapped_sample():
     """The oracle's apply on trilinear cells (quadrature blocks cell by cell,
     one core) on a sample of cells of the benchmark meshes with the smooth
@@ -797,6 +818,24 @@ def main():
             "fp64_frac_model": round(gdofs * flops_per_dof(k) / 1e3 / FP64_PEAK_TFLOPS, 4),
             "n_dofs": nd, "kernel": APPLY_KERNEL[f"k{k}_n{n}"]}
 
+    # unrotated: the same (u, v) pair every launch (the L2/MALL may keep part
+    # of the working set), and the measured HBM copy rate as a second peak
+    for k, n, P, nd, us, vs in probs:
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps = max(args.steps, 1)
+        P.apply(us[0], vs[0], stream=stream)
+        e0.record(stream)
+        for i in range(reps):
+            P.apply(us[0], vs[0], stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        per_k[f"k{k}_n{n}"]["unrotated_gdof_s"] = round(nd / (ms * 1e-3) / 1e9, 2)
+    copy_gb_s = measured_copy_rate(stream)
+    for key in per_k:
+        per_k[key]["hbm_frac_of_copy"] = round(per_k[key]["hbm_gb_s"] / copy_gb_s, 4)
+
     # the same apply on the FP64 vector units (the paper's CUDA-core
     # comparison, App. A) where the default runs on the matrix cores
     units = {}
@@ -869,7 +908,8 @@ def main():
                                "k=3 on 64^3 cells, k=5 on 40^3, k=7 on 32^3; u ~ U[-1,1] seeded; "
                                "one step = one apply per degree",
                    "parallelism": "single GPU"},
-        "per_k": per_k, "roofline": roofline, "cpu_baseline": cpu, "apply_units": units,
+        "per_k": per_k, "roofline": roofline, "measured_copy_gb_s": round(copy_gb_s, 1),
+        "cpu_baseline": cpu, "apply_units": units,
         "lowprec_apply": lp_rates, "patchwise_sweep": patchwise, "solves": solves,
         "vcycles": vcycles,
         "krylov_smoother_comparison": comparisons, "batch": batch, "learned": learned,
