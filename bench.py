@@ -122,6 +122,26 @@ def measured_copy_rate(stream, nbytes=1 << 30, reps=20):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
+def _oracle_csr_sample(reps=100):
+    """The oracle's assembled CSR matrix (3D/2D quadrature) on the small
+    configuration (k=2, 8^3 cells, 13,824 DoFs): assembly time and 100
+    sparse products on one core (larger meshes need too much host memory
+    for the assembled matrix)."""
+    from oracle import sipg
+    from paper_2407_09621_amd import inputs
+    t0 = time.perf_counter()
+    A = sipg.assemble(8, 2)
+    ta = time.perf_counter() - t0
+    u = inputs.uniform_vector(A.shape[0], 1)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        A @ u
+    dt = time.perf_counter() - t0
+    return {"value": A.shape[0] * reps / dt / 1e9, "unit": "GDoF/s", "cores": 1,
+            "sample": f"k=2, 8^3 cells: assembly {ta:.2f} s, {reps} products in {dt:.3f} s, "
+                      f"{A.nnz} nonzeros"}
+
+
 def _oracle_mapped_sample():
     """The oracle's apply on trilinear cells (quadrature blocks cell by cell,
     one core) on a sample of cells of the benchmark meshes with the smooth
@@ -171,8 +191,9 @@ def cpu_baseline(max_workers=16):
                 os.environ[v] = val
     dofs_all = sum(r[0] for r in res)
     geo = _oracle_mapped_sample()
+    csr = _oracle_csr_sample()
     return {"value": dofs_all / wall / 1e9, "unit": "GDoF/s", "cores": W, "kind": "oracle",
-            "general_geometry": geo,
+            "general_geometry": geo, "csr_spmv_small": csr,
             "sample": f"{W} worker processes at once, each one FP64 apply at k=3 (64^3), "
                       f"k=5 (40^3) and k=7 (32^3) by the oracle's Kronecker-sum path "
                       f"(scipy.sparse, one thread each): {3 * W} applies, "
