@@ -110,7 +110,7 @@ sipg_status b_residual(sipg_batch* B, const Vecs& v, const std::vector<Item>& it
     }
     const DevTab& t = B->P[it[0].p]->tab;
     if (B->prec == SIPG_F64) SIPG_HIP(launch_apply_batch(0, N, jobs, cnt, t, s));
-    else if (B->prec == SIPG_F32) SIPG_HIP(launch_apply_batch(1, N, jobs, cnt, t, s));
+    else if (B->prec == SIPG_F32) SIPG_HIP(launch_apply_batch(3, N, jobs, cnt, t, s));
     else SIPG_HIP(launch_apply_lp_batch(N, B->prec == SIPG_BF16, B->ec, jobs, cnt, t, s));
     return SIPG_OK;
   });

@@ -106,7 +106,7 @@ sipg_status smooth(sipg_problem* p, int l, double* x, const double* b, int sweep
 sipg_status residual_lp(sipg_problem* p, int l, const float* b, const float* x, float* r,
                         hipStream_t s) {
   if (p->prec == SIPG_F32)
-    SIPG_HIP(launch_apply_f32(p->N, x, r, b, p->tab, p->n[l], level_h(p, l), s));
+    SIPG_HIP(launch_residual_f32(p->N, x, r, b, p->tab, p->n[l], level_h(p, l), s));
   else
     SIPG_HIP(launch_apply_lp(p->N, p->prec == SIPG_BF16, p->ec, x, r, b, p->tab, p->n[l],
                              level_h(p, l), s));

@@ -23,6 +23,10 @@ hipError_t launch_apply_f64(int N, const double* u, double* v, const double* b,
 
 hipError_t launch_apply_f32(int N, const float* u, float* v, const float* b, const DevTab& t,
                             int n, double h, hipStream_t s);
+// The FP32 V-cycle's residual: FP32 vectors; at N = 4 on the FP64 matrix
+// cores (widened on load, rounded on store), else as launch_apply_f32.
+hipError_t launch_residual_f32(int N, const float* u, float* v, const float* b, const DevTab& t,
+                               int n, double h, hipStream_t s);
 
 // x_P += A_PP^{-1} r_P for all vertex patches of `colour`.
 hipError_t launch_patch_fd_f64(int N, int colour, const double* r, double* x,
@@ -60,9 +64,10 @@ hipError_t launch_restrict_f32(int N, const float* rf, float* rc, const DevTab& 
 hipError_t launch_prolongate_add_f32(int N, const float* ec, float* xf, const DevTab& t, int nc,
                                      hipStream_t s);
 
-// FP64 apply of degree 3 on the matrix cores (one wave per up to 8 cells of
-// an x-row); same contract as launch_apply_batch with prec 0 and N = 4.
-hipError_t launch_apply_mfma4_batch(const ApplyJob* jobs, int count, const DevTab& t,
+// Apply of degree 3 on the FP64 matrix cores (one wave per up to 8 cells of
+// an x-row); same contract as launch_apply_batch with N = 4 (prec 0: FP64
+// vectors, 1: FP32 vectors, widened on load, FP64 products).
+hipError_t launch_apply_mfma4_batch(int prec, const ApplyJob* jobs, int count, const DevTab& t,
                                     hipStream_t s);
 // FP64 apply of degree 7 on the matrix cores (one cell per wave); same
 // contract as launch_apply_batch with prec 0 and N = 8.
@@ -77,7 +82,8 @@ hipError_t launch_patch_mfma4_batch(int prec, int colour, const PatchJob* jobs, 
 // Batched forms: up to kMaxBatch problems of one degree per launch.
 // prec 0 = FP64 vectors (the apply on the matrix cores for N = 4 and 8),
 // 1 = FP32 vectors (VALU arithmetic), 2 (apply only) = FP64 vectors on the
-// vector units for every N.
+// vector units for every N, 3 (apply only) = FP32 vectors with FP64
+// matrix-core products at N = 4 (else as 1).
 hipError_t launch_apply_batch(int prec, int N, const ApplyJob* jobs, int count, const DevTab& t,
                               hipStream_t s);
 hipError_t launch_patch_fd_batch(int prec, int N, int colour, const PatchJob* jobs, int count,

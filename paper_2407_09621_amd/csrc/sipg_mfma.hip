@@ -36,6 +36,18 @@ namespace {
 // no per-value select.  The choice of pointer is wave-uniform (scalar).
 // Never written.
 __device__ __align__(16) double g_zero_cells[512];
+__device__ __align__(16) float g_zero_cells_f[512];
+
+template <typename T>
+__device__ __forceinline__ const T* zero_cells();
+template <>
+__device__ __forceinline__ const double* zero_cells<double>() {
+  return g_zero_cells;
+}
+template <>
+__device__ __forceinline__ const float* zero_cells<float>() {
+  return g_zero_cells_f;
+}
 
 constexpr int kT = 256;  // 4 waves per workgroup
 
@@ -98,8 +110,11 @@ __device__ __forceinline__ int cell_of(int t, int n, int blk) {
 //        (y,x,z) -permute-> (x,y,z)
 // The y neighbours are read directly in (x,z,y).  Per cell: 14 products and
 // about five permutations.
-template <bool RES, int CPW>
-__global__ __launch_bounds__(kT) void apply_mfma4_kernel(Batch<double> B,
+// T is the vector type: FP32 vectors (the FP32 V-cycle's residuals) are
+// widened on load and the result is rounded to FP32 on store; the products
+// are FP64.
+template <typename T, bool RES, int CPW>
+__global__ __launch_bounds__(kT) void apply_mfma4_kernel(Batch<T> B,
                                                          const double* __restrict__ tab,
                                                          TableLayout lay) {
   const int lane = threadIdx.x & 63;
@@ -107,9 +122,9 @@ __global__ __launch_bounds__(kT) void apply_mfma4_kernel(Batch<double> B,
                                                 (threadIdx.x >> 6));
   if (gi >= B.start[B.count]) return;  // wave-uniform; no barriers in this kernel
   const int pb = batch_find(B, gi);
-  const double* __restrict__ u = B.d[pb].in;
-  double* __restrict__ v = B.d[pb].out;
-  const double* __restrict__ bv = B.d[pb].aux;
+  const T* __restrict__ u = B.d[pb].in;
+  T* __restrict__ v = B.d[pb].out;
+  const T* __restrict__ bv = B.d[pb].aux;
   const double h = B.d[pb].h;
   const int n = B.d[pb].n, nn = n * n;
   // tile t covers cells c0 .. c0 + CPW - 1 along x
@@ -129,24 +144,24 @@ __global__ __launch_bounds__(kT) void apply_mfma4_kernel(Batch<double> B,
   // cell's z neighbours (x,y,z) and y neighbours (x,z,y).  All loads are
   // unconditional (a missing neighbour row reads the cells of zeros): one
   // basic block the compiler can schedule freely.
-  const double* pc = u + (size_t)c0 * 64;
-  const double* zc = g_zero_cells;
-  const double* pym = cy > 0 ? pc - (ptrdiff_t)n * 64 : zc;
-  const double* pyp = cy < n - 1 ? pc + (ptrdiff_t)n * 64 : zc;
-  const double* pzm = cz > 0 ? pc - (ptrdiff_t)nn * 64 : zc;
-  const double* pzp = cz < n - 1 ? pc + (ptrdiff_t)nn * 64 : zc;
+  const T* pc = u + (size_t)c0 * 64;
+  const T* zc = zero_cells<T>();
+  const T* pym = cy > 0 ? pc - (ptrdiff_t)n * 64 : zc;
+  const T* pyp = cy < n - 1 ? pc + (ptrdiff_t)n * 64 : zc;
+  const T* pzm = cz > 0 ? pc - (ptrdiff_t)nn * 64 : zc;
+  const T* pzp = cz < n - 1 ? pc + (ptrdiff_t)nn * 64 : zc;
   double u0[CPW], uym[CPW], uyp[CPW], uzm[CPW], uzp[CPW], b0[CPW];
 #pragma unroll
   for (int q = 0; q < CPW; ++q) {
-    u0[q] = pc[q * 64 + lane];
-    uym[q] = pym[q * 64 + oXZY];
-    uyp[q] = pyp[q * 64 + oXZY];
-    uzm[q] = pzm[q * 64 + lane];
-    uzp[q] = pzp[q * 64 + lane];
-    b0[q] = RES ? bv[(size_t)(c0 + q) * 64 + lane] : 0.0;
+    u0[q] = (double)pc[q * 64 + lane];
+    uym[q] = (double)pym[q * 64 + oXZY];
+    uyp[q] = (double)pyp[q * 64 + oXZY];
+    uzm[q] = (double)pzm[q * 64 + lane];
+    uzp[q] = (double)pzp[q * 64 + lane];
+    b0[q] = RES ? (double)bv[(size_t)(c0 + q) * 64 + lane] : 0.0;
   }
-  const double uxm0 = (cx0 > 0 ? pc - 64 : zc)[lane];
-  const double uxpE = (cx0 + CPW < n ? pc + CPW * 64 : zc)[lane];
+  const double uxm0 = (double)(cx0 > 0 ? pc - 64 : zc)[lane];
+  const double uxpE = (double)(cx0 + CPW < n ? pc + CPW * 64 : zc)[lane];
 
   // ---- matrix operands (uniform tables; the same registers serve as A and B)
   auto var = [&](int q) { return (q == 0 ? 1 : 0) | (q == n - 1 ? 2 : 0); };
@@ -185,9 +200,9 @@ __global__ __launch_bounds__(kT) void apply_mfma4_kernel(Batch<double> B,
     s = mma(aM, w, s);
     // Mz (s1 + s2) + t3, back to (x,y,z)
     const double o = gather(mma(aM, gather(s, s12), t3), s01);
-    double* dst = v + (size_t)(c0 + q) * 64 + lane;
-    if (RES) *dst = b0[q] - h * o;
-    else *dst = h * o;
+    T* dst = v + (size_t)(c0 + q) * 64 + lane;
+    if (RES) *dst = (T)(b0[q] - h * o);
+    else *dst = (T)(h * o);
   }
 }
 
@@ -689,10 +704,12 @@ __global__ __launch_bounds__(kT) void patch_mfma4_kernel(Batch<T> B, const doubl
 
 }  // namespace
 
-hipError_t launch_apply_mfma4_batch(const ApplyJob* jobs, int count, const DevTab& t,
-                                    hipStream_t s) {
+namespace {
+
+template <typename T>
+hipError_t apply_mfma4(const ApplyJob* jobs, int count, const DevTab& t, hipStream_t s) {
   if (t.lay.N != 4 || count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
-  Batch<double> B;
+  Batch<T> B;
   const bool residual = jobs[0].b != nullptr;
   // cells per wave: 8 when every mesh of the launch allows it, else 4, 2 or 1
   int cpw = 8;
@@ -704,11 +721,11 @@ hipError_t launch_apply_mfma4_batch(const ApplyJob* jobs, int count, const DevTa
     const ApplyJob& j = jobs[i];
     if (j.n < 1 || j.n > 1024 || !j.u || !j.v || (j.b != nullptr) != residual)
       return hipErrorInvalidValue;
-    Desc<double>& d = B.d[i];
-    d.in = (const double*)j.u;
-    d.out = (double*)j.v;
-    d.aux = (const double*)j.b;
-    d.h = j.h;
+    Desc<T>& d = B.d[i];
+    d.in = (const T*)j.u;
+    d.out = (T*)j.v;
+    d.aux = (const T*)j.b;
+    d.h = (T)j.h;
     d.n = j.n;
     d.a0 = cpw;
     d.a1 = j.n / cpw;
@@ -720,7 +737,7 @@ hipError_t launch_apply_mfma4_batch(const ApplyJob* jobs, int count, const DevTa
   const int grid = (B.start[count] + kT / 64 - 1) / (kT / 64);
   if (grid == 0) return hipSuccess;
 #define LAUNCH(RR, CC) \
-  hipLaunchKernelGGL((apply_mfma4_kernel<RR, CC>), dim3(grid), dim3(kT), 0, s, B, t.tab, t.lay)
+  hipLaunchKernelGGL((apply_mfma4_kernel<T, RR, CC>), dim3(grid), dim3(kT), 0, s, B, t.tab, t.lay)
   if (cpw == 8) {
     if (residual) LAUNCH(true, 8); else LAUNCH(false, 8);
   } else if (cpw == 4) {
@@ -732,6 +749,14 @@ hipError_t launch_apply_mfma4_batch(const ApplyJob* jobs, int count, const DevTa
   }
 #undef LAUNCH
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_apply_mfma4_batch(int prec, const ApplyJob* jobs, int count, const DevTab& t,
+                                    hipStream_t s) {
+  return prec == 0 ? apply_mfma4<double>(jobs, count, t, s)
+                   : apply_mfma4<float>(jobs, count, t, s);
 }
 
 }  // namespace sipg

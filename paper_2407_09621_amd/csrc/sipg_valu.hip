@@ -1628,7 +1628,8 @@ hipError_t transfer_impl(bool restr, const TransferJob* jobs, int count, const D
 hipError_t launch_apply_batch(int prec, int N, const ApplyJob* jobs, int count, const DevTab& t,
                               hipStream_t s) {
   if (t.lay.N != N) return hipErrorInvalidValue;
-  if (prec == 0 && N == 4) return launch_apply_mfma4_batch(jobs, count, t, s);
+  if ((prec == 0 || prec == 3) && N == 4)
+    return launch_apply_mfma4_batch(prec == 0 ? 0 : 1, jobs, count, t, s);
   if (prec == 0 && N == 8) return launch_apply_mfma8_batch(jobs, count, t, s);
   if (prec == 0 || prec == 2) {
 #define CALL(NN) apply_impl<double, NN>(jobs, count, t, s)
@@ -1707,6 +1708,11 @@ hipError_t launch_apply_f32(int N, const float* u, float* v, const float* b, con
                             int n, double h, hipStream_t s) {
   ApplyJob j{u, v, b, n, h};
   return launch_apply_batch(1, N, &j, 1, t, s);
+}
+hipError_t launch_residual_f32(int N, const float* u, float* v, const float* b, const DevTab& t,
+                               int n, double h, hipStream_t s) {
+  ApplyJob j{u, v, b, n, h};
+  return launch_apply_batch(3, N, &j, 1, t, s);
 }
 hipError_t launch_patch_fd_f64(int N, int colour, const double* r, double* x, const DevTab& t,
                                int n, double h, hipStream_t s) {
