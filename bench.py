@@ -122,6 +122,25 @@ def measured_copy_rate(stream, nbytes=1 << 30, reps=20):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
+def _oracle_solve_sample():
+    """The oracle's FGMRES(30) + V(2,2) solve of the sine problem on the small
+    configuration (k=2, 8^3 cells), rtol 1e-10, one core: hierarchy setup
+    (assembly, patch factors, coarse factor) and solve time."""
+    from oracle import fgmres, multigrid, rhs
+    n, k = 8, 2
+    t0 = time.perf_counter()
+    H = multigrid.Hierarchy(n, k)
+    A = H.levels[-1].A
+    prob = rhs.single_sine()
+    b = rhs.rhs(prob, n, k)
+    t1 = time.perf_counter()
+    x, info = fgmres.fgmres(lambda v: A @ v, b, H.precondition, rtol=1e-10)
+    t2 = time.perf_counter()
+    return {"setup_seconds": round(t1 - t0, 3), "solve_seconds": round(t2 - t1, 3),
+            "iterations": info["iterations"], "l2_error": rhs.l2_error(prob, x, n, k),
+            "cores": 1, "sample": "k=2, 8^3 cells (13,824 DoFs), sine problem, rtol 1e-10"}
+
+
 def _oracle_csr_sample(reps=100):
     """The oracle's assembled CSR matrix (3D/2D quadrature) on the small
     configuration (k=2, 8^3 cells, 13,824 DoFs): assembly time and 100
@@ -192,8 +211,9 @@ def cpu_baseline(max_workers=16):
     dofs_all = sum(r[0] for r in res)
     geo = _oracle_mapped_sample()
     csr = _oracle_csr_sample()
+    solve = _oracle_solve_sample()
     return {"value": dofs_all / wall / 1e9, "unit": "GDoF/s", "cores": W, "kind": "oracle",
-            "general_geometry": geo, "csr_spmv_small": csr,
+            "general_geometry": geo, "csr_spmv_small": csr, "solve_small": solve,
             "sample": f"{W} worker processes at once, each one FP64 apply at k=3 (64^3), "
                       f"k=5 (40^3) and k=7 (32^3) by the oracle's Kronecker-sum path "
                       f"(scipy.sparse, one thread each): {3 * W} applies, "
@@ -333,6 +353,23 @@ def run_vcycles(configs=((3, 64), (5, 32), (7, 32)), reps=5):
             del b, x
     torch.cuda.empty_cache()
     progress("v-cycles done")
+    return out
+
+
+def run_small_solve():
+    """The small configuration (k=2, 8^3 cells, 13,824 DoFs): FP64 FGMRES(30)
+    + V(2,2) of the sine problem to rtol 1e-10 on the GPU, beside the
+    oracle's solve of the same problem in the CPU baseline."""
+    from paper_2407_09621_amd import Problem, inputs
+    P = Problem(2, 8)
+    amps, pqr = inputs.single_sine_modes()
+    b = P.rhs_sines(amps, pqr)
+    P.fgmres(b, rtol=1e-10)
+    x, info = P.fgmres(b, rtol=1e-10)
+    out = {"workload": "k=2, 8^3 cells, sine problem, rtol 1e-10",
+           "seconds": round(info["seconds"], 5), "iterations": info["iterations"],
+           "rel_res_true": info["rel_res_true"], "l2_error": P.l2_error_sines(amps, pqr, x)}
+    P.close()
     return out
 
 
@@ -912,6 +949,7 @@ def main():
                                                    else SOLVE_CONFIGS)
     vcycles = None if args.no_solve else run_vcycles()
     comparisons = None if args.no_solve else run_comparisons()
+    small_solve = None if args.no_solve else run_small_solve()
     batch = None
     if not args.no_batch:
         batch = {"large": run_batch(count=args.batch_count),
@@ -933,7 +971,8 @@ def main():
         "cpu_baseline": cpu, "apply_units": units,
         "lowprec_apply": lp_rates, "patchwise_sweep": patchwise, "solves": solves,
         "vcycles": vcycles,
-        "krylov_smoother_comparison": comparisons, "batch": batch, "learned": learned,
+        "krylov_smoother_comparison": comparisons, "small_solve": small_solve,
+        "batch": batch, "learned": learned,
         "general_geometry": mapped,
     }
     print(json.dumps(line))
