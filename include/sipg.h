@@ -142,7 +142,9 @@ sipg_status sipg_apply(sipg_problem* p, int level, const double* u, double* v,
  * coarse solve keep the Cartesian fast diagonalization (an approximate
  * inverse on mapped cells; the outer FGMRES corrects for it).  NULL
  * restores the Cartesian mesh.  SIPG_ERR_UNSUPPORTED unless mg_precision is
- * SIPG_F64 and the smoother is 0 or 1; while a geometry is set,
+ * SIPG_F64 or SIPG_F32 (the FP32 V-cycle's residuals then run on the
+ * trilinear cells with FP32 vectors and FP64 arithmetic) and the smoother
+ * is 0 or 1; while a geometry is set,
  * sipg_rhs_sines and sipg_l2_error_sines integrate over the mapped cells
  * (the same Gauss rules with det J at every point; the sine modes vanish on
  * the boundary only where it stays on the unit cube's faces), and

@@ -105,7 +105,9 @@ sipg_status smooth(sipg_problem* p, int l, double* x, const double* b, int sweep
 // ---- low-precision V-cycle on FP32 vectors
 sipg_status residual_lp(sipg_problem* p, int l, const float* b, const float* x, float* r,
                         hipStream_t s) {
-  if (p->prec == SIPG_F32)
+  if (p->prec == SIPG_F32 && p->mapped)
+    SIPG_HIP(launch_apply_mapped_f32(p->N, x, r, b, mapped_level(p, l), p->d_mtab, s));
+  else if (p->prec == SIPG_F32)
     SIPG_HIP(launch_residual_f32(p->N, x, r, b, p->tab, p->n[l], level_h(p, l), s));
   else
     SIPG_HIP(launch_apply_lp(p->N, p->prec == SIPG_BF16, p->ec, x, r, b, p->tab, p->n[l],
@@ -466,9 +468,9 @@ sipg_status sipg_set_geometry(sipg_problem* p, const double* vertices, hipStream
     free_geometry(p);
     return SIPG_OK;
   }
-  if (p->prec != SIPG_F64 || p->cfg.smoother == 2)
+  if ((p->prec != SIPG_F64 && p->prec != SIPG_F32) || p->cfg.smoother == 2)
     return fail(SIPG_ERR_UNSUPPORTED,
-                "general geometry needs mg_precision SIPG_F64 and smoother 0 or 1");
+                "general geometry needs mg_precision SIPG_F64 or SIPG_F32 and smoother 0 or 1");
   const int L = p->L, nf = p->n[L - 1];
   const size_t nf1 = (size_t)nf + 1;
   std::vector<std::vector<double>> verts(L), gams(L);

@@ -148,6 +148,10 @@ struct MappedLevel {
 // mtab is the device copy of mapped_table(k).  u and v must not alias.
 hipError_t launch_apply_mapped(int N, const double* u, double* v, const double* b,
                                const MappedLevel& g, const double* mtab, hipStream_t s);
+// the same on FP32 vectors (widened on load, FP64 arithmetic, rounded on
+// store): the FP32 V-cycle's residuals on trilinear cells
+hipError_t launch_apply_mapped_f32(int N, const float* u, float* v, const float* b,
+                                   const MappedLevel& g, const double* mtab, hipStream_t s);
 // b = int f phi on the trilinear cells, f a sum of nm sine modes (modes:
 // [nm][coefficient, p, q, r]); qtab = quad_table(k, k + 2).
 hipError_t launch_rhs_mapped(int N, const MappedLevel& g, int nm, const double* modes,

@@ -151,10 +151,12 @@ __device__ __forceinline__ void line2(const double* M, const double* src, double
 // Gauss points, S[q * N + a] = phi_a(g_q)), D [N x N] (derivatives), Gauss
 // weights [N], Gauss points [N], phi'(0) [N], phi'(1) [N].  Cell c of the
 // launch is (blockIdx % 8) * chunk + blockIdx / 8 (contiguous chunks of
-// cells per XCD); blocks beyond n^3 cells return at once.
-template <int N>
+// cells per XCD); blocks beyond n^3 cells return at once.  VT is the vector
+// type: FP32 vectors (the FP32 V-cycle's residuals) are widened on load and
+// the result is rounded to FP32 on store; the arithmetic is FP64.
+template <typename VT, int N>
 __global__ __launch_bounds__(mapped_threads<N>()) void apply_mapped_kernel(
-    const double* __restrict__ u, double* __restrict__ v, const double* __restrict__ b,
+    const VT* __restrict__ u, VT* __restrict__ v, const VT* __restrict__ b,
     const double* __restrict__ vert, const double* __restrict__ gam,
     const double* __restrict__ mtab, int n, int chunk) {
   constexpr int T = mapped_threads<N>();
@@ -201,8 +203,8 @@ __global__ __launch_bounds__(mapped_threads<N>()) void apply_mapped_kernel(
     s_Xn[it] = val;
   }
   if (tid < 6) s_gam[tid] = gam[(size_t)c * 6 + tid];
-  const double* __restrict__ uc = u + (size_t)c * N3;
-  for (int p = tid; p < N3; p += T) s_u[p] = uc[p];
+  const VT* __restrict__ uc = u + (size_t)c * N3;
+  for (int p = tid; p < N3; p += T) s_u[p] = (double)uc[p];
   __syncthreads();
 
   const double* S = s_tab;
@@ -299,11 +301,11 @@ __global__ __launch_bounds__(mapped_threads<N>()) void apply_mapped_kernel(
     double lp = 0.0, dp = 0.0;
     const int qd = pos[d] + (side ? 1 : -1);
     if (qd >= 0 && qd < n) {
-      const double* __restrict__ un = u + (size_t)(c + (side ? 1 : -1) * cstride[d]) * N3 + base;
+      const VT* __restrict__ un = u + (size_t)(c + (side ? 1 : -1) * cstride[d]) * N3 + base;
       const double* Do = side ? D0 : D1;
-      lp = un[(side ? 0 : N - 1) * st3[d]];
+      lp = (double)un[(side ? 0 : N - 1) * st3[d]];
 #pragma unroll
-      for (int e = 0; e < N; ++e) dp += Do[e] * un[e * st3[d]];
+      for (int e = 0; e < N; ++e) dp += Do[e] * (double)un[e * st3[d]];
     }
     R1[it] = lm;
     R1[F + it] = dm;
@@ -397,8 +399,8 @@ __global__ __launch_bounds__(mapped_threads<N>()) void apply_mapped_kernel(
   line2<N, T, 0, true, true>(D, R1 + F, R2, P2);
   line2<N, T, 0, true, false>(S, R1 + 2 * F, R2 + F, P2);
   __syncthreads();
-  const double* __restrict__ bc = b ? b + (size_t)c * N3 : nullptr;
-  double* __restrict__ vc = v + (size_t)c * N3;
+  const VT* __restrict__ bc = b ? b + (size_t)c * N3 : nullptr;
+  VT* __restrict__ vc = v + (size_t)c * N3;
 #pragma unroll
   for (int j = 0; j < CellPts<N, T>::PP; ++j) {
     if (!P3.ok(j)) continue;
@@ -414,7 +416,7 @@ __global__ __launch_bounds__(mapped_threads<N>()) void apply_mapped_kernel(
       if (id[d] == (side ? N - 1 : 0)) val += R2[t];
       val += (side ? D1 : D0)[id[d]] * R2[F + t];
     }
-    vc[p] = bc ? bc[p] - val : val;
+    vc[p] = (VT)(bc ? (double)bc[p] - val : val);
   }
 }
 
@@ -592,16 +594,19 @@ __global__ __launch_bounds__(256) void sum_partials_kernel(const double* __restr
 
 }  // namespace
 
-hipError_t launch_apply_mapped(int N, const double* u, double* v, const double* b,
-                               const MappedLevel& g, const double* mtab, hipStream_t s) {
+namespace {
+
+template <typename VT>
+hipError_t apply_mapped(int N, const VT* u, VT* v, const VT* b, const MappedLevel& g,
+                        const double* mtab, hipStream_t s) {
   if (N < 2 || N > kMaxN || g.n < 1 || g.n > 1024 || !u || !v || !g.vert || !g.gam || !mtab)
     return hipErrorInvalidValue;
   const int nc = g.n * g.n * g.n;
   const int chunk = (nc + 7) / 8;
   const dim3 grid(8 * chunk);
-#define LAUNCH(NN)                                                                          \
-  hipLaunchKernelGGL(apply_mapped_kernel<NN>, grid, dim3(mapped_threads<NN>()), 0, s, u, v, \
-                     b, g.vert, g.gam, mtab, g.n, chunk)
+#define LAUNCH(NN)                                                                      \
+  hipLaunchKernelGGL((apply_mapped_kernel<VT, NN>), grid, dim3(mapped_threads<NN>()), 0, s, \
+                     u, v, b, g.vert, g.gam, mtab, g.n, chunk)
   switch (N) {
     case 2: LAUNCH(2); break;
     case 3: LAUNCH(3); break;
@@ -614,6 +619,18 @@ hipError_t launch_apply_mapped(int N, const double* u, double* v, const double* 
   }
 #undef LAUNCH
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_apply_mapped(int N, const double* u, double* v, const double* b,
+                               const MappedLevel& g, const double* mtab, hipStream_t s) {
+  return apply_mapped<double>(N, u, v, b, g, mtab, s);
+}
+
+hipError_t launch_apply_mapped_f32(int N, const float* u, float* v, const float* b,
+                                   const MappedLevel& g, const double* mtab, hipStream_t s) {
+  return apply_mapped<float>(N, u, v, b, g, mtab, s);
 }
 
 hipError_t launch_rhs_mapped(int N, const MappedLevel& g, int nm, const double* modes,

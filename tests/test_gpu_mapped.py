@@ -141,7 +141,7 @@ def test_geometry_errors_and_cartesian_only_calls():
         P.apply_lp(u.float(), precision="f32")
     assert e.value.status == 2
     P.close()
-    Q = Problem(k, n, mg_precision="f32")
+    Q = Problem(k, n, mg_precision="f16", error_correction=True)
     with pytest.raises(SipgError) as e:
         Q.set_geometry(_mesh(n, "smooth", 1))
     assert e.value.status == 2
@@ -212,3 +212,32 @@ def test_mapped_vcycle_matches_oracle(k, n, kind):
     ref = M.vcycle(len(M.A) - 1, np.zeros_like(b), b)
     assert rel_l2(to_cpu(x), ref) < 1e-11
     P.close()
+
+
+@pytest.mark.parametrize("k,n,kind", [(3, 8, "smooth"), (2, 8, "smooth"), (5, 4, "smooth"),
+                                      (2, 4, "jitter")])
+def test_fp32_vcycle_on_mapped_mesh(k, n, kind):
+    """The FP32 V-cycle on trilinear cells (FP32 vectors, FP64 arithmetic in
+    the residuals): one cycle within FP32 rounding of the FP64 cycle, and
+    FGMRES with it reaches the oracle's direct solve.  (On jittered meshes
+    with interior levels the Cartesian patch inverses stop being a useful
+    approximation: the oracle's V-cycle diverges there, see
+    test_oracle_mapped.py.)"""
+    import scipy.sparse.linalg as spla
+    from paper_2407_09621_amd import Problem
+    announce("mapped fp32 vcycle", k, n, kind)
+    V = _mesh(n, kind, 8)
+    P64, P32 = Problem(k, n), Problem(k, n, mg_precision="f32")
+    P64.set_geometry(V)
+    P32.set_geometry(V)
+    b = inputs.uniform_vector(P64.n_dofs(), seed=14)
+    x64, x32 = to_gpu(np.zeros_like(b)), to_gpu(np.zeros_like(b))
+    P64.vcycle(x64, to_gpu(b))
+    P32.vcycle(x32, to_gpu(b))
+    assert rel_l2(to_cpu(x32), to_cpu(x64)) < 1e-5
+    x, info = P32.fgmres(to_gpu(b), rtol=1e-10, max_iters=300)
+    ref = spla.spsolve(mapped.assemble_mapped(n, k, V).tocsc(), b)
+    assert info["rel_res_true"] <= 1e-9
+    assert rel_l2(to_cpu(x), ref) < 1e-6
+    P64.close()
+    P32.close()

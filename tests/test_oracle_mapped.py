@@ -197,3 +197,19 @@ def test_mapped_vcycle_contracts_on_a_deformed_mesh():
         x = x + M.vcycle(len(M.A) - 1, np.zeros_like(b), b - A @ x)
         errs.append(np.linalg.norm(x - xs))
     assert errs[-1] < 0.05 * errs[0] and all(errs[i + 1] < errs[i] for i in range(3))
+
+
+def test_mapped_vcycle_diverges_on_a_strongly_jittered_mesh():
+    """The limit of the Cartesian inverses (reading R20 of the design): on
+    8^3 cells with interior vertices moved by up to 0.2 h the V-cycle with
+    Cartesian patch and coarse inverses amplifies the error; recorded so the
+    limitation stays visible."""
+    import scipy.sparse.linalg as spla
+    n, k = 8, 2
+    V = inputs.mesh_vertices(n, "jitter", 0.2, seed=8)
+    M = mapped.MappedHierarchy(n, k, V)
+    A = M.A[-1]
+    b = inputs.uniform_vector(A.shape[0], 14)
+    xs = spla.spsolve(A.tocsc(), b)
+    x = M.vcycle(len(M.A) - 1, np.zeros_like(b), b)
+    assert np.linalg.norm(x - xs) > np.linalg.norm(xs)
