@@ -511,10 +511,12 @@ def run_mapped(stream, reps=10):
         torch.cuda.empty_cache()
     solves = {}
     for k, n in ((3, 32), (7, 16)):
-        for geo in ("cartesian", "mapped"):
+        for geo in ("cartesian", "mapped", "jitter0.1"):
             P = Problem(k, n)
             if geo == "mapped":
                 P.set_geometry(inputs.mesh_vertices(n, "smooth", MAPPED_AMPLITUDE, seed=1))
+            elif geo == "jitter0.1":   # interior vertices moved by up to 0.1 h
+                P.set_geometry(inputs.mesh_vertices(n, "jitter", 0.1, seed=8))
             b = torch.from_numpy(inputs.uniform_vector(P.n_dofs(), seed=77)).cuda()
             P.fgmres(b, rtol=1e-10, max_iters=200, raise_on_nonconvergence=False)
             x, info = P.fgmres(b, rtol=1e-10, max_iters=200, raise_on_nonconvergence=False)
